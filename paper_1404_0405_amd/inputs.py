@@ -1,0 +1,138 @@
+"""Seeded synthetic initial conditions (point values at nodes and edge midpoints).
+
+This module holds no arithmetic of the method itself: it turns coordinates (supplied by the
+caller, each side computing its own) into initial fields.  The HIP library and the oracle
+both receive their inputs from here.
+
+Workloads (stand-ins for the paper's test cases, Sec. 6):
+
+* ``tc2``: steady geostrophic zonal flow (Williamson test 2, Sec. 6.2),
+  u = u0 cos(lat) eastward, g h = g h0 - (a Omega u0 + u0^2/2) sin^2(lat), u0 = 2 pi a / 12 d,
+  g h0 = 2.94e4 m^2/s^2.  The printed height uses cos(lat) and drops a from U; the form used
+  here is the one that is in gradient-wind balance.
+* ``tc2_perturbed``: tc2 plus a seeded smooth height perturbation, sum of real spherical
+  harmonics 1 <= l <= 32 with N(0,1) coefficients, scaled to 10 m maximum amplitude.
+* ``jet``: zonal jet u = 80 exp(-((lat-45)/8)^2) m/s with the height in gradient-wind balance
+  (composite Simpson quadrature), mean depth 10 km, plus a Gaussian height bump (stand-in for
+  the Galewsky jet of Sec. 6.4).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+EARTH_RADIUS = 6.371e6
+OMEGA = 7.292e-5
+GRAVITY = 9.80616
+DAY = 86400.0
+SEED_BASE = 14040405
+
+
+def tc2_constants(radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY):
+    u0 = 2.0 * math.pi * radius / (12.0 * DAY)
+    gh0 = 2.94e4
+    return u0, gh0, gh0 / gravity
+
+
+def tc2(node_xyz, edge_mid, edge_tan, radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY):
+    """Returns (dh, u, H): perturbation height at nodes, normal velocity at edges, mean depth."""
+    u0, gh0, H = tc2_constants(radius, omega, gravity)
+    z = node_xyz[:, 2] / np.linalg.norm(node_xyz, axis=1)
+    dh = -(radius * omega * u0 + 0.5 * u0 * u0) * z * z / gravity
+    m = edge_mid / np.linalg.norm(edge_mid, axis=1, keepdims=True)
+    vel = u0 * np.stack([-m[:, 1], m[:, 0], np.zeros_like(m[:, 0])], 1)   # u0 * z_hat x x
+    u = (vel * edge_tan).sum(1)
+    return dh, u, H
+
+
+def real_sph_harm_sum(xyz, coeffs, lmax):
+    """S(x) = sum_{l=1..lmax} sum_{m=-l..l} a_lm Y_lm(x), orthonormal real harmonics.
+
+    ``coeffs[l, lmax + m]`` holds a_lm.  Associated Legendre functions by the standard stable
+    recurrences in m then l.
+    """
+    x = xyz / np.linalg.norm(xyz, axis=1, keepdims=True)
+    ct = x[:, 2]
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    lon = np.arctan2(x[:, 1], x[:, 0])
+    out = np.zeros(x.shape[0])
+    pmm = np.full(x.shape[0], math.sqrt(1.0 / (4.0 * math.pi)))
+    for m in range(0, lmax + 1):
+        if m > 0:
+            pmm = -math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm
+        p_prev, p_cur = None, pmm
+        for l in range(m, lmax + 1):
+            if l == m + 1:
+                p_prev, p_cur = p_cur, math.sqrt(2.0 * m + 3.0) * ct * pmm
+            elif l > m + 1:
+                a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+                b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+                p_prev, p_cur = p_cur, a * (ct * p_cur - b * p_prev)
+            if l == 0:
+                continue
+            if m == 0:
+                out += coeffs[l, lmax] * p_cur
+            else:
+                out += coeffs[l, lmax + m] * math.sqrt(2.0) * p_cur * np.cos(m * lon)
+                out += coeffs[l, lmax - m] * math.sqrt(2.0) * p_cur * np.sin(m * lon)
+    return out
+
+
+def sh_coefficients(seed, lmax):
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((lmax + 1, 2 * lmax + 1))
+    c[0, :] = 0.0
+    return c
+
+
+def tc2_perturbed(node_xyz, edge_mid, edge_tan, seed=SEED_BASE + 1, lmax=32, amplitude=10.0,
+                  radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY):
+    dh, u, H = tc2(node_xyz, edge_mid, edge_tan, radius, omega, gravity)
+    S = real_sph_harm_sum(node_xyz, sh_coefficients(seed, lmax), lmax)
+    return dh + amplitude * S / np.abs(S).max(), u, H
+
+
+def random_state(n_nodes, n_edges, seed, dh_scale=100.0, u_scale=10.0):
+    """Unstructured random fields (for identity and parity tests, not physical)."""
+    rng = np.random.default_rng(seed)
+    return dh_scale * rng.standard_normal(n_nodes), u_scale * rng.standard_normal(n_edges)
+
+
+def jet_profile(radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY, umax=80.0, lat0=45.0, width=8.0,
+                mean_depth=1.0e4, npts=200001):
+    """Latitude table of the balanced jet height, h(lat) = h0 - (a/g) int u (f + u tan/a) dlat."""
+    lat = np.linspace(-math.pi / 2, math.pi / 2, npts)
+    u = umax * np.exp(-((np.degrees(lat) - lat0) / width) ** 2)
+    f = 2.0 * omega * np.sin(lat)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        integrand = np.where(np.abs(np.cos(lat)) > 1e-12, u * (f + u * np.tan(lat) / radius), 0.0)
+    step = lat[1] - lat[0]
+    cum = np.zeros(npts)
+    # composite Simpson on pairs of intervals, trapezoid for the odd leftover point
+    cum[2::2] = np.cumsum((integrand[0:-2:2] + 4 * integrand[1:-1:2] + integrand[2::2]) * step / 3.0)
+    cum[1::2] = cum[0:-1:2] + 0.5 * step * (integrand[0:-1:2] + integrand[1::2])
+    hrel = -(radius / gravity) * cum
+    # area mean of h equals mean_depth: mean over the sphere weights by cos(lat)
+    w = np.cos(lat)
+    h0 = mean_depth - (hrel * w).sum() / w.sum()
+    return lat, u, h0 + hrel
+
+
+def jet(node_xyz, edge_mid, edge_tan, bump=120.0, bump_lat=45.0, bump_lon=0.0,
+        radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY, mean_depth=1.0e4):
+    lat_t, u_t, h_t = jet_profile(radius, omega, gravity, mean_depth=mean_depth)
+    x = node_xyz / np.linalg.norm(node_xyz, axis=1, keepdims=True)
+    lat = np.arcsin(np.clip(x[:, 2], -1, 1))
+    lon = np.arctan2(x[:, 1], x[:, 0])
+    h = np.interp(lat, lat_t, h_t)
+    dlon = np.degrees(lon) - bump_lon
+    dlon = (dlon + 180.0) % 360.0 - 180.0
+    h = h + bump * np.exp(-((np.degrees(lat) - bump_lat) / 6.0) ** 2) * np.exp(-(dlon / 12.0) ** 2)
+    m = edge_mid / np.linalg.norm(edge_mid, axis=1, keepdims=True)
+    mlat = np.arcsin(np.clip(m[:, 2], -1, 1))
+    speed = np.interp(mlat, lat_t, u_t)
+    east = np.stack([-m[:, 1], m[:, 0], np.zeros_like(m[:, 0])], 1)
+    east /= np.maximum(np.linalg.norm(east, axis=1, keepdims=True), 1e-300)
+    u = speed * (east * edge_tan).sum(1)
+    return h - mean_depth, u, mean_depth
