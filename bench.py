@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Throughput of the TRiSK Runge-Kutta stage on one MI355X.
+
+Workload (default): uniform icosahedral C-grid J=10 (10,485,762 cells, 31,457,280 edges),
+Williamson test 2 zonal flow plus a seeded spherical-harmonic height perturbation (l <= 32,
+10 m), classical RK4, dt = 0.8 x the stable step.  A "step" is one RK4 step = four tendency
+evaluations (stages).  The metric is active-point RK-stage updates per second:
+(active nodes + active edges) x 4 stages x steps / wall time, inputs resident in HBM.
+
+Prints ONE JSON line.  Plain FP64 is the headline `value`; the FP32-tendency form is reported
+beside it under "fp32_tendency".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _algorithmic_bytes(N, E, T, fp32):
+    """Unique bytes read + written by each stage kernel per launch (tables, inputs, outputs;
+    each array element counted once), for the table-driven kernels.  RK4 stage-averaged
+    epilogue traffic: 3.25 state accesses of 8 B per degree of freedom."""
+    s = 4 if fp32 else 8           # intermediate (q_v, B, F, q_e) element size
+    vertex = T * (12 + 12 + 24 + 24 + 8) + T * s + E * 8 + N * 8
+    edge_cell = N * (24 + 48 + 8) + N * s + E * (8 + 8 + 8) + 2 * E * s + T * s
+    tend = N * (24 + 48) + E * (8 + 8 + 40 + 80) + (N + 2 * E) * s + (N + E) * 3.25 * 8
+    return {"trisk_vertex": vertex, "trisk_edge_cell": edge_cell, "trisk_tend": tend}
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    from paper_1404_0405_amd import inputs, wt
+
+    J = args.level
+    g = wt.Grid(J, J, 8)
+    stream = torch.cuda.current_stream()
+    g.set_stream(stream.cuda_stream)
+    N, E, T = g.info(J)
+    x, m, t = g.coords(J)
+    dh0, u0, H = inputs.tc2_perturbed(x, m, t, seed=inputs.SEED_BASE + 1, device="cuda")
+    g.set_params(mean_depth=H, rk=wt.WT_RK4, precision=wt.WT_FP64)
+    g.set_state(J, dh0, u0)
+    dt = g.suggest_dt(0.8)
+    out = {}
+    for mode in ("fp64", "fp32"):
+        g.set_params(precision=wt.WT_FP64 if mode == "fp64" else wt.WT_FP32_TENDENCY)
+        g.set_state(J, dh0, u0)
+        d0, _ = g.diagnostics()
+        for _ in range(args.warmup):
+            g.step(dt)
+        torch.cuda.synchronize()
+        g.timing_reset()
+        g.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.step(dt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.timing(False)
+        kt = {k: g.kernel_time(k) for k in wt.kernel_names()}
+        d1, code = g.diagnostics()
+        wall = t1 - t0
+        upd = (N + E) * 4 * args.steps / wall
+        ab = _algorithmic_bytes(N, E, T, mode == "fp32")
+        kernels = {}
+        for k, (ms, cnt) in kt.items():
+            avg_ms = ms / max(cnt, 1)
+            kernels[k] = {"avg_ms": avg_ms, "launches": cnt,
+                          "algorithmic_bytes": ab[k], "gbs": ab[k] / (avg_ms * 1e-3) / 1e9}
+        out[mode] = dict(value=upd, ms_per_step=wall * 1e3 / args.steps, kernels=kernels,
+                         mass_drift=abs(d1.mass / d0.mass - 1), energy_drift=abs(d1.energy / d0.energy - 1),
+                         finite=code == wt.WT_OK)
+        if mode == "fp64":
+            state64 = g.get_state(J)[:2]
+        else:
+            state32 = g.get_state(J)[:2]
+    # error of the FP32-tendency run against the FP64 run (same steps)
+    dh64, _ = state64
+    dh32, _ = state32
+    out["fp32"]["rel_l2_height_vs_fp64"] = float(
+        np.sqrt(((dh32 - dh64) ** 2).sum() / ((H + dh64) ** 2).sum()))
+    g.close()
+    return out, (N, E, T), dt
+
+
+def cpu_baseline(level=8, steps=4):
+    """The oracle as it stands (numpy FP64, one host thread), on a bounded sample of the same
+    workload: `steps` RK4 steps of the same flow on a level-`level` grid."""
+    from oracle import trisk
+    from oracle.grid import Grid
+    from paper_1404_0405_amd import inputs
+    og = Grid(level)
+    dh, u, H = inputs.tc2_perturbed(og.xyz, og.e_mid, og.e_tan)
+    p = trisk.Params(mean_depth=H)
+    dt = trisk.suggest_dt(og, dh, u, p, 0.8)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dh, u = trisk.step(og, dh, u, dt, p)
+    wall = time.perf_counter() - t0
+    return {"value": (og.N + og.E) * 4 * steps / wall, "unit": "active-point RK-stage updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the same TC2+SH flow on the uniform level-{level} grid "
+                      f"({og.N} cells, {og.E} edges), numpy FP64 oracle, one host thread; "
+                      f"{wall:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--level", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              "the multi-GPU path is not part of it", file=sys.stderr)
+        sys.exit(2)
+    res, (N, E, T), dt = run_gpu(args)
+    f64 = res["fp64"]
+    dom = max(f64["kernels"], key=lambda k: f64["kernels"][k]["avg_ms"])
+    kd = f64["kernels"][dom]
+    line = {
+        "metric": "active-point RK-stage updates/s",
+        "value": f64["value"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uniform icosahedral C-grid J={args.level} ({N} cells, {E} edges), "
+                               "TC2 zonal flow + seeded SH height perturbation (l<=32, 10 m), RK4, "
+                               f"dt={dt:.3f} s (CFL 0.8)",
+                   "level": args.level, "cells": N, "edges": E, "rk": "rk4", "stages_per_step": 4},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "kernels_fp64": f64["kernels"],
+        "stage_ms_fp64": f64["ms_per_step"] / 4,
+        "fp32_tendency": {"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"],
+                          "rel_l2_height_vs_fp64": res["fp32"]["rel_l2_height_vs_fp64"],
+                          "mass_drift": res["fp32"]["mass_drift"], "kernels": res["fp32"]["kernels"]},
+        "mass_drift_fp64": f64["mass_drift"],
+        "energy_drift_fp64": f64["energy_drift"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * wt.h -- C ABI of the MI355X (gfx950) adaptive wavelet TRiSK shallow-water library.
+ *
+ * Method: Aechtner, Kevlahan & Dubos, "A conservative adaptive wavelet method for the
+ * shallow water equations on the sphere" (arXiv:1404.0405).  Section, equation and table
+ * numbers below refer to that paper.
+ *
+ * Conventions shared by every call
+ *   - Every int-returning call returns WT_OK (0) or a negative WT_E* code; the message of the
+ *     last failure on the calling thread is returned by wt_last_error().
+ *   - Pointer arguments named *host* are caller-owned host memory, read or written during the
+ *     call only; the library keeps no pointer.  Device pointers are named *_device.
+ *   - Level j runs over jmin..jmax.  Level j has n = 2^j, N = 10 n^2 + 2 nodes,
+ *     E = 30 n^2 edges and T = 20 n^2 triangles (Table 1).
+ *   - Canonical ordering (the only layout exchanged at this boundary; device layouts are
+ *     internal): node (L,i,j) with lozenge 0 <= L < 10 and 0 <= i,j < n has id
+ *     (L*n + i)*n + j; the north and south poles are 10n^2 and 10n^2+1.  Lozenges 0..4 are
+ *     the faces (U_k, L_k, U_k+1) + (U_k, U_k+1, N), lozenges 5..9 the faces
+ *     (L_k, S, L_k+1) + (L_k, L_k+1, U_k+1) of the icosahedron with upper ring U_k at
+ *     longitude 72k and lower ring L_k at 72k+36 degrees; i runs from corner c00 to c10, j
+ *     from c00 to c01.  Edge 3*id + d joins node (i,j) to (i+1,j), (i+1,j+1), (i,j+1) for
+ *     d = 0,1,2; the normal velocity u_e is positive from the owning node to the other end.
+ *     Level j+1 node (L,2i,2j) is level j node (L,i,j) (nested grids, Sec. 2.1-2.2).
+ *   - Prognostic variables: dh = h - H at nodes (metres) and u at edges (m/s), point values.
+ *   - A wt_grid is used by one host thread at a time; all device work of a grid is ordered on
+ *     its stream.
+ */
+#ifndef WT_H
+#define WT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wt_grid wt_grid;
+
+enum {
+  WT_OK = 0,
+  WT_EINVAL = -1,   /* bad argument (level, size, null pointer, parameter range) */
+  WT_ENOMEM = -2,   /* host or device allocation failed */
+  WT_EDEVICE = -3,  /* HIP runtime error, or no gfx950 device */
+  WT_ESTATE = -4,   /* call out of order (e.g. wt_step before wt_set_state) */
+  WT_ENUMERIC = -5  /* non-finite value found in the state */
+};
+
+/* Time schemes (Sec. 3.1): the paper's four-stage third-order SSP Runge-Kutta, and classical
+ * four-stage RK4.  Both evaluate the tendencies four times per step. */
+enum { WT_RK4 = 0, WT_SSPRK43 = 1 };
+
+/* Arithmetic of the tendencies.  WT_FP64: everything in double.  WT_FP32_TENDENCY: the
+ * tendencies are computed in single precision while the prognostic state, the Runge-Kutta
+ * accumulation, the divergence sums and the mass/energy diagnostics stay in double (the
+ * paper keeps mimetic quantities in double and truncation-limited ones in single, Sec. 5.1). */
+enum { WT_FP64 = 0, WT_FP32_TENDENCY = 1 };
+
+typedef struct {
+  double radius;      /* sphere radius a [m], default 6.371e6 */
+  double omega;       /* rotation rate [1/s], default 7.292e-5 (Sec. 6) */
+  double gravity;     /* g [m/s^2], default 9.80616 (Sec. 6) */
+  double mean_depth;  /* H [m], h = H + dh; default 2.94e4 / g */
+  int rk;             /* WT_RK4 (default) or WT_SSPRK43 */
+  int precision;      /* WT_FP64 (default) or WT_FP32_TENDENCY */
+} wt_params;
+
+typedef struct {
+  double mass;        /* sum_k A_k (H + dh_k) on level jmin [m^3] (Sec. 3.2) */
+  double energy;      /* E of Sec. 7.2 on the finest full level [m^5/s^2] */
+  double max_abs_dh;  /* max |dh| over active nodes of all levels */
+  double max_abs_u;   /* max |u| over active edges of all levels */
+  int64_t active_nodes[16]; /* per level j (index j), active node count */
+  int64_t active_edges[16]; /* per level j (index j), active edge count */
+} wt_diag;
+
+/* Create a grid with levels jmin..jmax (0 <= jmin <= jmax <= 12) and adaptivity patch size
+ * patch in {4, 8, 16} (Sec. 5.2: patches are the smallest unit of the adapted structure;
+ * results do not depend on it).  Builds the geometry of every level on the host (Sec. 4.1)
+ * and uploads it; selects HIP device 0 unless one is current.  Returns NULL on error. */
+wt_grid* wt_grid_create(int jmin, int jmax, int patch);
+
+/* Frees all host and device memory of the grid.  NULL is accepted. */
+void wt_grid_destroy(wt_grid* g);
+
+/* Set / read the physical and numerical parameters.  wt_set_params before wt_set_state;
+ * radius and omega are fixed when the grid is created (they shape the geometry), so a
+ * different radius/omega returns WT_EINVAL. */
+int wt_set_params(wt_grid* g, const wt_params* p);
+int wt_get_params(const wt_grid* g, wt_params* p);
+
+/* Sizes of level `level`: nodes, edges, triangles.  Any pointer may be NULL. */
+int wt_grid_info(const wt_grid* g, int level, int64_t* n_nodes, int64_t* n_edges,
+                 int64_t* n_tris);
+
+/* Unit-sphere coordinates of level `level`, canonical order, host arrays:
+ * node_xyz_host[3N], edge_mid_xyz_host[3E] (arc midpoint), edge_tangent_xyz_host[3E] (unit
+ * tangent at the midpoint, pointing along positive u).  Any pointer may be NULL. */
+int wt_grid_coords(const wt_grid* g, int level, double* node_xyz_host,
+                   double* edge_mid_xyz_host, double* edge_tangent_xyz_host);
+
+/* Load the prognostic state of level `level` from host arrays dh_host[N], u_host[E]
+ * (canonical order).  The level becomes fully active.  On a uniform grid (jmin == jmax) this
+ * is the whole state. */
+int wt_set_state(wt_grid* g, int level, const double* dh_host, const double* u_host);
+
+/* Same, from device arrays (stream-ordered on the grid's stream). */
+int wt_set_state_device(wt_grid* g, int level, const void* dh_device, const void* u_device);
+
+/* Read the state of level `level` into host arrays dh_host[N], u_host[E] (canonical
+ * order); node_active_host[N] / edge_active_host[E] receive 1 for active points.  Any
+ * pointer may be NULL.  Synchronises the grid's stream. */
+int wt_get_state(wt_grid* g, int level, double* dh_host, double* u_host,
+                 uint8_t* node_active_host, uint8_t* edge_active_host);
+
+/* Advance the state by one Runge-Kutta step of length dt seconds (four tendency
+ * evaluations, eqs. (height) and (velo), TRiSK discretisation with the energy-conserving
+ * qF^perp, Sec. 3.1).  Asynchronous on the grid's stream. */
+int wt_step(wt_grid* g, double dt);
+
+/* Evaluate the tendencies d(dh)/dt and du/dt of the current state of a full level into host
+ * arrays ddh_host[N], du_host[E] (canonical order).  Test and diagnostic hook; synchronises. */
+int wt_tendency(wt_grid* g, int level, double* ddh_host, double* du_host);
+
+/* Diagnostics of the current state (mass Sec. 3.2, energy Sec. 7.2, maxima); synchronises.
+ * Returns WT_ENUMERIC (and fills the struct) if the state holds a non-finite value. */
+int wt_diagnostics(wt_grid* g, wt_diag* d);
+
+/* Stable time step dt = cfl * min(1/omega_max, min_e d_e/|u_e|) over the finest active
+ * level, omega_max = max sqrt(f^2 + g h (pi/d_e)^2) (Sec. 3.1, with the wavenumber squared).
+ * Returns a negative value on error. */
+double wt_suggest_dt(wt_grid* g, double cfl);
+
+/* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) for all
+ * later device work of the grid; NULL selects the library's own stream. */
+int wt_set_stream(wt_grid* g, void* hip_stream);
+
+/* Kernel timing for measurement: when enabled, every launch of the TRiSK stage kernels is
+ * bracketed by HIP events on the grid's stream.  wt_kernel_time returns the summed device
+ * time (ms) and launch count of the kernel named `name` since the last reset; names are
+ * listed by wt_kernel_names (comma separated). */
+int wt_timing_enable(wt_grid* g, int enable);
+int wt_timing_reset(wt_grid* g);
+int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches);
+const char* wt_kernel_names(void);
+
+/* Host-only inspection of the grid builder (no device needed): builds level `level` with
+ * the given radius [m] and omega [1/s] and copies selected tables into caller arrays, canonical
+ * order; any pointer may be NULL.  A_i_host[N] cell areas, A_v_host[T] triangle areas,
+ * d_e_host[E] node-node arc lengths, l_e_host[E] dual edge lengths, e_nodes_host[2E]
+ * from/to node of every edge, ecp_host[10E] and w_host[10E] the perpendicular-flux stencil
+ * and weights w_{e,e'} of the energy-conserving qF^perp (Sec. 3.1; padded slots hold e itself
+ * with weight 0).  Sizes are those of wt_grid_info.  For tests of the builder. */
+int wt_host_level_tables(int level, double radius, double omega, double* A_i_host,
+                         double* A_v_host, double* d_e_host, double* l_e_host,
+                         int32_t* e_nodes_host, int32_t* ecp_host, double* w_host);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* wt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WT_H */

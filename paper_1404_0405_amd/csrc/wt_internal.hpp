@@ -1,0 +1,86 @@
+// Internal device structures and kernel launchers of libwt.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wt_grid.hpp"
+
+namespace wt {
+
+// Device tables of one full level, laid out per element (canonical order): element `id`
+// owns node id, edges 3id..3id+2 and triangles 2id, 2id+1 (the two poles own only a node).
+struct DevTables {
+  int64_t N = 0, E = 0, T = 0, n_elem = 0;  // n_elem = 10 n^2 (elements with edges)
+  int32_t* c_e = nullptr;     // 6N edges of each cell (padded with a valid edge)
+  double* c_div = nullptr;    // 6N  n_{e,i} l_e / A_i          (0 in padded slots)
+  double* c_ke = nullptr;     // 6N  l_e d_e / (4 A_i)
+  int32_t* e_c = nullptr;     // 2E  from / to node
+  int32_t* e_v = nullptr;     // 2E  left / right triangle
+  double* inv_d = nullptr;    // E   1/d_e
+  int32_t* ecp = nullptr;     // 10E perpendicular-flux stencil
+  double* wl = nullptr;       // 10E w_{e,e'} l_{e'} / d_e
+  int32_t* t_n = nullptr;     // 3T  triangle nodes
+  int32_t* t_e = nullptr;     // 3T  triangle edges
+  double* t_curl = nullptr;   // 3T  t_{e,v} d_e / A_v
+  double* t_R = nullptr;      // 3T  kite / A_v  (weights of h_v)
+  double* f_v = nullptr;      // T   Coriolis parameter at the circumcentre
+  double* A_i = nullptr;      // N
+  double* l_e = nullptr;      // E
+  double* d_e = nullptr;      // E
+};
+
+// Work buffers of one level (double unless noted).
+struct DevWork {
+  double *dh = nullptr, *u = nullptr;          // prognostic state y
+  double *dh_acc = nullptr, *u_acc = nullptr;  // Runge-Kutta accumulator
+  double *dh_s[2] = {nullptr, nullptr}, *u_s[2] = {nullptr, nullptr};  // stage inputs
+  void *qv = nullptr, *B = nullptr, *F = nullptr, *qe = nullptr;     // T-typed intermediates
+  double* ddh = nullptr;                       // tendency output buffers (test hook)
+  double* du = nullptr;
+  double* red = nullptr;                       // reduction scratch
+};
+
+struct PhysParams {
+  double g, H;
+};
+
+// Generic Runge-Kutta epilogue evaluated at every point after the tendency k:
+//   o1 = a1*y + b1*acc + c1*x + d1*k     (if o1 != null)
+//   o2 = a2*y + b2*acc + c2*x + d2*k     (if o2 != null)
+struct StageOut {
+  double a1, b1, c1, d1, a2, b2, c2, d2;
+};
+struct StagePtrs {
+  const double *y, *acc, *x;
+  double *o1, *o2;
+};
+
+enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_COUNT };
+extern const char* const kKernelNames[K_COUNT];
+
+struct Timer {
+  bool enabled = false;
+  struct Rec {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+};
+
+void upload_tables(const Level& L, DevTables& t);
+void free_tables(DevTables& t);
+
+// One tendency evaluation on stage input (x_dh, x_u) followed by the RK epilogue.
+void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
+                  const StagePtrs& sdh, const StagePtrs& su, const StageOut& c,
+                  hipStream_t s, Timer* tm);
+
+// Diagnostics: out[0]=mass, out[1]=energy, out[2]=max|dh|, out[3]=max|u|, out[4]=non-finite
+// count, out[5]=omega_max, out[6]=min d_e/|u_e|.
+void launch_diagnostics(const DevTables& t, DevWork& w, const PhysParams& p, hipStream_t s,
+                        double* host_out);
+
+}  // namespace wt

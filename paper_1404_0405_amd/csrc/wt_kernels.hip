@@ -1,0 +1,342 @@
+// TRiSK stage kernels for gfx950 (table-driven form, one thread per element).
+//
+// One tendency evaluation of eqs. (height) and (velo) (Sec. 3.1) in three launches:
+//   k_vertex     q_v = (zeta_v + f_v) / h_v at both triangles of the element
+//   k_edge_cell  B_i = g dh_i + K_i at the node;  F_e = h_e u_e, q_e at its three edges
+//   k_tend       d(dh)/dt = -div F at the node, du/dt = -Q_e - grad B at the edges, fused
+//                with the Runge-Kutta stage combination (always in double)
+// The compute type T is double, or float for the single-precision tendency mode; the
+// divergence sum, the state and the stage combination are double in both.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <stdexcept>
+
+#include "wt_internal.hpp"
+
+namespace wt {
+
+const char* const kKernelNames[K_COUNT] = {"trisk_vertex", "trisk_edge_cell", "trisk_tend"};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_) + " at " #x); \
+  } while (0)
+
+constexpr int BS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __restrict__ t_n,
+                                               const int32_t* __restrict__ t_e,
+                                               const double* __restrict__ t_curl,
+                                               const double* __restrict__ t_R,
+                                               const double* __restrict__ f_v,
+                                               const double* __restrict__ dh,
+                                               const double* __restrict__ u, double H,
+                                               T* __restrict__ qv) {
+  int64_t t = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (t >= n_tri) return;
+  T z = T(0), hv = T(0);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    z += T(t_curl[3 * t + s]) * T(u[t_e[3 * t + s]]);
+    hv += T(t_R[3 * t + s]) * (T(H) + T(dh[t_n[3 * t + s]]));
+  }
+  qv[t] = (z + T(f_v[t])) / hv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
+                                                  const int32_t* __restrict__ c_e,
+                                                  const double* __restrict__ c_ke,
+                                                  const int32_t* __restrict__ e_c,
+                                                  const int32_t* __restrict__ e_v,
+                                                  const double* __restrict__ dh,
+                                                  const double* __restrict__ u,
+                                                  const T* __restrict__ qv, double g, double H,
+                                                  T* __restrict__ B, T* __restrict__ F,
+                                                  T* __restrict__ qe) {
+  int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (id >= N) return;
+  T K = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    T ue = T(u[c_e[6 * id + k]]);
+    K += T(c_ke[6 * id + k]) * ue * ue;
+  }
+  B[id] = T(g) * T(dh[id]) + K;
+  if (id >= n_elem) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int64_t e = 3 * id + d;
+    T he = T(0.5) * ((T(H) + T(dh[e_c[2 * e]])) + (T(H) + T(dh[e_c[2 * e + 1]])));
+    F[e] = he * T(u[e]);
+    qe[e] = T(0.5) * (qv[e_v[2 * e]] + qv[e_v[2 * e + 1]]);
+  }
+}
+
+__device__ __forceinline__ void rk_epilogue(int64_t i, double k, const StagePtrs& p,
+                                            const StageOut& c) {
+  if (p.o1) {
+    double v = c.d1 * k;
+    if (c.a1 != 0.0) v += c.a1 * p.y[i];
+    if (c.b1 != 0.0) v += c.b1 * p.acc[i];
+    if (c.c1 != 0.0) v += c.c1 * p.x[i];
+    p.o1[i] = v;
+  }
+  if (p.o2) {
+    double v = c.d2 * k;
+    if (c.a2 != 0.0) v += c.a2 * p.y[i];
+    if (c.b2 != 0.0) v += c.b2 * p.acc[i];
+    if (c.c2 != 0.0) v += c.c2 * p.x[i];
+    p.o2[i] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
+                                             const int32_t* __restrict__ c_e,
+                                             const double* __restrict__ c_div,
+                                             const int32_t* __restrict__ e_c,
+                                             const double* __restrict__ inv_d,
+                                             const int32_t* __restrict__ ecp,
+                                             const double* __restrict__ wl,
+                                             const T* __restrict__ B, const T* __restrict__ F,
+                                             const T* __restrict__ qe, StagePtrs pdh, StagePtrs pu,
+                                             StageOut c) {
+  int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (id >= N) return;
+  double div = 0.0;  // divergence sums stay in double in both precisions
+#pragma unroll
+  for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * double(F[c_e[6 * id + k]]);
+  rk_epilogue(id, -div, pdh, c);
+  if (id >= n_elem) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int64_t e = 3 * id + d;
+    T q0 = qe[e];
+    T Q = T(0);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      int32_t ep = ecp[10 * e + k];
+      Q += T(wl[10 * e + k]) * F[ep] * (T(0.5) * (q0 + qe[ep]));
+    }
+    T gradB = (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * T(inv_d[e]);
+    rk_epilogue(e, double(-Q - gradB), pu, c);
+  }
+}
+
+// ------------------------------------------------------------------ launch helpers
+static inline unsigned nblk(int64_t n) { return unsigned((n + BS - 1) / BS); }
+
+struct TimedLaunch {
+  Timer* tm;
+  int k;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(Timer* tm_, int k_, hipStream_t s_) : tm(tm_), k(k_), s(s_) {
+    if (tm && tm->enabled) {
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      HIPCHK(hipEventRecord(a, s));
+    }
+  }
+  ~TimedLaunch() {
+    if (a) {
+      hipEventRecord(b, s);
+      tm->recs.push_back({k, a, b});
+    }
+  }
+};
+
+template <typename T>
+static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, const StagePtrs& sdh,
+                       const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm) {
+  T* qv = static_cast<T*>(w.qv);
+  T* B = static_cast<T*>(w.B);
+  T* F = static_cast<T*>(w.F);
+  T* qe = static_cast<T*>(w.qe);
+  {
+    TimedLaunch tl(tm, K_VERTEX, s);
+    k_vertex<T><<<nblk(t.T), BS, 0, s>>>(t.T, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x,
+                                         p.H, qv);
+  }
+  {
+    TimedLaunch tl(tm, K_EDGE_CELL, s);
+    k_edge_cell<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x,
+                                            qv, p.g, p.H, B, F, qe);
+  }
+  {
+    TimedLaunch tl(tm, K_TEND, s);
+    k_tend<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl,
+                                       B, F, qe, sdh, su, c);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
+                  const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s,
+                  Timer* tm) {
+  if (fp32)
+    stage_impl<float>(t, w, p, sdh, su, c, s, tm);
+  else
+    stage_impl<double>(t, w, p, sdh, su, c, s, tm);
+}
+
+// ------------------------------------------------------------------ diagnostics
+constexpr int NRED = 7;
+constexpr int RED_BLOCKS = 1024;
+
+__global__ __launch_bounds__(BS) void k_diag_partial(
+    int64_t N, int64_t n_elem, const double* __restrict__ A_i, const double* __restrict__ l_e,
+    const double* __restrict__ d_e, const int32_t* __restrict__ e_c,
+    const int32_t* __restrict__ e_v, const double* __restrict__ f_v,
+    const double* __restrict__ dh, const double* __restrict__ u, double g, double H,
+    double* __restrict__ part) {
+  __shared__ double sh[NRED][BS];
+  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+  for (int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x; id < N; id += int64_t(gridDim.x) * BS) {
+    double h = H + dh[id];
+    acc[0] += A_i[id] * h;
+    acc[1] += 0.5 * A_i[id] * (g * h) * (g * h);
+    acc[2] = fmax(acc[2], fabs(dh[id]));
+    if (!isfinite(dh[id])) acc[4] += 1.0;
+    if (id < n_elem) {
+      for (int d = 0; d < 3; ++d) {
+        int64_t e = 3 * id + d;
+        double ue = u[e];
+        double he = 0.5 * ((H + dh[e_c[2 * e]]) + (H + dh[e_c[2 * e + 1]]));
+        acc[1] += g * 0.5 * l_e[e] * d_e[e] * he * ue * ue;
+        acc[3] = fmax(acc[3], fabs(ue));
+        if (!isfinite(ue)) acc[4] += 1.0;
+        double fe = 0.5 * (f_v[e_v[2 * e]] + f_v[e_v[2 * e + 1]]);
+        double kw = M_PI / d_e[e];
+        acc[5] = fmax(acc[5], sqrt(fe * fe + g * he * kw * kw));
+        if (fabs(ue) > 0.0) acc[6] = fmin(acc[6], d_e[e] / fabs(ue));
+      }
+    }
+  }
+  for (int q = 0; q < NRED; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) {
+      for (int q = 0; q < 2; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+      sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + st]);
+      sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + st]);
+      sh[4][threadIdx.x] += sh[4][threadIdx.x + st];
+      sh[5][threadIdx.x] = fmax(sh[5][threadIdx.x], sh[5][threadIdx.x + st]);
+      sh[6][threadIdx.x] = fmin(sh[6][threadIdx.x], sh[6][threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NRED; ++q) part[q * RED_BLOCKS + blockIdx.x] = sh[q][0];
+}
+
+__global__ __launch_bounds__(BS) void k_diag_final(const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[NRED][BS];
+  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+  for (int b = threadIdx.x; b < RED_BLOCKS; b += BS) {
+    acc[0] += part[0 * RED_BLOCKS + b];
+    acc[1] += part[1 * RED_BLOCKS + b];
+    acc[2] = fmax(acc[2], part[2 * RED_BLOCKS + b]);
+    acc[3] = fmax(acc[3], part[3 * RED_BLOCKS + b]);
+    acc[4] += part[4 * RED_BLOCKS + b];
+    acc[5] = fmax(acc[5], part[5 * RED_BLOCKS + b]);
+    acc[6] = fmin(acc[6], part[6 * RED_BLOCKS + b]);
+  }
+  for (int q = 0; q < NRED; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) {
+      for (int q = 0; q < 2; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+      sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + st]);
+      sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + st]);
+      sh[4][threadIdx.x] += sh[4][threadIdx.x + st];
+      sh[5][threadIdx.x] = fmax(sh[5][threadIdx.x], sh[5][threadIdx.x + st]);
+      sh[6][threadIdx.x] = fmin(sh[6][threadIdx.x], sh[6][threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NRED; ++q) out[q] = sh[q][0];
+}
+
+void launch_diagnostics(const DevTables& t, DevWork& w, const PhysParams& p, hipStream_t s,
+                        double* host_out) {
+  double* part = w.red;
+  double* out = w.red + NRED * RED_BLOCKS;
+  k_diag_partial<<<RED_BLOCKS, BS, 0, s>>>(t.N, t.n_elem, t.A_i, t.l_e, t.d_e, t.e_c, t.e_v, t.f_v,
+                                           w.dh, w.u, p.g, p.H, part);
+  k_diag_final<<<1, BS, 0, s>>>(part, out);
+  HIPCHK(hipGetLastError());
+  double r[NRED];
+  HIPCHK(hipMemcpyAsync(r, out, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // energy: subtract the rest-state term c^4 A_S / 2, c^2 = g * mass / A_S (Sec. 7.2)
+  for (int q = 0; q < NRED; ++q) host_out[q] = r[q];
+}
+
+// ------------------------------------------------------------------ table upload
+template <typename X>
+static X* dev_upload(const std::vector<X>& v) {
+  X* p = nullptr;
+  HIPCHK(hipMalloc(&p, v.size() * sizeof(X)));
+  HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
+  return p;
+}
+
+void upload_tables(const Level& L, DevTables& t) {
+  const int64_t N = L.N, E = L.E, T = L.T;
+  t.N = N; t.E = E; t.T = T; t.n_elem = 10 * L.n * L.n;
+  std::vector<int32_t> c_e(6 * N);
+  std::vector<double> c_div(6 * N), c_ke(6 * N);
+  for (int64_t i = 0; i < N; ++i)
+    for (int k = 0; k < 6; ++k) {
+      bool ok = k < L.c_deg[i];
+      int32_t e = L.c_e[6 * i + (ok ? k : 0)];
+      c_e[6 * i + k] = e;
+      c_div[6 * i + k] = ok ? L.c_s[6 * i + k] * L.l_e[e] / L.A_i[i] : 0.0;
+      c_ke[6 * i + k] = ok ? L.l_e[e] * L.d_e[e] / (4.0 * L.A_i[i]) : 0.0;
+    }
+  std::vector<double> inv_d(E), wl(10 * E);
+  for (int64_t e = 0; e < E; ++e) {
+    inv_d[e] = 1.0 / L.d_e[e];
+    for (int k = 0; k < 10; ++k) wl[10 * e + k] = L.w[10 * e + k] * L.l_e[L.ecp[10 * e + k]] / L.d_e[e];
+  }
+  std::vector<double> t_curl(3 * T), t_R(3 * T);
+  for (int64_t v = 0; v < T; ++v)
+    for (int s = 0; s < 3; ++s) {
+      t_curl[3 * v + s] = L.t_s[3 * v + s] * L.d_e[L.t_e[3 * v + s]] / L.A_v[v];
+      t_R[3 * v + s] = L.kite[3 * v + s] / L.A_v[v];
+    }
+  t.c_e = dev_upload(c_e);
+  t.c_div = dev_upload(c_div);
+  t.c_ke = dev_upload(c_ke);
+  t.e_c = dev_upload(L.e_c);
+  t.e_v = dev_upload(L.e_v);
+  t.inv_d = dev_upload(inv_d);
+  t.ecp = dev_upload(L.ecp);
+  t.wl = dev_upload(wl);
+  t.t_n = dev_upload(L.t_n);
+  t.t_e = dev_upload(L.t_e);
+  t.t_curl = dev_upload(t_curl);
+  t.t_R = dev_upload(t_R);
+  t.f_v = dev_upload(L.f_v);
+  t.A_i = dev_upload(L.A_i);
+  t.l_e = dev_upload(L.l_e);
+  t.d_e = dev_upload(L.d_e);
+}
+
+void free_tables(DevTables& t) {
+  void* ps[] = {t.c_e, t.c_div, t.c_ke, t.e_c, t.e_v, t.inv_d, t.ecp, t.wl,
+                t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, t.A_i, t.l_e, t.d_e};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  t = DevTables{};
+}
+
+}  // namespace wt

@@ -46,21 +46,27 @@ def tc2(node_xyz, edge_mid, edge_tan, radius=EARTH_RADIUS, omega=OMEGA, gravity=
     return dh, u, H
 
 
-def real_sph_harm_sum(xyz, coeffs, lmax):
+def real_sph_harm_sum(xyz, coeffs, lmax, device=None):
     """S(x) = sum_{l=1..lmax} sum_{m=-l..l} a_lm Y_lm(x), orthonormal real harmonics.
 
     ``coeffs[l, lmax + m]`` holds a_lm.  Associated Legendre functions by the standard stable
-    recurrences in m then l.
+    recurrences in m then l.  Evaluated with torch in float64 on ``device`` (CPU by default;
+    a GPU device only speeds up large grids) and returned as a numpy array.
     """
-    x = xyz / np.linalg.norm(xyz, axis=1, keepdims=True)
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cpu")
+    x = torch.as_tensor(np.ascontiguousarray(xyz), dtype=torch.float64, device=dev)
+    x = x / torch.linalg.norm(x, dim=1, keepdim=True)
     ct = x[:, 2]
-    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
-    lon = np.arctan2(x[:, 1], x[:, 0])
-    out = np.zeros(x.shape[0])
-    pmm = np.full(x.shape[0], math.sqrt(1.0 / (4.0 * math.pi)))
+    st = torch.sqrt(torch.clamp(1.0 - ct * ct, min=0.0))
+    lon = torch.atan2(x[:, 1], x[:, 0])
+    out = torch.zeros_like(ct)
+    pmm = torch.full_like(ct, math.sqrt(1.0 / (4.0 * math.pi)))
     for m in range(0, lmax + 1):
         if m > 0:
             pmm = -math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm
+        cm = torch.zeros_like(ct)
+        sm = torch.zeros_like(ct)
         p_prev, p_cur = None, pmm
         for l in range(m, lmax + 1):
             if l == m + 1:
@@ -71,12 +77,14 @@ def real_sph_harm_sum(xyz, coeffs, lmax):
                 p_prev, p_cur = p_cur, a * (ct * p_cur - b * p_prev)
             if l == 0:
                 continue
-            if m == 0:
-                out += coeffs[l, lmax] * p_cur
-            else:
-                out += coeffs[l, lmax + m] * math.sqrt(2.0) * p_cur * np.cos(m * lon)
-                out += coeffs[l, lmax - m] * math.sqrt(2.0) * p_cur * np.sin(m * lon)
-    return out
+            cm = cm + float(coeffs[l, lmax + m]) * p_cur
+            if m > 0:
+                sm = sm + float(coeffs[l, lmax - m]) * p_cur
+        if m == 0:
+            out = out + cm
+        else:
+            out = out + math.sqrt(2.0) * (cm * torch.cos(m * lon) + sm * torch.sin(m * lon))
+    return out.cpu().numpy()
 
 
 def sh_coefficients(seed, lmax):
@@ -87,9 +95,9 @@ def sh_coefficients(seed, lmax):
 
 
 def tc2_perturbed(node_xyz, edge_mid, edge_tan, seed=SEED_BASE + 1, lmax=32, amplitude=10.0,
-                  radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY):
+                  radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY, device=None):
     dh, u, H = tc2(node_xyz, edge_mid, edge_tan, radius, omega, gravity)
-    S = real_sph_harm_sum(node_xyz, sh_coefficients(seed, lmax), lmax)
+    S = real_sph_harm_sum(node_xyz, sh_coefficients(seed, lmax), lmax, device)
     return dh + amplitude * S / np.abs(S).max(), u, H
 
 

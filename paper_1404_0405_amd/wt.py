@@ -1,0 +1,225 @@
+"""Thin ctypes binding of ``libwt.so`` (argument marshalling only; every step runs in the HIP
+library).  Names follow the C ABI in ``include/wt.h``.
+
+The library is loaded from this package directory.  If it has not been built, or cannot be
+loaded, ``load()`` raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libwt.so")
+
+WT_OK, WT_EINVAL, WT_ENOMEM, WT_EDEVICE, WT_ESTATE, WT_ENUMERIC = 0, -1, -2, -3, -4, -5
+WT_RK4, WT_SSPRK43 = 0, 1
+WT_FP64, WT_FP32_TENDENCY = 0, 1
+
+
+class WtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class wt_params(C.Structure):
+    _fields_ = [("radius", C.c_double), ("omega", C.c_double), ("gravity", C.c_double),
+                ("mean_depth", C.c_double), ("rk", C.c_int), ("precision", C.c_int)]
+
+
+class wt_diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("energy", C.c_double), ("max_abs_dh", C.c_double),
+                ("max_abs_u", C.c_double), ("active_nodes", C.c_int64 * 16),
+                ("active_edges", C.c_int64 * 16)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+_I32 = C.POINTER(C.c_int32)
+_U8 = C.POINTER(C.c_uint8)
+
+# (name, restype, argtypes) for every function declared in include/wt.h
+SIGNATURES = [
+    ("wt_grid_create", _P, [C.c_int, C.c_int, C.c_int]),
+    ("wt_grid_destroy", None, [_P]),
+    ("wt_set_params", C.c_int, [_P, C.POINTER(wt_params)]),
+    ("wt_get_params", C.c_int, [_P, C.POINTER(wt_params)]),
+    ("wt_grid_info", C.c_int, [_P, C.c_int, _I64, _I64, _I64]),
+    ("wt_grid_coords", C.c_int, [_P, C.c_int, _D, _D, _D]),
+    ("wt_set_state", C.c_int, [_P, C.c_int, _D, _D]),
+    ("wt_set_state_device", C.c_int, [_P, C.c_int, _P, _P]),
+    ("wt_get_state", C.c_int, [_P, C.c_int, _D, _D, _U8, _U8]),
+    ("wt_step", C.c_int, [_P, C.c_double]),
+    ("wt_tendency", C.c_int, [_P, C.c_int, _D, _D]),
+    ("wt_diagnostics", C.c_int, [_P, C.POINTER(wt_diag)]),
+    ("wt_suggest_dt", C.c_double, [_P, C.c_double]),
+    ("wt_set_stream", C.c_int, [_P, _P]),
+    ("wt_timing_enable", C.c_int, [_P, C.c_int]),
+    ("wt_timing_reset", C.c_int, [_P]),
+    ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64]),
+    ("wt_kernel_names", C.c_char_p, []),
+    ("wt_host_level_tables", C.c_int, [C.c_int, C.c_double, C.c_double, _D, _D, _D, _D, _I32, _I32, _D]),
+    ("wt_last_error", C.c_char_p, []),
+]
+
+_lib = None
+
+
+def load():
+    """Load libwt.so (raises OSError / FileNotFoundError if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # libwt bind to that one, so the process has a single runtime and torch streams are
+        # valid handles for wt_set_stream.
+        import torch  # noqa: F401
+        lib = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, ct):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _check(code, what=""):
+    if code != WT_OK:
+        raise WtError(code, load().wt_last_error().decode() or what)
+
+
+def host_level_tables(level, radius=6.371e6, omega=7.292e-5):
+    """Host-only geometry of the library's grid builder (no GPU)."""
+    lib = load()
+    n = 2 ** level
+    N, E, T = 10 * n * n + 2, 30 * n * n, 20 * n * n
+    out = dict(A_i=np.empty(N), A_v=np.empty(T), d_e=np.empty(E), l_e=np.empty(E),
+               e_nodes=np.empty((E, 2), np.int32), ecp=np.empty((E, 10), np.int32), w=np.empty((E, 10)))
+    _check(lib.wt_host_level_tables(level, radius, omega, _ptr(out["A_i"], C.c_double),
+                                    _ptr(out["A_v"], C.c_double), _ptr(out["d_e"], C.c_double),
+                                    _ptr(out["l_e"], C.c_double), _ptr(out["e_nodes"], C.c_int32),
+                                    _ptr(out["ecp"], C.c_int32), _ptr(out["w"], C.c_double)))
+    return out
+
+
+class Grid:
+    """A multilevel grid owned by the HIP library (wt_grid)."""
+
+    def __init__(self, jmin, jmax, patch=8):
+        lib = load()
+        h = lib.wt_grid_create(jmin, jmax, patch)
+        if not h:
+            raise WtError(WT_EDEVICE, lib.wt_last_error().decode())
+        self._h = h
+        self.jmin, self.jmax, self.patch = jmin, jmax, patch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wt_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # parameters
+    def get_params(self):
+        p = wt_params()
+        _check(load().wt_get_params(self._h, C.byref(p)))
+        return p
+
+    def set_params(self, **kw):
+        p = self.get_params()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        _check(load().wt_set_params(self._h, C.byref(p)))
+
+    def info(self, level):
+        n, e, t = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().wt_grid_info(self._h, level, C.byref(n), C.byref(e), C.byref(t)))
+        return n.value, e.value, t.value
+
+    def coords(self, level):
+        N, E, _ = self.info(level)
+        x, m, t = np.empty((N, 3)), np.empty((E, 3)), np.empty((E, 3))
+        _check(load().wt_grid_coords(self._h, level, _ptr(x, C.c_double), _ptr(m, C.c_double),
+                                     _ptr(t, C.c_double)))
+        return x, m, t
+
+    def set_state(self, level, dh, u):
+        dh = np.ascontiguousarray(dh, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        N, E, _ = self.info(level)
+        if dh.shape != (N,) or u.shape != (E,):
+            raise ValueError(f"state shapes {dh.shape}, {u.shape} != ({N},), ({E},)")
+        _check(load().wt_set_state(self._h, level, _ptr(dh, C.c_double), _ptr(u, C.c_double)))
+
+    def set_state_device(self, level, dh_ptr, u_ptr):
+        _check(load().wt_set_state_device(self._h, level, C.c_void_p(dh_ptr), C.c_void_p(u_ptr)))
+
+    def get_state(self, level):
+        N, E, _ = self.info(level)
+        dh, u = np.empty(N), np.empty(E)
+        na, ea = np.empty(N, np.uint8), np.empty(E, np.uint8)
+        _check(load().wt_get_state(self._h, level, _ptr(dh, C.c_double), _ptr(u, C.c_double),
+                                   _ptr(na, C.c_uint8), _ptr(ea, C.c_uint8)))
+        return dh, u, na, ea
+
+    def step(self, dt):
+        _check(load().wt_step(self._h, float(dt)))
+
+    def tendency(self, level):
+        N, E, _ = self.info(level)
+        a, b = np.empty(N), np.empty(E)
+        _check(load().wt_tendency(self._h, level, _ptr(a, C.c_double), _ptr(b, C.c_double)))
+        return a, b
+
+    def diagnostics(self):
+        d = wt_diag()
+        code = load().wt_diagnostics(self._h, C.byref(d))
+        if code not in (WT_OK, WT_ENUMERIC):
+            _check(code)
+        return d, code
+
+    def suggest_dt(self, cfl):
+        v = load().wt_suggest_dt(self._h, float(cfl))
+        if v < 0:
+            _check(WT_EINVAL)
+        return v
+
+    def set_stream(self, stream_handle):
+        _check(load().wt_set_stream(self._h, C.c_void_p(stream_handle) if stream_handle else None))
+
+    def timing(self, enable=True):
+        _check(load().wt_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_reset(self):
+        _check(load().wt_timing_reset(self._h))
+
+    def kernel_time(self, name):
+        ms, cnt = C.c_double(), C.c_int64()
+        _check(load().wt_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+
+def kernel_names():
+    return load().wt_kernel_names().decode().split(",")
