@@ -161,6 +161,7 @@ class Grid:
         order = np.argsort(key)
         skey = key[order]
         assert (np.diff(skey) > 0).all(), "duplicate edge"
+        self._edge_order, self._edge_skey = order, skey
 
         def find(a, b):
             k = np.minimum(a, b).astype(np.int64) * self.N + np.maximum(a, b)
@@ -226,6 +227,25 @@ class Grid:
                                  self.e_tris[np.maximum(e_next, 0), 0])
         ok = (self.c_edges < 0) | (outward_right == self.c_tris)
         assert ok.all(), "cell edges are not in counter-clockwise order"
+
+    def edge_between(self, a, b):
+        """Edge joining nodes a and b (arrays), and +1 where it points from a to b."""
+        a = np.asarray(a, np.int64)
+        b = np.asarray(b, np.int64)
+        k = np.minimum(a, b) * self.N + np.maximum(a, b)
+        pos = np.searchsorted(self._edge_skey, k)
+        pos = np.minimum(pos, self._edge_skey.size - 1)
+        assert (self._edge_skey[pos] == k).all(), "nodes are not joined by an edge"
+        e = self._edge_order[pos]
+        return e, np.where(self.e_nodes[e, 0] == a, 1, -1)
+
+    def cell_polygon(self, nodes):
+        """Counter-clockwise dual-cell (hexagon/pentagon) vertices of `nodes`, padded to 6 by
+        repeating the first vertex; returns (K, 6, 3) unit vectors and the vertex counts."""
+        ct = self.c_tris[nodes]
+        deg = self.c_deg[nodes]
+        poly = self.t_cc[np.where(ct >= 0, ct, ct[:, :1])]
+        return poly, deg
 
     # ------------------------------------------------------------------ geometry
     def _geometry(self):
