@@ -29,10 +29,10 @@ def _algorithmic_bytes(N, E, T, fp32):
     """Unique bytes read + written by each stage kernel per launch (tables, inputs, outputs;
     each array element counted once), for the table-driven kernels.  RK4 stage-averaged
     epilogue traffic: 3.25 state accesses of 8 B per degree of freedom."""
-    s = 4 if fp32 else 8           # intermediate (q_v, B, F, q_e) element size
+    s = 4 if fp32 else 8           # intermediate (q_v, B, q_e) element size; F is always double
     vertex = T * (12 + 12 + 24 + 24 + 8) + T * s + E * 8 + N * 8
-    edge_cell = N * (24 + 48 + 8) + N * s + E * (8 + 8 + 8) + 2 * E * s + T * s
-    tend = N * (24 + 48) + E * (8 + 8 + 40 + 80) + (N + 2 * E) * s + (N + E) * 3.25 * 8
+    edge_cell = N * (24 + 48 + 8) + N * s + E * (8 + 8 + 8) + E * (8 + s) + T * s
+    tend = N * (24 + 48) + E * (8 + 8 + 40 + 80) + N * s + E * (8 + s) + (N + E) * 3.25 * 8
     return {"trisk_vertex": vertex, "trisk_edge_cell": edge_cell, "trisk_tend": tend}
 
 

@@ -51,9 +51,11 @@ enum {
 enum { WT_RK4 = 0, WT_SSPRK43 = 1 };
 
 /* Arithmetic of the tendencies.  WT_FP64: everything in double.  WT_FP32_TENDENCY: the
- * tendencies are computed in single precision while the prognostic state, the Runge-Kutta
- * accumulation, the divergence sums and the mass/energy diagnostics stay in double (the
- * paper keeps mimetic quantities in double and truncation-limited ones in single, Sec. 5.1). */
+ * tendencies and the velocity/vorticity parts of the transforms are computed in single
+ * precision while the prognostic state, the Runge-Kutta accumulation, the mass flux F and its
+ * restriction, the divergence sums, the height transform and the mass/energy diagnostics stay
+ * in double (the paper keeps the quantities that carry the mimetic properties in double and
+ * truncation-limited ones in single, Sec. 5.1), so mass is conserved to round-off in both. */
 enum { WT_FP64 = 0, WT_FP32_TENDENCY = 1 };
 
 typedef struct {
@@ -66,8 +68,10 @@ typedef struct {
 } wt_params;
 
 typedef struct {
-  double mass;        /* sum_k A_k (H + dh_k) on level jmin [m^3] (Sec. 3.2) */
-  double energy;      /* E of Sec. 7.2 on the finest full level [m^5/s^2] */
+  double mass;        /* sum_k A_k (H + dh_k) on level jmin [m^3] (Sec. 3.2); below jmax A_k
+                         are the effective areas of the height transform */
+  double mass_reconstructed; /* the same sum of the jmax reconstruction (equal up to rounding) */
+  double energy;      /* E of Sec. 7.2 of the jmax reconstruction [m^5/s^2] */
   double max_abs_dh;  /* max |dh| over active nodes of all levels */
   double max_abs_u;   /* max |u| over active edges of all levels */
   int64_t active_nodes[16]; /* per level j (index j), active node count */
@@ -100,23 +104,62 @@ int wt_grid_coords(const wt_grid* g, int level, double* node_xyz_host,
                    double* edge_mid_xyz_host, double* edge_tangent_xyz_host);
 
 /* Load the prognostic state of level `level` from host arrays dh_host[N], u_host[E]
- * (canonical order).  The level becomes fully active.  On a uniform grid (jmin == jmax) this
- * is the whole state. */
+ * (canonical order).  Levels jmin..level become fully active, the coarser ones computed by the
+ * forward transform (height restriction eq. (Rh), velocity restriction by half-edge means);
+ * levels above `level` become inactive.  On a uniform grid (jmin == jmax) this is the whole
+ * state. */
 int wt_set_state(wt_grid* g, int level, const double* dh_host, const double* u_host);
 
 /* Same, from device arrays (stream-ordered on the grid's stream). */
 int wt_set_state_device(wt_grid* g, int level, const void* dh_device, const void* u_device);
 
 /* Read the state of level `level` into host arrays dh_host[N], u_host[E] (canonical
- * order); node_active_host[N] / edge_active_host[E] receive 1 for active points.  Any
- * pointer may be NULL.  Synchronises the grid's stream. */
+ * order): on a multilevel grid the level is reconstructed by the inverse transform from jmin
+ * with the details of the active points (zero elsewhere), so its mass equals the mass on jmin.
+ * node_active_host[N] / edge_active_host[E] receive 1 for active points.  Any pointer may be
+ * NULL.  Synchronises the grid's stream. */
 int wt_get_state(wt_grid* g, int level, double* dh_host, double* u_host,
                  uint8_t* node_active_host, uint8_t* edge_active_host);
 
 /* Advance the state by one Runge-Kutta step of length dt seconds (four tendency
  * evaluations, eqs. (height) and (velo), TRiSK discretisation with the energy-conserving
- * qF^perp, Sec. 3.1).  Asynchronous on the grid's stream. */
+ * qF^perp, Sec. 3.1).  On a multilevel grid every stage (Sec. 3.1, time step) fills inactive
+ * points by zero-detail prediction, computes q, K, B, F and qF^perp on every level, restricts
+ * F (flux restriction R_F, eqs. (restr_flux), (ho_flux), (kml)), qF^perp (half-edge mean) and
+ * B (injection) to coarser levels at non-leaf points, and updates the active points of every
+ * level; after the step the coarse heights at complete nodes are replaced by the height
+ * restriction of the finer level (partial transform, height only).  No adaptation.
+ * Asynchronous on the grid's stream. */
 int wt_step(wt_grid* g, double dt);
+
+/* Adapt the grid (Sec. 2.3, 3.1): wavelet details of all levels; thresholds
+ * eps_h = eps max|dh|, eps_u = eps max|u| over active points; significant iff |d| >= eps_var;
+ * adjacent zone (same-level neighbours and next-level children of significant points); all of
+ * jmin; h/u consistency and the coarse prediction stencils of every active point; then the
+ * inverse transform rewrites every active fine point from its coarse level and the kept
+ * details.  Coarse values and the mass on jmin are unchanged.  eps = 0 keeps every point.
+ * No-op on a uniform grid.  Synchronises. */
+int wt_adapt(wt_grid* g, double eps);
+
+/* Forward transform: compute and keep the wavelet details of every level pair (eqs. (WTpred)
+ * for height, the velocity prediction of Sec. 4.1) from the current state.  Read them with
+ * wt_get_details.  No-op on a uniform grid. */
+int wt_forward(wt_grid* g);
+
+/* Inverse transform: rewrite every fine level from jmin with the details of the active
+ * points, making all levels consistent (R_h of each level is the level below).  No-op on a
+ * uniform grid. */
+int wt_inverse(wt_grid* g);
+
+/* Details computed by the last wt_forward / wt_adapt for the pair (level-1, level), coarse
+ * canonical order of level-1: dh_host[E_c] height detail of the midpoint node of each coarse
+ * edge, dpair_host[E_c] velocity detail of each pair of half-edges, dint_host[3 T_c] velocity
+ * details of the three fine edges inside each coarse triangle.  Test hook; synchronises. */
+int wt_get_details(wt_grid* g, int level, double* dh_host, double* dpair_host, double* dint_host);
+
+/* Replace the active masks of `level` (host arrays of N and E bytes, 1 = active).  Test hook,
+ * used to resynchronise masks with a reference at exact threshold ties. */
+int wt_set_mask(wt_grid* g, int level, const uint8_t* node_active_host, const uint8_t* edge_active_host);
 
 /* Evaluate the tendencies d(dh)/dt and du/dt of the current state of a full level into host
  * arrays ddh_host[N], du_host[E] (canonical order).  Test and diagnostic hook; synchronises. */
@@ -154,6 +197,24 @@ const char* wt_kernel_names(void);
 int wt_host_level_tables(int level, double radius, double omega, double* A_i_host,
                          double* A_v_host, double* d_e_host, double* l_e_host,
                          int32_t* e_nodes_host, int32_t* ecp_host, double* w_host);
+
+/* Host-only inspection of the inter-scale tables between levels jc and jc+1 of a hierarchy
+ * jc..jmax (no device needed; jc < jmax <= 8).  Coarse sizes Nc, Ec, Tc are those of level jc.
+ * cells_host[4Ec]: for every coarse edge a->b its cells (a, b, p, q), p opposite in the left
+ * and q in the right triangle; st_host[4Ec] prediction weights s~_cm = A_cm / A_m of the
+ * height transform (eq. (WTpred), Sec. 4.2); s_upd_host[4Ec] update weights s_km = A_km / A_k
+ * (eq. (WTupd)); A_c_host[Nc] effective coarse cell areas; v_sten_host[9Tc] the coarse edges of
+ * each coarse triangle's velocity stencil; w_int_host[27Tc] prediction weights of its three
+ * interior fine edges (Sec. 4.1); w_pl_host[9Ec], w_pr_host[9Ec] weights of (p1 - p2) on the
+ * stencils of the left / right triangle; rf_f_host[3Ec], rf_fw_host[3Ec], rf_c_host[16Ec],
+ * rf_cw_host[16Ec] the flux restriction (eqs. (restr_flux), (ho_flux), (kml)): integrated
+ * coarse flux = sum rf_fw * (l F)[rf_f] + sum rf_cw * c[rf_c], fine edge / node ids.  Any
+ * pointer may be NULL.  For tests of the builder. */
+int wt_host_pair_tables(int jc, int jmax, double radius, double omega, int32_t* cells_host,
+                        double* st_host, double* s_upd_host, double* A_c_host,
+                        int32_t* v_sten_host, double* w_int_host, double* w_pl_host,
+                        double* w_pr_host, int32_t* rf_f_host, double* rf_fw_host,
+                        int32_t* rf_c_host, double* rf_cw_host);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);

@@ -480,6 +480,10 @@ class Hierarchy:
         dh, u = self.inverse(self.details(), self._active)
         return dh[level], u[level], self.node_act[level].copy(), self.edge_act[level].copy()
 
+    def resync(self):
+        """Inverse transform with the details of the active points applied to the state."""
+        self.dh, self.u = self.inverse(self.details(), self._active)
+
     def _active(self, f, pts, kind, node_act=None, edge_act=None):
         na = self.node_act if node_act is None else node_act
         ea = self.edge_act if edge_act is None else edge_act

@@ -12,6 +12,8 @@
 #include "../../include/wt.h"
 #include "wt_grid.hpp"
 #include "wt_internal.hpp"
+#include "wt_ml.hpp"
+#include "wt_pair.hpp"
 
 using namespace wt;
 
@@ -29,20 +31,31 @@ static int fail(int code, const std::string& m) {
   } while (0)
 
 struct LevelState {
-  Level geo;         // host geometry
+  Level geo;         // host geometry (cell areas replaced by effective areas below jmax)
   DevTables tab;     // device tables
   DevWork work;      // device buffers
-  bool full = false;  // state loaded on every point of the level
+  uint8_t *na = nullptr, *ea = nullptr;  // active nodes / edges
+  uint8_t *nn = nullptr, *ne = nullptr;  // masks under construction (adapt)
+  uint8_t *sn = nullptr, *se = nullptr;  // significant points (adapt)
+};
+
+struct PairState {
+  PairTables host;
+  DevPair dev{};
+  double *d_h = nullptr, *d_p = nullptr, *d_i = nullptr, *d_k = nullptr;  // details
 };
 
 struct wt_grid {
   int jmin = 0, jmax = 0, patch = 8;
   wt_params prm{};
-  std::vector<std::unique_ptr<LevelState>> lev;  // index j - jmin
+  std::vector<std::unique_ptr<LevelState>> lev;    // index j - jmin
+  std::vector<std::unique_ptr<PairState>> pairs;   // pair (j, j+1) at index j - jmin
   hipStream_t own = nullptr, stream = nullptr;
   bool have_state = false;
   Timer timer;
   LevelState& L(int j) { return *lev[j - jmin]; }
+  PairState& P(int j) { return *pairs[j - jmin]; }
+  bool multi() const { return jmax > jmin; }
 };
 
 static void alloc_work(LevelState& ls) {
@@ -59,18 +72,227 @@ static void alloc_work(LevelState& ls) {
   A(&p, N); w.B = p;
   A(&p, E); w.F = p;
   A(&p, E); w.qe = p;
+  A(&p, E); w.Q = p;
+  A(&w.c, N);
   A(&w.red, 8 * 1024 + 16);
+  auto M = [](uint8_t** q, int64_t n) { HIPCHK(hipMalloc(q, n)); HIPCHK(hipMemset(*q, 0, n)); };
+  M(&ls.na, N); M(&ls.ea, E); M(&ls.nn, N); M(&ls.ne, E); M(&ls.sn, N); M(&ls.se, E);
 }
 
-static void free_work(DevWork& w) {
+static void free_work(LevelState& ls) {
+  DevWork& w = ls.work;
   void* ps[] = {w.dh, w.u, w.dh_acc, w.u_acc, w.dh_s[0], w.u_s[0], w.dh_s[1], w.u_s[1],
-                w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.red};
+                w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red,
+                ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   w = DevWork{};
 }
 
 static PhysParams phys(const wt_grid* g) { return PhysParams{g->prm.gravity, g->prm.mean_depth}; }
+
+// ---------------------------------------------------------------- Runge-Kutta stages
+// Stage s of a step: input x, and the epilogue o1/o2 = a*y + b*acc + c*x + d*k (see
+// StageOut).  Classical RK4 in three registers (y, acc, two stage buffers); the SSP scheme in
+// Shu-Osher form.
+struct StageSpec {
+  const double *xdh, *xu;
+  StagePtrs pdh, pu;
+  StageOut c;
+};
+
+static StageSpec rk_stage(int rk, int s, DevWork& w, double dt) {
+  StageSpec r{};
+  StageOut c{};
+  const double *xdh, *xu;
+  double *o1dh = nullptr, *o1u = nullptr, *o2dh = nullptr, *o2u = nullptr;
+  if (rk == WT_RK4) {
+    const double bk[4] = {dt / 6, dt / 3, dt / 3, dt / 6};
+    const double ck[4] = {dt / 2, dt / 2, dt, 0};
+    const double* X[4] = {w.dh, w.dh_s[0], w.dh_s[1], w.dh_s[0]};
+    const double* XU[4] = {w.u, w.u_s[0], w.u_s[1], w.u_s[0]};
+    double* O2[4] = {w.dh_s[0], w.dh_s[1], w.dh_s[0], nullptr};
+    double* O2U[4] = {w.u_s[0], w.u_s[1], w.u_s[0], nullptr};
+    xdh = X[s]; xu = XU[s];
+    c.d1 = bk[s];
+    if (s == 0) c.a1 = 1.0; else c.b1 = 1.0;
+    o1dh = s == 3 ? w.dh : w.dh_acc;
+    o1u = s == 3 ? w.u : w.u_acc;
+    if (s < 3) { c.a2 = 1.0; c.d2 = ck[s]; o2dh = O2[s]; o2u = O2U[s]; }
+  } else {
+    const double* X[4] = {w.dh, w.dh_s[0], w.dh_s[1], w.dh_s[0]};
+    const double* XU[4] = {w.u, w.u_s[0], w.u_s[1], w.u_s[0]};
+    double* O1[4] = {w.dh_s[0], w.dh_s[1], w.dh_s[0], w.dh};
+    double* O1U[4] = {w.u_s[0], w.u_s[1], w.u_s[0], w.u};
+    xdh = X[s]; xu = XU[s]; o1dh = O1[s]; o1u = O1U[s];
+    if (s == 0) { c.a1 = 1.0; c.d1 = dt / 2; }
+    else if (s == 1) { c.c1 = 1.0; c.d1 = dt / 2; }
+    else if (s == 2) { c.a1 = 2.0 / 3.0; c.c1 = 1.0 / 3.0; c.d1 = dt / 6; }
+    else { c.c1 = 1.0; c.d1 = dt / 2; }
+  }
+  r.xdh = xdh; r.xu = xu; r.c = c;
+  r.pdh = StagePtrs{w.dh, w.dh_acc, xdh, o1dh, o2dh};
+  r.pu = StagePtrs{w.u, w.u_acc, xu, o1u, o2u};
+  return r;
+}
+
+static void uniform_step(wt_grid* g, LevelState& ls, double dt) {
+  const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
+  for (int s = 0; s < 4; ++s) {
+    StageSpec sp = rk_stage(g->prm.rk, s, ls.work, dt);
+    launch_stage(ls.tab, ls.work, phys(g), fp32, sp.pdh, sp.pu, sp.c, g->stream, &g->timer);
+  }
+}
+
+// ---------------------------------------------------------------- multilevel operations
+// Fill inactive points of every level above jmin from the level below (top-down).
+static void prolong_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u) {
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    LevelState& F = g->L(j + 1);
+    ml_prolong(g->P(j).dev, g->L(j).tab, F.na, F.ea, dh[j - g->jmin], u[j - g->jmin],
+               dh[j + 1 - g->jmin], u[j + 1 - g->jmin], g->stream);
+  }
+}
+
+static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u) {
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    ml_details(P.dev, g->L(j).tab, dh[j + 1 - g->jmin], u[j + 1 - g->jmin], u[j - g->jmin], P.d_h, P.d_p,
+               P.d_i, g->stream);
+  }
+}
+
+// Inverse transform top-down with the details kept where (old & new) activity holds.
+static void inverse_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
+                        bool use_new) {
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    LevelState& F = g->L(j + 1);
+    ml_inverse(P.dev, g->L(j).tab, F.na, use_new ? F.nn : F.na, F.ea, use_new ? F.ne : F.ea, P.d_h, P.d_p,
+               P.d_i, P.d_k, dh[j - g->jmin], u[j - g->jmin], dh[j + 1 - g->jmin], u[j + 1 - g->jmin],
+               g->stream);
+  }
+}
+
+static std::vector<double*> state_dh(wt_grid* g) {
+  std::vector<double*> v;
+  for (auto& l : g->lev) v.push_back(l->work.dh);
+  return v;
+}
+static std::vector<double*> state_u(wt_grid* g) {
+  std::vector<double*> v;
+  for (auto& l : g->lev) v.push_back(l->work.u);
+  return v;
+}
+
+// Reconstruction of every level into the first stage buffers (the state is not changed).
+static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<double*>& ru) {
+  rdh.clear();
+  ru.clear();
+  for (auto& l : g->lev) {
+    HIPCHK(hipMemcpyAsync(l->work.dh_s[0], l->work.dh, l->tab.N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(l->work.u_s[0], l->work.u, l->tab.E * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    rdh.push_back(l->work.dh_s[0]);
+    ru.push_back(l->work.u_s[0]);
+  }
+  prolong_all(g, rdh, ru);
+  details_all(g, rdh, ru);
+  inverse_all(g, rdh, ru, false);
+}
+
+static void ml_step(wt_grid* g, double dt) {
+  const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
+  const int nl = g->jmax - g->jmin + 1;
+  PhysParams p = phys(g);
+  for (int s = 0; s < 4; ++s) {
+    std::vector<StageSpec> sp(nl);
+    std::vector<double*> xdh(nl), xu(nl);
+    for (int q = 0; q < nl; ++q) {
+      sp[q] = rk_stage(g->prm.rk, s, g->lev[q]->work, dt);
+      xdh[q] = const_cast<double*>(sp[q].xdh);
+      xu[q] = const_cast<double*>(sp[q].xu);
+    }
+    prolong_all(g, xdh, xu);
+    for (int q = 0; q < nl; ++q) ml_level_intermediates(g->lev[q]->tab, g->lev[q]->work, p, fp32, xdh[q], xu[q], g->stream);
+    for (int j = g->jmax - 1; j >= g->jmin; --j) {
+      LevelState &C = g->L(j), &F = g->L(j + 1);
+      ml_restrict(g->P(j).dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, fp32, g->stream);
+    }
+    for (int q = 0; q < nl; ++q) {
+      LevelState& l = *g->lev[q];
+      ml_tend(l.tab, l.work, l.na, l.ea, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream);
+    }
+  }
+  // partial height transform at complete nodes, bottom-up
+  for (int j = g->jmax - 1; j >= g->jmin; --j) {
+    LevelState &C = g->L(j), &F = g->L(j + 1);
+    ml_partial_h(g->P(j).dev, C.tab, C.na, F.na, F.ea, F.work.dh, C.work.dh, g->stream);
+  }
+}
+
+static double masked_max_all(wt_grid* g, bool nodes) {
+  double best = 0.0;
+  for (auto& l : g->lev) {
+    double* scratch = l->work.red;
+    double* out = l->work.red + 4096;
+    if (nodes) ml_masked_max(l->tab.N, l->work.dh, l->na, scratch, out, g->stream);
+    else ml_masked_max(l->tab.E, l->work.u, l->ea, scratch, out, g->stream);
+    double v;
+    HIPCHK(hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    best = std::fmax(best, v);
+  }
+  return best;
+}
+
+static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out) {
+  std::vector<double*> dh = state_dh(g), u = state_u(g);
+  prolong_all(g, dh, u);
+  details_all(g, dh, u);
+  double eh = eps * masked_max_all(g, true), eu = eps * masked_max_all(g, false);
+  for (auto& l : g->lev) {
+    HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
+    HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
+  }
+  // R1: significant points
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    LevelState& F = g->L(j + 1);
+    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream);
+  }
+  for (auto& l : g->lev) {
+    HIPCHK(hipMemcpyAsync(l->nn, l->sn, l->tab.N, hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(l->ne, l->se, l->tab.E, hipMemcpyDeviceToDevice, g->stream));
+  }
+  // R2: same-level neighbours; R3: children on the next level
+  for (int j = g->jmin; j <= g->jmax; ++j) {
+    LevelState& l = g->L(j);
+    ml_r2(l.tab, l.sn, l.se, l.nn, l.ne, g->stream);
+    if (j < g->jmax) {
+      LevelState& F = g->L(j + 1);
+      ml_r3(g->P(j).dev, F.tab, l.sn, l.se, F.nn, F.ne, g->stream);
+    }
+  }
+  LevelState& L0 = g->L(g->jmin);
+  HIPCHK(hipMemsetAsync(L0.nn, 1, L0.tab.N, g->stream));
+  HIPCHK(hipMemsetAsync(L0.ne, 1, L0.tab.E, g->stream));
+  // R4 consistency and R5 prediction stencils, top-down
+  for (int j = g->jmax; j >= g->jmin; --j) {
+    LevelState& l = g->L(j);
+    ml_r4(l.tab, l.nn, l.ne, g->stream);
+    if (j > g->jmin) {
+      LevelState& C = g->L(j - 1);
+      ml_r5(g->P(j - 1).dev, C.tab, l.nn, l.ne, C.nn, C.ne, g->stream);
+    }
+  }
+  inverse_all(g, dh, u, true);
+  for (auto& l : g->lev) {
+    std::swap(l->na, l->nn);
+    std::swap(l->ea, l->ne);
+  }
+  if (eh_out) *eh_out = eh;
+  if (eu_out) *eu_out = eu;
+}
 
 extern "C" {
 
@@ -118,9 +340,30 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
     for (int j = jmin; j <= jmax; ++j) {
       auto ls = std::make_unique<LevelState>();
       build_level(j, g->prm.radius, g->prm.omega, ls->geo);
+      g->lev.push_back(std::move(ls));
+    }
+    for (int j = jmin; j < jmax; ++j) {
+      auto ps = std::make_unique<PairState>();
+      build_pair(g->L(j).geo, g->L(j + 1).geo, ps->host);
+      g->pairs.push_back(std::move(ps));
+    }
+    // effective areas, bottom-up from the geometric areas of jmax (area conditions, Sec. 4.2)
+    std::vector<double> A = g->L(jmax).geo.A_i, Ac;
+    for (int j = jmax - 1; j >= jmin; --j) {
+      finish_pair(g->L(j).geo, g->L(j + 1).geo, A, g->P(j).host, Ac);
+      g->L(j).geo.A_i = Ac;
+      A = Ac;
+    }
+    for (auto& ls : g->lev) {
       upload_tables(ls->geo, ls->tab);
       alloc_work(*ls);
-      g->lev.push_back(std::move(ls));
+    }
+    for (auto& ps : g->pairs) {
+      upload_pair(ps->host, ps->dev);
+      auto A2 = [](double** q, int64_t n) { HIPCHK(hipMalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };
+      A2(&ps->d_h, ps->host.Ec); A2(&ps->d_p, ps->host.Ec); A2(&ps->d_k, ps->host.Ec); A2(&ps->d_i, 3 * ps->host.Tc);
+      // keep only what the device path needs on the host
+      ps->host = PairTables{};
     }
     g_err.clear();
     return g.release();
@@ -141,7 +384,13 @@ void wt_grid_destroy(wt_grid* g) {
   }
   for (auto& ls : g->lev) {
     free_tables(ls->tab);
-    free_work(ls->work);
+    free_work(*ls);
+  }
+  for (auto& ps : g->pairs) {
+    free_pair(ps->dev);
+    void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k};
+    for (void* x : q)
+      if (x) (void)hipFree(x);
   }
   if (g->own) (void)hipStreamDestroy(g->own);
   delete g;
@@ -201,13 +450,19 @@ int wt_grid_coords(const wt_grid* g, int level, double* nx, double* em, double* 
 static int set_state_impl(wt_grid* g, int level, const void* dh, const void* u, hipMemcpyKind k) {
   if (bad_level(g, level)) return fail(WT_EINVAL, "wt_set_state: bad level");
   if (!dh || !u) return fail(WT_EINVAL, "wt_set_state: null array");
-  if (g->jmin != g->jmax) return fail(WT_EINVAL, "wt_set_state: adaptive grids not supported yet");
   try {
     LevelState& ls = g->L(level);
     HIPCHK(hipMemcpyAsync(ls.work.dh, dh, ls.tab.N * sizeof(double), k, g->stream));
     HIPCHK(hipMemcpyAsync(ls.work.u, u, ls.tab.E * sizeof(double), k, g->stream));
-    if (k == hipMemcpyHostToDevice) HIPCHK(hipStreamSynchronize(g->stream));
-    ls.full = true;
+    for (int j = g->jmin; j <= g->jmax; ++j) {
+      LevelState& l = g->L(j);
+      HIPCHK(hipMemsetAsync(l.na, j <= level ? 1 : 0, l.tab.N, g->stream));
+      HIPCHK(hipMemsetAsync(l.ea, j <= level ? 1 : 0, l.tab.E, g->stream));
+    }
+    for (int j = level - 1; j >= g->jmin; --j)
+      ml_restrict_state(g->P(j).dev, g->L(j + 1).work.dh, g->L(j + 1).work.u, g->L(j).work.dh,
+                        g->L(j).work.u, g->stream);
+    HIPCHK(hipStreamSynchronize(g->stream));
     g->have_state = true;
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_set_state: ") + e.what());
@@ -228,61 +483,22 @@ int wt_get_state(wt_grid* g, int level, double* dh, double* u, uint8_t* na, uint
   if (!g->have_state) return fail(WT_ESTATE, "wt_get_state: no state loaded");
   try {
     LevelState& ls = g->L(level);
-    if (dh) HIPCHK(hipMemcpyAsync(dh, ls.work.dh, ls.tab.N * sizeof(double), hipMemcpyDeviceToHost, g->stream));
-    if (u) HIPCHK(hipMemcpyAsync(u, ls.work.u, ls.tab.E * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    const double *sdh = ls.work.dh, *su = ls.work.u;
+    if (g->multi()) {
+      std::vector<double*> rdh, ru;
+      reconstruct(g, rdh, ru);
+      sdh = rdh[level - g->jmin];
+      su = ru[level - g->jmin];
+    }
+    if (dh) HIPCHK(hipMemcpyAsync(dh, sdh, ls.tab.N * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    if (u) HIPCHK(hipMemcpyAsync(u, su, ls.tab.E * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    if (na) HIPCHK(hipMemcpyAsync(na, ls.na, ls.tab.N, hipMemcpyDeviceToHost, g->stream));
+    if (ea) HIPCHK(hipMemcpyAsync(ea, ls.ea, ls.tab.E, hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
-    if (na) std::memset(na, ls.full ? 1 : 0, ls.tab.N);
-    if (ea) std::memset(ea, ls.full ? 1 : 0, ls.tab.E);
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_get_state: ") + e.what());
   }
   return WT_OK;
-}
-
-// One Runge-Kutta step on a uniform level.
-static void uniform_step(wt_grid* g, LevelState& ls, double dt) {
-  DevWork& w = ls.work;
-  const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
-  PhysParams p = phys(g);
-  auto P = [](const double* y, const double* acc, const double* x, double* o1, double* o2) {
-    return StagePtrs{y, acc, x, o1, o2};
-  };
-  if (g->prm.rk == WT_RK4) {
-    // acc = y + dt/6 k1 ; s0 = y + dt/2 k1 ; acc += dt/3 k2 ; s1 = y + dt/2 k2 ;
-    // acc += dt/3 k3 ; s0 = y + dt k3 ; y = acc + dt/6 k4
-    const double* X[4] = {w.dh, w.dh_s[0], w.dh_s[1], w.dh_s[0]};
-    const double* XU[4] = {w.u, w.u_s[0], w.u_s[1], w.u_s[0]};
-    double* O2[4] = {w.dh_s[0], w.dh_s[1], w.dh_s[0], nullptr};
-    double* O2U[4] = {w.u_s[0], w.u_s[1], w.u_s[0], nullptr};
-    const double bk[4] = {dt / 6, dt / 3, dt / 3, dt / 6};
-    const double ck[4] = {dt / 2, dt / 2, dt, 0};
-    for (int s = 0; s < 4; ++s) {
-      StageOut c{};
-      c.d1 = bk[s];
-      if (s == 0) c.a1 = 1.0; else c.b1 = 1.0;
-      c.a2 = 1.0; c.d2 = ck[s];
-      double* o1 = s == 3 ? w.dh : w.dh_acc;
-      double* o1u = s == 3 ? w.u : w.u_acc;
-      launch_stage(ls.tab, w, p, fp32, P(w.dh, w.dh_acc, X[s], o1, O2[s]),
-                   P(w.u, w.u_acc, XU[s], o1u, O2U[s]), c, g->stream, &g->timer);
-    }
-  } else {
-    // y1 = y + dt/2 L(y); y2 = y1 + dt/2 L(y1); y3 = 2/3 y + 1/3 y2 + dt/6 L(y2);
-    // y = y3 + dt/2 L(y3)
-    StageOut c{};
-    c.a1 = 1.0; c.d1 = dt / 2;
-    launch_stage(ls.tab, w, p, fp32, P(w.dh, nullptr, w.dh, w.dh_s[0], nullptr),
-                 P(w.u, nullptr, w.u, w.u_s[0], nullptr), c, g->stream, &g->timer);
-    c = StageOut{}; c.c1 = 1.0; c.d1 = dt / 2;
-    launch_stage(ls.tab, w, p, fp32, P(w.dh, nullptr, w.dh_s[0], w.dh_s[1], nullptr),
-                 P(w.u, nullptr, w.u_s[0], w.u_s[1], nullptr), c, g->stream, &g->timer);
-    c = StageOut{}; c.a1 = 2.0 / 3.0; c.c1 = 1.0 / 3.0; c.d1 = dt / 6;
-    launch_stage(ls.tab, w, p, fp32, P(w.dh, nullptr, w.dh_s[1], w.dh_s[0], nullptr),
-                 P(w.u, nullptr, w.u_s[1], w.u_s[0], nullptr), c, g->stream, &g->timer);
-    c = StageOut{}; c.c1 = 1.0; c.d1 = dt / 2;
-    launch_stage(ls.tab, w, p, fp32, P(w.dh, nullptr, w.dh_s[0], w.dh, nullptr),
-                 P(w.u, nullptr, w.u_s[0], w.u, nullptr), c, g->stream, &g->timer);
-  }
 }
 
 int wt_step(wt_grid* g, double dt) {
@@ -290,13 +506,83 @@ int wt_step(wt_grid* g, double dt) {
   if (!g->have_state) return fail(WT_ESTATE, "wt_step: call wt_set_state first");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(WT_EINVAL, "wt_step: dt must be positive");
   try {
-    if (g->jmin == g->jmax) {
+    if (g->multi())
+      ml_step(g, dt);
+    else
       uniform_step(g, g->L(g->jmax), dt);
-    } else {
-      return fail(WT_EINVAL, "wt_step: adaptive grids not supported yet");
-    }
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_step: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_adapt(wt_grid* g, double eps) {
+  if (!g) return fail(WT_EINVAL, "wt_adapt: null grid");
+  if (!g->have_state) return fail(WT_ESTATE, "wt_adapt: call wt_set_state first");
+  if (!(eps >= 0) || !std::isfinite(eps)) return fail(WT_EINVAL, "wt_adapt: eps must be >= 0");
+  if (!g->multi()) return WT_OK;
+  try {
+    adapt_impl(g, eps, nullptr, nullptr);
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_adapt: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_forward(wt_grid* g) {
+  if (!g) return fail(WT_EINVAL, "wt_forward: null grid");
+  if (!g->have_state) return fail(WT_ESTATE, "wt_forward: call wt_set_state first");
+  if (!g->multi()) return WT_OK;
+  try {
+    std::vector<double*> dh = state_dh(g), u = state_u(g);
+    prolong_all(g, dh, u);
+    details_all(g, dh, u);
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_forward: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_inverse(wt_grid* g) {
+  if (!g) return fail(WT_EINVAL, "wt_inverse: null grid");
+  if (!g->have_state) return fail(WT_ESTATE, "wt_inverse: call wt_set_state first");
+  if (!g->multi()) return WT_OK;
+  try {
+    std::vector<double*> dh = state_dh(g), u = state_u(g);
+    prolong_all(g, dh, u);
+    details_all(g, dh, u);
+    inverse_all(g, dh, u, false);
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_inverse: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_get_details(wt_grid* g, int level, double* dh, double* dpair, double* dint) {
+  if (!g || level <= g->jmin || level > g->jmax) return fail(WT_EINVAL, "wt_get_details: bad level");
+  try {
+    PairState& P = g->P(level - 1);
+    const LevelState& C = g->L(level - 1);
+    if (dh) HIPCHK(hipMemcpyAsync(dh, P.d_h, C.tab.E * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    if (dpair) HIPCHK(hipMemcpyAsync(dpair, P.d_p, C.tab.E * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    if (dint) HIPCHK(hipMemcpyAsync(dint, P.d_i, 3 * C.tab.T * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_get_details: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_set_mask(wt_grid* g, int level, const uint8_t* na, const uint8_t* ea) {
+  if (bad_level(g, level) || !na || !ea) return fail(WT_EINVAL, "wt_set_mask: bad argument");
+  try {
+    LevelState& l = g->L(level);
+    HIPCHK(hipMemcpyAsync(l.na, na, l.tab.N, hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(l.ea, ea, l.tab.E, hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_set_mask: ") + e.what());
   }
   return WT_OK;
 }
@@ -321,34 +607,57 @@ int wt_tendency(wt_grid* g, int level, double* ddh, double* du) {
   return WT_OK;
 }
 
-static int diag_raw(wt_grid* g, double* r) {
+// raw reductions of the finest level's reconstruction (multilevel) or state (uniform)
+static void diag_fine(wt_grid* g, double* r) {
   LevelState& ls = g->L(g->jmax);
-  launch_diagnostics(ls.tab, ls.work, phys(g), g->stream, r);
-  return WT_OK;
+  if (g->multi()) {
+    std::vector<double*> rdh, ru;
+    reconstruct(g, rdh, ru);
+    launch_diagnostics(ls.tab, ls.work, phys(g), g->stream, r, rdh.back(), ru.back());
+  } else {
+    launch_diagnostics(ls.tab, ls.work, phys(g), g->stream, r);
+  }
 }
 
 int wt_diagnostics(wt_grid* g, wt_diag* d) {
   if (!g || !d) return fail(WT_EINVAL, "wt_diagnostics: null argument");
   if (!g->have_state) return fail(WT_ESTATE, "wt_diagnostics: no state loaded");
   try {
-    double r[8];
-    diag_raw(g, r);
     std::memset(d, 0, sizeof(*d));
+    double r[8], r0[8];
+    diag_fine(g, r);
     const Level& L = g->L(g->jmax).geo;
     double A_S = 0;
     for (double a : L.A_i) A_S += a;
     double c2 = g->prm.gravity * r[0] / A_S;
-    d->mass = r[0];
+    d->mass_reconstructed = r[0];
     d->energy = r[1] - 0.5 * c2 * c2 * A_S;
-    d->max_abs_dh = r[2];
-    d->max_abs_u = r[3];
-    for (int j = g->jmin; j <= g->jmax; ++j) {
-      if (j < 16) {
-        d->active_nodes[j] = g->L(j).full ? g->L(j).tab.N : 0;
-        d->active_edges[j] = g->L(j).full ? g->L(j).tab.E : 0;
-      }
+    double nonfinite = r[4];
+    if (g->multi()) {
+      LevelState& l0 = g->L(g->jmin);
+      launch_diagnostics(l0.tab, l0.work, phys(g), g->stream, r0);
+      d->mass = r0[0];
+      nonfinite += r0[4];
+      d->max_abs_dh = masked_max_all(g, true);
+      d->max_abs_u = masked_max_all(g, false);
+    } else {
+      d->mass = r[0];
+      d->max_abs_dh = r[2];
+      d->max_abs_u = r[3];
     }
-    if (r[4] > 0) return fail(WT_ENUMERIC, "wt_diagnostics: non-finite values in the state");
+    for (int j = g->jmin; j <= g->jmax && j < 16; ++j) {
+      LevelState& l = g->L(j);
+      double cn, ce;
+      ml_count(l.tab.N, l.na, l.work.red, l.work.red + 4096, g->stream);
+      HIPCHK(hipMemcpyAsync(&cn, l.work.red + 4096, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+      HIPCHK(hipStreamSynchronize(g->stream));
+      ml_count(l.tab.E, l.ea, l.work.red, l.work.red + 4096, g->stream);
+      HIPCHK(hipMemcpyAsync(&ce, l.work.red + 4096, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+      HIPCHK(hipStreamSynchronize(g->stream));
+      d->active_nodes[j] = int64_t(cn);
+      d->active_edges[j] = int64_t(ce);
+    }
+    if (nonfinite > 0) return fail(WT_ENUMERIC, "wt_diagnostics: non-finite values in the state");
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_diagnostics: ") + e.what());
   }
@@ -360,7 +669,7 @@ double wt_suggest_dt(wt_grid* g, double cfl) {
   if (!g->have_state) { fail(WT_ESTATE, "wt_suggest_dt: no state loaded"); return -1.0; }
   try {
     double r[8];
-    diag_raw(g, r);
+    diag_fine(g, r);
     return cfl * std::fmin(1.0 / r[5], r[6]);
   } catch (const std::exception& e) {
     fail(WT_EDEVICE, std::string("wt_suggest_dt: ") + e.what());
@@ -428,6 +737,33 @@ int wt_host_level_tables(int level, double radius, double omega, double* A_i, do
     if (w) std::memcpy(w, L.w.data(), 10 * L.E * sizeof(double));
   } catch (const std::bad_alloc&) {
     return fail(WT_ENOMEM, "wt_host_level_tables: out of memory");
+  }
+  return WT_OK;
+}
+
+int wt_host_pair_tables(int jc, int jmax, double radius, double omega, int32_t* cells, double* st,
+                        double* s_upd, double* A_c, int32_t* v_sten, double* w_int, double* w_pl,
+                        double* w_pr, int32_t* rf_f, double* rf_fw, int32_t* rf_c, double* rf_cw) {
+  if (jc < 0 || jmax <= jc || jmax > 8) return fail(WT_EINVAL, "wt_host_pair_tables: need 0 <= jc < jmax <= 8");
+  try {
+    std::vector<Level> L(jmax - jc + 1);
+    for (int j = jc; j <= jmax; ++j) build_level(j, radius, omega, L[j - jc]);
+    std::vector<double> A = L.back().A_i, Ac;
+    PairTables P;
+    for (int j = jmax - 1; j >= jc; --j) {
+      P = PairTables{};
+      build_pair(L[j - jc], L[j + 1 - jc], P);
+      finish_pair(L[j - jc], L[j + 1 - jc], A, P, Ac);
+      A.swap(Ac);
+    }
+    auto cp = [](auto* dst, const auto& v) {
+      if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    cp(cells, P.cells); cp(st, P.st); cp(s_upd, P.s_upd); cp(A_c, A); cp(v_sten, P.v_sten);
+    cp(w_int, P.w_int); cp(w_pl, P.w_pl); cp(w_pr, P.w_pr); cp(rf_f, P.rf_f); cp(rf_fw, P.rf_fw);
+    cp(rf_c, P.rf_c); cp(rf_cw, P.rf_cw);
+  } catch (const std::bad_alloc&) {
+    return fail(WT_ENOMEM, "wt_host_pair_tables: out of memory");
   }
   return WT_OK;
 }

@@ -38,6 +38,8 @@ struct DevWork {
   double *dh_acc = nullptr, *u_acc = nullptr;  // Runge-Kutta accumulator
   double *dh_s[2] = {nullptr, nullptr}, *u_s[2] = {nullptr, nullptr};  // stage inputs
   void *qv = nullptr, *B = nullptr, *F = nullptr, *qe = nullptr;     // T-typed intermediates
+  void* Q = nullptr;                           // T-typed qF^perp (multilevel path)
+  double* c = nullptr;                         // fine divergence (multilevel path)
   double* ddh = nullptr;                       // tendency output buffers (test hook)
   double* du = nullptr;
   double* red = nullptr;                       // reduction scratch
@@ -78,9 +80,13 @@ void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32
                   const StagePtrs& sdh, const StagePtrs& su, const StageOut& c,
                   hipStream_t s, Timer* tm);
 
+// q_v, B, F, q_e of one level (no tendency, no stage output).
+void launch_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
+                          const StagePtrs& sdh, const StagePtrs& su, hipStream_t s);
+
 // Diagnostics: out[0]=mass, out[1]=energy, out[2]=max|dh|, out[3]=max|u|, out[4]=non-finite
 // count, out[5]=omega_max, out[6]=min d_e/|u_e|.
 void launch_diagnostics(const DevTables& t, DevWork& w, const PhysParams& p, hipStream_t s,
-                        double* host_out);
+                        double* host_out, const double* dh = nullptr, const double* u = nullptr);
 
 }  // namespace wt

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
                                                   const double* __restrict__ dh,
                                                   const double* __restrict__ u,
                                                   const T* __restrict__ qv, double g, double H,
-                                                  T* __restrict__ B, T* __restrict__ F,
+                                                  T* __restrict__ B, double* __restrict__ F,
                                                   T* __restrict__ qe) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
   for (int d = 0; d < 3; ++d) {
     int64_t e = 3 * id + d;
     T he = T(0.5) * ((T(H) + T(dh[e_c[2 * e]])) + (T(H) + T(dh[e_c[2 * e + 1]])));
-    F[e] = he * T(u[e]);
+    F[e] = double(he * T(u[e]));  // the mass flux is stored in double in both precisions
     qe[e] = T(0.5) * (qv[e_v[2 * e]] + qv[e_v[2 * e + 1]]);
   }
 }
@@ -103,14 +103,14 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
                                              const double* __restrict__ inv_d,
                                              const int32_t* __restrict__ ecp,
                                              const double* __restrict__ wl,
-                                             const T* __restrict__ B, const T* __restrict__ F,
+                                             const T* __restrict__ B, const double* __restrict__ F,
                                              const T* __restrict__ qe, StagePtrs pdh, StagePtrs pu,
                                              StageOut c) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
   double div = 0.0;  // divergence sums stay in double in both precisions
 #pragma unroll
-  for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * double(F[c_e[6 * id + k]]);
+  for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * F[c_e[6 * id + k]];
   rk_epilogue(id, -div, pdh, c);
   if (id >= n_elem) return;
 #pragma unroll
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
       int32_t ep = ecp[10 * e + k];
-      Q += T(wl[10 * e + k]) * F[ep] * (T(0.5) * (q0 + qe[ep]));
+      Q += T(wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
     }
     T gradB = (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * T(inv_d[e]);
     rk_epilogue(e, double(-Q - gradB), pu, c);
@@ -156,7 +156,7 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
                        const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm) {
   T* qv = static_cast<T*>(w.qv);
   T* B = static_cast<T*>(w.B);
-  T* F = static_cast<T*>(w.F);
+  double* F = static_cast<double*>(w.F);
   T* qe = static_cast<T*>(w.qe);
   {
     TimedLaunch tl(tm, K_VERTEX, s);
@@ -174,6 +174,25 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
                                        B, F, qe, sdh, su, c);
   }
   HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+static void intermediates_impl(const DevTables& t, DevWork& w, const PhysParams& p, const StagePtrs& sdh,
+                               const StagePtrs& su, hipStream_t s) {
+  T* qv = static_cast<T*>(w.qv);
+  k_vertex<T><<<nblk(t.T), BS, 0, s>>>(t.T, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
+  k_edge_cell<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv, p.g,
+                                          p.H, static_cast<T*>(w.B), static_cast<double*>(w.F),
+                                          static_cast<T*>(w.qe));
+  HIPCHK(hipGetLastError());
+}
+
+void launch_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
+                          const StagePtrs& sdh, const StagePtrs& su, hipStream_t s) {
+  if (fp32)
+    intermediates_impl<float>(t, w, p, sdh, su, s);
+  else
+    intermediates_impl<double>(t, w, p, sdh, su, s);
 }
 
 void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
@@ -266,11 +285,11 @@ __global__ __launch_bounds__(BS) void k_diag_final(const double* __restrict__ pa
 }
 
 void launch_diagnostics(const DevTables& t, DevWork& w, const PhysParams& p, hipStream_t s,
-                        double* host_out) {
+                        double* host_out, const double* dh, const double* u) {
   double* part = w.red;
   double* out = w.red + NRED * RED_BLOCKS;
   k_diag_partial<<<RED_BLOCKS, BS, 0, s>>>(t.N, t.n_elem, t.A_i, t.l_e, t.d_e, t.e_c, t.e_v, t.f_v,
-                                           w.dh, w.u, p.g, p.H, part);
+                                           dh ? dh : w.dh, u ? u : w.u, p.g, p.H, part);
   k_diag_final<<<1, BS, 0, s>>>(part, out);
   HIPCHK(hipGetLastError());
   double r[NRED];

@@ -1,0 +1,714 @@
+// Multilevel kernels for gfx950: prolongation of inactive points, flux / Q / B restriction,
+// masked tendencies, partial height transform, wavelet details, adaptivity masks and the
+// inverse transform (Sec. 2.2-2.3, 3.1, 4.1-4.4).  One thread per coarse node, edge or
+// triangle of a level pair; every kernel is a gather, or a scatter of the value 1 into a byte
+// mask (idempotent), so results do not depend on thread order.
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "wt_ml.hpp"
+
+namespace wt {
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_) + " at " #x); \
+  } while (0)
+
+constexpr int BS = 256;
+static inline unsigned nb(int64_t n) { return unsigned((n + BS - 1) / BS); }
+#define TID (int64_t(blockIdx.x) * BS + threadIdx.x)
+
+// ------------------------------------------------------------------ shared device helpers
+__device__ __forceinline__ double pair_pred(const DevPair& P, int64_t e, const int32_t* __restrict__ e_v,
+                                            const double* __restrict__ uc) {
+  int32_t tl = e_v[2 * e], tr = e_v[2 * e + 1];
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s += P.w_pl[9 * e + k] * uc[P.v_sten[9 * tl + k]];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s += P.w_pr[9 * e + k] * uc[P.v_sten[9 * tr + k]];
+  return s;
+}
+
+__device__ __forceinline__ double int_pred(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v += P.w_int[27 * t + 9 * s + k] * uc[P.v_sten[9 * t + k]];
+  return v;
+}
+
+__device__ __forceinline__ double h_detail(const DevPair& P, int64_t e, const double* __restrict__ hf) {
+  double s = hf[P.mid[e]];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s -= P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
+  return s;
+}
+
+// ------------------------------------------------------------------ prolongation
+// Inactive even node: the coarse value; inactive odd node: s~-weighted mean of its four even
+// fine neighbours; inactive half-edges: u^j -+ (p1-p2)/2; inactive interior edges: prediction.
+__global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* __restrict__ naf,
+                                                     const double* __restrict__ hc, double* __restrict__ hf) {
+  int64_t k = TID;
+  if (k >= P.Nc) return;
+  int32_t f = P.even[k];
+  if (!naf[f]) hf[f] = hc[k];
+}
+
+__global__ __launch_bounds__(BS) void k_prolong_odd_pair(DevPair P, const uint8_t* __restrict__ naf,
+                                                         const uint8_t* __restrict__ eaf,
+                                                         const int32_t* __restrict__ e_v_c,
+                                                         const double* __restrict__ uc,
+                                                         double* __restrict__ hf, double* __restrict__ uf) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  int32_t m = P.mid[e];
+  if (!naf[m]) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
+    hf[m] = s;
+  }
+  int32_t h1 = P.h1[e], h2 = P.h2[e];
+  bool a1 = eaf[h1], a2 = eaf[h2];
+  if (!a1 || !a2) {
+    double half = 0.5 * pair_pred(P, e, e_v_c, uc);
+    if (!a1) uf[h1] = uc[e] + half;
+    if (!a2) uf[h2] = uc[e] - half;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_prolong_int(DevPair P, const uint8_t* __restrict__ eaf,
+                                                    const double* __restrict__ uc, double* __restrict__ uf) {
+  int64_t t = TID;
+  if (t >= P.Tc) return;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    int32_t f = P.int_e[3 * t + s];
+    if (!eaf[f]) uf[f] = int_pred(P, t, s, uc);
+  }
+}
+
+void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
+                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s) {
+  k_prolong_even<<<nb(P.Nc), BS, 0, s>>>(P, naf, hc, hf);
+  k_prolong_odd_pair<<<nb(P.Ec), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf);
+  k_prolong_int<<<nb(P.Tc), BS, 0, s>>>(P, eaf, uc, uf);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Q, divergence, restriction
+template <typename T>
+__global__ __launch_bounds__(BS) void k_Q(int64_t E, const int32_t* __restrict__ ecp,
+                                          const double* __restrict__ wl, const double* __restrict__ F,
+                                          const T* __restrict__ qe, T* __restrict__ Q) {
+  int64_t e = TID;
+  if (e >= E) return;
+  T q0 = qe[e], s = T(0);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    int32_t ep = ecp[10 * e + k];
+    s += T(wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
+  }
+  Q[e] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_div(int64_t N, const int32_t* __restrict__ c_e,
+                                            const double* __restrict__ c_div, const double* __restrict__ F,
+                                            double* __restrict__ c) {
+  int64_t i = TID;
+  if (i >= N) return;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s += c_div[6 * i + k] * F[c_e[6 * i + k]];
+  c[i] = s;
+}
+
+// F^j = R_F(F^{j+1}, c^{j+1}) and Q^j = mean of the half-edges at non-leaf edges;
+// B^j = B^{j+1} at non-leaf nodes.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict_edges(DevPair P, const uint8_t* __restrict__ eaf,
+                                                       const double* __restrict__ l_f,
+                                                       const double* __restrict__ l_c,
+                                                       const double* __restrict__ Ff, const double* __restrict__ cf,
+                                                       const T* __restrict__ Qf, double* __restrict__ Fc,
+                                                       T* __restrict__ Qc) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  int32_t h1 = P.h1[e], h2 = P.h2[e];
+  if (!(eaf[h1] && eaf[h2])) return;
+  double phi = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int32_t f = P.rf_f[3 * e + k];
+    phi += P.rf_fw[3 * e + k] * (l_f[f] * Ff[f]);
+  }
+#pragma unroll
+  for (int k = 0; k < RF_NC; ++k) phi += P.rf_cw[RF_NC * e + k] * cf[P.rf_c[RF_NC * e + k]];
+  Fc[e] = phi / l_c[e];
+  Qc[e] = T(0.5) * (Qf[h1] + Qf[h2]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict_B(DevPair P, const uint8_t* __restrict__ naf,
+                                                   const T* __restrict__ Bf, T* __restrict__ Bc) {
+  int64_t k = TID;
+  if (k >= P.Nc) return;
+  int32_t f = P.even[k];
+  if (naf[f]) Bc[k] = Bf[f];
+}
+
+__device__ __forceinline__ void rk_out(int64_t i, double k, const StagePtrs& p, const StageOut& c) {
+  if (p.o1) {
+    double v = c.d1 * k;
+    if (c.a1 != 0.0) v += c.a1 * p.y[i];
+    if (c.b1 != 0.0) v += c.b1 * p.acc[i];
+    if (c.c1 != 0.0) v += c.c1 * p.x[i];
+    p.o1[i] = v;
+  }
+  if (p.o2) {
+    double v = c.d2 * k;
+    if (c.a2 != 0.0) v += c.a2 * p.y[i];
+    if (c.b2 != 0.0) v += c.b2 * p.acc[i];
+    if (c.c2 != 0.0) v += c.c2 * p.x[i];
+    p.o2[i] = v;
+  }
+}
+
+// Tendencies at active points of one level with that level's (possibly restricted) F, Q, B,
+// zero elsewhere, followed by the Runge-Kutta stage combination.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_tend_ml(int64_t N, int64_t n_elem, const int32_t* __restrict__ c_e,
+                                                const double* __restrict__ c_div,
+                                                const int32_t* __restrict__ e_c,
+                                                const double* __restrict__ inv_d,
+                                                const uint8_t* __restrict__ na,
+                                                const uint8_t* __restrict__ ea, const T* __restrict__ B,
+                                                const double* __restrict__ F, const T* __restrict__ Q,
+                                                StagePtrs pdh, StagePtrs pu, StageOut c) {
+  int64_t id = TID;
+  if (id >= N) return;
+  double k = 0.0;
+  if (na[id]) {
+    double div = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) div += c_div[6 * id + q] * F[c_e[6 * id + q]];
+    k = -div;
+  }
+  rk_out(id, k, pdh, c);
+  if (id >= n_elem) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int64_t e = 3 * id + d;
+    double ku = 0.0;
+    if (ea[e]) ku = double(-Q[e] - (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * T(inv_d[e]));
+    rk_out(e, ku, pu, c);
+  }
+}
+
+template <typename T>
+void ml_level_trisk_t(const DevTables& t, DevWork& w, const PhysParams& p, const double* xdh,
+                      const double* xu, hipStream_t s);
+
+void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
+                            const double* xdh, const double* xu, hipStream_t s) {
+  StageOut c{};
+  StagePtrs none{nullptr, nullptr, xdh, nullptr, nullptr};
+  StagePtrs noneu{nullptr, nullptr, xu, nullptr, nullptr};
+  // q_v, B, F, q_e through the uniform kernels (no stage output), then Q
+  launch_intermediates(t, w, p, fp32, none, noneu, s);
+  if (fp32)
+    k_Q<float><<<nb(t.E), BS, 0, s>>>(t.E, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<float*>(w.qe),
+                                      static_cast<float*>(w.Q));
+  else
+    k_Q<double><<<nb(t.E), BS, 0, s>>>(t.E, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<double*>(w.qe),
+                                       static_cast<double*>(w.Q));
+  HIPCHK(hipGetLastError());
+  (void)c;
+}
+
+void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, DevWork& wc, DevWork& wf,
+                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s) {
+  if (fp32) {
+    k_div<float><<<nb(tf.N), BS, 0, s>>>(tf.N, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c);
+    k_restrict_edges<float><<<nb(P.Ec), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
+                                                    static_cast<float*>(wf.Q), static_cast<double*>(wc.F),
+                                                    static_cast<float*>(wc.Q));
+    k_restrict_B<float><<<nb(P.Nc), BS, 0, s>>>(P, naf, static_cast<float*>(wf.B), static_cast<float*>(wc.B));
+  } else {
+    k_div<double><<<nb(tf.N), BS, 0, s>>>(tf.N, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c);
+    k_restrict_edges<double><<<nb(P.Ec), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
+                                                     static_cast<double*>(wf.Q), static_cast<double*>(wc.F),
+                                                     static_cast<double*>(wc.Q));
+    k_restrict_B<double><<<nb(P.Nc), BS, 0, s>>>(P, naf, static_cast<double*>(wf.B), static_cast<double*>(wc.B));
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, bool fp32,
+             const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s) {
+  if (fp32)
+    k_tend_ml<float><<<nb(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
+                                            static_cast<float*>(w.B), static_cast<double*>(w.F),
+                                            static_cast<float*>(w.Q), sdh, su, c);
+  else
+    k_tend_ml<double><<<nb(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
+                                             static_cast<double*>(w.B), static_cast<double*>(w.F),
+                                             static_cast<double*>(w.Q), sdh, su, c);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ restriction of the state
+__global__ __launch_bounds__(BS) void k_restrict_h(DevPair P, const double* __restrict__ hf,
+                                                   double* __restrict__ hc) {
+  int64_t k = TID;
+  if (k >= P.Nc) return;
+  double s = hf[P.even[k]];
+  for (int q = 0; q < MK_MAX; ++q) {
+    int32_t ec = P.mk[MK_MAX * k + q];
+    if (ec < 0) break;
+    s += P.s_upd[ec] * h_detail(P, ec >> 2, hf);
+  }
+  hc[k] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_restrict_u(DevPair P, const double* __restrict__ uf,
+                                                   double* __restrict__ uc) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  uc[e] = 0.5 * (uf[P.h1[e]] + uf[P.h2[e]]);
+}
+
+void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, double* hc, double* uc,
+                       hipStream_t s) {
+  k_restrict_h<<<nb(P.Nc), BS, 0, s>>>(P, hf, hc);
+  k_restrict_u<<<nb(P.Ec), BS, 0, s>>>(P, uf, uc);
+  HIPCHK(hipGetLastError());
+}
+
+// Partial height transform at complete coarse nodes: the whole height-restriction stencil is
+// active and every coarse edge of the node is non-leaf.
+__global__ __launch_bounds__(BS) void k_partial_h(DevPair P, const int32_t* __restrict__ c_e_c,
+                                                  const uint8_t* __restrict__ nac,
+                                                  const uint8_t* __restrict__ naf,
+                                                  const uint8_t* __restrict__ eaf,
+                                                  const double* __restrict__ hf, double* __restrict__ hc) {
+  int64_t k = TID;
+  if (k >= P.Nc) return;
+  if (!nac[k] || !naf[P.even[k]]) return;
+  for (int q = 0; q < MK_MAX; ++q) {
+    int32_t ec = P.mk[MK_MAX * k + q];
+    if (ec < 0) break;
+    int64_t e = ec >> 2;
+    if (!naf[P.mid[e]]) return;
+    for (int c = 0; c < 4; ++c)
+      if (!naf[P.even[P.cells[4 * e + c]]]) return;
+  }
+  for (int q = 0; q < 6; ++q) {
+    int32_t e = c_e_c[6 * k + q];
+    if (!(eaf[P.h1[e]] && eaf[P.h2[e]])) return;
+  }
+  double s = hf[P.even[k]];
+  for (int q = 0; q < MK_MAX; ++q) {
+    int32_t ec = P.mk[MK_MAX * k + q];
+    if (ec < 0) break;
+    s += P.s_upd[ec] * h_detail(P, ec >> 2, hf);
+  }
+  hc[k] = s;
+}
+
+void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
+                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s) {
+  k_partial_h<<<nb(P.Nc), BS, 0, s>>>(P, tc.c_e, nac, naf, eaf, hf, hc);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ details
+__global__ __launch_bounds__(BS) void k_details_edge(DevPair P, const int32_t* __restrict__ e_v_c,
+                                                     const double* __restrict__ hf,
+                                                     const double* __restrict__ uf,
+                                                     const double* __restrict__ uc,
+                                                     double* __restrict__ dh, double* __restrict__ dp) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  dh[e] = h_detail(P, e, hf);
+  dp[e] = (uf[P.h1[e]] - uf[P.h2[e]]) - pair_pred(P, e, e_v_c, uc);
+}
+
+__global__ __launch_bounds__(BS) void k_details_int(DevPair P, const double* __restrict__ uf,
+                                                    const double* __restrict__ uc, double* __restrict__ di) {
+  int64_t t = TID;
+  if (t >= P.Tc) return;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) di[3 * t + s] = uf[P.int_e[3 * t + s]] - int_pred(P, t, s, uc);
+}
+
+void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
+                const double* uc, double* dh, double* dp, double* di, hipStream_t s) {
+  k_details_edge<<<nb(P.Ec), BS, 0, s>>>(P, tc.e_v, hf, uf, uc, dh, dp);
+  k_details_int<<<nb(P.Tc), BS, 0, s>>>(P, uf, uc, di);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ masks
+// R1: significant points of the fine level of a pair (active, |d| >= eps).
+__global__ __launch_bounds__(BS) void k_sig_edge(DevPair P, const uint8_t* __restrict__ naf,
+                                                 const uint8_t* __restrict__ eaf,
+                                                 const double* __restrict__ dh, const double* __restrict__ dp,
+                                                 double eh, double eu, uint8_t* __restrict__ sn,
+                                                 uint8_t* __restrict__ se) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  int32_t m = P.mid[e];
+  if (naf[m] && fabs(dh[e]) >= eh) sn[m] = 1;
+  int32_t h1 = P.h1[e], h2 = P.h2[e];
+  if (eaf[h1] && eaf[h2] && fabs(dp[e]) >= eu) {
+    se[h1] = 1;
+    se[h2] = 1;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_sig_int(DevPair P, const uint8_t* __restrict__ eaf,
+                                                const double* __restrict__ di, double eu,
+                                                uint8_t* __restrict__ se) {
+  int64_t t = TID;
+  if (t >= P.Tc) return;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    int32_t f = P.int_e[3 * t + s];
+    if (eaf[f] && fabs(di[3 * t + s]) >= eu) se[f] = 1;
+  }
+}
+
+void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
+                    const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
+                    hipStream_t s) {
+  k_sig_edge<<<nb(P.Ec), BS, 0, s>>>(P, naf, eaf, dh, dp, eh, eu, sn, se);
+  k_sig_int<<<nb(P.Tc), BS, 0, s>>>(P, eaf, di, eu, se);
+  HIPCHK(hipGetLastError());
+}
+
+// R2: same-level neighbours of significant nodes (neighbour nodes, incident edges) and edges
+// (end nodes, the edges of both triangles).
+__global__ __launch_bounds__(BS) void k_r2_nodes(int64_t N, const int32_t* __restrict__ c_e,
+                                                 const double* __restrict__ c_div,
+                                                 const int32_t* __restrict__ e_c,
+                                                 const uint8_t* __restrict__ sn, uint8_t* __restrict__ nn,
+                                                 uint8_t* __restrict__ ne) {
+  int64_t i = TID;
+  if (i >= N || !sn[i]) return;
+  for (int q = 0; q < 6; ++q) {
+    if (c_div[6 * i + q] == 0.0) continue;  // padded pentagon slot
+    int32_t e = c_e[6 * i + q];
+    ne[e] = 1;
+    nn[e_c[2 * e]] = 1;
+    nn[e_c[2 * e + 1]] = 1;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_r2_edges(int64_t E, const int32_t* __restrict__ e_c,
+                                                 const int32_t* __restrict__ e_v,
+                                                 const int32_t* __restrict__ t_e,
+                                                 const uint8_t* __restrict__ se, uint8_t* __restrict__ nn,
+                                                 uint8_t* __restrict__ ne) {
+  int64_t e = TID;
+  if (e >= E || !se[e]) return;
+  nn[e_c[2 * e]] = 1;
+  nn[e_c[2 * e + 1]] = 1;
+  for (int side = 0; side < 2; ++side) {
+    int32_t t = e_v[2 * e + side];
+    for (int s = 0; s < 3; ++s) ne[t_e[3 * t + s]] = 1;
+  }
+}
+
+void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s) {
+  k_r2_nodes<<<nb(t.N), BS, 0, s>>>(t.N, t.c_e, t.c_div, t.e_c, sn, nn, ne);
+  k_r2_edges<<<nb(t.E), BS, 0, s>>>(t.E, t.e_c, t.e_v, t.t_e, se, nn, ne);
+  HIPCHK(hipGetLastError());
+}
+
+// R3: children on the next level of significant coarse nodes (fine copy, its neighbours and
+// incident fine edges) and edges (midpoint and the fine edges at it).
+__device__ __forceinline__ void mark_cell(int64_t f, const int32_t* __restrict__ c_e,
+                                          const double* __restrict__ c_div,
+                                          const int32_t* __restrict__ e_c, uint8_t* __restrict__ nn,
+                                          uint8_t* __restrict__ ne, bool nbrs) {
+  nn[f] = 1;
+  for (int q = 0; q < 6; ++q) {
+    if (c_div[6 * f + q] == 0.0) continue;
+    int32_t e = c_e[6 * f + q];
+    ne[e] = 1;
+    if (nbrs) {
+      nn[e_c[2 * e]] = 1;
+      nn[e_c[2 * e + 1]] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_r3_nodes(DevPair P, const uint8_t* __restrict__ snc,
+                                                 const int32_t* __restrict__ c_e_f,
+                                                 const double* __restrict__ c_div_f,
+                                                 const int32_t* __restrict__ e_c_f, uint8_t* __restrict__ nnf,
+                                                 uint8_t* __restrict__ nef) {
+  int64_t k = TID;
+  if (k >= P.Nc || !snc[k]) return;
+  mark_cell(P.even[k], c_e_f, c_div_f, e_c_f, nnf, nef, true);
+}
+
+__global__ __launch_bounds__(BS) void k_r3_edges(DevPair P, const uint8_t* __restrict__ sec,
+                                                 const int32_t* __restrict__ c_e_f,
+                                                 const double* __restrict__ c_div_f,
+                                                 const int32_t* __restrict__ e_c_f, uint8_t* __restrict__ nnf,
+                                                 uint8_t* __restrict__ nef) {
+  int64_t e = TID;
+  if (e >= P.Ec || !sec[e]) return;
+  mark_cell(P.mid[e], c_e_f, c_div_f, e_c_f, nnf, nef, false);
+}
+
+void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
+           uint8_t* nef, hipStream_t s) {
+  k_r3_nodes<<<nb(P.Nc), BS, 0, s>>>(P, snc, tf.c_e, tf.c_div, tf.e_c, nnf, nef);
+  k_r3_edges<<<nb(P.Ec), BS, 0, s>>>(P, sec, tf.c_e, tf.c_div, tf.e_c, nnf, nef);
+  HIPCHK(hipGetLastError());
+}
+
+// R4: edges at active nodes, then end nodes of active edges.
+__global__ __launch_bounds__(BS) void k_r4_a(int64_t N, const int32_t* __restrict__ c_e,
+                                             const double* __restrict__ c_div,
+                                             const uint8_t* __restrict__ nn, uint8_t* __restrict__ ne) {
+  int64_t i = TID;
+  if (i >= N || !nn[i]) return;
+  for (int q = 0; q < 6; ++q)
+    if (c_div[6 * i + q] != 0.0) ne[c_e[6 * i + q]] = 1;
+}
+
+__global__ __launch_bounds__(BS) void k_r4_b(int64_t E, const int32_t* __restrict__ e_c,
+                                             const uint8_t* __restrict__ ne, uint8_t* __restrict__ nn) {
+  int64_t e = TID;
+  if (e >= E || !ne[e]) return;
+  nn[e_c[2 * e]] = 1;
+  nn[e_c[2 * e + 1]] = 1;
+}
+
+void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s) {
+  k_r4_a<<<nb(t.N), BS, 0, s>>>(t.N, t.c_e, t.c_div, nn, ne);
+  k_r4_b<<<nb(t.E), BS, 0, s>>>(t.E, t.e_c, ne, nn);
+  HIPCHK(hipGetLastError());
+}
+
+// R5: prediction stencils on the coarse level of every active fine point.
+__global__ __launch_bounds__(BS) void k_r5_edge(DevPair P, const int32_t* __restrict__ e_v_c,
+                                                const uint8_t* __restrict__ nnf,
+                                                const uint8_t* __restrict__ nef, uint8_t* __restrict__ nnc,
+                                                uint8_t* __restrict__ nec) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  if (nnf[P.mid[e]])
+    for (int c = 0; c < 4; ++c) nnc[P.cells[4 * e + c]] = 1;
+  if (nef[P.h1[e]] || nef[P.h2[e]]) {
+    nec[e] = 1;
+    int32_t tl = e_v_c[2 * e], tr = e_v_c[2 * e + 1];
+    for (int k = 0; k < 9; ++k) {
+      nec[P.v_sten[9 * tl + k]] = 1;
+      nec[P.v_sten[9 * tr + k]] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_r5_node(DevPair P, const uint8_t* __restrict__ nnf,
+                                                uint8_t* __restrict__ nnc) {
+  int64_t k = TID;
+  if (k >= P.Nc) return;
+  if (nnf[P.even[k]]) nnc[k] = 1;
+}
+
+__global__ __launch_bounds__(BS) void k_r5_tri(DevPair P, const uint8_t* __restrict__ nef,
+                                               uint8_t* __restrict__ nec) {
+  int64_t t = TID;
+  if (t >= P.Tc) return;
+  if (nef[P.int_e[3 * t]] || nef[P.int_e[3 * t + 1]] || nef[P.int_e[3 * t + 2]])
+    for (int k = 0; k < 9; ++k) nec[P.v_sten[9 * t + k]] = 1;
+}
+
+void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
+           uint8_t* nec, hipStream_t s) {
+  k_r5_edge<<<nb(P.Ec), BS, 0, s>>>(P, tc.e_v, nnf, nef, nnc, nec);
+  k_r5_node<<<nb(P.Nc), BS, 0, s>>>(P, nnf, nnc);
+  k_r5_tri<<<nb(P.Tc), BS, 0, s>>>(P, nef, nec);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ inverse transform
+// Top-down, one pair at a time: kept details (points active before and after) or zero;
+// even fine nodes h^j_k - sum_m s_km d_m, then odd nodes d_m + sum_c s~_cm h_even(c);
+// half-edges u^j -+ ((p1-p2) + d)/2; interior edges d + prediction.
+__global__ __launch_bounds__(BS) void k_inv_keep(DevPair P, const uint8_t* __restrict__ na_old,
+                                                 const uint8_t* __restrict__ na_new,
+                                                 const double* __restrict__ dh, double* __restrict__ dk) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  int32_t m = P.mid[e];
+  dk[e] = (na_old[m] && na_new[m]) ? dh[e] : 0.0;
+}
+
+__global__ __launch_bounds__(BS) void k_inv_even(DevPair P, const double* __restrict__ dk,
+                                                 const double* __restrict__ hc, double* __restrict__ hf) {
+  int64_t k = TID;
+  if (k >= P.Nc) return;
+  double s = hc[k];
+  for (int q = 0; q < MK_MAX; ++q) {
+    int32_t ec = P.mk[MK_MAX * k + q];
+    if (ec < 0) break;
+    s -= P.s_upd[ec] * dk[ec >> 2];
+  }
+  hf[P.even[k]] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* __restrict__ e_v_c,
+                                                     const uint8_t* __restrict__ ea_old,
+                                                     const uint8_t* __restrict__ ea_new,
+                                                     const double* __restrict__ dk,
+                                                     const double* __restrict__ dp,
+                                                     const double* __restrict__ uc, double* __restrict__ hf,
+                                                     double* __restrict__ uf) {
+  int64_t e = TID;
+  if (e >= P.Ec) return;
+  double s = dk[e];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
+  hf[P.mid[e]] = s;
+  int32_t h1 = P.h1[e], h2 = P.h2[e];
+  bool keep = ea_old[h1] && ea_old[h2] && ea_new[h1] && ea_new[h2];
+  double half = 0.5 * (pair_pred(P, e, e_v_c, uc) + (keep ? dp[e] : 0.0));
+  uf[h1] = uc[e] + half;
+  uf[h2] = uc[e] - half;
+}
+
+__global__ __launch_bounds__(BS) void k_inv_int(DevPair P, const uint8_t* __restrict__ ea_old,
+                                                const uint8_t* __restrict__ ea_new,
+                                                const double* __restrict__ di, const double* __restrict__ uc,
+                                                double* __restrict__ uf) {
+  int64_t t = TID;
+  if (t >= P.Tc) return;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    int32_t f = P.int_e[3 * t + s];
+    bool keep = ea_old[f] && ea_new[f];
+    uf[f] = (keep ? di[3 * t + s] : 0.0) + int_pred(P, t, s, uc);
+  }
+}
+
+void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, const uint8_t* na_new,
+                const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
+                const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
+                hipStream_t s) {
+  k_inv_keep<<<nb(P.Ec), BS, 0, s>>>(P, na_old, na_new, dh, dk);
+  k_inv_even<<<nb(P.Nc), BS, 0, s>>>(P, dk, hc, hf);
+  k_inv_odd_pair<<<nb(P.Ec), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf);
+  k_inv_int<<<nb(P.Tc), BS, 0, s>>>(P, ea_old, ea_new, di, uc, uf);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ masked maxima
+__global__ __launch_bounds__(BS) void k_masked_max(int64_t n, const double* __restrict__ v,
+                                                   const uint8_t* __restrict__ act, double* __restrict__ part) {
+  __shared__ double sh[BS];
+  double m = 0.0;
+  for (int64_t i = TID; i < n; i += int64_t(gridDim.x) * BS)
+    if (act[i]) m = fmax(m, fabs(v[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(BS) void k_max_final(int n, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[BS];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += BS) m = fmax(m, part[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
+                   hipStream_t s) {
+  const int nblk = 512;
+  k_masked_max<<<nblk, BS, 0, s>>>(n, v, act, scratch);
+  k_max_final<<<1, BS, 0, s>>>(nblk, scratch, out);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ active counts
+__global__ __launch_bounds__(BS) void k_count_part(int64_t n, const uint8_t* __restrict__ act,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[BS];
+  double c = 0.0;
+  for (int64_t i = TID; i < n; i += int64_t(gridDim.x) * BS) c += act[i] ? 1.0 : 0.0;
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(BS) void k_sum_final(int n, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[BS];
+  double c = 0.0;
+  for (int i = threadIdx.x; i < n; i += BS) c += part[i];
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipStream_t s) {
+  const int nblk = 512;
+  k_count_part<<<nblk, BS, 0, s>>>(n, act, scratch);
+  k_sum_final<<<1, BS, 0, s>>>(nblk, scratch, out);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ upload
+template <typename X>
+static const X* up(const std::vector<X>& v) {
+  X* p = nullptr;
+  HIPCHK(hipMalloc(&p, v.size() * sizeof(X)));
+  HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
+  return p;
+}
+
+void upload_pair(const PairTables& P, DevPair& d) {
+  d.Nc = P.Nc; d.Ec = P.Ec; d.Tc = P.Tc; d.Nf = P.Nf; d.Ef = P.Ef;
+  d.even = up(P.even); d.mid = up(P.mid); d.h1 = up(P.h1); d.h2 = up(P.h2); d.cells = up(P.cells);
+  d.mk = up(P.mk); d.int_e = up(P.int_e); d.v_sten = up(P.v_sten); d.rf_f = up(P.rf_f); d.rf_c = up(P.rf_c);
+  d.st = up(P.st); d.s_upd = up(P.s_upd); d.w_int = up(P.w_int); d.w_pl = up(P.w_pl); d.w_pr = up(P.w_pr);
+  d.rf_fw = up(P.rf_fw); d.rf_cw = up(P.rf_cw);
+}
+
+void free_pair(DevPair& d) {
+  const void* ps[] = {d.even, d.mid, d.h1, d.h2, d.cells, d.mk, d.int_e, d.v_sten, d.rf_f, d.rf_c,
+                      d.st, d.s_upd, d.w_int, d.w_pl, d.w_pr, d.rf_fw, d.rf_cw};
+  for (const void* p : ps)
+    if (p) (void)hipFree(const_cast<void*>(p));
+  d = DevPair{};
+}
+
+}  // namespace wt

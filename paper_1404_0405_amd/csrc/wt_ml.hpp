@@ -1,0 +1,52 @@
+// Device tables of a level pair and launchers of the multilevel kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wt_internal.hpp"
+#include "wt_pair.hpp"
+
+namespace wt {
+
+struct DevPair {
+  int64_t Nc, Ec, Tc, Nf, Ef;
+  const int32_t *even, *mid, *h1, *h2, *cells, *mk, *int_e, *v_sten, *rf_f, *rf_c;
+  const double *st, *s_upd, *w_int, *w_pl, *w_pr, *rf_fw, *rf_cw;
+};
+
+void upload_pair(const PairTables& P, DevPair& d);
+void free_pair(DevPair& d);
+
+void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
+                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s);
+void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
+                            const double* xdh, const double* xu, hipStream_t s);
+void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, DevWork& wc, DevWork& wf,
+                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s);
+void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, bool fp32,
+             const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s);
+void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, double* hc, double* uc,
+                       hipStream_t s);
+void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
+                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s);
+void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
+                const double* uc, double* dh, double* dp, double* di, hipStream_t s);
+void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
+                    const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
+                    hipStream_t s);
+void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
+void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
+           uint8_t* nef, hipStream_t s);
+void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s);
+void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
+           uint8_t* nec, hipStream_t s);
+void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, const uint8_t* na_new,
+                const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
+                const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
+                hipStream_t s);
+void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
+                   hipStream_t s);
+void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipStream_t s);
+
+}  // namespace wt

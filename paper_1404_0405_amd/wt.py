@@ -31,7 +31,7 @@ class wt_params(C.Structure):
 
 
 class wt_diag(C.Structure):
-    _fields_ = [("mass", C.c_double), ("energy", C.c_double), ("max_abs_dh", C.c_double),
+    _fields_ = [("mass", C.c_double), ("mass_reconstructed", C.c_double), ("energy", C.c_double), ("max_abs_dh", C.c_double),
                 ("max_abs_u", C.c_double), ("active_nodes", C.c_int64 * 16),
                 ("active_edges", C.c_int64 * 16)]
 
@@ -55,6 +55,11 @@ SIGNATURES = [
     ("wt_get_state", C.c_int, [_P, C.c_int, _D, _D, _U8, _U8]),
     ("wt_step", C.c_int, [_P, C.c_double]),
     ("wt_tendency", C.c_int, [_P, C.c_int, _D, _D]),
+    ("wt_adapt", C.c_int, [_P, C.c_double]),
+    ("wt_forward", C.c_int, [_P]),
+    ("wt_inverse", C.c_int, [_P]),
+    ("wt_get_details", C.c_int, [_P, C.c_int, _D, _D, _D]),
+    ("wt_set_mask", C.c_int, [_P, C.c_int, _U8, _U8]),
     ("wt_diagnostics", C.c_int, [_P, C.POINTER(wt_diag)]),
     ("wt_suggest_dt", C.c_double, [_P, C.c_double]),
     ("wt_set_stream", C.c_int, [_P, _P]),
@@ -63,6 +68,8 @@ SIGNATURES = [
     ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64]),
     ("wt_kernel_names", C.c_char_p, []),
     ("wt_host_level_tables", C.c_int, [C.c_int, C.c_double, C.c_double, _D, _D, _D, _D, _I32, _I32, _D]),
+    ("wt_host_pair_tables", C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, _I32, _D, _D, _D, _I32, _D,
+                                      _D, _D, _I32, _D, _I32, _D]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -111,6 +118,24 @@ def host_level_tables(level, radius=6.371e6, omega=7.292e-5):
                                     _ptr(out["l_e"], C.c_double), _ptr(out["e_nodes"], C.c_int32),
                                     _ptr(out["ecp"], C.c_int32), _ptr(out["w"], C.c_double)))
     return out
+
+
+def host_pair_tables(jc, jmax, radius=6.371e6, omega=7.292e-5):
+    """Host-only inter-scale tables of the library between levels jc and jc+1 (no GPU)."""
+    lib = load()
+    n = 2 ** jc
+    Nc, Ec, Tc = 10 * n * n + 2, 30 * n * n, 20 * n * n
+    o = dict(cells=np.empty((Ec, 4), np.int32), st=np.empty((Ec, 4)), s_upd=np.empty((Ec, 4)),
+             A_c=np.empty(Nc), v_sten=np.empty((Tc, 9), np.int32), w_int=np.empty((Tc, 3, 9)),
+             w_pl=np.empty((Ec, 9)), w_pr=np.empty((Ec, 9)), rf_f=np.empty((Ec, 3), np.int32),
+             rf_fw=np.empty((Ec, 3)), rf_c=np.empty((Ec, 16), np.int32), rf_cw=np.empty((Ec, 16)))
+    d, i = C.c_double, C.c_int32
+    _check(lib.wt_host_pair_tables(jc, jmax, radius, omega, _ptr(o["cells"], i), _ptr(o["st"], d),
+                                   _ptr(o["s_upd"], d), _ptr(o["A_c"], d), _ptr(o["v_sten"], i),
+                                   _ptr(o["w_int"], d), _ptr(o["w_pl"], d), _ptr(o["w_pr"], d),
+                                   _ptr(o["rf_f"], i), _ptr(o["rf_fw"], d), _ptr(o["rf_c"], i),
+                                   _ptr(o["rf_cw"], d)))
+    return o
 
 
 class Grid:
@@ -192,6 +217,27 @@ class Grid:
         a, b = np.empty(N), np.empty(E)
         _check(load().wt_tendency(self._h, level, _ptr(a, C.c_double), _ptr(b, C.c_double)))
         return a, b
+
+    def adapt(self, eps):
+        _check(load().wt_adapt(self._h, float(eps)))
+
+    def forward(self):
+        _check(load().wt_forward(self._h))
+
+    def inverse(self):
+        _check(load().wt_inverse(self._h))
+
+    def get_details(self, level):
+        Nc, Ec, Tc = self.info(level - 1)
+        a, b, c = np.empty(Ec), np.empty(Ec), np.empty(3 * Tc)
+        _check(load().wt_get_details(self._h, level, _ptr(a, C.c_double), _ptr(b, C.c_double),
+                                     _ptr(c, C.c_double)))
+        return a, b, c.reshape(Tc, 3)
+
+    def set_mask(self, level, node_active, edge_active):
+        na = np.ascontiguousarray(node_active, np.uint8)
+        ea = np.ascontiguousarray(edge_active, np.uint8)
+        _check(load().wt_set_mask(self._h, level, _ptr(na, C.c_uint8), _ptr(ea, C.c_uint8)))
 
     def diagnostics(self):
         d = wt_diag()
