@@ -25,17 +25,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def _algorithmic_bytes(N, E, T, fp32):
-    """Unique bytes read + written by each stage kernel per launch (tables, inputs, outputs;
-    each array element counted once), for the table-driven kernels.  RK4 stage-averaged
-    epilogue traffic: 3.25 state accesses of 8 B per degree of freedom."""
-    s = 4 if fp32 else 8           # intermediate (q_v, B, q_e) element size; F is always double
-    vertex = T * (12 + 12 + 24 + 24 + 8) + T * s + E * 8 + N * 8
-    edge_cell = N * (24 + 48 + 8) + N * s + E * (8 + 8 + 8) + E * (8 + s) + T * s
-    tend = N * (24 + 48) + E * (8 + 8 + 40 + 80) + N * s + E * (8 + s) + (N + E) * 3.25 * 8
-    return {"trisk_vertex": vertex, "trisk_edge_cell": edge_cell, "trisk_tend": tend}
-
-
 def run_gpu(args):
     import numpy as np
     import torch
@@ -73,12 +62,14 @@ def run_gpu(args):
         d1, code = g.diagnostics()
         wall = t1 - t0
         upd = (N + E) * 4 * args.steps / wall
-        ab = _algorithmic_bytes(N, E, T, mode == "fp32")
         kernels = {}
-        for k, (ms, cnt) in kt.items():
-            avg_ms = ms / max(cnt, 1)
-            kernels[k] = {"avg_ms": avg_ms, "launches": cnt,
-                          "algorithmic_bytes": ab[k], "gbs": ab[k] / (avg_ms * 1e-3) / 1e9}
+        for k, (ms, cnt, by) in kt.items():
+            if cnt == 0:
+                continue
+            avg_ms = ms / cnt
+            avg_b = by / cnt
+            kernels[k] = {"avg_ms": avg_ms, "launches": cnt, "algorithmic_bytes": avg_b,
+                          "gbs": avg_b / (avg_ms * 1e-3) / 1e9}
         out[mode] = dict(value=upd, ms_per_step=wall * 1e3 / args.steps, kernels=kernels,
                          mass_drift=abs(d1.mass / d0.mass - 1), energy_drift=abs(d1.energy / d0.energy - 1),
                          finite=code == wt.WT_OK)

@@ -178,13 +178,18 @@ double wt_suggest_dt(wt_grid* g, double cfl);
  * later device work of the grid; NULL selects the library's own stream. */
 int wt_set_stream(wt_grid* g, void* hip_stream);
 
-/* Kernel timing for measurement: when enabled, every launch of the TRiSK stage kernels is
- * bracketed by HIP events on the grid's stream.  wt_kernel_time returns the summed device
- * time (ms) and launch count of the kernel named `name` since the last reset; names are
- * listed by wt_kernel_names (comma separated). */
+/* Kernel timing for measurement: when enabled, every launch of the uniform-level TRiSK stage
+ * kernels is bracketed by HIP events on the grid's stream.  wt_kernel_time returns the summed
+ * device time (ms), the launch count and the summed algorithmic bytes of the kernel named
+ * `name` since the last reset (total_bytes may be NULL).  Algorithmic bytes count every table
+ * entry, input and output element of a launch once: table-driven kernels per triangle 96 B +
+ * q_v, per element 176 B + 6 intermediates (edge_cell) and 504 B + 4 intermediates + the
+ * stage's Runge-Kutta arrays (tend); the lattice kernel per element the stage input (32 B)
+ * and the Runge-Kutta arrays, plus its shared geometry (464 B per tile position) once for the
+ * 10 lozenges.  Names are listed by wt_kernel_names (comma separated). */
 int wt_timing_enable(wt_grid* g, int enable);
 int wt_timing_reset(wt_grid* g);
-int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches);
+int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches, double* total_bytes);
 const char* wt_kernel_names(void);
 
 /* Host-only inspection of the grid builder (no device needed): builds level `level` with
@@ -215,6 +220,16 @@ int wt_host_pair_tables(int jc, int jmax, double radius, double omega, int32_t* 
                         int32_t* v_sten_host, double* w_int_host, double* w_pl_host,
                         double* w_pr_host, int32_t* rf_f_host, double* rf_fw_host,
                         int32_t* rf_c_host, double* rf_cw_host);
+
+/* Host-only check of the lattice form of the uniform stage for level `level` (6 <= level <= 9;
+ * no device needed): builds the shared reference geometry of the lozenge lattice (all 10
+ * lozenges are congruent under rotations of the icosahedron, Sec. 2.2), verifies the halo
+ * addressing of every regular tile, and compares the reference geometry with the canonical
+ * tables of every lozenge.  n_tiles: regular tiles per lozenge; n_rim: elements left to the
+ * table-driven kernels; max_rel_err: largest relative difference of cell areas, edge lengths
+ * and sorted perpendicular-flux weights (relative to the row's largest weight) between the
+ * reference and every lozenge.  For tests. */
+int wt_host_lattice_check(int level, int64_t* n_tiles, int64_t* n_rim, double* max_rel_err);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);

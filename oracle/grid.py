@@ -97,15 +97,55 @@ def _match_rows(canonical, query):
 
 
 def _sph_tri_area(a, b, c):
-    """Signed spherical triangle area on the unit sphere (Van Oosterom & Strackee, 1983)."""
-    num = (a * np.cross(b, c)).sum(-1)
+    """Signed spherical triangle area on the unit sphere (Van Oosterom & Strackee, 1983).
+
+    The triple product is formed from vertex differences (exact for nearby points), so its
+    rounding does not grow like 1/h^2 for small triangles of size h."""
+    num = ((a - c) * np.cross(b - c, c)).sum(-1)
     den = 1.0 + (a * b).sum(-1) + (b * c).sum(-1) + (c * a).sum(-1)
     return 2.0 * np.arctan2(num, den)
 
 
 def _arc(a, b):
-    """Great-circle angle between unit vectors."""
-    return np.arctan2(np.sqrt((np.cross(a, b) ** 2).sum(-1)), (a * b).sum(-1))
+    """Great-circle angle between unit vectors (cross product from the exact difference)."""
+    return np.arctan2(np.sqrt((np.cross(a - b, b) ** 2).sum(-1)), (a * b).sum(-1))
+
+
+def _two_square(x):
+    """x*x as an unevaluated sum p + e, exactly (Dekker's splitting)."""
+    p = x * x
+    c = 134217729.0 * x
+    hi = c - (c - x)
+    lo = x - hi
+    e = ((hi * hi - p) + 2.0 * hi * lo) + lo * lo
+    return p, e
+
+
+def _norm2_minus_one(v):
+    """|v|^2 - 1 to full relative precision for |v| ~ 1 (exact squares, Neumaier summation)."""
+    terms = []
+    for k in range(3):
+        terms += list(_two_square(v[..., k]))
+    terms.append(np.full(v.shape[:-1], -1.0))
+    s = terms[0]
+    comp = np.zeros_like(s)
+    for t in terms[1:]:
+        u = s + t
+        comp = comp + np.where(np.abs(s) >= np.abs(t), (s - u) + t, (t - u) + s)
+        s = u
+    return s + comp
+
+
+def _circumcentre(a, b, c):
+    """Circumcentre of a counter-clockwise spherical triangle: the normal of the plane
+    through the three unit directions, from direction differences b/|b| - a/|a| in which the
+    (rounding-size) length error of each normalised position is removed exactly; otherwise it
+    would tilt the plane by O(1e-16/h)."""
+    def ddiff(q, p):
+        sp = 0.5 * _norm2_minus_one(p)[..., None]
+        sq = 0.5 * _norm2_minus_one(q)[..., None]
+        return (q - p) + (sp * p - sq * q)
+    return _normalize(np.cross(ddiff(b, a), ddiff(c, a)))
 
 
 class Grid:
@@ -253,7 +293,7 @@ class Grid:
         x = self.xyz
         tn = self.t_nodes
         a, b, c = x[tn[:, 0]], x[tn[:, 1]], x[tn[:, 2]]
-        cc = _normalize(np.cross(b - a, c - a))           # circumcentre (dual vertex)
+        cc = _circumcentre(a, b, c)                        # circumcentre (dual vertex)
         self.t_cc = cc
         self.f_v = 2.0 * self.omega * cc[:, 2]
         en = self.e_nodes

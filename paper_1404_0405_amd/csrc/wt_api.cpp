@@ -1,6 +1,7 @@
 // C ABI of libwt (declared in include/wt.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include "../../include/wt.h"
 #include "wt_grid.hpp"
 #include "wt_internal.hpp"
+#include "wt_lattice_dev.hpp"
 #include "wt_ml.hpp"
 #include "wt_pair.hpp"
 
@@ -37,6 +39,7 @@ struct LevelState {
   uint8_t *na = nullptr, *ea = nullptr;  // active nodes / edges
   uint8_t *nn = nullptr, *ne = nullptr;  // masks under construction (adapt)
   uint8_t *sn = nullptr, *se = nullptr;  // significant points (adapt)
+  DevLattice lat;                        // fused lattice form (uniform grids, n >= 64)
 };
 
 struct PairState {
@@ -140,7 +143,7 @@ static void uniform_step(wt_grid* g, LevelState& ls, double dt) {
   const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
   for (int s = 0; s < 4; ++s) {
     StageSpec sp = rk_stage(g->prm.rk, s, ls.work, dt);
-    launch_stage(ls.tab, ls.work, phys(g), fp32, sp.pdh, sp.pu, sp.c, g->stream, &g->timer);
+    launch_stage(ls.tab, ls.work, phys(g), fp32, sp.pdh, sp.pu, sp.c, g->stream, &g->timer, &ls.lat);
   }
 }
 
@@ -298,7 +301,7 @@ extern "C" {
 
 const char* wt_last_error(void) { return g_err.c_str(); }
 
-const char* wt_kernel_names(void) { return "trisk_vertex,trisk_edge_cell,trisk_tend"; }
+const char* wt_kernel_names(void) { return "trisk_vertex,trisk_edge_cell,trisk_tend,trisk_lattice"; }
 
 wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
   if (jmin < 0 || jmax < jmin || jmax > 12) {
@@ -358,6 +361,10 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
       upload_tables(ls->geo, ls->tab);
       alloc_work(*ls);
     }
+    if (!g->multi()) {
+      LatticeHost lh;
+      if (build_lattice(g->L(jmax).geo, lh)) upload_lattice(lh, g->L(jmax).lat);
+    }
     for (auto& ps : g->pairs) {
       upload_pair(ps->host, ps->dev);
       auto A2 = [](double** q, int64_t n) { HIPCHK(hipMalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };
@@ -385,6 +392,7 @@ void wt_grid_destroy(wt_grid* g) {
   for (auto& ls : g->lev) {
     free_tables(ls->tab);
     free_work(*ls);
+    free_lattice(ls->lat);
   }
   for (auto& ps : g->pairs) {
     free_pair(ps->dev);
@@ -597,7 +605,7 @@ int wt_tendency(wt_grid* g, int level, double* ddh, double* du) {
     c.d1 = 1.0;
     launch_stage(ls.tab, w, phys(g), g->prm.precision == WT_FP32_TENDENCY,
                  StagePtrs{w.dh, nullptr, w.dh, w.ddh, nullptr},
-                 StagePtrs{w.u, nullptr, w.u, w.du, nullptr}, c, g->stream, nullptr);
+                 StagePtrs{w.u, nullptr, w.u, w.du, nullptr}, c, g->stream, nullptr, &ls.lat);
     if (ddh) HIPCHK(hipMemcpyAsync(ddh, w.ddh, ls.tab.N * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     if (du) HIPCHK(hipMemcpyAsync(du, w.du, ls.tab.E * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -700,16 +708,17 @@ int wt_timing_reset(wt_grid* g) {
   return WT_OK;
 }
 
-int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches) {
+int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches, double* total_bytes) {
   if (!g || !name || !total_ms || !launches) return fail(WT_EINVAL, "wt_kernel_time: null argument");
   int k = -1;
   for (int q = 0; q < K_COUNT; ++q)
     if (std::strcmp(name, kKernelNames[q]) == 0) k = q;
   if (k < 0) return fail(WT_EINVAL, std::string("wt_kernel_time: unknown kernel ") + name);
-  double tot = 0;
+  double tot = 0, by = 0;
   int64_t cnt = 0;
   for (auto& r : g->timer.recs) {
     if (r.k != k) continue;
+    by += r.bytes;
     if (hipEventSynchronize(r.b) != hipSuccess) return fail(WT_EDEVICE, "wt_kernel_time: event");
     float ms = 0;
     if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(WT_EDEVICE, "wt_kernel_time: elapsed");
@@ -718,6 +727,7 @@ int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* laun
   }
   *total_ms = tot;
   *launches = cnt;
+  if (total_bytes) *total_bytes = by;
   return WT_OK;
 }
 
@@ -764,6 +774,46 @@ int wt_host_pair_tables(int jc, int jmax, double radius, double omega, int32_t* 
     cp(rf_c, P.rf_c); cp(rf_cw, P.rf_cw);
   } catch (const std::bad_alloc&) {
     return fail(WT_ENOMEM, "wt_host_pair_tables: out of memory");
+  }
+  return WT_OK;
+}
+
+int wt_host_lattice_check(int level, int64_t* n_tiles, int64_t* n_rim, double* max_rel_err) {
+  if (level < 6 || level > 9) return fail(WT_EINVAL, "wt_host_lattice_check: level must be 6..9");
+  try {
+    Level L;
+    build_level(level, 6.371e6, 7.292e-5, L);
+    LatticeHost h;
+    if (!build_lattice(L, h)) return fail(WT_EINVAL, "wt_host_lattice_check: no regular tiles");
+    const int64_t n = L.n, W = h.W, W2 = h.W2;
+    double err = 0;
+    auto rel = [&](double a, double b) { err = std::fmax(err, std::fabs(a / b - 1.0)); };
+    for (int Lz = 0; Lz < 10; ++Lz)
+      for (int64_t i = 1; i < n - 1; ++i)
+        for (int64_t j = 1; j < n - 1; ++j) {
+          if ((i < 4 && j < 4) || (i > n - 5 && j > n - 5) || (i < 4 && j > n - 5) || (i > n - 5 && j < 4)) continue;
+          int64_t id = (int64_t(Lz) * n + i) * n + j, p = (i + LT_G) * W + (j + LT_G);
+          rel(1.0 / L.A_i[id], h.tab[LQ_INVA * W2 + p]);
+          for (int d = 0; d < 3; ++d) {
+            int64_t e = 3 * id + d;
+            rel(L.l_e[e], h.tab[(LQ_LEN + d) * W2 + p]);
+            rel(1.0 / L.d_e[e], h.tab[(LQ_INVD + d) * W2 + p]);
+            double a[10], b[10];
+            for (int k = 0; k < 10; ++k) {
+              a[k] = L.w[10 * e + k] * L.l_e[L.ecp[10 * e + k]] / L.d_e[e];
+              b[k] = h.tab[(LQ_WL + 10 * d + k) * W2 + p];
+            }
+            std::sort(a, a + 10);
+            std::sort(b, b + 10);
+            double scale = std::fmax(std::fabs(a[0]), std::fabs(a[9]));
+            for (int k = 0; k < 10; ++k) err = std::fmax(err, std::fabs(a[k] - b[k]) / scale);
+          }
+        }
+    if (n_tiles) *n_tiles = int64_t(h.tiles.size() / 2);
+    if (n_rim) *n_rim = int64_t(h.rim_elems.size());
+    if (max_rel_err) *max_rel_err = err;
+  } catch (const std::bad_alloc&) {
+    return fail(WT_ENOMEM, "wt_host_lattice_check: out of memory");
   }
   return WT_OK;
 }

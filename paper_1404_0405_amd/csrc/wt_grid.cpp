@@ -38,12 +38,40 @@ V3 unit(V3 a) {
   double s = std::sqrt(dot(a, a));
   return {a.x / s, a.y / s, a.z / s};
 }
+
+// Geometry of small figures on the unit sphere, written so that rounding is not amplified by
+// the figure's size h: vertex differences of nearby points are exact (Sterbenz), so triple and
+// cross products are formed from differences; and the normalised positions' residual length
+// error |x|^2 - 1 (~1e-16, which a plane through three points would turn into an O(1e-16/h)
+// tilt) is computed exactly with fma and removed from direction differences.
+static double norm2_minus_one(V3 a) {
+  const double v[3] = {a.x, a.y, a.z};
+  double t[7];
+  for (int k = 0; k < 3; ++k) {
+    t[2 * k] = v[k] * v[k];
+    t[2 * k + 1] = std::fma(v[k], v[k], -t[2 * k]);
+  }
+  t[6] = -1.0;
+  double s = t[0], c = 0.0;  // Neumaier summation
+  for (int k = 1; k < 7; ++k) {
+    double u = s + t[k];
+    c += std::fabs(s) >= std::fabs(t[k]) ? (s - u) + t[k] : (t[k] - u) + s;
+    s = u;
+  }
+  return s + c;
+}
+// b/|b| - a/|a| to full relative precision for nearby nearly-unit vectors
+static V3 dir_diff(V3 b, V3 a) {
+  double sa = 0.5 * norm2_minus_one(a), sb = 0.5 * norm2_minus_one(b);
+  return (b - a) + (sa * a - sb * b);
+}
+V3 circumcentre(V3 a, V3 b, V3 c) { return unit(cross(dir_diff(b, a), dir_diff(c, a))); }
 double arc(V3 a, V3 b) {
-  V3 c = cross(a, b);
+  V3 c = cross(a - b, b);
   return std::atan2(std::sqrt(dot(c, c)), dot(a, b));
 }
 double tri_area(V3 a, V3 b, V3 c) {
-  double num = dot(a, cross(b, c));
+  double num = dot(a - c, cross(b - c, c));
   double den = 1.0 + dot(a, b) + dot(b, c) + dot(c, a);
   return 2.0 * std::atan2(num, den);
 }
@@ -265,7 +293,7 @@ void build_level(int J, double radius, double omega, Level& G) {
   parallel_for(T, [&](int64_t t) {
     V3 a = G.pos[G.t_n[3 * t]], b = G.pos[G.t_n[3 * t + 1]], c3 = G.pos[G.t_n[3 * t + 2]];
     WT_CHECK(tri_area(a, b, c3) > 0, "triangle not counter-clockwise");
-    V3 cc = unit(cross(b - a, c3 - a));
+    V3 cc = circumcentre(a, b, c3);
     G.cc[t] = cc;
     G.f_v[t] = 2.0 * omega * cc.z;
     double sum = 0;

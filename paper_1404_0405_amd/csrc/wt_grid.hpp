@@ -23,6 +23,7 @@ inline V3 cross(V3 a, V3 b) {
 V3 unit(V3 a);
 double arc(V3 a, V3 b);                    // great-circle angle
 double tri_area(V3 a, V3 b, V3 c);         // signed spherical excess (Van Oosterom-Strackee)
+V3 circumcentre(V3 a, V3 b, V3 c);         // of a counter-clockwise spherical triangle
 
 // Lattice <-> canonical numbering for level J (n = 2^J):
 //   node (L,i,j), 0<=i,j<n  ->  (L*n+i)*n+j ; poles 10n^2 (north), 10n^2+1 (south)

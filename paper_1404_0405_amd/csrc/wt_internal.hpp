@@ -60,7 +60,7 @@ struct StagePtrs {
   double *o1, *o2;
 };
 
-enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_COUNT };
+enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_LATTICE, K_COUNT };
 extern const char* const kKernelNames[K_COUNT];
 
 struct Timer {
@@ -68,6 +68,7 @@ struct Timer {
   struct Rec {
     int k;
     hipEvent_t a, b;
+    double bytes;  // algorithmic bytes of the launch
   };
   std::vector<Rec> recs;
 };
@@ -75,10 +76,14 @@ struct Timer {
 void upload_tables(const Level& L, DevTables& t);
 void free_tables(DevTables& t);
 
-// One tendency evaluation on stage input (x_dh, x_u) followed by the RK epilogue.
+struct DevLattice;
+
+// One tendency evaluation on stage input (x_dh, x_u) followed by the RK epilogue; with a
+// lattice, the regular tiles go through the fused lattice kernel and only the rim through the
+// table-driven kernels.
 void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
                   const StagePtrs& sdh, const StagePtrs& su, const StageOut& c,
-                  hipStream_t s, Timer* tm);
+                  hipStream_t s, Timer* tm, const DevLattice* lat = nullptr);
 
 // q_v, B, F, q_e of one level (no tendency, no stage output).
 void launch_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,

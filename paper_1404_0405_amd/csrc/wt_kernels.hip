@@ -14,10 +14,13 @@
 #include <stdexcept>
 
 #include "wt_internal.hpp"
+#include "wt_lattice_dev.hpp"
+
+#include <type_traits>
 
 namespace wt {
 
-const char* const kKernelNames[K_COUNT] = {"trisk_vertex", "trisk_edge_cell", "trisk_tend"};
+const char* const kKernelNames[K_COUNT] = {"trisk_vertex", "trisk_edge_cell", "trisk_tend", "trisk_lattice"};
 
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
@@ -28,7 +31,8 @@ const char* const kKernelNames[K_COUNT] = {"trisk_vertex", "trisk_edge_cell", "t
 constexpr int BS = 256;
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __restrict__ t_n,
+__global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __restrict__ list,
+                                               const int32_t* __restrict__ t_n,
                                                const int32_t* __restrict__ t_e,
                                                const double* __restrict__ t_curl,
                                                const double* __restrict__ t_R,
@@ -38,6 +42,7 @@ __global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __r
                                                T* __restrict__ qv) {
   int64_t t = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (t >= n_tri) return;
+  if (list) t = list[t];
   T z = T(0), hv = T(0);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -49,6 +54,7 @@ __global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __r
 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
+                                                  const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ c_e,
                                                   const double* __restrict__ c_ke,
                                                   const int32_t* __restrict__ e_c,
@@ -60,6 +66,7 @@ __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
                                                   T* __restrict__ qe) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
+  if (list) id = list[id];
   T K = T(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -97,6 +104,7 @@ __device__ __forceinline__ void rk_epilogue(int64_t i, double k, const StagePtrs
 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
+                                             const int32_t* __restrict__ list,
                                              const int32_t* __restrict__ c_e,
                                              const double* __restrict__ c_div,
                                              const int32_t* __restrict__ e_c,
@@ -108,6 +116,7 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
                                              StageOut c) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
+  if (list) id = list[id];
   double div = 0.0;  // divergence sums stay in double in both precisions
 #pragma unroll
   for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * F[c_e[6 * id + k]];
@@ -135,8 +144,9 @@ struct TimedLaunch {
   Timer* tm;
   int k;
   hipStream_t s;
+  double bytes;
   hipEvent_t a = nullptr, b = nullptr;
-  TimedLaunch(Timer* tm_, int k_, hipStream_t s_) : tm(tm_), k(k_), s(s_) {
+  TimedLaunch(Timer* tm_, int k_, hipStream_t s_, double bytes_) : tm(tm_), k(k_), s(s_), bytes(bytes_) {
     if (tm && tm->enabled) {
       HIPCHK(hipEventCreate(&a));
       HIPCHK(hipEventCreate(&b));
@@ -146,42 +156,75 @@ struct TimedLaunch {
   ~TimedLaunch() {
     if (a) {
       hipEventRecord(b, s);
-      tm->recs.push_back({k, a, b});
+      tm->recs.push_back({k, a, b, bytes});
     }
   }
 };
 
 template <typename T>
 static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, const StagePtrs& sdh,
-                       const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm) {
+                       const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm,
+                       const DevLattice* lat) {
   T* qv = static_cast<T*>(w.qv);
   T* B = static_cast<T*>(w.B);
   double* F = static_cast<double*>(w.F);
   T* qe = static_cast<T*>(w.qe);
+  const bool use_lat = lat && lat->ok;
+  // table-driven kernels: the whole level, or only the rim left by the lattice tiles
+  const int32_t* tl = use_lat ? lat->sup_tris : nullptr;
+  const int32_t* el = use_lat ? lat->sup_elems : nullptr;
+  const int32_t* rl = use_lat ? lat->rim : nullptr;
+  const int64_t nt = use_lat ? lat->n_sup_tris : t.T;
+  const int64_t ne = use_lat ? lat->n_sup_elems : t.N;
+  const int64_t nr = use_lat ? lat->n_rim : t.N;
+  // Algorithmic bytes of each launch: every table entry, input and output element once.
+  // Per triangle: 3+3 indices, 3+3 weights, f (80 B), its share of the state read (16 B) and
+  // q_v.  Per element: the cell/edge tables (edge_cell 120 B, tend 480 B), the state or the
+  // intermediates it reads, and the Runge-Kutta arrays of the stage (8 B per array per dof).
+  const double sz = double(sizeof(T));
+  auto epi = [](const StageOut& c, const StagePtrs& q, bool count_x) {
+    int r = 0;
+    if (c.a1 != 0.0 || c.a2 != 0.0) ++r;
+    if (c.b1 != 0.0 || c.b2 != 0.0) ++r;
+    if (count_x && (c.c1 != 0.0 || c.c2 != 0.0)) ++r;
+    if (q.o1) ++r;
+    if (q.o2) ++r;
+    return 8.0 * r;
+  };
+  const double e_dof = epi(c, sdh, true);
   {
-    TimedLaunch tl(tm, K_VERTEX, s);
-    k_vertex<T><<<nblk(t.T), BS, 0, s>>>(t.T, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x,
-                                         p.H, qv);
+    TimedLaunch tl_(tm, K_VERTEX, s, double(nt) * (80.0 + 16.0 + sz));
+    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tl, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
   }
   {
-    TimedLaunch tl(tm, K_EDGE_CELL, s);
-    k_edge_cell<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x,
-                                            qv, p.g, p.H, B, F, qe);
+    TimedLaunch tl_(tm, K_EDGE_CELL, s, double(ne) * (120.0 + 32.0 + 24.0 + 6.0 * sz));
+    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, t.n_elem, el, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv,
+                                           p.g, p.H, B, F, qe);
   }
   {
-    TimedLaunch tl(tm, K_TEND, s);
-    k_tend<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl,
-                                       B, F, qe, sdh, su, c);
+    TimedLaunch tl_(tm, K_TEND, s, double(nr) * (480.0 + 24.0 + 4.0 * sz + 4.0 * e_dof));
+    k_tend<T><<<nblk(nr), BS, 0, s>>>(nr, t.n_elem, rl, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl, B, F,
+                                      qe, sdh, su, c);
   }
   HIPCHK(hipGetLastError());
+  if (use_lat) {
+    // stage input read once (dh + 3 u), the stage arrays, and the shared geometry of the
+    // regular tile positions once for all 10 lozenges (58 values per position)
+    const double nreg = double(lat->n_reg_elems);
+    TimedLaunch tl_(tm, K_LATTICE, s, nreg * (32.0 + 4.0 * epi(c, sdh, false)) + nreg / 10.0 * 58.0 * 8.0);
+    LatArgs a = lat->args;
+    a.g = p.g;
+    a.H = p.H;
+    launch_lattice(a, std::is_same<T, float>::value, sdh, su, c, s);
+  }
 }
 
 template <typename T>
 static void intermediates_impl(const DevTables& t, DevWork& w, const PhysParams& p, const StagePtrs& sdh,
                                const StagePtrs& su, hipStream_t s) {
   T* qv = static_cast<T*>(w.qv);
-  k_vertex<T><<<nblk(t.T), BS, 0, s>>>(t.T, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
-  k_edge_cell<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv, p.g,
+  k_vertex<T><<<nblk(t.T), BS, 0, s>>>(t.T, nullptr, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
+  k_edge_cell<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, nullptr, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv, p.g,
                                           p.H, static_cast<T*>(w.B), static_cast<double*>(w.F),
                                           static_cast<T*>(w.qe));
   HIPCHK(hipGetLastError());
@@ -197,11 +240,11 @@ void launch_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, b
 
 void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
                   const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s,
-                  Timer* tm) {
+                  Timer* tm, const DevLattice* lat) {
   if (fp32)
-    stage_impl<float>(t, w, p, sdh, su, c, s, tm);
+    stage_impl<float>(t, w, p, sdh, su, c, s, tm, lat);
   else
-    stage_impl<double>(t, w, p, sdh, su, c, s, tm);
+    stage_impl<double>(t, w, p, sdh, su, c, s, tm, lat);
 }
 
 // ------------------------------------------------------------------ diagnostics

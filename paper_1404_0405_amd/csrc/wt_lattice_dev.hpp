@@ -1,0 +1,33 @@
+// Device side of the lattice stage: kernel arguments and launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wt_internal.hpp"
+#include "wt_lattice.hpp"
+
+namespace wt {
+
+struct LatArgs {
+  const double* tab = nullptr;   // LQ_COUNT x W2 reference geometry
+  const int32_t* tiles = nullptr;
+  int ntile = 0, n = 0;
+  int64_t W = 0, W2 = 0;
+  double g = 0, H = 0;
+  double frot[30] = {};
+};
+
+struct DevLattice {
+  bool ok = false;
+  LatArgs args;
+  const int32_t *rim = nullptr, *sup_elems = nullptr, *sup_tris = nullptr;
+  int64_t n_rim = 0, n_sup_elems = 0, n_sup_tris = 0, n_reg_elems = 0, table_bytes = 0;
+};
+
+void upload_lattice(const LatticeHost& h, DevLattice& d);
+void free_lattice(DevLattice& d);
+void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,
+                    const StageOut& c, hipStream_t s);
+
+}  // namespace wt

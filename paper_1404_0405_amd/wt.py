@@ -65,11 +65,12 @@ SIGNATURES = [
     ("wt_set_stream", C.c_int, [_P, _P]),
     ("wt_timing_enable", C.c_int, [_P, C.c_int]),
     ("wt_timing_reset", C.c_int, [_P]),
-    ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64]),
+    ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64, _D]),
     ("wt_kernel_names", C.c_char_p, []),
     ("wt_host_level_tables", C.c_int, [C.c_int, C.c_double, C.c_double, _D, _D, _D, _D, _I32, _I32, _D]),
     ("wt_host_pair_tables", C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, _I32, _D, _D, _D, _I32, _D,
                                       _D, _D, _I32, _D, _I32, _D]),
+    ("wt_host_lattice_check", C.c_int, [C.c_int, _I64, _I64, _D]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -118,6 +119,14 @@ def host_level_tables(level, radius=6.371e6, omega=7.292e-5):
                                     _ptr(out["l_e"], C.c_double), _ptr(out["e_nodes"], C.c_int32),
                                     _ptr(out["ecp"], C.c_int32), _ptr(out["w"], C.c_double)))
     return out
+
+
+def host_lattice_check(level):
+    """Host-only check of the lattice form (no GPU): (tiles per lozenge, rim elements, max
+    relative difference between the shared reference geometry and every lozenge)."""
+    nt, nr, err = C.c_int64(), C.c_int64(), C.c_double()
+    _check(load().wt_host_lattice_check(level, C.byref(nt), C.byref(nr), C.byref(err)))
+    return nt.value, nr.value, err.value
 
 
 def host_pair_tables(jc, jmax, radius=6.371e6, omega=7.292e-5):
@@ -262,9 +271,10 @@ class Grid:
         _check(load().wt_timing_reset(self._h))
 
     def kernel_time(self, name):
-        ms, cnt = C.c_double(), C.c_int64()
-        _check(load().wt_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(cnt)))
-        return ms.value, cnt.value
+        """(total ms, launches, total algorithmic bytes) since the last timing reset."""
+        ms, cnt, by = C.c_double(), C.c_int64(), C.c_double()
+        _check(load().wt_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(cnt), C.byref(by)))
+        return ms.value, cnt.value, by.value
 
 
 def kernel_names():

@@ -56,3 +56,16 @@ def test_host_builder_matches_oracle(J, oracle_grid):
         ref = {int(g.ecp[e, k]): g.w[e, k] for k in range(g.ecp_n[e])}
         assert mine.keys() == ref.keys()
         assert all(abs(mine[k] - ref[k]) < 1e-14 for k in ref)
+
+
+@pytest.mark.parametrize("J", [6, 7, 8])
+def test_lattice_reference_geometry(J):
+    """The 10 lozenges are congruent (rotations of the icosahedron map lattice to lattice), so
+    one reference geometry serves all of them: it agrees with every lozenge's own tables to
+    round-off; the builder's emulation of the kernel's halo addressing matched the canonical
+    seam lookup for every regular tile (it aborts otherwise)."""
+    tiles, rim, err = wt.host_lattice_check(J)
+    n = 2 ** J
+    assert tiles == (n // 16) * (n // 32) - 4
+    assert rim == 4 * 16 * 32 * 10 + 2
+    assert err < 1e-12, err
