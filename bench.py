@@ -24,6 +24,35 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the lattice stage kernel, from two rocprofv3 counter runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0 --modes fp64`, scaled by
+# what the same counters read for a 2 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).
+# Valid only for the kernel source it was taken on: a changed source reports null.
+MEASURED_TRAFFIC = {
+    "trisk_lattice": {
+        "sources": ("paper_1404_0405_amd/csrc/wt_lattice.hip", "paper_1404_0405_amd/csrc/wt_lattice_dev.hpp"),
+        "sha256": ("eae2410a2ad4b1832c57ea1c0872d96eeeea56f4c0b0bd64147ffa4ea76a4472",
+                   "67492eda7ad1558bc8dfcf39ef6757221c2ebd22ca59db129d4cf93d8c38dd94"),
+        "fetch_kib": 893548.5, "write_kib": 831908.1, "fetch_scale": 2.000, "write_scale": 1.000,
+    },
+}
+
+
+def measured_traffic(kernel):
+    """Scaled HBM bytes per launch of `kernel`, or None if not measured on the current source."""
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    for path, digest in zip(rec["sources"], rec["sha256"]):
+        try:
+            with open(os.path.join(ROOT, path), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
 
 def run_gpu(args):
     import numpy as np
@@ -165,7 +194,8 @@ def main():
                                f"dt={dt:.3f} s (CFL 0.8)",
                    "level": args.level, "cells": N, "edges": E, "rk": "rk4", "stages_per_step": 4},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "algorithmic_bytes": kd["algorithmic_bytes"]},
         "kernels_fp64": f64["kernels"],
         "stage_ms_fp64": f64["ms_per_step"] / 4,
         "fp32_tendency": ({"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"],
