@@ -163,8 +163,18 @@ struct TimedLaunch {
 
 template <typename T>
 static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, const StagePtrs& sdh,
-                       const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm,
+                       const StagePtrs& su, const StageOut& c_in, hipStream_t s, Timer* tm,
                        const DevLattice* lat) {
+  // A stage array that is the stage input itself (the first stage reads y as x) is read once.
+  StageOut c = c_in;
+  if (sdh.y == sdh.x && su.y == su.x) {
+    c.c1 += c.a1; c.a1 = 0.0;
+    c.c2 += c.a2; c.a2 = 0.0;
+  }
+  if (sdh.acc == sdh.x && su.acc == su.x) {
+    c.c1 += c.b1; c.b1 = 0.0;
+    c.c2 += c.b2; c.b2 = 0.0;
+  }
   T* qv = static_cast<T*>(w.qv);
   T* B = static_cast<T*>(w.B);
   double* F = static_cast<double*>(w.F);
