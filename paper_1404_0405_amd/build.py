@@ -17,6 +17,10 @@ SOURCES = ["wt_grid.cpp", "wt_pair.cpp", "wt_lattice.cpp", "wt_api.cpp", "wt_ker
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{ROOT}/include"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics"]
+# per-source extra flags: the lattice kernel holds its tile geometry in registers and prefetches
+# the next lozenge; the iterative ILP scheduler keeps it within 256 VGPRs without spilling
+# (a spill reload would make the kernel wait for the prefetch)
+EXTRA = {"wt_lattice.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
 
 
 def _hipcc():
@@ -31,6 +35,7 @@ def _compile(src):
     cmd = [_hipcc(), *COMMON]
     if src.endswith(".hip"):
         cmd += ["-x", "hip", *HIP_FLAGS]
+    cmd += EXTRA.get(src, [])
     cmd += ["-c", path, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

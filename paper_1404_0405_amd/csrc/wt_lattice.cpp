@@ -268,6 +268,13 @@ bool build_lattice(const Level& Lv, LatticeHost& H) {
                 "lozenges are not congruent");
       for (int c = 0; c < 3; ++c) H.frot[3 * L + c] = 2.0 * Lv.omega * RL[2][c];
     }
+    // the kernel takes f from lozenge 0 for all northern lozenges and from lozenge 5 for all
+    // southern ones: they are rotations of one another about the polar axis
+    for (int L = 1; L < 10; ++L)
+      if (L != 5)
+        for (int c = 0; c < 3; ++c)
+          LAT_CHECK(std::fabs(H.frot[3 * L + c] - H.frot[(L < 5 ? 0 : 15) + c]) < 1e-13 * 2.0 * Lv.omega,
+                    "northern (southern) lozenges are not turned into one another about the polar axis");
   }
   // regular tiles: the halo (LT_G positions) contains no lozenge corner
   H.tiles.clear();

@@ -16,6 +16,7 @@
 
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 #include "wt_lattice_dev.hpp"
 
@@ -54,9 +55,14 @@ __device__ __forceinline__ void seam(int L, int i, int j, int n, int& L2, int& i
   }
 }
 
-// stencil slot k of the perpendicular-flux sum of frame edge d: owner offset and direction
-__device__ __forceinline__ void ecp_slot(int d, int k, int& oi, int& oj, int& dd) {
-  int ci = 0, cj = 0, s;
+// Stencil slot k of the perpendicular-flux sum of frame edge d (the five other edges of the
+// element's cell, then the five of the cell across edge d, counter-clockwise): offset of the
+// owning element and the owner's frame direction.
+struct Slot {
+  int oi, oj, dd;
+};
+constexpr Slot stencil_slot(int d, int k) {
+  int ci = 0, cj = 0, s = 0;
   if (k < 5) {
     s = (d + 1 + k) % 6;
   } else {
@@ -64,55 +70,103 @@ __device__ __forceinline__ void ecp_slot(int d, int k, int& oi, int& oj, int& dd
     cj = DD1[d];
     s = (d + k - 1) % 6;
   }
-  if (s < 3) { oi = ci; oj = cj; dd = s; }
-  else { dd = s - 3; oi = ci - DD0[dd]; oj = cj - DD1[dd]; }
+  if (s < 3) return Slot{ci, cj, s};
+  return Slot{ci - DD0[s - 3], cj - DD1[s - 3], s - 3};
 }
 
-// Global addresses of the stage input of halo position idx of lozenge L: node, three edge
-// velocities in the frame of L, and the sign of the first and third (a rotated seam turns an
-// edge of the neighbour around).
+// The 30 slots of an element's three edges name 19 distinct edges (the six edges of the
+// element's own cell serve several stencils): each distinct edge is read once and feeds every
+// slot that names it.
+struct StencilUnion {
+  int count = 0;
+  int oi[30] = {}, oj[30] = {}, dd[30] = {}, nuse[30] = {}, use[30][3] = {};
+};
+constexpr StencilUnion make_union() {
+  StencilUnion t;
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < 10; ++k) {
+      const Slot sl = stencil_slot(d, k);
+      int f = -1;
+      for (int u = 0; u < t.count; ++u)
+        if (t.oi[u] == sl.oi && t.oj[u] == sl.oj && t.dd[u] == sl.dd) f = u;
+      if (f < 0) {
+        f = t.count++;
+        t.oi[f] = sl.oi;
+        t.oj[f] = sl.oj;
+        t.dd[f] = sl.dd;
+      }
+      t.use[f][t.nuse[f]++] = 10 * d + k;
+    }
+  return t;
+}
+constexpr StencilUnion SU = make_union();
+static_assert(SU.count == 19, "distinct edges of the three perpendicular-flux stencils");
+
+// Halo addressing of the stage input, split into a lozenge-independent part computed once
+// per workgroup and a cheap per-lozenge part.  A halo position (i,j) either lies inside the
+// lozenge or crosses one side (side 1: i<0, 2: j<0, 3: i>=n, 4: j>=n, in the precedence of the
+// seam rules); where it lands in the neighbour, and the lattice map, depend only on whether the
+// lozenge is northern or southern, the neighbour's number on the lozenge.
+struct ASlot {
+  int offN, offS;   // i2*n + j2 in the neighbour for a northern / southern lozenge
+  int code;         // side | (rotN+1) << 3 | (rotS+1) << 5
+};
+
+__device__ __forceinline__ ASlot a_slot(int idx, int i0, int j0, int n) {
+  const int ai = idx / AJ, aj = idx % AJ;
+  const int i = i0 - 2 + ai, j = j0 - 2 + aj;
+  const int side = i < 0 ? 1 : j < 0 ? 2 : i >= n ? 3 : j >= n ? 4 : 0;
+  int L2, iN, jN, rN, iS, jS, rS;
+  seam(0, i, j, n, L2, iN, jN, rN);
+  seam(5, i, j, n, L2, iS, jS, rS);
+  return ASlot{iN * n + jN, iS * n + jS, side | ((rN + 1) << 3) | ((rS + 1) << 5)};
+}
+
+// Stage-input addresses of a halo slot in lozenge L: node, three edge velocities in the frame
+// of L, and which of the first and third to reverse (a rotated seam turns the neighbour's edge
+// around).
 struct AAddr {
   int64_t node, e0, e1, e2;
   int neg;   // bit 0: reverse e0, bit 1: reverse e2
 };
 
-__device__ __forceinline__ AAddr a_address(int idx, int L, int i0, int j0, int n) {
-  const int ai = idx / AJ, aj = idx % AJ;
-  const int i = i0 - 2 + ai, j = j0 - 2 + aj;
+__device__ __forceinline__ AAddr a_address(const ASlot& sl, int L, int n) {
+  const bool north = L < 5;
+  const int k = north ? L : L - 5, km = (k + 4) % 5, kp = (k + 1) % 5;
+  const int side = sl.code & 7;
+  const int L2 = side == 0 ? L : side == 1 ? (north ? km : k) : side == 2 ? 5 + km
+               : side == 3 ? (north ? 5 + k : 5 + kp) : kp;
+  const int rot = ((sl.code >> (north ? 3 : 5)) & 3) - 1;
+  const int64_t id = int64_t(L2) * n * n + (north ? sl.offN : sl.offS);
   AAddr r;
+  r.node = id;
   r.neg = 0;
-  if (i >= 0 && i < n && j >= 0 && j < n) {
-    const int64_t id = (int64_t(L) * n + i) * n + j;
-    r.node = id; r.e0 = 3 * id; r.e1 = 3 * id + 1; r.e2 = 3 * id + 2;
+  if (rot == 0) {
+    r.e0 = 3 * id; r.e1 = 3 * id + 1; r.e2 = 3 * id + 2;
+  } else if (rot == 1) {
+    r.e0 = 3 * id + 1; r.e1 = 3 * id + 2; r.e2 = 3 * (id - n); r.neg = 2;   // E0 one row above, reversed
   } else {
-    int L2, i2, j2, rot;
-    seam(L, i, j, n, L2, i2, j2, rot);
-    const int64_t id = (int64_t(L2) * n + i2) * n + j2;
-    r.node = id;
-    if (rot == 0) {
-      r.e0 = 3 * id; r.e1 = 3 * id + 1; r.e2 = 3 * id + 2;
-    } else if (rot == 1) {
-      r.e0 = 3 * id + 1; r.e1 = 3 * id + 2; r.e2 = 3 * (id - n); r.neg = 2;   // E0 one row above, reversed
-    } else {
-      r.e0 = 3 * (id - 1) + 2; r.neg = 1; r.e1 = 3 * id; r.e2 = 3 * id + 1;   // E2 one column left, reversed
-    }
+    r.e0 = 3 * (id - 1) + 2; r.neg = 1; r.e1 = 3 * id; r.e2 = 3 * id + 1;   // E2 one column left, reversed
   }
   return r;
 }
 
-// Epilogue variants: which of y and acc the stage combination reads from HBM (x comes from LDS).
-enum { EPI_Y = 1, EPI_ACC = 2 };
+// Epilogue variants: which of y and acc the stage combination reads from HBM (x comes from LDS)
+// and whether there is a second output (the first is always written).  Keeping these out of
+// run-time branches lets the compiler count outstanding memory operations exactly, so waiting
+// for this lozenge's operands never waits for the next lozenge's prefetch.
+enum { EPI_Y = 1, EPI_ACC = 2, EPI_O2 = 4 };
 
 template <typename T, int EPI>
 __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, StagePtrs pu, StageOut c) {
   __shared__ double s_dh[NA], s_u[3][NA];
   __shared__ T s_qv[2][NB];
-  __shared__ double s_F[3][NC];
-  __shared__ T s_qe[3][NC], s_B[NC];
-  __shared__ T s_gR[6][NB];          // kite weights of h_v, all B positions
-  __shared__ double s_gcc[6][NB];     // circumcentres, all B positions
+  __shared__ T s_F[3][NC];           // mass flux (exactly a T value in both precisions)
+  __shared__ T s_Fq[3][NC], s_B[NC];  // F q_e and the Bernoulli function
+  __shared__ T s_gR[4][NB];          // kite weights of h_v (two per triangle; the third is 1 - both)
+  __shared__ T s_gf[4][NB];          // Coriolis parameter of both triangles, northern / southern lozenges
   __shared__ T s_gcurl[6][NB2];      // curl weights of the second B slot
-  __shared__ T s_gc[6][NC2];         // kinetic-energy weights of the second C slot
+  __shared__ T s_gke[6][NC];         // kinetic-energy weights
 
   // Tiles are dealt to the 8 XCDs (workgroups go round-robin) in contiguous bands, so the
   // workgroups running together on one XCD hold neighbouring tiles and share halos in its L2.
@@ -133,44 +187,49 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
   // ---- geometry of this tile position, shared by the 10 lozenges
   // phase B: curl weights of the first slot in registers, the rest in LDS
   T gcurl[6];
+  // The northern lozenges are turned into one another by rotations about the polar axis, and so
+  // are the southern ones: f = 2 Omega sin(latitude) of a lattice position takes one value in
+  // all northern lozenges and one in all southern ones.
+  auto coriolis = [&](int64_t p, int idx) {
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr) {
+      const double c0 = TAB(LQ_CC + 3 * tr, p), c1 = TAB(LQ_CC + 3 * tr + 1, p), c2 = TAB(LQ_CC + 3 * tr + 2, p);
+      s_gf[tr][idx] = T(a.frot[0] * c0 + a.frot[1] * c1 + a.frot[2] * c2);
+      s_gf[2 + tr][idx] = T(a.frot[15] * c0 + a.frot[16] * c1 + a.frot[17] * c2);
+    }
+  };
   auto pb = [&](int idx) { return int64_t(i0 - 2 + idx / BJ + LT_G) * W + (j0 - 2 + idx % BJ + LT_G); };
   {
     const int64_t p = pb(tid);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      gcurl[q] = T(TAB(LQ_CURL + q, p));
-      s_gR[q][tid] = T(TAB(LQ_R + q, p));
-      s_gcc[q][tid] = TAB(LQ_CC + q, p);
-    }
+    for (int q = 0; q < 6; ++q) gcurl[q] = T(TAB(LQ_CURL + q, p));
+    coriolis(p, tid);
+    s_gR[0][tid] = T(TAB(LQ_R + 0, p));
+    s_gR[1][tid] = T(TAB(LQ_R + 1, p));
+    s_gR[2][tid] = T(TAB(LQ_R + 3, p));
+    s_gR[3][tid] = T(TAB(LQ_R + 4, p));
   }
   if (tid < NB2) {
     const int idx = tid + LBS;
     const int64_t p = pb(idx);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      s_gcurl[q][tid] = T(TAB(LQ_CURL + q, p));
-      s_gR[q][idx] = T(TAB(LQ_R + q, p));
-      s_gcc[q][idx] = TAB(LQ_CC + q, p);
-    }
+    for (int q = 0; q < 6; ++q) s_gcurl[q][tid] = T(TAB(LQ_CURL + q, p));
+    coriolis(p, idx);
+    s_gR[0][idx] = T(TAB(LQ_R + 0, p));
+    s_gR[1][idx] = T(TAB(LQ_R + 1, p));
+    s_gR[2][idx] = T(TAB(LQ_R + 3, p));
+    s_gR[3][idx] = T(TAB(LQ_R + 4, p));
   }
-  // phase C: K_i = sum over the 6 cell edges of (l d / 4A) u^2, first slot registers, second LDS
-  auto kc6 = [&](int64_t p, T* o) {
+  // phase C: K_i = sum over the 6 cell edges of (l d / 4A) u^2
+  for (int idx = tid; idx < NC; idx += LBS) {
+    const int64_t p = int64_t(i0 - 1 + idx / CJ + LT_G) * W + (j0 - 1 + idx % CJ + LT_G);
     const double ia = TAB(LQ_INVA, p);
-    o[0] = T(ia * TAB(LQ_KC + 0, p));
-    o[1] = T(ia * TAB(LQ_KC + 1, p));
-    o[2] = T(ia * TAB(LQ_KC + 2, p));
-    o[3] = T(ia * TAB(LQ_KC + 0, p - W));
-    o[4] = T(ia * TAB(LQ_KC + 1, p - W - 1));
-    o[5] = T(ia * TAB(LQ_KC + 2, p - 1));
-  };
-  T gke[6];
-  kc6(int64_t(i0 - 1 + tid / CJ + LT_G) * W + (j0 - 1 + tid % CJ + LT_G), gke);
-  if (tid < NC2) {
-    const int idx = tid + LBS;
-    T o[6];
-    kc6(int64_t(i0 - 1 + idx / CJ + LT_G) * W + (j0 - 1 + idx % CJ + LT_G), o);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) s_gc[q][tid] = o[q];
+    s_gke[0][idx] = T(ia * TAB(LQ_KC + 0, p));
+    s_gke[1][idx] = T(ia * TAB(LQ_KC + 1, p));
+    s_gke[2][idx] = T(ia * TAB(LQ_KC + 2, p));
+    s_gke[3][idx] = T(ia * TAB(LQ_KC + 0, p - W));
+    s_gke[4][idx] = T(ia * TAB(LQ_KC + 1, p - W - 1));
+    s_gke[5][idx] = T(ia * TAB(LQ_KC + 2, p - 1));
   }
   // phase D: divergence weights n l / A (FP64), perpendicular-flux weights, 1/d
   const int di = tid / LT_TJ, dj = tid % LT_TJ;
@@ -193,12 +252,13 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
 
   // ---- stage input of lozenge 0 into registers
   const int a1idx = tid < NA2 ? tid + LBS : tid;   // second A slot (threads without one repeat the first)
+  const ASlot aslot[2] = {a_slot(tid, i0, j0, n), a_slot(a1idx, i0, j0, n)};
   double r_dh[2], r_u0[2], r_u1[2], r_u2[2];
   int r_neg[2];   // bit 0: reverse u0, bit 1: reverse u2
   auto issue_a = [&](int L) {
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      const AAddr ad = a_address(sl == 0 ? tid : a1idx, L, i0, j0, n);
+      const AAddr ad = a_address(aslot[sl], L, n);
       r_dh[sl] = xdh[ad.node];
       r_u0[sl] = xu[ad.e0];
       r_u1[sl] = xu[ad.e1];
@@ -211,7 +271,9 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
   const int la_d = (di + 2) * AJ + (dj + 2);   // tile element in the A layout
   const int lc = (di + 1) * CJ + (dj + 1);     // tile element in the C layout
 
-  for (int L = 0; L < 10; ++L) {
+  // One lozenge; the next lozenge's input is prefetched in all but the last.  The last is a
+  // separate copy so that no memory operation sits under a run-time branch.
+  auto lozenge = [&](int L, auto prefetch) {
     __syncthreads();   // the previous lozenge's phase D has read s_dh, s_u
     s_dh[tid] = r_dh[0];
     s_u[0][tid] = (r_neg[0] & 1) ? -r_u0[0] : r_u0[0];
@@ -225,32 +287,24 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
     }
     // stage-combination operands of this lozenge, then the next lozenge's input
     const int64_t id = (int64_t(L) * n + i0 + di) * n + (j0 + dj);
-    double ydh = 0, yu[3] = {0, 0, 0}, adh = 0, au[3] = {0, 0, 0};
-    if (EPI & EPI_Y) {
-      ydh = pdh.y[id];
-      yu[0] = pu.y[3 * id]; yu[1] = pu.y[3 * id + 1]; yu[2] = pu.y[3 * id + 2];
-    }
-    if (EPI & EPI_ACC) {
-      adh = pdh.acc[id];
-      au[0] = pu.acc[3 * id]; au[1] = pu.acc[3 * id + 1]; au[2] = pu.acc[3 * id + 2];
-    }
-    if (L < 9) issue_a(L + 1);
+    if constexpr (decltype(prefetch)::value) issue_a(L + 1);
     __syncthreads();
 
     // ---- phase B: q_v of both triangles, positions [-2, TI+1) x [-2, TJ+1)
-    const double f0 = a.frot[3 * L], f1 = a.frot[3 * L + 1], f2 = a.frot[3 * L + 2];
+    const int hf = L < 5 ? 0 : 2;
     auto qv_at = [&](int idx, const T* cu) {
       const int bi = idx / BJ, bj = idx % BJ;
       const int la = bi * AJ + bj;
       const T h0 = T(H) + T(s_dh[la]), h10 = T(H) + T(s_dh[la + AJ]), h11 = T(H) + T(s_dh[la + AJ + 1]),
               h01 = T(H) + T(s_dh[la + 1]);
       const T z0 = cu[0] * T(s_u[0][la]) + cu[1] * T(s_u[2][la + AJ]) + cu[2] * T(s_u[1][la]);
-      const T hv0 = s_gR[0][idx] * h0 + s_gR[1][idx] * h10 + s_gR[2][idx] * h11;
-      const T fa = T(f0 * s_gcc[0][idx] + f1 * s_gcc[1][idx] + f2 * s_gcc[2][idx]);
+      const T R0 = s_gR[0][idx], R1 = s_gR[1][idx], R3 = s_gR[2][idx], R4 = s_gR[3][idx];
+      const T hv0 = R0 * h0 + R1 * h10 + (T(1) - R0 - R1) * h11;
+      const T fa = s_gf[hf][idx];
       s_qv[0][idx] = (z0 + fa) / hv0;
       const T z1 = cu[3] * T(s_u[1][la]) + cu[4] * T(s_u[0][la + 1]) + cu[5] * T(s_u[2][la]);
-      const T hv1 = s_gR[3][idx] * h0 + s_gR[4][idx] * h11 + s_gR[5][idx] * h01;
-      const T fb = T(f0 * s_gcc[3][idx] + f1 * s_gcc[4][idx] + f2 * s_gcc[5][idx]);
+      const T hv1 = R3 * h0 + R4 * h11 + (T(1) - R3 - R4) * h01;
+      const T fb = s_gf[hf + 1][idx];
       s_qv[1][idx] = (z1 + fb) / hv1;
     };
     qv_at(tid, gcurl);
@@ -262,86 +316,110 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
     }
     __syncthreads();
 
+    double ydh = 0, yu[3] = {0, 0, 0}, adh = 0, au[3] = {0, 0, 0};
+    if (EPI & EPI_Y) {
+      ydh = pdh.y[id];
+      yu[0] = pu.y[3 * id]; yu[1] = pu.y[3 * id + 1]; yu[2] = pu.y[3 * id + 2];
+    }
+    if (EPI & EPI_ACC) {
+      adh = pdh.acc[id];
+      au[0] = pu.acc[3 * id]; au[1] = pu.acc[3 * id + 1]; au[2] = pu.acc[3 * id + 2];
+    }
     // ---- phase C: F, q_e at the three edges and B at the node, positions [-1, TI+1) x [-1, TJ+1)
-    auto c_at = [&](int idx, const T* ke) {
+    auto c_at = [&](int idx) {
       const int ci = idx / CJ, cj = idx % CJ;
       const int la = (ci + 1) * AJ + (cj + 1);
       const int lb = (ci + 1) * BJ + (cj + 1);
       const T h = T(H) + T(s_dh[la]);
       const T u0 = T(s_u[0][la]), u1 = T(s_u[1][la]), u2 = T(s_u[2][la]);
-      s_F[0][idx] = double(T(0.5) * (h + (T(H) + T(s_dh[la + AJ]))) * u0);
-      s_F[1][idx] = double(T(0.5) * (h + (T(H) + T(s_dh[la + AJ + 1]))) * u1);
-      s_F[2][idx] = double(T(0.5) * (h + (T(H) + T(s_dh[la + 1]))) * u2);
-      s_qe[0][idx] = T(0.5) * (s_qv[0][lb] + s_qv[1][lb - 1]);
-      s_qe[1][idx] = T(0.5) * (s_qv[0][lb] + s_qv[1][lb]);
-      s_qe[2][idx] = T(0.5) * (s_qv[1][lb] + s_qv[0][lb - BJ]);
+      const T F0 = T(0.5) * (h + (T(H) + T(s_dh[la + AJ]))) * u0;
+      const T F1 = T(0.5) * (h + (T(H) + T(s_dh[la + AJ + 1]))) * u1;
+      const T F2 = T(0.5) * (h + (T(H) + T(s_dh[la + 1]))) * u2;
+      s_F[0][idx] = F0;
+      s_F[1][idx] = F1;
+      s_F[2][idx] = F2;
+      s_Fq[0][idx] = F0 * (T(0.5) * (s_qv[0][lb] + s_qv[1][lb - 1]));
+      s_Fq[1][idx] = F1 * (T(0.5) * (s_qv[0][lb] + s_qv[1][lb]));
+      s_Fq[2][idx] = F2 * (T(0.5) * (s_qv[1][lb] + s_qv[0][lb - BJ]));
       const T ua = T(s_u[0][la - AJ]), ub = T(s_u[1][la - AJ - 1]), uc = T(s_u[2][la - 1]);
-      const T K = ke[0] * u0 * u0 + ke[1] * u1 * u1 + ke[2] * u2 * u2 + ke[3] * ua * ua + ke[4] * ub * ub +
-                  ke[5] * uc * uc;
+      const T K = s_gke[0][idx] * u0 * u0 + s_gke[1][idx] * u1 * u1 + s_gke[2][idx] * u2 * u2 +
+                  s_gke[3][idx] * ua * ua + s_gke[4][idx] * ub * ub + s_gke[5][idx] * uc * uc;
       s_B[idx] = T(g) * T(s_dh[la]) + K;
     };
-    c_at(tid, gke);
-    if (tid < NC2) {
-      T ke[6];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) ke[q] = s_gc[q][tid];
-      c_at(tid + LBS, ke);
-    }
+    c_at(tid);
+    if (tid < NC2) c_at(tid + LBS);
     __syncthreads();
 
     // ---- phase D: tendencies of the tile element of this thread and the stage combination
     {
-      const double div = gdiv[0] * s_F[0][lc] + gdiv[1] * s_F[1][lc] + gdiv[2] * s_F[2][lc] +
-                         gdiv[3] * s_F[0][lc - CJ] + gdiv[4] * s_F[1][lc - CJ - 1] + gdiv[5] * s_F[2][lc - 1];
+      const double div = gdiv[0] * double(s_F[0][lc]) + gdiv[1] * double(s_F[1][lc]) +
+                         gdiv[2] * double(s_F[2][lc]) + gdiv[3] * double(s_F[0][lc - CJ]) +
+                         gdiv[4] * double(s_F[1][lc - CJ - 1]) + gdiv[5] * double(s_F[2][lc - 1]);
       const double k = -div;
-      if (pdh.o1) pdh.o1[id] = c.d1 * k + c.a1 * ydh + c.b1 * adh + c.c1 * s_dh[la_d];
-      if (pdh.o2) pdh.o2[id] = c.d2 * k + c.a2 * ydh + c.b2 * adh + c.c2 * s_dh[la_d];
+      pdh.o1[id] = c.d1 * k + c.a1 * ydh + c.b1 * adh + c.c1 * s_dh[la_d];
+      if (EPI & EPI_O2) pdh.o2[id] = c.d2 * k + c.a2 * ydh + c.b2 * adh + c.c2 * s_dh[la_d];
     }
+    // Q_e = (1/d_e) sum_e' w l' F' (q_e + q_e')/2 = (q_e S1 + S2) / 2 with S1 = sum w l'/d F' and
+    // S2 = sum w l'/d F' q_e', summed over the distinct stencil edges
+    {
+      T S1[3] = {T(0), T(0), T(0)}, S2[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const T q0 = s_qe[d][lc];
-      T Q = T(0);
+      for (int u = 0; u < SU.count; ++u) {
+        const int le = lc + SU.oi[u] * CJ + SU.oj[u];
+        const T F = s_F[SU.dd[u]][le], Fq = s_Fq[SU.dd[u]][le];
 #pragma unroll
-      for (int k = 0; k < 10; ++k) {
-        int oi, oj, dd;
-        ecp_slot(d, k, oi, oj, dd);
-        const int le = lc + oi * CJ + oj;
-        Q += gwl[10 * d + k] * T(s_F[dd][le]) * (T(0.5) * (q0 + s_qe[dd][le]));
+        for (int r = 0; r < SU.nuse[u]; ++r) {
+          const int w = SU.use[u][r];
+          S1[w / 10] += gwl[w] * F;
+          S2[w / 10] += gwl[w] * Fq;
+        }
+        // a few distinct edges at a time: bounds the operands the scheduler keeps in flight
+        if (u % 5 == 4) __builtin_amdgcn_sched_barrier(0);
       }
-      const int lo = lc + DD0[d] * CJ + DD1[d];
-      const T gradB = (s_B[lo] - s_B[lc]) * ginvd[d];
-      const double k = double(-Q - gradB);
-      const double x = s_u[d][la_d];
-      if (pu.o1) pu.o1[3 * id + d] = c.d1 * k + c.a1 * yu[d] + c.b1 * au[d] + c.c1 * x;
-      if (pu.o2) pu.o2[3 * id + d] = c.d2 * k + c.a2 * yu[d] + c.b2 * au[d] + c.c2 * x;
-      // one edge at a time: keeps the scheduler from holding all 60 stencil operands at once
-      __builtin_amdgcn_sched_barrier(0);
+      const int lb = (di + 2) * BJ + (dj + 2);
+      const T qe[3] = {T(0.5) * (s_qv[0][lb] + s_qv[1][lb - 1]), T(0.5) * (s_qv[0][lb] + s_qv[1][lb]),
+                       T(0.5) * (s_qv[1][lb] + s_qv[0][lb - BJ])};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T Q = T(0.5) * (qe[d] * S1[d] + S2[d]);
+        const int lo = lc + DD0[d] * CJ + DD1[d];
+        const T gradB = (s_B[lo] - s_B[lc]) * ginvd[d];
+        const double k = double(-Q - gradB);
+        const double x = s_u[d][la_d];
+        pu.o1[3 * id + d] = c.d1 * k + c.a1 * yu[d] + c.b1 * au[d] + c.c1 * x;
+        if (EPI & EPI_O2) pu.o2[3 * id + d] = c.d2 * k + c.a2 * yu[d] + c.b2 * au[d] + c.c2 * x;
+      }
     }
-  }
+  };
+  for (int L = 0; L < 9; ++L) lozenge(L, std::true_type{});
+  lozenge(9, std::false_type{});
 }
 
 void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,
                     const StageOut& c, hipStream_t s) {
   const unsigned grid = unsigned((a.ntile + 7) / 8) * 8u;
   const bool ry = c.a1 != 0.0 || c.a2 != 0.0, racc = c.b1 != 0.0 || c.b2 != 0.0;
-  const int epi = (ry ? EPI_Y : 0) | (racc ? EPI_ACC : 0);
-#define WT_LAT_LAUNCH(T_, E_) k_lattice<T_, E_><<<grid, LBS, 0, s>>>(a, pdh, pu, c)
-  if (fp32) {
+  if (!pdh.o1 || !pu.o1 || (pdh.o2 == nullptr) != (pu.o2 == nullptr))
+    throw std::runtime_error("lattice stage: needs the first output, and the second for both or neither of dh, u");
+  const int epi = (ry ? EPI_Y : 0) | (racc ? EPI_ACC : 0) | (pdh.o2 ? EPI_O2 : 0);
+  auto go = [&](auto tag, auto e) {
+    using T = decltype(tag);
+    k_lattice<T, decltype(e)::value><<<grid, LBS, 0, s>>>(a, pdh, pu, c);
+  };
+  auto dispatch = [&](auto tag) {
     switch (epi) {
-      case 0: WT_LAT_LAUNCH(float, 0); break;
-      case 1: WT_LAT_LAUNCH(float, 1); break;
-      case 2: WT_LAT_LAUNCH(float, 2); break;
-      default: WT_LAT_LAUNCH(float, 3); break;
+      case 0: go(tag, std::integral_constant<int, 0>{}); break;
+      case 1: go(tag, std::integral_constant<int, 1>{}); break;
+      case 2: go(tag, std::integral_constant<int, 2>{}); break;
+      case 3: go(tag, std::integral_constant<int, 3>{}); break;
+      case 4: go(tag, std::integral_constant<int, 4>{}); break;
+      case 5: go(tag, std::integral_constant<int, 5>{}); break;
+      case 6: go(tag, std::integral_constant<int, 6>{}); break;
+      default: go(tag, std::integral_constant<int, 7>{}); break;
     }
-  } else {
-    switch (epi) {
-      case 0: WT_LAT_LAUNCH(double, 0); break;
-      case 1: WT_LAT_LAUNCH(double, 1); break;
-      case 2: WT_LAT_LAUNCH(double, 2); break;
-      default: WT_LAT_LAUNCH(double, 3); break;
-    }
-  }
-#undef WT_LAT_LAUNCH
+  };
+  if (fp32) dispatch(float{});
+  else dispatch(double{});
   HIPCHK(hipGetLastError());
 }
 
