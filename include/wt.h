@@ -231,6 +231,43 @@ int wt_host_pair_tables(int jc, int jmax, double radius, double omega, int32_t* 
  * reference and every lozenge.  For tests. */
 int wt_host_lattice_check(int level, int64_t* n_tiles, int64_t* n_rim, double* max_rel_err);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned adjacent zone (an addition to the method, not from the paper).  The paper's adjacent
+ * zone (Sec. 2.3) activates the next-level children of every significant point.  A small
+ * network proposes instead, for every quadrant of every patch, whether those children are
+ * needed; the exact threshold test after each step redoes the step with the blanket zone when
+ * a dropped quadrant still holds a significant point.
+ *
+ * Network: 64 features -> 128 -> 128 (ReLU) -> 4 (sigmoid).  Parameters are one float vector
+ * of WT_MLP_PARAMS values in the order W1 [64][128] (row-major, [input][output]), b1[128],
+ * W2 [128][128], b2[128], W3 [128][4], b3[4].  Matrix products run on the matrix cores with
+ * bfloat16 operands (rounded to nearest even: inputs, weights, hidden activations and, in the
+ * backward pass, the errors) and FP32 accumulation; biases, the master weights, the optimiser
+ * and the loss are FP32.  Loss: mean binary cross-entropy over samples and the 4 outputs.
+ * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).  Feature and label
+ * arrays are device memory, row-major [n][64] and [n][4]. */
+typedef struct wt_mlp wt_mlp;
+enum { WT_MLP_INPUTS = 64, WT_MLP_OUTPUTS = 4, WT_MLP_PARAMS = 25348 };
+
+/* Create a network with the given initial parameters (host array of WT_MLP_PARAMS floats;
+ * the caller draws them).  Uses the current HIP device.  Returns NULL on error. */
+wt_mlp* wt_mlp_create(const float* params_host);
+void wt_mlp_destroy(wt_mlp* m);
+/* Stream for the network's device work (NULL: the library's own stream). */
+int wt_mlp_set_stream(wt_mlp* m, void* hip_stream);
+/* Copy the current FP32 parameters to params_host[WT_MLP_PARAMS]; synchronises. */
+int wt_mlp_get_params(wt_mlp* m, float* params_host);
+/* p_device[n][4] = sigmoid(network(x_device[n][64])).  Asynchronous on the network's stream. */
+int wt_mlp_forward(wt_mlp* m, const float* x_device, int64_t n, float* p_device);
+/* Gradient of the loss on (x, y) with respect to the parameters into grad_host[WT_MLP_PARAMS]
+ * (may be NULL) and the loss into *loss (may be NULL); no update.  Synchronises. */
+int wt_mlp_gradient(wt_mlp* m, const float* x_device, const float* y_device, int64_t n,
+                    float* grad_host, double* loss);
+/* One Adam step with learning rate lr on the batch (x, y); *loss (may be NULL) receives the
+ * loss before the step, which synchronises; with loss NULL the call is asynchronous. */
+int wt_mlp_train_step(wt_mlp* m, const float* x_device, const float* y_device, int64_t n, double lr,
+                      double* loss);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);
 

@@ -26,6 +26,10 @@ static int fail(int code, const std::string& m) {
   return code;
 }
 
+namespace wt {
+int api_fail(int code, const std::string& m) { return fail(code, m); }
+}  // namespace wt
+
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \

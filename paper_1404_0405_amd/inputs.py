@@ -144,3 +144,15 @@ def jet(node_xyz, edge_mid, edge_tan, bump=120.0, bump_lat=45.0, bump_lon=0.0,
     east /= np.maximum(np.linalg.norm(east, axis=1, keepdims=True), 1e-300)
     u = speed * (east * edge_tan).sum(1)
     return h - mean_depth, u, mean_depth
+
+
+def mlp_init(seed=SEED_BASE + 3, n_in=64, n_hidden=128, n_out=4):
+    """Initial parameters of the child-patch predictor network (flat float32 vector, the layout
+    of the C ABI): weights uniform in +-sqrt(6 / fan_in), biases zero.  Random numbers only."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in ((n_in, n_hidden), (n_hidden, n_hidden), (n_hidden, n_out)):
+        b = np.sqrt(6.0 / fi)
+        parts.append(rng.uniform(-b, b, fi * fo))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)

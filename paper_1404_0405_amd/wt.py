@@ -41,6 +41,7 @@ _D = C.POINTER(C.c_double)
 _I64 = C.POINTER(C.c_int64)
 _I32 = C.POINTER(C.c_int32)
 _U8 = C.POINTER(C.c_uint8)
+_F = C.POINTER(C.c_float)
 
 # (name, restype, argtypes) for every function declared in include/wt.h
 SIGNATURES = [
@@ -71,8 +72,17 @@ SIGNATURES = [
     ("wt_host_pair_tables", C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, _I32, _D, _D, _D, _I32, _D,
                                       _D, _D, _I32, _D, _I32, _D]),
     ("wt_host_lattice_check", C.c_int, [C.c_int, _I64, _I64, _D]),
+    ("wt_mlp_create", _P, [_F]),
+    ("wt_mlp_destroy", None, [_P]),
+    ("wt_mlp_set_stream", C.c_int, [_P, _P]),
+    ("wt_mlp_get_params", C.c_int, [_P, _F]),
+    ("wt_mlp_forward", C.c_int, [_P, _P, C.c_int64, _P]),
+    ("wt_mlp_gradient", C.c_int, [_P, _P, _P, C.c_int64, _F, _D]),
+    ("wt_mlp_train_step", C.c_int, [_P, _P, _P, C.c_int64, C.c_double, _D]),
     ("wt_last_error", C.c_char_p, []),
 ]
+
+MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 64, 4, 25348
 
 _lib = None
 
@@ -279,3 +289,72 @@ class Grid:
 
 def kernel_names():
     return load().wt_kernel_names().decode().split(",")
+
+
+def _dev_ptr(t, dtype_name, shape_tail):
+    """Device pointer of a contiguous torch CUDA tensor of the given dtype and trailing shape."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor")
+    if str(t.dtype) != "torch." + dtype_name or tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"expected {dtype_name} [n, {shape_tail}], got {t.dtype} {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """Child-patch predictor network (64 -> 128 -> 128 -> 4) on the matrix cores; thin wrapper
+    of the wt_mlp_* calls.  Feature/label/probability arrays are float32 CUDA tensors."""
+
+    def __init__(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"need {MLP_PARAMS} parameters")
+        lib = load()
+        h = lib.wt_mlp_create(_ptr(p, C.c_float))
+        if not h:
+            raise WtError(WT_EDEVICE, lib.wt_last_error().decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wt_mlp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream):
+        _check(load().wt_mlp_set_stream(self._h, C.c_void_p(stream) if stream else None))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(load().wt_mlp_get_params(self._h, _ptr(out, C.c_float)))
+        return out
+
+    def forward(self, x, p):
+        n = x.shape[0]
+        _check(load().wt_mlp_forward(self._h, _dev_ptr(x, "float32", (MLP_INPUTS,)), n,
+                                     _dev_ptr(p, "float32", (MLP_OUTPUTS,))))
+
+    def gradient(self, x, y):
+        import numpy as np
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        _check(load().wt_mlp_gradient(self._h, _dev_ptr(x, "float32", (MLP_INPUTS,)),
+                                      _dev_ptr(y, "float32", (MLP_OUTPUTS,)), x.shape[0], _ptr(g, C.c_float),
+                                      C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, y, lr, want_loss=True):
+        loss = C.c_double()
+        _check(load().wt_mlp_train_step(self._h, _dev_ptr(x, "float32", (MLP_INPUTS,)),
+                                        _dev_ptr(y, "float32", (MLP_OUTPUTS,)), x.shape[0], float(lr),
+                                        C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
