@@ -268,6 +268,37 @@ int wt_mlp_gradient(wt_mlp* m, const float* x_device, const float* y_device, int
 int wt_mlp_train_step(wt_mlp* m, const float* x_device, const float* y_device, int64_t n, double lr,
                       double* loss);
 
+/* Patches of the learned zone: at level j (jmin < j < jmax, j >= 3) the lattice of every
+ * lozenge is cut into 8 x 8 element patches, patch (L, pi, pj) -> index (L m + pi) m + pj with
+ * m = 2^j / 8; quadrant c = 2a + b of a patch holds the elements (8pi + 4a .. +3, 8pj + 4b .. +3),
+ * whose next-level children form patch (L, 2pi + a, 2pj + b) of level j+1.  wt_patch_count
+ * returns the number of patches of `level` (0 for levels without a gate, negative on error). */
+int64_t wt_patch_count(const wt_grid* g, int level);
+/* Features x_device[count][64] of every patch of `level`, from the wavelet details and
+ * thresholds of the last wt_adapt (or of the last judged step) and the current masks: with
+ * r = clamp(log2(|d| / eps_var), -16, 4) / 8 the size of a detail against its threshold,
+ * [0..35] the largest r of level-j height, level-j velocity, level-(j+1) height and
+ * level-(j+1) velocity details over the patch and its 8 lattice neighbours (9 each; a
+ * neighbour outside the lozenge repeats the patch), [36..51] the same four per quadrant,
+ * [52..55] the active fraction of each quadrant's child patch, [56..59] the fraction of
+ * significant level-j points of each quadrant, [60] the active fraction of the patch's nodes,
+ * [61] (j - jmin) / (jmax - jmin), [62] 1, [63] 0.  Synchronises. */
+int wt_patch_features(wt_grid* g, int level, float* x_device);
+/* Labels y_device[count][4]: 1 where the quadrant holds a significant level-j point of the
+ * current significant set (the last wt_adapt, or the test after the last judged step) -- the
+ * quadrants whose children the blanket zone activates.  Synchronises. */
+int wt_patch_labels(wt_grid* g, int level, float* y_device);
+/* Use network m (NULL: the paper's blanket zone) to gate the children rule of later wt_adapt
+ * calls: a quadrant's significant points activate their children only where the network's
+ * probability is >= threshold (threshold > 1 drops every quadrant).  The step after a gated
+ * adapt is judged by the threshold test on the new state: if a quadrant whose children were
+ * dropped holds a significant point, the state and masks from before that adapt are restored
+ * and the adapt and step are redone with the blanket zone.  The grid keeps the pointer; the
+ * caller keeps m alive while it is set. */
+int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold);
+/* Number of steps redone by the threshold test since the grid was created. */
+int wt_redo_count(const wt_grid* g, int64_t* redo);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);
 

@@ -14,6 +14,7 @@
 #include "wt_grid.hpp"
 #include "wt_internal.hpp"
 #include "wt_lattice_dev.hpp"
+#include "wt_learn.hpp"
 #include "wt_ml.hpp"
 #include "wt_pair.hpp"
 
@@ -44,16 +45,35 @@ struct LevelState {
   uint8_t *nn = nullptr, *ne = nullptr;  // masks under construction (adapt)
   uint8_t *sn = nullptr, *se = nullptr;  // significant points (adapt)
   DevLattice lat;                        // fused lattice form (uniform grids, n >= 64)
+  // learned adjacent zone
+  float *rn = nullptr, *re = nullptr;    // detail size of every point (details of the pair below)
+  int64_t npatch = 0;                    // patches with a learned gate of the children rule
+  float *stats = nullptr, *X = nullptr, *Pr = nullptr;
+  uint8_t *allow = nullptr, *dropped = nullptr, *viol = nullptr;
+  double *snap_dh = nullptr, *snap_u = nullptr;   // state and masks before a gated adapt
+  uint8_t *snap_na = nullptr, *snap_ea = nullptr;
 };
 
 struct PairState {
   PairTables host;
   DevPair dev{};
   double *d_h = nullptr, *d_p = nullptr, *d_i = nullptr, *d_k = nullptr;  // details
+  double *r_h = nullptr, *r_p = nullptr, *r_i = nullptr;  // details of a reconstruction (read-out)
 };
+
+struct wt_mlp;
+namespace wt {
+void mlp_predict(wt_mlp* m, const float* X, int64_t n, float* P, hipStream_t s);
+}
 
 struct wt_grid {
   int jmin = 0, jmax = 0, patch = 8;
+  // learned adjacent zone
+  wt_mlp* predictor = nullptr;
+  double pred_thr = 0.5;
+  bool gated = false;         // the last adapt used the learned gate; the next step is judged
+  double last_eps = 0, last_eh = 0, last_eu = 0;
+  int64_t redo = 0;
   wt_params prm{};
   std::vector<std::unique_ptr<LevelState>> lev;    // index j - jmin
   std::vector<std::unique_ptr<PairState>> pairs;   // pair (j, j+1) at index j - jmin
@@ -90,7 +110,9 @@ static void free_work(LevelState& ls) {
   DevWork& w = ls.work;
   void* ps[] = {w.dh, w.u, w.dh_acc, w.u_acc, w.dh_s[0], w.u_s[0], w.dh_s[1], w.u_s[1],
                 w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red,
-                ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se};
+                ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
+                ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
+                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   w = DevWork{};
@@ -192,7 +214,9 @@ static std::vector<double*> state_u(wt_grid* g) {
   return v;
 }
 
-// Reconstruction of every level into the first stage buffers (the state is not changed).
+// Reconstruction of every level into the first stage buffers (the state is not changed, nor
+// are the details kept from the last forward transform / adapt: the reconstruction computes its
+// own details in separate buffers).
 static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<double*>& ru) {
   rdh.clear();
   ru.clear();
@@ -202,9 +226,23 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
     rdh.push_back(l->work.dh_s[0]);
     ru.push_back(l->work.u_s[0]);
   }
-  prolong_all(g, rdh, ru);
-  details_all(g, rdh, ru);
-  inverse_all(g, rdh, ru, false);
+  auto swap_details = [&]() {
+    for (auto& ps : g->pairs) {
+      std::swap(ps->d_h, ps->r_h);
+      std::swap(ps->d_p, ps->r_p);
+      std::swap(ps->d_i, ps->r_i);
+    }
+  };
+  swap_details();
+  try {
+    prolong_all(g, rdh, ru);
+    details_all(g, rdh, ru);
+    inverse_all(g, rdh, ru, false);
+  } catch (...) {
+    swap_details();
+    throw;
+  }
+  swap_details();
 }
 
 static void ml_step(wt_grid* g, double dt) {
@@ -252,7 +290,77 @@ static double masked_max_all(wt_grid* g, bool nodes) {
   return best;
 }
 
-static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out) {
+// ---------------------------------------------------------------- learned adjacent zone
+// Levels whose children rule can be gated: jmin < j < jmax (level jmin has no significant
+// points of its own) with at least one 8 x 8 patch per lozenge side.
+static bool learnable(const wt_grid* g, int j) { return j > g->jmin && j < g->jmax && j >= 3; }
+
+static void ensure_learn_buffers(wt_grid* g) {
+  for (int j = g->jmin + 1; j <= g->jmax; ++j) {
+    LevelState& l = g->L(j);
+    if (!l.rn) {
+      HIPCHK(hipMalloc(&l.rn, l.tab.N * sizeof(float)));
+      HIPCHK(hipMalloc(&l.re, l.tab.E * sizeof(float)));
+    }
+    if (learnable(g, j) && !l.stats) {
+      const int64_t n = int64_t(1) << j, m = n / 8;
+      l.npatch = 10 * m * m;
+      HIPCHK(hipMalloc(&l.stats, l.npatch * LEARN_STATS * sizeof(float)));
+      HIPCHK(hipMalloc(&l.X, l.npatch * 64 * sizeof(float)));
+      HIPCHK(hipMalloc(&l.Pr, l.npatch * 4 * sizeof(float)));
+      HIPCHK(hipMalloc(&l.allow, l.npatch * 4));
+      HIPCHK(hipMalloc(&l.dropped, l.npatch * 4));
+      HIPCHK(hipMalloc(&l.viol, l.npatch * 4));
+    }
+  }
+}
+
+// Patch statistics of every learnable level from the current details (thresholds eh, eu) and
+// the current significant points.
+static void learn_stats_all(wt_grid* g, double eh, double eu) {
+  ensure_learn_buffers(g);
+  for (int j = g->jmin + 1; j <= g->jmax; ++j) {
+    PairState& P = g->P(j - 1);
+    LevelState& l = g->L(j);
+    learn_point_r(P.dev, P.d_h, P.d_p, P.d_i, eh, eu, l.rn, l.re, g->stream);
+  }
+  for (int j = g->jmin + 1; j < g->jmax; ++j) {
+    if (!learnable(g, j)) continue;
+    LevelState &l = g->L(j), &F = g->L(j + 1);
+    learn_patch_stats(l.npatch, 1 << j, l.rn, l.re, F.rn, F.re, l.na, F.na, l.sn, l.se, l.stats, g->stream);
+  }
+}
+
+static float level_pos(const wt_grid* g, int j) { return float(j - g->jmin) / float(g->jmax - g->jmin); }
+
+static void snapshot(wt_grid* g, bool restore) {
+  for (auto& lp : g->lev) {
+    LevelState& l = *lp;
+    const int64_t N = l.tab.N, E = l.tab.E;
+    if (!l.snap_dh) {
+      HIPCHK(hipMalloc(&l.snap_dh, N * sizeof(double)));
+      HIPCHK(hipMalloc(&l.snap_u, E * sizeof(double)));
+      HIPCHK(hipMalloc(&l.snap_na, N));
+      HIPCHK(hipMalloc(&l.snap_ea, E));
+    }
+    auto cp = [&](void* dst, const void* src, size_t b) {
+      HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, g->stream));
+    };
+    if (restore) {
+      cp(l.work.dh, l.snap_dh, N * sizeof(double));
+      cp(l.work.u, l.snap_u, E * sizeof(double));
+      cp(l.na, l.snap_na, N);
+      cp(l.ea, l.snap_ea, E);
+    } else {
+      cp(l.snap_dh, l.work.dh, N * sizeof(double));
+      cp(l.snap_u, l.work.u, E * sizeof(double));
+      cp(l.snap_na, l.na, N);
+      cp(l.snap_ea, l.ea, E);
+    }
+  }
+}
+
+static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, bool gate = false) {
   std::vector<double*> dh = state_dh(g), u = state_u(g);
   prolong_all(g, dh, u);
   details_all(g, dh, u);
@@ -271,13 +379,27 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out) {
     HIPCHK(hipMemcpyAsync(l->nn, l->sn, l->tab.N, hipMemcpyDeviceToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(l->ne, l->se, l->tab.E, hipMemcpyDeviceToDevice, g->stream));
   }
+  g->last_eh = eh;
+  g->last_eu = eu;
+  // learned zone: the predictor proposes, per patch quadrant, whether the children rule applies
+  if (gate) {
+    learn_stats_all(g, eh, eu);
+    for (int j = g->jmin + 1; j < g->jmax; ++j) {
+      if (!learnable(g, j)) continue;
+      LevelState& l = g->L(j);
+      learn_features(l.npatch, 1 << j, level_pos(g, j), l.stats, l.X, g->stream);
+      mlp_predict(g->predictor, l.X, l.npatch, l.Pr, g->stream);
+      learn_gate(l.npatch, l.Pr, g->pred_thr, l.stats, l.allow, l.dropped, g->stream);
+    }
+  }
   // R2: same-level neighbours; R3: children on the next level
   for (int j = g->jmin; j <= g->jmax; ++j) {
     LevelState& l = g->L(j);
     ml_r2(l.tab, l.sn, l.se, l.nn, l.ne, g->stream);
     if (j < g->jmax) {
       LevelState& F = g->L(j + 1);
-      ml_r3(g->P(j).dev, F.tab, l.sn, l.se, F.nn, F.ne, g->stream);
+      const bool gj = gate && learnable(g, j);
+      ml_r3(g->P(j).dev, F.tab, l.sn, l.se, F.nn, F.ne, g->stream, gj ? l.allow : nullptr, gj ? (1 << j) : 0);
     }
   }
   LevelState& L0 = g->L(g->jmin);
@@ -299,6 +421,40 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out) {
   }
   if (eh_out) *eh_out = eh;
   if (eu_out) *eu_out = eu;
+}
+
+// Threshold test after a gated step: the significant points of the new state (thresholds from
+// eps and the new maxima) must not fall in a quadrant whose children the gate dropped.  Returns
+// the number of such quadrants.
+static int64_t judge_gated_step(wt_grid* g) {
+  std::vector<double*> dh = state_dh(g), u = state_u(g);
+  prolong_all(g, dh, u);
+  details_all(g, dh, u);
+  const double eh = g->last_eps * masked_max_all(g, true), eu = g->last_eps * masked_max_all(g, false);
+  for (auto& l : g->lev) {
+    HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
+    HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
+  }
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    LevelState& F = g->L(j + 1);
+    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream);
+  }
+  g->last_eh = eh;
+  g->last_eu = eu;
+  learn_stats_all(g, eh, eu);
+  int64_t total = 0;
+  for (int j = g->jmin + 1; j < g->jmax; ++j) {
+    if (!learnable(g, j)) continue;
+    LevelState& l = g->L(j);
+    learn_violations(l.npatch, l.stats, l.dropped, l.viol, g->stream);
+    ml_count(4 * l.npatch, l.viol, l.work.red, l.work.red + 4096, g->stream);
+    double c = 0;
+    HIPCHK(hipMemcpyAsync(&c, l.work.red + 4096, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    total += int64_t(c);
+  }
+  return total;
 }
 
 extern "C" {
@@ -373,6 +529,7 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
       upload_pair(ps->host, ps->dev);
       auto A2 = [](double** q, int64_t n) { HIPCHK(hipMalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };
       A2(&ps->d_h, ps->host.Ec); A2(&ps->d_p, ps->host.Ec); A2(&ps->d_k, ps->host.Ec); A2(&ps->d_i, 3 * ps->host.Tc);
+      A2(&ps->r_h, ps->host.Ec); A2(&ps->r_p, ps->host.Ec); A2(&ps->r_i, 3 * ps->host.Tc);
       // keep only what the device path needs on the host
       ps->host = PairTables{};
     }
@@ -400,7 +557,7 @@ void wt_grid_destroy(wt_grid* g) {
   }
   for (auto& ps : g->pairs) {
     free_pair(ps->dev);
-    void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k};
+    void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k, ps->r_h, ps->r_p, ps->r_i};
     for (void* x : q)
       if (x) (void)hipFree(x);
   }
@@ -518,10 +675,22 @@ int wt_step(wt_grid* g, double dt) {
   if (!g->have_state) return fail(WT_ESTATE, "wt_step: call wt_set_state first");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(WT_EINVAL, "wt_step: dt must be positive");
   try {
-    if (g->multi())
+    if (g->multi()) {
       ml_step(g, dt);
-    else
+      if (g->gated) {
+        // the exact threshold test judges the learned zone; a miss redoes the step from the
+        // state before the gated adapt with the blanket zone
+        g->gated = false;
+        if (judge_gated_step(g) > 0) {
+          snapshot(g, true);
+          adapt_impl(g, g->last_eps, nullptr, nullptr, false);
+          ml_step(g, dt);
+          ++g->redo;
+        }
+      }
+    } else {
       uniform_step(g, g->L(g->jmax), dt);
+    }
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_step: ") + e.what());
   }
@@ -534,12 +703,64 @@ int wt_adapt(wt_grid* g, double eps) {
   if (!(eps >= 0) || !std::isfinite(eps)) return fail(WT_EINVAL, "wt_adapt: eps must be >= 0");
   if (!g->multi()) return WT_OK;
   try {
-    adapt_impl(g, eps, nullptr, nullptr);
+    const bool gate = g->predictor != nullptr;
+    if (gate) snapshot(g, false);
+    adapt_impl(g, eps, nullptr, nullptr, gate);
+    g->gated = gate;
+    g->last_eps = eps;
     HIPCHK(hipStreamSynchronize(g->stream));
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_adapt: ") + e.what());
   }
   return WT_OK;
+}
+
+int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
+  if (!g) return fail(WT_EINVAL, "wt_set_predictor: null grid");
+  if (m && !(threshold >= 0.0 && threshold <= 1.5)) return fail(WT_EINVAL, "wt_set_predictor: threshold out of range");
+  g->predictor = m;
+  g->pred_thr = threshold;
+  g->gated = false;
+  return WT_OK;
+}
+
+int wt_redo_count(const wt_grid* g, int64_t* redo) {
+  if (!g || !redo) return fail(WT_EINVAL, "wt_redo_count: null argument");
+  *redo = g->redo;
+  return WT_OK;
+}
+
+int64_t wt_patch_count(const wt_grid* g, int level) {
+  if (!g) return fail(WT_EINVAL, "wt_patch_count: null grid");
+  if (level < g->jmin || level > g->jmax) return fail(WT_EINVAL, "wt_patch_count: level out of range");
+  if (!learnable(g, level)) return 0;
+  const int64_t m = (int64_t(1) << level) / 8;
+  return 10 * m * m;
+}
+
+static int patch_data(wt_grid* g, int level, float* out, bool labels, const char* who) {
+  if (!g || !out) return fail(WT_EINVAL, std::string(who) + ": null argument");
+  if (!g->have_state) return fail(WT_ESTATE, std::string(who) + ": call wt_set_state first");
+  if (level < g->jmin || level > g->jmax || !learnable(g, level))
+    return fail(WT_EINVAL, std::string(who) + ": level has no patches (needs jmin < level < jmax, level >= 3)");
+  try {
+    learn_stats_all(g, g->last_eh, g->last_eu);
+    LevelState& l = g->L(level);
+    if (labels) learn_labels(l.npatch, l.stats, out, g->stream);
+    else learn_features(l.npatch, 1 << level, level_pos(g, level), l.stats, out, g->stream);
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string(who) + ": " + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_patch_features(wt_grid* g, int level, float* x_device) {
+  return patch_data(g, level, x_device, false, "wt_patch_features");
+}
+
+int wt_patch_labels(wt_grid* g, int level, float* y_device) {
+  return patch_data(g, level, y_device, true, "wt_patch_labels");
 }
 
 int wt_forward(wt_grid* g) {

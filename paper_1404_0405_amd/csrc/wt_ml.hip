@@ -450,13 +450,24 @@ __device__ __forceinline__ void mark_cell(int64_t f, const int32_t* __restrict__
   }
 }
 
+// Learned gate of the children rule: allow[4 patch + quadrant] for the element owning a coarse
+// point (null: every point passes; the poles always pass).
+__device__ __forceinline__ bool r3_allowed(const uint8_t* __restrict__ allow, int n, int64_t elem) {
+  if (!allow || elem >= int64_t(10) * n * n) return true;
+  const int64_t L = elem / (int64_t(n) * n);
+  const int i = int((elem / n) % n), j = int(elem % n), m = n / 8;
+  const int64_t patch = (L * m + i / 8) * m + j / 8;
+  return allow[4 * patch + 2 * ((i % 8) / 4) + (j % 8) / 4] != 0;
+}
+
 __global__ __launch_bounds__(BS) void k_r3_nodes(DevPair P, const uint8_t* __restrict__ snc,
                                                  const int32_t* __restrict__ c_e_f,
                                                  const double* __restrict__ c_div_f,
                                                  const int32_t* __restrict__ e_c_f, uint8_t* __restrict__ nnf,
-                                                 uint8_t* __restrict__ nef) {
+                                                 uint8_t* __restrict__ nef, const uint8_t* __restrict__ allow,
+                                                 int nc) {
   int64_t k = TID;
-  if (k >= P.Nc || !snc[k]) return;
+  if (k >= P.Nc || !snc[k] || !r3_allowed(allow, nc, k)) return;
   mark_cell(P.even[k], c_e_f, c_div_f, e_c_f, nnf, nef, true);
 }
 
@@ -464,16 +475,17 @@ __global__ __launch_bounds__(BS) void k_r3_edges(DevPair P, const uint8_t* __res
                                                  const int32_t* __restrict__ c_e_f,
                                                  const double* __restrict__ c_div_f,
                                                  const int32_t* __restrict__ e_c_f, uint8_t* __restrict__ nnf,
-                                                 uint8_t* __restrict__ nef) {
+                                                 uint8_t* __restrict__ nef, const uint8_t* __restrict__ allow,
+                                                 int nc) {
   int64_t e = TID;
-  if (e >= P.Ec || !sec[e]) return;
+  if (e >= P.Ec || !sec[e] || !r3_allowed(allow, nc, e / 3)) return;
   mark_cell(P.mid[e], c_e_f, c_div_f, e_c_f, nnf, nef, false);
 }
 
 void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
-           uint8_t* nef, hipStream_t s) {
-  k_r3_nodes<<<nb(P.Nc), BS, 0, s>>>(P, snc, tf.c_e, tf.c_div, tf.e_c, nnf, nef);
-  k_r3_edges<<<nb(P.Ec), BS, 0, s>>>(P, sec, tf.c_e, tf.c_div, tf.e_c, nnf, nef);
+           uint8_t* nef, hipStream_t s, const uint8_t* allow, int nc) {
+  k_r3_nodes<<<nb(P.Nc), BS, 0, s>>>(P, snc, tf.c_e, tf.c_div, tf.e_c, nnf, nef, allow, nc);
+  k_r3_edges<<<nb(P.Ec), BS, 0, s>>>(P, sec, tf.c_e, tf.c_div, tf.e_c, nnf, nef, allow, nc);
   HIPCHK(hipGetLastError());
 }
 

@@ -36,8 +36,9 @@ void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, co
                     const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
                     hipStream_t s);
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
+// allow (optional): learned gate per quadrant of the 8 x 8 patches of the coarse level (lattice size nc)
 void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
-           uint8_t* nef, hipStream_t s);
+           uint8_t* nef, hipStream_t s, const uint8_t* allow = nullptr, int nc = 0);
 void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s);
 void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
            uint8_t* nec, hipStream_t s);

@@ -18,6 +18,11 @@ struct wt_mlp {
   hipStream_t own = nullptr, stream = nullptr;
 };
 
+namespace wt {
+// Inference for the learned adjacent zone, on the grid's stream.
+void mlp_predict(wt_mlp* m, const float* X, int64_t n, float* P, hipStream_t s) { m->dev.forward(X, n, P, s); }
+}  // namespace wt
+
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \

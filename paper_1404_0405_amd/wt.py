@@ -79,6 +79,11 @@ SIGNATURES = [
     ("wt_mlp_forward", C.c_int, [_P, _P, C.c_int64, _P]),
     ("wt_mlp_gradient", C.c_int, [_P, _P, _P, C.c_int64, _F, _D]),
     ("wt_mlp_train_step", C.c_int, [_P, _P, _P, C.c_int64, C.c_double, _D]),
+    ("wt_patch_count", C.c_int64, [_P, C.c_int]),
+    ("wt_patch_features", C.c_int, [_P, C.c_int, _P]),
+    ("wt_patch_labels", C.c_int, [_P, C.c_int, _P]),
+    ("wt_set_predictor", C.c_int, [_P, _P, C.c_double]),
+    ("wt_redo_count", C.c_int, [_P, _I64]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -279,6 +284,27 @@ class Grid:
 
     def timing_reset(self):
         _check(load().wt_timing_reset(self._h))
+
+    def patch_count(self, level):
+        n = load().wt_patch_count(self._h, level)
+        if n < 0:
+            _check(int(n))
+        return int(n)
+
+    def patch_features(self, level, x):
+        _check(load().wt_patch_features(self._h, level, _dev_ptr(x, "float32", (MLP_INPUTS,))))
+
+    def patch_labels(self, level, y):
+        _check(load().wt_patch_labels(self._h, level, _dev_ptr(y, "float32", (MLP_OUTPUTS,))))
+
+    def set_predictor(self, mlp, threshold=0.5):
+        self._predictor = mlp   # keeps the network alive while the grid uses it
+        _check(load().wt_set_predictor(self._h, mlp._h if mlp is not None else None, float(threshold)))
+
+    def redo_count(self):
+        r = C.c_int64()
+        _check(load().wt_redo_count(self._h, C.byref(r)))
+        return r.value
 
     def kernel_time(self, name):
         """(total ms, launches, total algorithmic bytes) since the last timing reset."""
