@@ -117,6 +117,99 @@ def run_gpu(args):
     return out, (N, E, T), dt
 
 
+def _jet_grid(jmin, jmax, precision, bump_lon=0.0):
+    from paper_1404_0405_amd import inputs, wt
+    g = wt.Grid(jmin, jmax, 8)
+    x, m, t = g.coords(jmax)
+    dh, u, H = inputs.jet(x, m, t, bump_lon=bump_lon)
+    g.set_params(mean_depth=H, rk=wt.WT_RK4, precision=precision)
+    g.set_state(jmax, dh, u)
+    return g, H
+
+
+def train_predictor(jmin, jmax, eps, steps=12, iters=300, lr=2e-3, bump_lon=-40.0):
+    """The child-patch predictor trained on the plain method's own history (a jet run with a
+    different bump position): features after each adapt, labels = the quadrants still holding a
+    significant point after the step."""
+    import torch
+    from paper_1404_0405_amd import inputs, wt
+    g, _ = _jet_grid(jmin, jmax, wt.WT_FP64, bump_lon)
+    Xs, Ys = [], []
+    with g:
+        dt = g.suggest_dt(0.8)
+        prev = None
+        for _ in range(steps):
+            g.adapt(eps)
+            if prev is not None:
+                for j, x in prev:
+                    y = torch.empty((x.shape[0], 4), dtype=torch.float32, device="cuda")
+                    g.patch_labels(j, y)
+                    Xs.append(x)
+                    Ys.append(y)
+            prev = []
+            for j in range(jmin + 1, jmax):
+                if g.patch_count(j) > 0:
+                    x = torch.empty((g.patch_count(j), 64), dtype=torch.float32, device="cuda")
+                    g.patch_features(j, x)
+                    prev.append((j, x))
+            g.step(dt)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    m = wt.Mlp(inputs.mlp_init())
+    l0 = m.gradient(X, Y)[1]
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        m.train_step(X, Y, lr, want_loss=False)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    l1 = m.gradient(X, Y)[1]
+    return m, {"samples": int(X.shape[0]), "loss_before": l0, "loss_after": l1, "train_s": train_s,
+               "iterations": iters}
+
+
+def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, warmup=2):
+    """Adaptive jet workload: plain FP64 (blanket zone) against FP32 tendencies with the learned
+    zone.  Metric: active-point RK-stage updates/s = sum over steps of (active nodes + active
+    edges of all levels) x 4 stages / wall time of adapt + step (the threshold test and any
+    redo included)."""
+    import numpy as np
+    import torch
+    from paper_1404_0405_amd import wt
+    mlp, train = train_predictor(jmin, jmax, eps)
+    out = {"workload": f"zonal jet + 120 m bump, levels {jmin}..{jmax}, eps={eps}, RK4, dt = 0.8 x stable step",
+           "training": train}
+    final = {}
+    for name, prec, learned in (("plain_fp64", wt.WT_FP64, False), ("fp32_learned", wt.WT_FP32_TENDENCY, True)):
+        g, H = _jet_grid(jmin, jmax, prec)
+        with g:
+            dt = g.suggest_dt(0.8)
+            if learned:
+                g.set_predictor(mlp, 0.5)
+            d0, _ = g.diagnostics()
+            for _ in range(warmup):
+                g.adapt(eps)
+                g.step(dt)
+            active, wall = 0, 0.0
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.adapt(eps)
+                g.step(dt)
+                torch.cuda.synchronize()
+                wall += time.perf_counter() - t0
+                d, _ = g.diagnostics()    # untimed: active counts of the mask the step used
+                active += sum(d.active_nodes) + sum(d.active_edges)
+            d1, code = g.diagnostics()
+            final[name] = g.get_state(jmax)[0]
+            out[name] = {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / steps,
+                         "active_dof_per_step": active / steps, "mass_drift": abs(d1.mass / d0.mass - 1),
+                         "redo": g.redo_count(), "finite": code == wt.WT_OK}
+    a, b = final["fp32_learned"], final["plain_fp64"]
+    out["fp32_learned"]["rel_l2_height_vs_plain_fp64"] = float(np.sqrt(((a - b) ** 2).sum() / ((H + b) ** 2).sum()))
+    out["speedup_fp32_learned_over_plain_fp64"] = out["fp32_learned"]["value"] / out["plain_fp64"]["value"]
+    mlp.close()
+    return out
+
+
 def cpu_baseline(level=8, steps=12):
     """The oracle as it stands (numpy FP64, one host thread), on a bounded sample of the same
     workload: `steps` RK4 steps of the same flow on a level-`level` grid."""
@@ -165,9 +258,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,fp32", help="comma list of fp64, fp32")
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy calibration")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive jet comparison")
+    ap.add_argument("--adaptive-steps", type=int, default=10)
+    ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive jet comparison")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.only_adaptive:
+        print(json.dumps({"adaptive": run_adaptive(steps=args.adaptive_steps)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -206,6 +305,8 @@ def main():
         "mass_drift_fp64": f64["mass_drift"],
         "energy_drift_fp64": f64["energy_drift"],
     }
+    if not args.no_adaptive:
+        line["adaptive"] = run_adaptive(steps=args.adaptive_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

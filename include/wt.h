@@ -157,6 +157,14 @@ int wt_inverse(wt_grid* g);
  * details of the three fine edges inside each coarse triangle.  Test hook; synchronises. */
 int wt_get_details(wt_grid* g, int level, double* dh_host, double* dpair_host, double* dint_host);
 
+/* The adaptive stage runs over work lists: after every change of the masks the library builds,
+ * per level, the rings of the active points (3 rings: where q_v, F, B, q_e, Q and the fine
+ * divergence are computed; 5 rings: where inactive points are prolonged) and compacts them into
+ * index lists by wavefront ballot and prefix scan (Sec. 5.2 works on the active patches only).
+ * enable = 0 runs every stage kernel over whole levels instead (test hook: the two agree
+ * bitwise at every active point).  Default: enabled.  Synchronises. */
+int wt_set_work_lists(wt_grid* g, int enable);
+
 /* Replace the active masks of `level` (host arrays of N and E bytes, 1 = active).  Test hook,
  * used to resynchronise masks with a reference at exact threshold ties. */
 int wt_set_mask(wt_grid* g, int level, const uint8_t* node_active_host, const uint8_t* edge_active_host);

@@ -13,6 +13,7 @@
 #include "../../include/wt.h"
 #include "wt_grid.hpp"
 #include "wt_internal.hpp"
+#include "wt_compact.hpp"
 #include "wt_lattice_dev.hpp"
 #include "wt_learn.hpp"
 #include "wt_ml.hpp"
@@ -52,9 +53,14 @@ struct LevelState {
   uint8_t *allow = nullptr, *dropped = nullptr, *viol = nullptr;
   double *snap_dh = nullptr, *snap_u = nullptr;   // state and masks before a gated adapt
   uint8_t *snap_na = nullptr, *snap_ea = nullptr;
+  // work lists of the adaptive stage: support rings of the active points (3 rings: where the
+  // stage intermediates are computed; 5 rings: where inactive points are prolonged)
+  uint8_t *s3n = nullptr, *s3e = nullptr, *s5n = nullptr, *s5e = nullptr, *pred = nullptr;
+  WorkList l_tri, l_elem, l_edge, l_node, l_tend;
 };
 
 struct PairState {
+  WorkList l_cn, l_ce, l_ct;   // coarse nodes / edges / triangles with a fine point in the 5-ring support
   PairTables host;
   DevPair dev{};
   double *d_h = nullptr, *d_p = nullptr, *d_i = nullptr, *d_k = nullptr;  // details
@@ -74,6 +80,14 @@ struct wt_grid {
   bool gated = false;         // the last adapt used the learned gate; the next step is judged
   double last_eps = 0, last_eh = 0, last_eu = 0;
   int64_t redo = 0;
+  bool use_lists = true;      // adaptive stage over work lists (false: whole levels)
+  bool lists_ok = false;      // the lists match the current masks
+  CompactScratch csc;
+  // batched read-backs: device slots and pinned host copies
+  static constexpr int kSlots = 256;
+  int64_t* dev_cnt = nullptr;
+  int64_t* host_cnt = nullptr;
+  double* host_val = nullptr;
   wt_params prm{};
   std::vector<std::unique_ptr<LevelState>> lev;    // index j - jmin
   std::vector<std::unique_ptr<PairState>> pairs;   // pair (j, j+1) at index j - jmin
@@ -112,10 +126,15 @@ static void free_work(LevelState& ls) {
                 w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red,
                 ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
                 ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
-                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea};
+                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.pred};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   w = DevWork{};
+  free_list(ls.l_tri);
+  free_list(ls.l_elem);
+  free_list(ls.l_edge);
+  free_list(ls.l_node);
+  free_list(ls.l_tend);
 }
 
 static PhysParams phys(const wt_grid* g) { return PhysParams{g->prm.gravity, g->prm.mean_depth}; }
@@ -245,10 +264,77 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
   swap_details();
 }
 
+// ---------------------------------------------------------------- work lists
+static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
+
+// Support rings of the active points of every level and the index lists of the adaptive stage
+// (ballot / prefix-scan compaction).  Called whenever the masks change.
+static void build_work_lists(wt_grid* g) {
+  g->lists_ok = false;
+  if (!g->multi() || !g->use_lists) return;
+  hipStream_t s = g->stream;
+  if (!g->dev_cnt) {
+    HIPCHK(hipMalloc(&g->dev_cnt, wt_grid::kSlots * sizeof(int64_t)));
+    HIPCHK(hipHostMalloc(&g->host_cnt, wt_grid::kSlots * sizeof(int64_t), hipHostMallocDefault));
+  }
+  std::vector<WorkList*> batch;
+  auto cmp = [&](const uint8_t* pred, int64_t n, WorkList& L) {
+    if (int(batch.size()) >= wt_grid::kSlots) throw std::runtime_error("work lists: too many lists");
+    compact(pred, n, L, g->csc, s, g->dev_cnt + batch.size());
+    batch.push_back(&L);
+  };
+  for (auto& lp : g->lev) {
+    LevelState& l = *lp;
+    const int64_t N = l.tab.N, E = l.tab.E, T = l.tab.T;
+    if (!l.s3n) {
+      HIPCHK(hipMalloc(&l.s3n, N));
+      HIPCHK(hipMalloc(&l.s3e, E));
+      HIPCHK(hipMalloc(&l.s5n, N));
+      HIPCHK(hipMalloc(&l.s5e, E));
+      HIPCHK(hipMalloc(&l.pred, std::max(N, T)));
+    }
+    // one ring of same-level neighbours
+    auto ring = [&](const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be) { ml_ring(l.tab, an, ae, bn, be, s); };
+    ring(l.na, l.ea, l.nn, l.ne);      // 1
+    ring(l.nn, l.ne, l.s5n, l.s5e);    // 2
+    ring(l.s5n, l.s5e, l.s3n, l.s3e);  // 3
+    ring(l.s3n, l.s3e, l.nn, l.ne);    // 4
+    ring(l.nn, l.ne, l.s5n, l.s5e);    // 5
+    pred_tri(T, l.tab.t_e, l.s3e, l.pred, s);
+    cmp(l.pred, T, l.l_tri);
+    pred_elem(N, l.tab.n_elem, l.s3n, l.s3e, l.pred, s);
+    cmp(l.pred, N, l.l_elem);
+    cmp(l.s3e, E, l.l_edge);
+    cmp(l.s3n, N, l.l_node);
+    pred_elem(N, l.tab.n_elem, l.na, l.ea, l.pred, s);
+    cmp(l.pred, N, l.l_tend);
+  }
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    LevelState& F = g->L(j + 1);
+    const int64_t Nc = P.dev.Nc, Ec = P.dev.Ec, Tc = P.dev.Tc;
+    // three predicate arrays of the coarse level live in the fine level's scratch (N_f > E_c + ...)
+    uint8_t* pn = F.pred;
+    uint8_t* pe = F.pred + Nc;
+    uint8_t* pt = F.pred + Nc + Ec;
+    if (Nc + Ec + Tc > std::max(F.tab.N, F.tab.T)) throw std::runtime_error("work lists: predicate scratch too small");
+    pred_pair(P.dev, F.s5n, F.s5e, pn, pe, pt, s);
+    cmp(pn, Nc, P.l_cn);
+    cmp(pe, Ec, P.l_ce);
+    cmp(pt, Tc, P.l_ct);
+  }
+  HIPCHK(hipMemcpyAsync(g->host_cnt, g->dev_cnt, batch.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (size_t k = 0; k < batch.size(); ++k) batch[k]->n = g->host_cnt[k];
+  g->lists_ok = true;
+}
+
 static void ml_step(wt_grid* g, double dt) {
   const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
   const int nl = g->jmax - g->jmin + 1;
   PhysParams p = phys(g);
+  const bool wl = g->use_lists && g->lists_ok;
+  auto LS = [&](const WorkList& L) { return wl ? span(L) : Span{}; };
   for (int s = 0; s < 4; ++s) {
     std::vector<StageSpec> sp(nl);
     std::vector<double*> xdh(nl), xu(nl);
@@ -257,36 +343,49 @@ static void ml_step(wt_grid* g, double dt) {
       xdh[q] = const_cast<double*>(sp[q].xdh);
       xu[q] = const_cast<double*>(sp[q].xu);
     }
-    prolong_all(g, xdh, xu);
-    for (int q = 0; q < nl; ++q) ml_level_intermediates(g->lev[q]->tab, g->lev[q]->work, p, fp32, xdh[q], xu[q], g->stream);
-    for (int j = g->jmax - 1; j >= g->jmin; --j) {
-      LevelState &C = g->L(j), &F = g->L(j + 1);
-      ml_restrict(g->P(j).dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, fp32, g->stream);
+    // prolongation of the inactive points of the support (every inactive point without lists)
+    for (int j = g->jmin; j < g->jmax; ++j) {
+      LevelState& F = g->L(j + 1);
+      PairState& P = g->P(j);
+      ml_prolong(P.dev, g->L(j).tab, F.na, F.ea, xdh[j - g->jmin], xu[j - g->jmin], xdh[j + 1 - g->jmin],
+                 xu[j + 1 - g->jmin], g->stream, LS(P.l_cn), LS(P.l_ce), LS(P.l_ct));
     }
     for (int q = 0; q < nl; ++q) {
       LevelState& l = *g->lev[q];
-      ml_tend(l.tab, l.work, l.na, l.ea, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream);
+      ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, LS(l.l_tri), LS(l.l_elem),
+                             LS(l.l_edge));
+    }
+    for (int j = g->jmax - 1; j >= g->jmin; --j) {
+      LevelState &C = g->L(j), &F = g->L(j + 1);
+      PairState& P = g->P(j);
+      ml_restrict(P.dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, fp32, g->stream, LS(F.l_node), LS(P.l_ce),
+                  LS(P.l_cn));
+    }
+    for (int q = 0; q < nl; ++q) {
+      LevelState& l = *g->lev[q];
+      ml_tend(l.tab, l.work, l.na, l.ea, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, LS(l.l_tend));
     }
   }
   // partial height transform at complete nodes, bottom-up
   for (int j = g->jmax - 1; j >= g->jmin; --j) {
     LevelState &C = g->L(j), &F = g->L(j + 1);
-    ml_partial_h(g->P(j).dev, C.tab, C.na, F.na, F.ea, F.work.dh, C.work.dh, g->stream);
+    ml_partial_h(g->P(j).dev, C.tab, C.na, F.na, F.ea, F.work.dh, C.work.dh, g->stream, LS(g->P(j).l_cn));
   }
 }
 
 static double masked_max_all(wt_grid* g, bool nodes) {
-  double best = 0.0;
+  if (!g->host_val) HIPCHK(hipHostMalloc(&g->host_val, wt_grid::kSlots * sizeof(double), hipHostMallocDefault));
+  int k = 0;
   for (auto& l : g->lev) {
     double* scratch = l->work.red;
     double* out = l->work.red + 4096;
     if (nodes) ml_masked_max(l->tab.N, l->work.dh, l->na, scratch, out, g->stream);
     else ml_masked_max(l->tab.E, l->work.u, l->ea, scratch, out, g->stream);
-    double v;
-    HIPCHK(hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, g->stream));
-    HIPCHK(hipStreamSynchronize(g->stream));
-    best = std::fmax(best, v);
+    HIPCHK(hipMemcpyAsync(g->host_val + k++, out, sizeof(double), hipMemcpyDeviceToHost, g->stream));
   }
+  HIPCHK(hipStreamSynchronize(g->stream));
+  double best = 0.0;
+  for (int q = 0; q < k; ++q) best = std::fmax(best, g->host_val[q]);
   return best;
 }
 
@@ -419,6 +518,7 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     std::swap(l->na, l->nn);
     std::swap(l->ea, l->ne);
   }
+  build_work_lists(g);
   if (eh_out) *eh_out = eh;
   if (eu_out) *eu_out = eu;
 }
@@ -557,10 +657,17 @@ void wt_grid_destroy(wt_grid* g) {
   }
   for (auto& ps : g->pairs) {
     free_pair(ps->dev);
+    free_list(ps->l_cn);
+    free_list(ps->l_ce);
+    free_list(ps->l_ct);
     void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k, ps->r_h, ps->r_p, ps->r_i};
     for (void* x : q)
       if (x) (void)hipFree(x);
   }
+  free_scratch(g->csc);
+  if (g->dev_cnt) (void)hipFree(g->dev_cnt);
+  if (g->host_cnt) (void)hipHostFree(g->host_cnt);
+  if (g->host_val) (void)hipHostFree(g->host_val);
   if (g->own) (void)hipStreamDestroy(g->own);
   delete g;
 }
@@ -631,6 +738,7 @@ static int set_state_impl(wt_grid* g, int level, const void* dh, const void* u, 
     for (int j = level - 1; j >= g->jmin; --j)
       ml_restrict_state(g->P(j).dev, g->L(j + 1).work.dh, g->L(j + 1).work.u, g->L(j).work.dh,
                         g->L(j).work.u, g->stream);
+    build_work_lists(g);
     HIPCHK(hipStreamSynchronize(g->stream));
     g->have_state = true;
   } catch (const std::exception& e) {
@@ -724,6 +832,18 @@ int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
   return WT_OK;
 }
 
+int wt_set_work_lists(wt_grid* g, int enable) {
+  if (!g) return fail(WT_EINVAL, "wt_set_work_lists: null grid");
+  try {
+    g->use_lists = enable != 0;
+    build_work_lists(g);
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_set_work_lists: ") + e.what());
+  }
+  return WT_OK;
+}
+
 int wt_redo_count(const wt_grid* g, int64_t* redo) {
   if (!g || !redo) return fail(WT_EINVAL, "wt_redo_count: null argument");
   *redo = g->redo;
@@ -813,6 +933,7 @@ int wt_set_mask(wt_grid* g, int level, const uint8_t* na, const uint8_t* ea) {
     LevelState& l = g->L(level);
     HIPCHK(hipMemcpyAsync(l.na, na, l.tab.N, hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(l.ea, ea, l.tab.E, hipMemcpyHostToDevice, g->stream));
+    build_work_lists(g);
     HIPCHK(hipStreamSynchronize(g->stream));
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_set_mask: ") + e.what());

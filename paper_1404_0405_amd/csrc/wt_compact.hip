@@ -1,0 +1,202 @@
+// Work lists of the adaptive stage: stream compaction of byte predicates into index lists by
+// wavefront ballot and prefix scan, and the predicates themselves (support rings of the active
+// points, and the coarse entities of a level pair whose fine points lie in the support).
+//
+// Compaction is three launches: per-chunk counts (ballot + popcount), one workgroup scanning the
+// chunk counts, and the scatter, where every lane finds its slot from the popcount of the ballot
+// bits below it plus the chunk offset.  The output is in increasing index order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "wt_compact.hpp"
+
+namespace wt {
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_) + " at " #x); \
+  } while (0)
+
+constexpr int CB = 256;              // threads per workgroup
+constexpr int CITEMS = 8;            // items per thread
+constexpr int CHUNK = CB * CITEMS;   // indices per workgroup
+constexpr int NWAVE = CB / 64;
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ unsigned long long lanes_below() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__global__ __launch_bounds__(CB) void k_count(const uint8_t* __restrict__ pred, int64_t n, int32_t* __restrict__ cnt) {
+  __shared__ int s_w[NWAVE];
+  const int64_t base = int64_t(blockIdx.x) * CHUNK;
+  int c = 0;
+#pragma unroll
+  for (int it = 0; it < CITEMS; ++it) {
+    const int64_t i = base + it * CB + threadIdx.x;
+    const bool p = i < n && pred[i] != 0;
+    c += __popcll(ballot(p));   // every lane holds the wave's count
+  }
+  if (lane_id() == 0) s_w[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < NWAVE; ++w) t += s_w[w];
+    cnt[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of the chunk counts by one workgroup; off[nchunk] = total.
+__global__ __launch_bounds__(CB) void k_scan(const int32_t* __restrict__ cnt, int64_t nchunk, int64_t* __restrict__ off) {
+  __shared__ int64_t s_sum[CB];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nchunk; b0 += CB) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t v = b < nchunk ? cnt[b] : 0;
+    s_sum[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < CB; o <<= 1) {   // inclusive Hillis-Steele scan
+      const int64_t a = threadIdx.x >= o ? s_sum[threadIdx.x - o] : 0;
+      __syncthreads();
+      s_sum[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (b < nchunk) off[b] = carry + s_sum[threadIdx.x] - v;
+    carry += s_sum[CB - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) off[nchunk] = carry;
+}
+
+__global__ __launch_bounds__(CB) void k_scatter(const uint8_t* __restrict__ pred, int64_t n,
+                                                const int64_t* __restrict__ off, int32_t* __restrict__ out) {
+  __shared__ int s_w[NWAVE];
+  const int64_t base = int64_t(blockIdx.x) * CHUNK;
+  int64_t slot = off[blockIdx.x];
+  const int w = threadIdx.x / 64;
+  for (int it = 0; it < CITEMS; ++it) {
+    const int64_t i = base + it * CB + threadIdx.x;
+    const bool p = i < n && pred[i] != 0;
+    const unsigned long long m = ballot(p);
+    if (lane_id() == 0) s_w[w] = __popcll(m);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < NWAVE; ++q) {
+      before += q < w ? s_w[q] : 0;
+      total += s_w[q];
+    }
+    if (p) out[slot + before + __popcll(m & lanes_below())] = int32_t(i);
+    slot += total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_store_total(const int64_t* __restrict__ off, int64_t nchunk, int64_t* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = off[nchunk];
+}
+
+void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hipStream_t s, int64_t* total_dev) {
+  const int64_t nchunk = (n + CHUNK - 1) / CHUNK;
+  if (nchunk + 1 > sc.cap) {
+    // the previous scratch may still be read by queued work of this stream
+    HIPCHK(hipStreamSynchronize(s));
+    if (sc.cnt) HIPCHK(hipFree(sc.cnt));
+    if (sc.off) HIPCHK(hipFree(sc.off));
+    sc.cap = nchunk + 1;
+    HIPCHK(hipMalloc(&sc.cnt, sc.cap * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&sc.off, sc.cap * sizeof(int64_t)));
+  }
+  if (!L.idx || L.cap < n) {
+    if (L.idx) HIPCHK(hipFree(L.idx));
+    L.cap = n > 0 ? n : 1;
+    HIPCHK(hipMalloc(&L.idx, L.cap * sizeof(int32_t)));
+  }
+  if (n == 0) {
+    L.n = 0;
+    if (total_dev) HIPCHK(hipMemsetAsync(total_dev, 0, sizeof(int64_t), s));
+    return;
+  }
+  k_count<<<unsigned(nchunk), CB, 0, s>>>(pred, n, sc.cnt);
+  k_scan<<<1, CB, 0, s>>>(sc.cnt, nchunk, sc.off);
+  k_scatter<<<unsigned(nchunk), CB, 0, s>>>(pred, n, sc.off, L.idx);
+  HIPCHK(hipGetLastError());
+  if (total_dev) {
+    // the count stays on the device; the caller reads all counts of a batch at once
+    k_store_total<<<1, 64, 0, s>>>(sc.off, nchunk, total_dev);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, sc.off + nchunk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  L.n = total;
+}
+
+void free_list(WorkList& L) {
+  if (L.idx) (void)hipFree(L.idx);
+  L = WorkList{};
+}
+
+void free_scratch(CompactScratch& sc) {
+  if (sc.cnt) (void)hipFree(sc.cnt);
+  if (sc.off) (void)hipFree(sc.off);
+  sc = CompactScratch{};
+}
+
+// ------------------------------------------------------------------ predicates
+#define TIDX (int64_t(blockIdx.x) * CB + threadIdx.x)
+static inline unsigned nbk(int64_t n) { return unsigned((n + CB - 1) / CB); }
+
+// triangles with an edge in the edge support
+__global__ __launch_bounds__(CB) void k_pred_tri(int64_t T, const int32_t* __restrict__ t_e,
+                                                 const uint8_t* __restrict__ se, uint8_t* __restrict__ pt) {
+  const int64_t t = TIDX;
+  if (t >= T) return;
+  pt[t] = (se[t_e[3 * t]] | se[t_e[3 * t + 1]] | se[t_e[3 * t + 2]]) ? 1 : 0;
+}
+
+// elements (node + the 3 edges it owns; poles own none) with a point in the support
+__global__ __launch_bounds__(CB) void k_pred_elem(int64_t N, int64_t n_elem, const uint8_t* __restrict__ sn,
+                                                  const uint8_t* __restrict__ se, uint8_t* __restrict__ pe) {
+  const int64_t i = TIDX;
+  if (i >= N) return;
+  bool p = sn[i] != 0;
+  if (i < n_elem) p = p || se[3 * i] || se[3 * i + 1] || se[3 * i + 2];
+  pe[i] = p ? 1 : 0;
+}
+
+// coarse entities of a pair whose fine points lie in the fine support
+__global__ __launch_bounds__(CB) void k_pred_pair(DevPair P, const uint8_t* __restrict__ snf,
+                                                  const uint8_t* __restrict__ sef, uint8_t* __restrict__ pn,
+                                                  uint8_t* __restrict__ pe, uint8_t* __restrict__ pt) {
+  const int64_t k = TIDX;
+  if (k < P.Nc) pn[k] = snf[P.even[k]] ? 1 : 0;
+  if (k < P.Ec) pe[k] = (snf[P.mid[k]] | sef[P.h1[k]] | sef[P.h2[k]]) ? 1 : 0;
+  if (k < P.Tc) pt[k] = (sef[P.int_e[3 * k]] | sef[P.int_e[3 * k + 1]] | sef[P.int_e[3 * k + 2]]) ? 1 : 0;
+}
+
+void pred_tri(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt, hipStream_t s) {
+  k_pred_tri<<<nbk(T), CB, 0, s>>>(T, t_e, se, pt);
+  HIPCHK(hipGetLastError());
+}
+
+void pred_elem(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe, hipStream_t s) {
+  k_pred_elem<<<nbk(N), CB, 0, s>>>(N, n_elem, sn, se, pe);
+  HIPCHK(hipGetLastError());
+}
+
+void pred_pair(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe, uint8_t* pt,
+               hipStream_t s) {
+  int64_t m = P.Nc;
+  if (P.Ec > m) m = P.Ec;
+  if (P.Tc > m) m = P.Tc;
+  k_pred_pair<<<nbk(m), CB, 0, s>>>(P, snf, sef, pn, pe, pt);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace wt

@@ -1,0 +1,37 @@
+// Work lists of the adaptive stage (index lists built by ballot / prefix-scan compaction).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wt_ml.hpp"
+
+namespace wt {
+
+struct WorkList {
+  int32_t* idx = nullptr;   // device, increasing indices
+  int64_t n = 0, cap = 0;
+};
+
+struct CompactScratch {
+  int32_t* cnt = nullptr;
+  int64_t* off = nullptr;
+  int64_t cap = 0;
+};
+
+// L = { i < n : pred[i] != 0 } in increasing order.  With total_dev null the call synchronises
+// and sets L.n; otherwise the count is written to total_dev (device) and L.n is left to the
+// caller, who reads a batch of counts with one synchronisation.
+void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hipStream_t s,
+             int64_t* total_dev = nullptr);
+void free_list(WorkList& L);
+void free_scratch(CompactScratch& sc);
+
+// predicates: triangles with an edge in `se`; elements with a point in (sn, se); coarse nodes,
+// edges, triangles of a pair with a fine point in the fine support (snf, sef)
+void pred_tri(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt, hipStream_t s);
+void pred_elem(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe, hipStream_t s);
+void pred_pair(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe, uint8_t* pt,
+               hipStream_t s);
+
+}  // namespace wt

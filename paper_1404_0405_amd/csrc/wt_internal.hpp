@@ -85,9 +85,12 @@ void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32
                   const StagePtrs& sdh, const StagePtrs& su, const StageOut& c,
                   hipStream_t s, Timer* tm, const DevLattice* lat = nullptr);
 
-// q_v, B, F, q_e of one level (no tendency, no stage output).
+// q_v, B, F, q_e of one level (no tendency, no stage output): every triangle / element, or the
+// listed ones (nt, ne < 0: the whole level).
 void launch_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
-                          const StagePtrs& sdh, const StagePtrs& su, hipStream_t s);
+                          const StagePtrs& sdh, const StagePtrs& su, hipStream_t s,
+                          const int32_t* tri_list = nullptr, int64_t nt = -1, const int32_t* elem_list = nullptr,
+                          int64_t ne = -1);
 
 // Diagnostics: out[0]=mass, out[1]=energy, out[2]=max|dh|, out[3]=max|u|, out[4]=non-finite
 // count, out[5]=omega_max, out[6]=min d_e/|u_e|.

@@ -231,21 +231,27 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
 
 template <typename T>
 static void intermediates_impl(const DevTables& t, DevWork& w, const PhysParams& p, const StagePtrs& sdh,
-                               const StagePtrs& su, hipStream_t s) {
+                               const StagePtrs& su, hipStream_t s, const int32_t* tri_list, int64_t nt,
+                               const int32_t* elem_list, int64_t ne) {
   T* qv = static_cast<T*>(w.qv);
-  k_vertex<T><<<nblk(t.T), BS, 0, s>>>(t.T, nullptr, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
-  k_edge_cell<T><<<nblk(t.N), BS, 0, s>>>(t.N, t.n_elem, nullptr, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv, p.g,
-                                          p.H, static_cast<T*>(w.B), static_cast<double*>(w.F),
-                                          static_cast<T*>(w.qe));
+  if (nt)
+    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tri_list, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
+  if (ne)
+    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, t.n_elem, elem_list, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv,
+                                           p.g, p.H, static_cast<T*>(w.B), static_cast<double*>(w.F),
+                                           static_cast<T*>(w.qe));
   HIPCHK(hipGetLastError());
 }
 
 void launch_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
-                          const StagePtrs& sdh, const StagePtrs& su, hipStream_t s) {
+                          const StagePtrs& sdh, const StagePtrs& su, hipStream_t s, const int32_t* tri_list,
+                          int64_t nt, const int32_t* elem_list, int64_t ne) {
+  if (nt < 0) nt = t.T;
+  if (ne < 0) ne = t.N;
   if (fp32)
-    intermediates_impl<float>(t, w, p, sdh, su, s);
+    intermediates_impl<float>(t, w, p, sdh, su, s, tri_list, nt, elem_list, ne);
   else
-    intermediates_impl<double>(t, w, p, sdh, su, s);
+    intermediates_impl<double>(t, w, p, sdh, su, s, tri_list, nt, elem_list, ne);
 }
 
 void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,

@@ -21,6 +21,12 @@ namespace wt {
 constexpr int BS = 256;
 static inline unsigned nb(int64_t n) { return unsigned((n + BS - 1) / BS); }
 #define TID (int64_t(blockIdx.x) * BS + threadIdx.x)
+// thread index into an optional work list: the i-th listed index, or i itself
+#define LISTED(var, count, lst)            \
+  int64_t var = TID;                       \
+  if (var >= (count)) return;              \
+  if (lst) var = (lst)[var];
+static inline int64_t span_n(const Span& sp, int64_t dense) { return sp.idx ? sp.n : dense; }
 
 // ------------------------------------------------------------------ shared device helpers
 __device__ __forceinline__ double pair_pred(const DevPair& P, int64_t e, const int32_t* __restrict__ e_v,
@@ -52,9 +58,9 @@ __device__ __forceinline__ double h_detail(const DevPair& P, int64_t e, const do
 // Inactive even node: the coarse value; inactive odd node: s~-weighted mean of its four even
 // fine neighbours; inactive half-edges: u^j -+ (p1-p2)/2; inactive interior edges: prediction.
 __global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* __restrict__ naf,
-                                                     const double* __restrict__ hc, double* __restrict__ hf) {
-  int64_t k = TID;
-  if (k >= P.Nc) return;
+                                                     const double* __restrict__ hc, double* __restrict__ hf,
+                                                     const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(k, cnt, lst)
   int32_t f = P.even[k];
   if (!naf[f]) hf[f] = hc[k];
 }
@@ -63,9 +69,9 @@ __global__ __launch_bounds__(BS) void k_prolong_odd_pair(DevPair P, const uint8_
                                                          const uint8_t* __restrict__ eaf,
                                                          const int32_t* __restrict__ e_v_c,
                                                          const double* __restrict__ uc,
-                                                         double* __restrict__ hf, double* __restrict__ uf) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
+                                                         double* __restrict__ hf, double* __restrict__ uf,
+                                                         const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(e, cnt, lst)
   int32_t m = P.mid[e];
   if (!naf[m]) {
     double s = 0.0;
@@ -83,9 +89,9 @@ __global__ __launch_bounds__(BS) void k_prolong_odd_pair(DevPair P, const uint8_
 }
 
 __global__ __launch_bounds__(BS) void k_prolong_int(DevPair P, const uint8_t* __restrict__ eaf,
-                                                    const double* __restrict__ uc, double* __restrict__ uf) {
-  int64_t t = TID;
-  if (t >= P.Tc) return;
+                                                    const double* __restrict__ uc, double* __restrict__ uf,
+                                                    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(t, cnt, lst)
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     int32_t f = P.int_e[3 * t + s];
@@ -94,10 +100,12 @@ __global__ __launch_bounds__(BS) void k_prolong_int(DevPair P, const uint8_t* __
 }
 
 void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
-                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s) {
-  k_prolong_even<<<nb(P.Nc), BS, 0, s>>>(P, naf, hc, hf);
-  k_prolong_odd_pair<<<nb(P.Ec), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf);
-  k_prolong_int<<<nb(P.Tc), BS, 0, s>>>(P, eaf, uc, uf);
+                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s, Span ln, Span le,
+                Span lt) {
+  const int64_t nn = span_n(ln, P.Nc), ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
+  if (nn) k_prolong_even<<<nb(nn), BS, 0, s>>>(P, naf, hc, hf, ln.idx, nn);
+  if (ne) k_prolong_odd_pair<<<nb(ne), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf, le.idx, ne);
+  if (nt) k_prolong_int<<<nb(nt), BS, 0, s>>>(P, eaf, uc, uf, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 
@@ -105,9 +113,9 @@ void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const
 template <typename T>
 __global__ __launch_bounds__(BS) void k_Q(int64_t E, const int32_t* __restrict__ ecp,
                                           const double* __restrict__ wl, const double* __restrict__ F,
-                                          const T* __restrict__ qe, T* __restrict__ Q) {
-  int64_t e = TID;
-  if (e >= E) return;
+                                          const T* __restrict__ qe, T* __restrict__ Q,
+                                          const int32_t* __restrict__ lst) {
+  LISTED(e, E, lst)
   T q0 = qe[e], s = T(0);
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
@@ -120,9 +128,8 @@ __global__ __launch_bounds__(BS) void k_Q(int64_t E, const int32_t* __restrict__
 template <typename T>
 __global__ __launch_bounds__(BS) void k_div(int64_t N, const int32_t* __restrict__ c_e,
                                             const double* __restrict__ c_div, const double* __restrict__ F,
-                                            double* __restrict__ c) {
-  int64_t i = TID;
-  if (i >= N) return;
+                                            double* __restrict__ c, const int32_t* __restrict__ lst) {
+  LISTED(i, N, lst)
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 6; ++k) s += c_div[6 * i + k] * F[c_e[6 * i + k]];
@@ -137,9 +144,9 @@ __global__ __launch_bounds__(BS) void k_restrict_edges(DevPair P, const uint8_t*
                                                        const double* __restrict__ l_c,
                                                        const double* __restrict__ Ff, const double* __restrict__ cf,
                                                        const T* __restrict__ Qf, double* __restrict__ Fc,
-                                                       T* __restrict__ Qc) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
+                                                       T* __restrict__ Qc, const int32_t* __restrict__ lst,
+                                                       int64_t cnt) {
+  LISTED(e, cnt, lst)
   int32_t h1 = P.h1[e], h2 = P.h2[e];
   if (!(eaf[h1] && eaf[h2])) return;
   double phi = 0.0;
@@ -156,9 +163,9 @@ __global__ __launch_bounds__(BS) void k_restrict_edges(DevPair P, const uint8_t*
 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict_B(DevPair P, const uint8_t* __restrict__ naf,
-                                                   const T* __restrict__ Bf, T* __restrict__ Bc) {
-  int64_t k = TID;
-  if (k >= P.Nc) return;
+                                                   const T* __restrict__ Bf, T* __restrict__ Bc,
+                                                   const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(k, cnt, lst)
   int32_t f = P.even[k];
   if (naf[f]) Bc[k] = Bf[f];
 }
@@ -190,9 +197,9 @@ __global__ __launch_bounds__(BS) void k_tend_ml(int64_t N, int64_t n_elem, const
                                                 const uint8_t* __restrict__ na,
                                                 const uint8_t* __restrict__ ea, const T* __restrict__ B,
                                                 const double* __restrict__ F, const T* __restrict__ Q,
-                                                StagePtrs pdh, StagePtrs pu, StageOut c) {
-  int64_t id = TID;
-  if (id >= N) return;
+                                                StagePtrs pdh, StagePtrs pu, StageOut c,
+                                                const int32_t* __restrict__ lst) {
+  LISTED(id, N, lst)
   double k = 0.0;
   if (na[id]) {
     double div = 0.0;
@@ -216,50 +223,59 @@ void ml_level_trisk_t(const DevTables& t, DevWork& w, const PhysParams& p, const
                       const double* xu, hipStream_t s);
 
 void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
-                            const double* xdh, const double* xu, hipStream_t s) {
-  StageOut c{};
+                            const double* xdh, const double* xu, hipStream_t s, Span ltri, Span lel, Span led) {
   StagePtrs none{nullptr, nullptr, xdh, nullptr, nullptr};
   StagePtrs noneu{nullptr, nullptr, xu, nullptr, nullptr};
   // q_v, B, F, q_e through the uniform kernels (no stage output), then Q
-  launch_intermediates(t, w, p, fp32, none, noneu, s);
+  launch_intermediates(t, w, p, fp32, none, noneu, s, ltri.idx, span_n(ltri, t.T), lel.idx, span_n(lel, t.N));
+  const int64_t ne = span_n(led, t.E);
+  if (ne == 0) return;
   if (fp32)
-    k_Q<float><<<nb(t.E), BS, 0, s>>>(t.E, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<float*>(w.qe),
-                                      static_cast<float*>(w.Q));
+    k_Q<float><<<nb(ne), BS, 0, s>>>(ne, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<float*>(w.qe),
+                                     static_cast<float*>(w.Q), led.idx);
   else
-    k_Q<double><<<nb(t.E), BS, 0, s>>>(t.E, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<double*>(w.qe),
-                                       static_cast<double*>(w.Q));
+    k_Q<double><<<nb(ne), BS, 0, s>>>(ne, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<double*>(w.qe),
+                                      static_cast<double*>(w.Q), led.idx);
   HIPCHK(hipGetLastError());
-  (void)c;
 }
 
 void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, DevWork& wc, DevWork& wf,
-                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s) {
+                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s, Span lfn, Span lce, Span lcn) {
+  const int64_t nf = span_n(lfn, tf.N), ne = span_n(lce, P.Ec), nn = span_n(lcn, P.Nc);
   if (fp32) {
-    k_div<float><<<nb(tf.N), BS, 0, s>>>(tf.N, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c);
-    k_restrict_edges<float><<<nb(P.Ec), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
+    if (nf) k_div<float><<<nb(nf), BS, 0, s>>>(nf, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c, lfn.idx);
+    if (ne)
+      k_restrict_edges<float><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
                                                     static_cast<float*>(wf.Q), static_cast<double*>(wc.F),
-                                                    static_cast<float*>(wc.Q));
-    k_restrict_B<float><<<nb(P.Nc), BS, 0, s>>>(P, naf, static_cast<float*>(wf.B), static_cast<float*>(wc.B));
+                                                    static_cast<float*>(wc.Q), lce.idx, ne);
+    if (nn)
+      k_restrict_B<float><<<nb(nn), BS, 0, s>>>(P, naf, static_cast<float*>(wf.B), static_cast<float*>(wc.B),
+                                                lcn.idx, nn);
   } else {
-    k_div<double><<<nb(tf.N), BS, 0, s>>>(tf.N, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c);
-    k_restrict_edges<double><<<nb(P.Ec), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
+    if (nf) k_div<double><<<nb(nf), BS, 0, s>>>(nf, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c, lfn.idx);
+    if (ne)
+      k_restrict_edges<double><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
                                                      static_cast<double*>(wf.Q), static_cast<double*>(wc.F),
-                                                     static_cast<double*>(wc.Q));
-    k_restrict_B<double><<<nb(P.Nc), BS, 0, s>>>(P, naf, static_cast<double*>(wf.B), static_cast<double*>(wc.B));
+                                                     static_cast<double*>(wc.Q), lce.idx, ne);
+    if (nn)
+      k_restrict_B<double><<<nb(nn), BS, 0, s>>>(P, naf, static_cast<double*>(wf.B), static_cast<double*>(wc.B),
+                                                 lcn.idx, nn);
   }
   HIPCHK(hipGetLastError());
 }
 
 void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, bool fp32,
-             const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s) {
+             const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Span lel) {
+  const int64_t n = span_n(lel, t.N);
+  if (n == 0) return;
   if (fp32)
-    k_tend_ml<float><<<nb(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
-                                            static_cast<float*>(w.B), static_cast<double*>(w.F),
-                                            static_cast<float*>(w.Q), sdh, su, c);
+    k_tend_ml<float><<<nb(n), BS, 0, s>>>(n, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
+                                          static_cast<float*>(w.B), static_cast<double*>(w.F),
+                                          static_cast<float*>(w.Q), sdh, su, c, lel.idx);
   else
-    k_tend_ml<double><<<nb(t.N), BS, 0, s>>>(t.N, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
-                                             static_cast<double*>(w.B), static_cast<double*>(w.F),
-                                             static_cast<double*>(w.Q), sdh, su, c);
+    k_tend_ml<double><<<nb(n), BS, 0, s>>>(n, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
+                                           static_cast<double*>(w.B), static_cast<double*>(w.F),
+                                           static_cast<double*>(w.Q), sdh, su, c, lel.idx);
   HIPCHK(hipGetLastError());
 }
 
@@ -297,9 +313,9 @@ __global__ __launch_bounds__(BS) void k_partial_h(DevPair P, const int32_t* __re
                                                   const uint8_t* __restrict__ nac,
                                                   const uint8_t* __restrict__ naf,
                                                   const uint8_t* __restrict__ eaf,
-                                                  const double* __restrict__ hf, double* __restrict__ hc) {
-  int64_t k = TID;
-  if (k >= P.Nc) return;
+                                                  const double* __restrict__ hf, double* __restrict__ hc,
+                                                  const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(k, cnt, lst)
   if (!nac[k] || !naf[P.even[k]]) return;
   for (int q = 0; q < MK_MAX; ++q) {
     int32_t ec = P.mk[MK_MAX * k + q];
@@ -323,8 +339,9 @@ __global__ __launch_bounds__(BS) void k_partial_h(DevPair P, const int32_t* __re
 }
 
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
-                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s) {
-  k_partial_h<<<nb(P.Nc), BS, 0, s>>>(P, tc.c_e, nac, naf, eaf, hf, hc);
+                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s, Span lcn) {
+  const int64_t n = span_n(lcn, P.Nc);
+  if (n) k_partial_h<<<nb(n), BS, 0, s>>>(P, tc.c_e, nac, naf, eaf, hf, hc, lcn.idx, n);
   HIPCHK(hipGetLastError());
 }
 
@@ -424,6 +441,44 @@ __global__ __launch_bounds__(BS) void k_r2_edges(int64_t E, const int32_t* __res
     int32_t t = e_v[2 * e + side];
     for (int s = 0; s < 3; ++s) ne[t_e[3 * t + s]] = 1;
   }
+}
+
+// One ring in gather form: B = A and the same-level neighbours of A in the sense of R2 (a node
+// joins if it, a neighbour node or an incident edge is in A; an edge joins if it, an end node or
+// an edge of one of its triangles is in A).  No copy of A and no scatter.
+__global__ __launch_bounds__(BS) void k_ring_nodes(int64_t N, const int32_t* __restrict__ c_e,
+                                                   const double* __restrict__ c_div,
+                                                   const int32_t* __restrict__ e_c, const uint8_t* __restrict__ an,
+                                                   const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn) {
+  int64_t i = TID;
+  if (i >= N) return;
+  uint8_t m = an[i];
+  for (int q = 0; q < 6 && !m; ++q) {
+    if (c_div[6 * i + q] == 0.0) continue;  // padded pentagon slot
+    const int32_t e = c_e[6 * i + q];
+    m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
+  }
+  bn[i] = m ? 1 : 0;
+}
+
+__global__ __launch_bounds__(BS) void k_ring_edges(int64_t E, const int32_t* __restrict__ e_c,
+                                                   const int32_t* __restrict__ e_v,
+                                                   const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
+                                                   const uint8_t* __restrict__ ae, uint8_t* __restrict__ be) {
+  int64_t e = TID;
+  if (e >= E) return;
+  uint8_t m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
+  for (int side = 0; side < 2 && !m; ++side) {
+    const int32_t t = e_v[2 * e + side];
+    m = ae[t_e[3 * t]] | ae[t_e[3 * t + 1]] | ae[t_e[3 * t + 2]];
+  }
+  be[e] = m ? 1 : 0;
+}
+
+void ml_ring(const DevTables& t, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be, hipStream_t s) {
+  k_ring_nodes<<<nb(t.N), BS, 0, s>>>(t.N, t.c_e, t.c_div, t.e_c, an, ae, bn);
+  k_ring_edges<<<nb(t.E), BS, 0, s>>>(t.E, t.e_c, t.e_v, t.t_e, an, ae, be);
+  HIPCHK(hipGetLastError());
 }
 
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s) {

@@ -9,6 +9,12 @@
 
 namespace wt {
 
+// Optional work list of a launch: indices idx[0..n) (device), or every index when idx is null.
+struct Span {
+  const int32_t* idx = nullptr;
+  int64_t n = 0;
+};
+
 struct DevPair {
   int64_t Nc, Ec, Tc, Nf, Ef;
   const int32_t *even, *mid, *h1, *h2, *cells, *mk, *int_e, *v_sten, *rf_f, *rf_c;
@@ -18,24 +24,31 @@ struct DevPair {
 void upload_pair(const PairTables& P, DevPair& d);
 void free_pair(DevPair& d);
 
+// Stage kernels take optional work lists (coarse nodes / edges / triangles of the pair; the
+// level's triangles, elements, edges; fine nodes): only listed entities are processed.
 void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
-                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s);
+                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s, Span ln = {},
+                Span le = {}, Span lt = {});
 void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
-                            const double* xdh, const double* xu, hipStream_t s);
+                            const double* xdh, const double* xu, hipStream_t s, Span ltri = {}, Span lel = {},
+                            Span led = {});
 void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, DevWork& wc, DevWork& wf,
-                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s);
+                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s, Span lfn = {}, Span lce = {},
+                 Span lcn = {});
 void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, bool fp32,
-             const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s);
+             const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Span lel = {});
 void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, double* hc, double* uc,
                        hipStream_t s);
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
-                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s);
+                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s, Span lcn = {});
 void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
                 const double* uc, double* dh, double* dp, double* di, hipStream_t s);
 void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
                     const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
                     hipStream_t s);
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
+// (bn, be) = (an, ae) grown by one ring of same-level neighbours (the R2 relation, gather form)
+void ml_ring(const DevTables& t, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be, hipStream_t s);
 // allow (optional): learned gate per quadrant of the 8 x 8 patches of the coarse level (lattice size nc)
 void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
            uint8_t* nef, hipStream_t s, const uint8_t* allow = nullptr, int nc = 0);

@@ -333,14 +333,17 @@ __global__ __launch_bounds__(TPB) void k_grad_tiles(const float* __restrict__ X,
   }
 }
 
-// Sum of the tile contributions in tile order (the loss sum is entry NP).
+// Sum of the tile contributions in a fixed order (the loss sum is entry NP): groups of
+// SUM_GROUP consecutive tiles first, then the groups.
+constexpr int SUM_GROUP = 64;
 __global__ __launch_bounds__(256) void k_sum_tiles(const float* __restrict__ part, int64_t ntile,
-                                                   float* __restrict__ g) {
+                                                   float* __restrict__ out) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q > MLP_NP) return;
+  const int64_t t0 = int64_t(blockIdx.y) * SUM_GROUP, t1 = t0 + SUM_GROUP < ntile ? t0 + SUM_GROUP : ntile;
   float s = 0.f;
-  for (int64_t t = 0; t < ntile; ++t) s += part[t * (MLP_NP + 1) + q];
-  g[q] = s;
+  for (int64_t t = t0; t < t1; ++t) s += part[t * (MLP_NP + 1) + q];
+  out[int64_t(blockIdx.y) * (MLP_NP + 1) + q] = s;
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
@@ -392,11 +395,17 @@ void MlpDev::gradient(const float* X, const float* Y, int64_t n, hipStream_t s) 
   const int64_t tiles = (n + 15) / 16;
   if (tiles > part_tiles) {
     if (part) HIPCHK(hipFree(part));
-    HIPCHK(hipMalloc(&part, tiles * (MLP_NP + 1) * sizeof(float)));
+    // tile contributions, then one row per group of tiles
+    const int64_t rows = tiles + (tiles + SUM_GROUP - 1) / SUM_GROUP;
+    HIPCHK(hipMalloc(&part, rows * (MLP_NP + 1) * sizeof(float)));
     part_tiles = tiles;
   }
   k_grad_tiles<<<unsigned((tiles + WAVES - 1) / WAVES), TPB, 0, s>>>(X, Y, n, theta, frag, part);
-  k_sum_tiles<<<(MLP_NP + 1 + 255) / 256, 256, 0, s>>>(part, tiles, grad);
+  // group sums go to their own rows after the tile rows
+  const int64_t groups = (tiles + SUM_GROUP - 1) / SUM_GROUP;
+  float* gsum = part + tiles * (MLP_NP + 1);
+  k_sum_tiles<<<dim3((MLP_NP + 1 + 255) / 256, unsigned(groups)), 256, 0, s>>>(part, tiles, gsum);
+  k_sum_tiles<<<dim3((MLP_NP + 1 + 255) / 256, 1), 256, 0, s>>>(gsum, groups, grad);
   HIPCHK(hipGetLastError());
 }
 

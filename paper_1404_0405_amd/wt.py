@@ -84,6 +84,7 @@ SIGNATURES = [
     ("wt_patch_labels", C.c_int, [_P, C.c_int, _P]),
     ("wt_set_predictor", C.c_int, [_P, _P, C.c_double]),
     ("wt_redo_count", C.c_int, [_P, _I64]),
+    ("wt_set_work_lists", C.c_int, [_P, C.c_int]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -300,6 +301,9 @@ class Grid:
     def set_predictor(self, mlp, threshold=0.5):
         self._predictor = mlp   # keeps the network alive while the grid uses it
         _check(load().wt_set_predictor(self._h, mlp._h if mlp is not None else None, float(threshold)))
+
+    def set_work_lists(self, enable):
+        _check(load().wt_set_work_lists(self._h, 1 if enable else 0))
 
     def redo_count(self):
         r = C.c_int64()

@@ -188,3 +188,35 @@ def test_tc2_adaptive_levels_4_to_6(precision):
     assert abs(d.mass / m0 - 1) < 1e-13
     x, _, _, _ = H.get_state(6)
     assert np.abs(x - dh).max() / np.abs(dh).max() < 2e-2
+
+
+@pytest.mark.parametrize("case,jmin,jmax,eps,prec", [("jet", 4, 7, 5e-3, "fp64"), ("tc2p", 3, 6, 1e-3, "fp64"),
+                                                     ("jet", 5, 8, 5e-3, "fp32")])
+def test_work_lists_equal_whole_levels(case, jmin, jmax, eps, prec):
+    """The adaptive stage over ballot/prefix-scan work lists (support rings of the active
+    points) gives bitwise the same states, masks and diagnostics as the stage over whole
+    levels."""
+    _say(f"work lists {case} {jmin}..{jmax} eps={eps} {prec}")
+    out = []
+    for lists in (True, False):
+        g = wt.Grid(jmin, jmax, 8)
+        with g:
+            x, m, t = g.coords(jmax)
+            dh, u, Hd = _ic(case, (x, m, t))
+            g.set_params(mean_depth=Hd, precision=wt.WT_FP64 if prec == "fp64" else wt.WT_FP32_TENDENCY)
+            g.set_state(jmax, dh, u)
+            g.set_work_lists(lists)
+            dt = g.suggest_dt(0.8)
+            for _ in range(6):
+                g.adapt(eps)
+                g.step(dt)
+            d, code = g.diagnostics()
+            assert code == wt.WT_OK
+            out.append(([g.get_state(j) for j in range(jmin, jmax + 1)], d.mass, d.energy,
+                        list(d.active_nodes), list(d.active_edges)))
+    (sa, ma, ea_, an, ae), (sb, mb, eb, bn, be) = out
+    for a, b in zip(sa, sb):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    assert ma == mb and ea_ == eb and an == bn and ae == be
+    _say(f"active nodes per level {an[jmin:jmax + 1]}")
