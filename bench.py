@@ -188,19 +188,23 @@ def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, warmup=2):
             for _ in range(warmup):
                 g.adapt(eps)
                 g.step(dt)
-            active, wall = 0, 0.0
+            active, wall, wall_adapt = 0, 0.0, 0.0
             for _ in range(steps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 g.adapt(eps)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
                 g.step(dt)
                 torch.cuda.synchronize()
                 wall += time.perf_counter() - t0
+                wall_adapt += t1 - t0
                 d, _ = g.diagnostics()    # untimed: active counts of the mask the step used
                 active += sum(d.active_nodes) + sum(d.active_edges)
             d1, code = g.diagnostics()
             final[name] = g.get_state(jmax)[0]
             out[name] = {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / steps,
+                         "ms_adapt_per_step": wall_adapt * 1e3 / steps,
                          "active_dof_per_step": active / steps, "mass_drift": abs(d1.mass / d0.mass - 1),
                          "redo": g.redo_count(), "finite": code == wt.WT_OK}
     a, b = final["fp32_learned"], final["plain_fp64"]

@@ -307,6 +307,25 @@ int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold);
 /* Number of steps redone by the threshold test since the grid was created. */
 int wt_redo_count(const wt_grid* g, int64_t* redo);
 
+/* ---------------------------------------------------------------------------------------
+ * Ensembles (an addition to the method, not from the paper): independent members -- grids of
+ * any levels, thresholds and precision -- advanced together.  One step of the ensemble is ONE
+ * launch of a HIP graph that holds every member's Runge-Kutta step, each member on its own
+ * stream so the members' kernels run concurrently; the graph is captured again (or updated in
+ * place) only when a member's work lists or time step changed since the last capture.  Adapt
+ * runs member by member (it reads thresholds back to the host).  With the learned zone, each
+ * member's step is judged after the graph and redone on its own if needed. */
+typedef struct wt_ensemble wt_ensemble;
+/* members: n distinct grids with distinct streams (the caller keeps them alive). */
+wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n);
+void wt_ensemble_destroy(wt_ensemble* e);
+/* wt_adapt of every member with eps_host[k]. */
+int wt_ensemble_adapt(wt_ensemble* e, const double* eps_host);
+/* One step of every member with dt_host[k] as one graph launch; synchronises. */
+int wt_ensemble_step(wt_ensemble* e, const double* dt_host);
+/* Number of graph captures and launches so far. */
+int wt_ensemble_stats(const wt_ensemble* e, int64_t* captures, int64_t* launches);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);
 

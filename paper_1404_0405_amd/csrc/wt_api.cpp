@@ -82,6 +82,7 @@ struct wt_grid {
   int64_t redo = 0;
   bool use_lists = true;      // adaptive stage over work lists (false: whole levels)
   bool lists_ok = false;      // the lists match the current masks
+  uint64_t epoch = 0;         // bumped whenever the work lists (and so the launches of a step) change
   CompactScratch csc;
   // batched read-backs: device slots and pinned host copies
   static constexpr int kSlots = 256;
@@ -271,6 +272,7 @@ static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
 // (ballot / prefix-scan compaction).  Called whenever the masks change.
 static void build_work_lists(wt_grid* g) {
   g->lists_ok = false;
+  ++g->epoch;
   if (!g->multi() || !g->use_lists) return;
   hipStream_t s = g->stream;
   if (!g->dev_cnt) {
@@ -327,6 +329,7 @@ static void build_work_lists(wt_grid* g) {
   HIPCHK(hipStreamSynchronize(s));
   for (size_t k = 0; k < batch.size(); ++k) batch[k]->n = g->host_cnt[k];
   g->lists_ok = true;
+  ++g->epoch;
 }
 
 static void ml_step(wt_grid* g, double dt) {
@@ -1161,6 +1164,149 @@ int wt_host_lattice_check(int level, int64_t* n_tiles, int64_t* n_rim, double* m
   } catch (const std::bad_alloc&) {
     return fail(WT_ENOMEM, "wt_host_lattice_check: out of memory");
   }
+  return WT_OK;
+}
+
+// ---------------------------------------------------------------- ensemble
+struct wt_ensemble {
+  std::vector<wt_grid*> m;
+  hipStream_t s0 = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> epochs;   // member epochs the graph was captured with
+  std::vector<double> dts;
+  int64_t captures = 0, launches = 0;
+};
+
+wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n) {
+  if (!members || n < 1) {
+    fail(WT_EINVAL, "wt_ensemble_create: need at least one member");
+    return nullptr;
+  }
+  for (int k = 0; k < n; ++k)
+    for (int q = 0; q < k; ++q)
+      if (!members[k] || members[k] == members[q] || members[k]->stream == members[q]->stream) {
+        fail(WT_EINVAL, "wt_ensemble_create: members must be distinct grids on distinct streams");
+        return nullptr;
+      }
+  if (!members[0]) {
+    fail(WT_EINVAL, "wt_ensemble_create: null member");
+    return nullptr;
+  }
+  auto* e = new wt_ensemble;
+  try {
+    e->m.assign(members, members + n);
+    HIPCHK(hipStreamCreateWithFlags(&e->s0, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
+    e->join.resize(n);
+    for (auto& j : e->join) HIPCHK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+  } catch (const std::exception& x) {
+    fail(WT_EDEVICE, std::string("wt_ensemble_create: ") + x.what());
+    delete e;
+    return nullptr;
+  }
+  return e;
+}
+
+void wt_ensemble_destroy(wt_ensemble* e) {
+  if (!e) return;
+  if (e->s0) (void)hipStreamSynchronize(e->s0);
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  for (auto& j : e->join)
+    if (j) (void)hipEventDestroy(j);
+  if (e->fork) (void)hipEventDestroy(e->fork);
+  if (e->s0) (void)hipStreamDestroy(e->s0);
+  delete e;
+}
+
+int wt_ensemble_adapt(wt_ensemble* e, const double* eps) {
+  if (!e || !eps) return fail(WT_EINVAL, "wt_ensemble_adapt: null argument");
+  for (size_t k = 0; k < e->m.size(); ++k) {
+    const int rc = wt_adapt(e->m[k], eps[k]);
+    if (rc != WT_OK) return rc;
+  }
+  return WT_OK;
+}
+
+int wt_ensemble_step(wt_ensemble* e, const double* dt) {
+  if (!e || !dt) return fail(WT_EINVAL, "wt_ensemble_step: null argument");
+  const size_t n = e->m.size();
+  for (size_t k = 0; k < n; ++k) {
+    if (!e->m[k]->have_state) return fail(WT_ESTATE, "wt_ensemble_step: a member has no state");
+    if (!(dt[k] > 0) || !std::isfinite(dt[k])) return fail(WT_EINVAL, "wt_ensemble_step: dt must be positive");
+  }
+  try {
+    bool stale = !e->exec || e->dts.size() != n;
+    for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
+    if (stale) {
+      // capture every member's step on its own stream, forked from and joined into s0
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed));
+      try {
+        HIPCHK(hipEventRecord(e->fork, e->s0));
+        for (size_t k = 0; k < n; ++k) {
+          wt_grid* m = e->m[k];
+          HIPCHK(hipStreamWaitEvent(m->stream, e->fork, 0));
+          if (m->multi()) ml_step(m, dt[k]);
+          else uniform_step(m, m->L(m->jmax), dt[k]);
+          HIPCHK(hipEventRecord(e->join[k], m->stream));
+          HIPCHK(hipStreamWaitEvent(e->s0, e->join[k], 0));
+        }
+      } catch (...) {
+        hipGraph_t dropped = nullptr;
+        (void)hipStreamEndCapture(e->s0, &dropped);
+        if (dropped) (void)hipGraphDestroy(dropped);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(e->s0, &g));
+      bool updated = false;
+      if (e->exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        updated = hipGraphExecUpdate(e->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+          (void)hipGetLastError();
+          HIPCHK(hipGraphExecDestroy(e->exec));
+          e->exec = nullptr;
+        }
+      }
+      if (!updated) HIPCHK(hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0));
+      if (e->graph) HIPCHK(hipGraphDestroy(e->graph));
+      e->graph = g;
+      e->epochs.resize(n);
+      for (size_t k = 0; k < n; ++k) e->epochs[k] = e->m[k]->epoch;
+      e->dts.assign(dt, dt + n);
+      ++e->captures;
+    }
+    HIPCHK(hipGraphLaunch(e->exec, e->s0));
+    HIPCHK(hipStreamSynchronize(e->s0));
+    ++e->launches;
+    // the threshold test of the learned zone needs the host: members judged one by one
+    for (size_t k = 0; k < n; ++k) {
+      wt_grid* m = e->m[k];
+      if (!m->multi() || !m->gated) continue;
+      m->gated = false;
+      if (judge_gated_step(m) > 0) {
+        snapshot(m, true);
+        adapt_impl(m, m->last_eps, nullptr, nullptr, false);
+        ml_step(m, dt[k]);
+        ++m->redo;
+      }
+      HIPCHK(hipStreamSynchronize(m->stream));
+    }
+  } catch (const std::exception& x) {
+    return fail(WT_EDEVICE, std::string("wt_ensemble_step: ") + x.what());
+  }
+  return WT_OK;
+}
+
+int wt_ensemble_stats(const wt_ensemble* e, int64_t* captures, int64_t* launches) {
+  if (!e) return fail(WT_EINVAL, "wt_ensemble_stats: null ensemble");
+  if (captures) *captures = e->captures;
+  if (launches) *launches = e->launches;
   return WT_OK;
 }
 

@@ -156,3 +156,15 @@ def mlp_init(seed=SEED_BASE + 3, n_in=64, n_hidden=128, n_out=4):
         parts.append(rng.uniform(-b, b, fi * fo))
         parts.append(np.zeros(fo))
     return np.concatenate(parts).astype(np.float32)
+
+
+def ensemble_members(m, seed=SEED_BASE + 4, jmax_choices=(7, 8, 9), eps_choices=(2e-3, 5e-3, 1e-2)):
+    """Seeded draws of an ensemble of jet members: bump amplitude U[60, 180] m, bump centre
+    45 deg + U[-15, 15] deg latitude, U[-15, 15] deg longitude, Jmax and eps from the choices."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(m):
+        out.append(dict(bump=float(rng.uniform(60.0, 180.0)), bump_lat=float(45.0 + rng.uniform(-15.0, 15.0)),
+                        bump_lon=float(rng.uniform(-15.0, 15.0)), jmax=int(rng.choice(jmax_choices)),
+                        eps=float(rng.choice(eps_choices))))
+    return out

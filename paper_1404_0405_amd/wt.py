@@ -85,6 +85,11 @@ SIGNATURES = [
     ("wt_set_predictor", C.c_int, [_P, _P, C.c_double]),
     ("wt_redo_count", C.c_int, [_P, _I64]),
     ("wt_set_work_lists", C.c_int, [_P, C.c_int]),
+    ("wt_ensemble_create", _P, [C.POINTER(_P), C.c_int]),
+    ("wt_ensemble_destroy", None, [_P]),
+    ("wt_ensemble_adapt", C.c_int, [_P, _D]),
+    ("wt_ensemble_step", C.c_int, [_P, _D]),
+    ("wt_ensemble_stats", C.c_int, [_P, _I64, _I64]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -388,3 +393,42 @@ class Mlp:
                                         _dev_ptr(y, "float32", (MLP_OUTPUTS,)), x.shape[0], float(lr),
                                         C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+
+class Ensemble:
+    """Members advanced together: one HIP graph launch per ensemble step (wt_ensemble_*)."""
+
+    def __init__(self, grids):
+        self._grids = list(grids)   # keeps the members alive
+        arr = (_P * len(self._grids))(*[g._h for g in self._grids])
+        lib = load()
+        h = lib.wt_ensemble_create(arr, len(self._grids))
+        if not h:
+            raise WtError(WT_EINVAL, lib.wt_last_error().decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wt_ensemble_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def adapt(self, eps):
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (len(self._grids),)))
+        _check(load().wt_ensemble_adapt(self._h, _ptr(e, C.c_double)))
+
+    def step(self, dt):
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (len(self._grids),)))
+        _check(load().wt_ensemble_step(self._h, _ptr(d, C.c_double)))
+
+    def stats(self):
+        c, l = C.c_int64(), C.c_int64()
+        _check(load().wt_ensemble_stats(self._h, C.byref(c), C.byref(l)))
+        return c.value, l.value
