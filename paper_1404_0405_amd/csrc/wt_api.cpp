@@ -55,12 +55,14 @@ struct LevelState {
   uint8_t *snap_na = nullptr, *snap_ea = nullptr;
   // work lists of the adaptive stage: support rings of the active points (3 rings: where the
   // stage intermediates are computed; 5 rings: where inactive points are prolonged)
-  uint8_t *s3n = nullptr, *s3e = nullptr, *s5n = nullptr, *s5e = nullptr, *pred = nullptr;
+  uint8_t *s3n = nullptr, *s3e = nullptr, *s5n = nullptr, *s5e = nullptr;
+  uint8_t *pred_t = nullptr, *pred_e = nullptr, *pred_a = nullptr;   // triangles, support / active elements
   WorkList l_tri, l_elem, l_edge, l_node, l_tend;
 };
 
 struct PairState {
   WorkList l_cn, l_ce, l_ct;   // coarse nodes / edges / triangles with a fine point in the 5-ring support
+  uint8_t* pred = nullptr;     // their predicates (Nc + Ec + Tc bytes)
   PairTables host;
   DevPair dev{};
   double *d_h = nullptr, *d_p = nullptr, *d_i = nullptr, *d_k = nullptr;  // details
@@ -84,10 +86,9 @@ struct wt_grid {
   bool lists_ok = false;      // the lists match the current masks
   uint64_t epoch = 0;         // bumped whenever the work lists (and so the launches of a step) change
   CompactScratch csc;
-  // batched read-backs: device slots and pinned host copies
+  CompactBatch cb;
+  // batched read-backs of per-level maxima (pinned)
   static constexpr int kSlots = 256;
-  int64_t* dev_cnt = nullptr;
-  int64_t* host_cnt = nullptr;
   double* host_val = nullptr;
   wt_params prm{};
   std::vector<std::unique_ptr<LevelState>> lev;    // index j - jmin
@@ -127,7 +128,8 @@ static void free_work(LevelState& ls) {
                 w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red,
                 ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
                 ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
-                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.pred};
+                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.pred_t,
+                ls.pred_e, ls.pred_a};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   w = DevWork{};
@@ -275,16 +277,7 @@ static void build_work_lists(wt_grid* g) {
   ++g->epoch;
   if (!g->multi() || !g->use_lists) return;
   hipStream_t s = g->stream;
-  if (!g->dev_cnt) {
-    HIPCHK(hipMalloc(&g->dev_cnt, wt_grid::kSlots * sizeof(int64_t)));
-    HIPCHK(hipHostMalloc(&g->host_cnt, wt_grid::kSlots * sizeof(int64_t), hipHostMallocDefault));
-  }
-  std::vector<WorkList*> batch;
-  auto cmp = [&](const uint8_t* pred, int64_t n, WorkList& L) {
-    if (int(batch.size()) >= wt_grid::kSlots) throw std::runtime_error("work lists: too many lists");
-    compact(pred, n, L, g->csc, s, g->dev_cnt + batch.size());
-    batch.push_back(&L);
-  };
+  CompactBatch& cb = g->cb;
   for (auto& lp : g->lev) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E, T = l.tab.T;
@@ -293,41 +286,37 @@ static void build_work_lists(wt_grid* g) {
       HIPCHK(hipMalloc(&l.s3e, E));
       HIPCHK(hipMalloc(&l.s5n, N));
       HIPCHK(hipMalloc(&l.s5e, E));
-      HIPCHK(hipMalloc(&l.pred, std::max(N, T)));
+      HIPCHK(hipMalloc(&l.pred_t, T));
+      HIPCHK(hipMalloc(&l.pred_e, N));
+      HIPCHK(hipMalloc(&l.pred_a, N));
     }
-    // one ring of same-level neighbours
-    auto ring = [&](const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be) { ml_ring(l.tab, an, ae, bn, be, s); };
-    ring(l.na, l.ea, l.nn, l.ne);      // 1
-    ring(l.nn, l.ne, l.s5n, l.s5e);    // 2
-    ring(l.s5n, l.s5e, l.s3n, l.s3e);  // 3
-    ring(l.s3n, l.s3e, l.nn, l.ne);    // 4
-    ring(l.nn, l.ne, l.s5n, l.s5e);    // 5
-    pred_tri(T, l.tab.t_e, l.s3e, l.pred, s);
-    cmp(l.pred, T, l.l_tri);
-    pred_elem(N, l.tab.n_elem, l.s3n, l.s3e, l.pred, s);
-    cmp(l.pred, N, l.l_elem);
-    cmp(l.s3e, E, l.l_edge);
-    cmp(l.s3n, N, l.l_node);
-    pred_elem(N, l.tab.n_elem, l.na, l.ea, l.pred, s);
-    cmp(l.pred, N, l.l_tend);
+    // rings of same-level neighbours: 1, 2 (scratch), 3 (kept), 4, 5 (kept)
+    ml_ring(l.tab, l.na, l.ea, l.nn, l.ne, s);
+    ml_ring(l.tab, l.nn, l.ne, l.s5n, l.s5e, s);
+    ml_ring(l.tab, l.s5n, l.s5e, l.s3n, l.s3e, s);
+    ml_ring(l.tab, l.s3n, l.s3e, l.nn, l.ne, s);
+    ml_ring(l.tab, l.nn, l.ne, l.s5n, l.s5e, s);
+    pred_tri(T, l.tab.t_e, l.s3e, l.pred_t, s);
+    pred_elem(N, l.tab.n_elem, l.s3n, l.s3e, l.pred_e, s);
+    pred_elem(N, l.tab.n_elem, l.na, l.ea, l.pred_a, s);
+    cb.add(l.pred_t, T, l.l_tri);
+    cb.add(l.pred_e, N, l.l_elem);
+    cb.add(l.s3e, E, l.l_edge);
+    cb.add(l.s3n, N, l.l_node);
+    cb.add(l.pred_a, N, l.l_tend);
   }
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);
     const int64_t Nc = P.dev.Nc, Ec = P.dev.Ec, Tc = P.dev.Tc;
-    // three predicate arrays of the coarse level live in the fine level's scratch (N_f > E_c + ...)
-    uint8_t* pn = F.pred;
-    uint8_t* pe = F.pred + Nc;
-    uint8_t* pt = F.pred + Nc + Ec;
-    if (Nc + Ec + Tc > std::max(F.tab.N, F.tab.T)) throw std::runtime_error("work lists: predicate scratch too small");
+    if (!P.pred) HIPCHK(hipMalloc(&P.pred, Nc + Ec + Tc));
+    uint8_t *pn = P.pred, *pe = P.pred + Nc, *pt = P.pred + Nc + Ec;
     pred_pair(P.dev, F.s5n, F.s5e, pn, pe, pt, s);
-    cmp(pn, Nc, P.l_cn);
-    cmp(pe, Ec, P.l_ce);
-    cmp(pt, Tc, P.l_ct);
+    cb.add(pn, Nc, P.l_cn);
+    cb.add(pe, Ec, P.l_ce);
+    cb.add(pt, Tc, P.l_ct);
   }
-  HIPCHK(hipMemcpyAsync(g->host_cnt, g->dev_cnt, batch.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (size_t k = 0; k < batch.size(); ++k) batch[k]->n = g->host_cnt[k];
+  cb.run(s);
   g->lists_ok = true;
   ++g->epoch;
 }
@@ -663,13 +652,13 @@ void wt_grid_destroy(wt_grid* g) {
     free_list(ps->l_cn);
     free_list(ps->l_ce);
     free_list(ps->l_ct);
+    if (ps->pred) (void)hipFree(ps->pred);
     void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k, ps->r_h, ps->r_p, ps->r_i};
     for (void* x : q)
       if (x) (void)hipFree(x);
   }
   free_scratch(g->csc);
-  if (g->dev_cnt) (void)hipFree(g->dev_cnt);
-  if (g->host_cnt) (void)hipHostFree(g->host_cnt);
+  g->cb.release();
   if (g->host_val) (void)hipHostFree(g->host_val);
   if (g->own) (void)hipStreamDestroy(g->own);
   delete g;

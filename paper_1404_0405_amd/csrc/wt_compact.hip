@@ -7,8 +7,11 @@
 // bits below it plus the chunk offset.  The output is in increasing index order (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "wt_compact.hpp"
 
@@ -135,6 +138,162 @@ void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hi
   HIPCHK(hipMemcpyAsync(&total, sc.off + nchunk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   L.n = total;
+}
+
+// ------------------------------------------------------------------ batched compaction
+// Several predicate arrays compacted by three launches: chunk counts of every job, one workgroup
+// per job scanning its chunk counts, and the scatter.  A chunk finds its job by binary search
+// over the jobs' first chunks.
+struct CJob {
+  const uint8_t* pred;
+  int64_t n;
+  int32_t* out;
+  int64_t chunk0;
+};
+
+__device__ __forceinline__ int job_of(const CJob* __restrict__ jobs, int njob, int64_t chunk) {
+  int lo = 0, hi = njob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].chunk0 <= chunk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(CB) void k_count_b(const CJob* __restrict__ jobs, int njob, int32_t* __restrict__ cnt) {
+  __shared__ int s_w[NWAVE];
+  const int64_t chunk = blockIdx.x;
+  const CJob J = jobs[job_of(jobs, njob, chunk)];
+  const int64_t base = (chunk - J.chunk0) * CHUNK;
+  int c = 0;
+#pragma unroll
+  for (int it = 0; it < CITEMS; ++it) {
+    const int64_t i = base + it * CB + threadIdx.x;
+    c += __popcll(ballot(i < J.n && J.pred[i] != 0));
+  }
+  if (lane_id() == 0) s_w[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < NWAVE; ++w) t += s_w[w];
+    cnt[chunk] = t;
+  }
+}
+
+__global__ __launch_bounds__(CB) void k_scan_b(const CJob* __restrict__ jobs, int njob, int64_t nchunk_total,
+                                               const int32_t* __restrict__ cnt, int64_t* __restrict__ off,
+                                               int64_t* __restrict__ totals) {
+  __shared__ int64_t s_sum[CB];
+  const int k = blockIdx.x;
+  const int64_t c0 = jobs[k].chunk0, c1 = k + 1 < njob ? jobs[k + 1].chunk0 : nchunk_total;
+  int64_t carry = 0;
+  for (int64_t b0 = c0; b0 < c1; b0 += CB) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t v = b < c1 ? cnt[b] : 0;
+    s_sum[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < CB; o <<= 1) {
+      const int64_t a = threadIdx.x >= o ? s_sum[threadIdx.x - o] : 0;
+      __syncthreads();
+      s_sum[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (b < c1) off[b] = carry + s_sum[threadIdx.x] - v;
+    carry += s_sum[CB - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) totals[k] = carry;
+}
+
+__global__ __launch_bounds__(CB) void k_scatter_b(const CJob* __restrict__ jobs, int njob,
+                                                  const int64_t* __restrict__ off) {
+  __shared__ int s_w[NWAVE];
+  const int64_t chunk = blockIdx.x;
+  const CJob J = jobs[job_of(jobs, njob, chunk)];
+  const int64_t base = (chunk - J.chunk0) * CHUNK;
+  int64_t slot = off[chunk];
+  const int w = threadIdx.x / 64;
+  for (int it = 0; it < CITEMS; ++it) {
+    const int64_t i = base + it * CB + threadIdx.x;
+    const bool p = i < J.n && J.pred[i] != 0;
+    const unsigned long long m = ballot(p);
+    if (lane_id() == 0) s_w[w] = __popcll(m);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < NWAVE; ++q) {
+      before += q < w ? s_w[q] : 0;
+      total += s_w[q];
+    }
+    if (p) J.out[slot + before + __popcll(m & lanes_below())] = int32_t(i);
+    slot += total;
+    __syncthreads();
+  }
+}
+
+void CompactBatch::add(const uint8_t* pred, int64_t n, WorkList& L) {
+  if (!L.idx || L.cap < n) {
+    // the list may still be read by queued work: let it drain before freeing
+    if (L.idx) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(L.idx));
+    }
+    L.cap = n > 0 ? n : 1;
+    HIPCHK(hipMalloc(&L.idx, L.cap * sizeof(int32_t)));
+  }
+  jobs.push_back(Job{pred, n, &L});
+}
+
+void CompactBatch::run(hipStream_t s) {
+  const int njob = int(jobs.size());
+  if (njob == 0) return;
+  std::vector<CJob> cj(njob);
+  int64_t nchunk = 0;
+  for (int k = 0; k < njob; ++k) {
+    cj[k] = CJob{jobs[k].pred, jobs[k].n, jobs[k].list->idx, nchunk};
+    nchunk += std::max<int64_t>(1, (jobs[k].n + CHUNK - 1) / CHUNK);   // every job owns a chunk
+  }
+  if (njob > job_cap || nchunk > chunk_cap) {
+    HIPCHK(hipStreamSynchronize(s));
+    release();
+    job_cap = std::max(njob, 64);
+    chunk_cap = std::max<int64_t>(nchunk, 1024);
+    HIPCHK(hipMalloc(&d_jobs, job_cap * sizeof(CJob)));
+    HIPCHK(hipHostMalloc(&h_jobs, job_cap * sizeof(CJob), hipHostMallocDefault));
+    HIPCHK(hipMalloc(&d_cnt, chunk_cap * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&d_off, chunk_cap * sizeof(int64_t)));
+    HIPCHK(hipMalloc(&d_tot, job_cap * sizeof(int64_t)));
+    HIPCHK(hipHostMalloc(&h_tot, job_cap * sizeof(int64_t), hipHostMallocDefault));
+  }
+  // the pinned staging buffer may still feed a queued copy of the previous batch
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(h_jobs, cj.data(), njob * sizeof(CJob));
+  HIPCHK(hipMemcpyAsync(d_jobs, h_jobs, njob * sizeof(CJob), hipMemcpyHostToDevice, s));
+  const CJob* J = static_cast<const CJob*>(d_jobs);
+  k_count_b<<<unsigned(nchunk), CB, 0, s>>>(J, njob, d_cnt);
+  k_scan_b<<<unsigned(njob), CB, 0, s>>>(J, njob, nchunk, d_cnt, d_off, d_tot);
+  k_scatter_b<<<unsigned(nchunk), CB, 0, s>>>(J, njob, d_off);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h_tot, d_tot, njob * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < njob; ++k) jobs[k].list->n = h_tot[k];
+  jobs.clear();
+}
+
+void CompactBatch::release() {
+  void* dv[] = {d_jobs, d_cnt, d_off, d_tot};
+  for (void* p : dv)
+    if (p) (void)hipFree(p);
+  if (h_jobs) (void)hipHostFree(h_jobs);
+  if (h_tot) (void)hipHostFree(h_tot);
+  d_jobs = nullptr;
+  d_cnt = nullptr;
+  d_off = nullptr;
+  d_tot = nullptr;
+  h_jobs = nullptr;
+  h_tot = nullptr;
+  job_cap = 0;
+  chunk_cap = 0;
 }
 
 void free_list(WorkList& L) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "wt_ml.hpp"
 
@@ -25,6 +26,26 @@ struct CompactScratch {
 void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hipStream_t s,
              int64_t* total_dev = nullptr);
 void free_list(WorkList& L);
+
+// Many compactions in three launches and one read-back of the counts: add() the jobs, run().
+struct CompactBatch {
+  struct Job {
+    const uint8_t* pred;
+    int64_t n;
+    WorkList* list;
+  };
+  std::vector<Job> jobs;
+  void* d_jobs = nullptr;
+  void* h_jobs = nullptr;
+  int32_t* d_cnt = nullptr;
+  int64_t *d_off = nullptr, *d_tot = nullptr, *h_tot = nullptr;
+  int job_cap = 0;
+  int64_t chunk_cap = 0;
+
+  void add(const uint8_t* pred, int64_t n, WorkList& L);   // sizes L for n indices
+  void run(hipStream_t s);                                  // compacts every job, sets the counts
+  void release();
+};
 void free_scratch(CompactScratch& sc);
 
 // predicates: triangles with an edge in `se`; elements with a point in (sn, se); coarse nodes,
