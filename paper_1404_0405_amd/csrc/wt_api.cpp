@@ -55,7 +55,7 @@ struct LevelState {
   uint8_t *snap_na = nullptr, *snap_ea = nullptr;
   // work lists of the adaptive stage: support rings of the active points (3 rings: where the
   // stage intermediates are computed; 5 rings: where inactive points are prolonged)
-  uint8_t *s3n = nullptr, *s3e = nullptr, *s5n = nullptr, *s5e = nullptr;
+  uint8_t *s3n = nullptr, *s3e = nullptr, *s5n = nullptr, *s5e = nullptr, *rn_ = nullptr, *re_ = nullptr;
   uint8_t *pred_t = nullptr, *pred_e = nullptr, *pred_a = nullptr;   // triangles, support / active elements
   WorkList l_tri, l_elem, l_edge, l_node, l_tend;
 };
@@ -128,7 +128,7 @@ static void free_work(LevelState& ls) {
                 w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red,
                 ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
                 ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
-                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.pred_t,
+                ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.rn_, ls.re_, ls.pred_t,
                 ls.pred_e, ls.pred_a};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -214,14 +214,23 @@ static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::v
 }
 
 // Inverse transform top-down with the details kept where (old & new) activity holds.
+static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
+
+// swapped: the new masks are already in na/ea and the old ones in nn/ne (adapt); listed: only
+// the fine points of the current work-list support are rewritten (the others are inactive, and
+// every stage prolongs the inactive points of the support before reading them)
 static void inverse_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
-                        bool use_new) {
+                        bool use_new, bool swapped = false, bool listed = false) {
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);
-    ml_inverse(P.dev, g->L(j).tab, F.na, use_new ? F.nn : F.na, F.ea, use_new ? F.ne : F.ea, P.d_h, P.d_p,
-               P.d_i, P.d_k, dh[j - g->jmin], u[j - g->jmin], dh[j + 1 - g->jmin], u[j + 1 - g->jmin],
-               g->stream);
+    const uint8_t *na_old = F.na, *ea_old = F.ea, *na_new = F.na, *ea_new = F.ea;
+    if (use_new && !swapped) { na_new = F.nn; ea_new = F.ne; }
+    if (use_new && swapped) { na_old = F.nn; ea_old = F.ne; }
+    const bool L = listed && g->lists_ok;
+    ml_inverse(P.dev, g->L(j).tab, na_old, na_new, ea_old, ea_new, P.d_h, P.d_p, P.d_i, P.d_k, dh[j - g->jmin],
+               u[j - g->jmin], dh[j + 1 - g->jmin], u[j + 1 - g->jmin], g->stream, L ? span(P.l_cn) : Span{},
+               L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
 }
 
@@ -268,7 +277,6 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
 }
 
 // ---------------------------------------------------------------- work lists
-static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
 
 // Support rings of the active points of every level and the index lists of the adaptive stage
 // (ballot / prefix-scan compaction).  Called whenever the masks change.
@@ -286,16 +294,19 @@ static void build_work_lists(wt_grid* g) {
       HIPCHK(hipMalloc(&l.s3e, E));
       HIPCHK(hipMalloc(&l.s5n, N));
       HIPCHK(hipMalloc(&l.s5e, E));
+      HIPCHK(hipMalloc(&l.rn_, N));
+      HIPCHK(hipMalloc(&l.re_, E));
       HIPCHK(hipMalloc(&l.pred_t, T));
       HIPCHK(hipMalloc(&l.pred_e, N));
       HIPCHK(hipMalloc(&l.pred_a, N));
     }
     // rings of same-level neighbours: 1, 2 (scratch), 3 (kept), 4, 5 (kept)
-    ml_ring(l.tab, l.na, l.ea, l.nn, l.ne, s);
-    ml_ring(l.tab, l.nn, l.ne, l.s5n, l.s5e, s);
-    ml_ring(l.tab, l.s5n, l.s5e, l.s3n, l.s3e, s);
-    ml_ring(l.tab, l.s3n, l.s3e, l.nn, l.ne, s);
-    ml_ring(l.tab, l.nn, l.ne, l.s5n, l.s5e, s);
+    const int nl = 1 << l.geo.J;
+    ml_ring(l.tab, nl, l.na, l.ea, l.rn_, l.re_, s);
+    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s);
+    ml_ring(l.tab, nl, l.s5n, l.s5e, l.s3n, l.s3e, s);
+    ml_ring(l.tab, nl, l.s3n, l.s3e, l.rn_, l.re_, s);
+    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s);
     pred_tri(T, l.tab.t_e, l.s3e, l.pred_t, s);
     pred_elem(N, l.tab.n_elem, l.s3n, l.s3e, l.pred_e, s);
     pred_elem(N, l.tab.n_elem, l.na, l.ea, l.pred_a, s);
@@ -505,12 +516,14 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
       ml_r5(g->P(j - 1).dev, C.tab, l.nn, l.ne, C.nn, C.ne, g->stream);
     }
   }
-  inverse_all(g, dh, u, true);
   for (auto& l : g->lev) {
     std::swap(l->na, l->nn);
     std::swap(l->ea, l->ne);
   }
+  // the new masks' work lists first: the inverse then rewrites only the support (the old masks
+  // stay in nn/ne for it)
   build_work_lists(g);
+  inverse_all(g, dh, u, true, true, true);
   if (eh_out) *eh_out = eh;
   if (eu_out) *eu_out = eu;
 }

@@ -445,39 +445,68 @@ __global__ __launch_bounds__(BS) void k_r2_edges(int64_t E, const int32_t* __res
 
 // One ring in gather form: B = A and the same-level neighbours of A in the sense of R2 (a node
 // joins if it, a neighbour node or an incident edge is in A; an edge joins if it, an end node or
-// an edge of one of its triangles is in A).  No copy of A and no scatter.
-__global__ __launch_bounds__(BS) void k_ring_nodes(int64_t N, const int32_t* __restrict__ c_e,
-                                                   const double* __restrict__ c_div,
+// an edge of one of its triangles is in A).  No copy of A and no scatter.  Points away from the
+// lozenge sides find their neighbours by lattice index arithmetic (only mask bytes are read);
+// the others, and the poles, through the level's tables (a padded pentagon slot repeats an edge
+// of the cell, which changes nothing here).
+__global__ __launch_bounds__(BS) void k_ring_nodes(int64_t N, int n, const int32_t* __restrict__ c_e,
                                                    const int32_t* __restrict__ e_c, const uint8_t* __restrict__ an,
                                                    const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn) {
-  int64_t i = TID;
-  if (i >= N) return;
-  uint8_t m = an[i];
-  for (int q = 0; q < 6 && !m; ++q) {
-    if (c_div[6 * i + q] == 0.0) continue;  // padded pentagon slot
-    const int32_t e = c_e[6 * i + q];
-    m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
+  const int64_t id = TID;
+  if (id >= N) return;
+  const int64_t nn = int64_t(n) * n;
+  uint8_t m = an[id];
+  const int i = int((id / n) % n), j = int(id % n);
+  if (id < 10 * nn && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
+    const int64_t r = n;   // next row
+    m |= an[id + r] | an[id + r + 1] | an[id + 1] | an[id - r] | an[id - r - 1] | an[id - 1];
+    m |= ae[3 * id] | ae[3 * id + 1] | ae[3 * id + 2] | ae[3 * (id - r)] | ae[3 * (id - r - 1) + 1] |
+         ae[3 * (id - 1) + 2];
+  } else {
+    for (int q = 0; q < 6 && !m; ++q) {
+      const int32_t e = c_e[6 * id + q];
+      m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
+    }
   }
-  bn[i] = m ? 1 : 0;
+  bn[id] = m ? 1 : 0;
 }
 
-__global__ __launch_bounds__(BS) void k_ring_edges(int64_t E, const int32_t* __restrict__ e_c,
+__global__ __launch_bounds__(BS) void k_ring_edges(int64_t E, int n, const int32_t* __restrict__ e_c,
                                                    const int32_t* __restrict__ e_v,
                                                    const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
                                                    const uint8_t* __restrict__ ae, uint8_t* __restrict__ be) {
-  int64_t e = TID;
+  const int64_t e = TID;
   if (e >= E) return;
-  uint8_t m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
-  for (int side = 0; side < 2 && !m; ++side) {
-    const int32_t t = e_v[2 * e + side];
-    m = ae[t_e[3 * t]] | ae[t_e[3 * t + 1]] | ae[t_e[3 * t + 2]];
+  const int64_t id = e / 3;
+  const int d = int(e % 3);
+  const int i = int((id / n) % n), j = int(id % n);
+  uint8_t m;
+  if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
+    const int64_t r = n;
+    if (d == 0) {          // P -> P+(1,0): triangles (P, P+(1,0), P+(1,1)) and ((i,j-1), (i+1,j), P)
+      m = an[id] | an[id + r] | ae[3 * id] | ae[3 * (id + r) + 2] | ae[3 * id + 1] | ae[3 * (id - 1) + 1] |
+          ae[3 * (id - 1) + 2];
+    } else if (d == 1) {   // P -> P+(1,1): triangles (P, P+(1,0), P+(1,1)) and (P, P+(1,1), P+(0,1))
+      m = an[id] | an[id + r + 1] | ae[3 * id] | ae[3 * (id + r) + 2] | ae[3 * id + 1] | ae[3 * (id + 1)] |
+          ae[3 * id + 2];
+    } else {               // P -> P+(0,1): triangles (P, P+(1,1), P+(0,1)) and ((i-1,j), P, P+(0,1))
+      m = an[id] | an[id + 1] | ae[3 * id + 1] | ae[3 * (id + 1)] | ae[3 * id + 2] | ae[3 * (id - r)] |
+          ae[3 * (id - r) + 1];
+    }
+  } else {
+    m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
+    for (int side = 0; side < 2 && !m; ++side) {
+      const int32_t t = e_v[2 * e + side];
+      m = ae[t_e[3 * t]] | ae[t_e[3 * t + 1]] | ae[t_e[3 * t + 2]];
+    }
   }
   be[e] = m ? 1 : 0;
 }
 
-void ml_ring(const DevTables& t, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be, hipStream_t s) {
-  k_ring_nodes<<<nb(t.N), BS, 0, s>>>(t.N, t.c_e, t.c_div, t.e_c, an, ae, bn);
-  k_ring_edges<<<nb(t.E), BS, 0, s>>>(t.E, t.e_c, t.e_v, t.t_e, an, ae, be);
+void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
+             hipStream_t s) {
+  k_ring_nodes<<<nb(t.N), BS, 0, s>>>(t.N, n, t.c_e, t.e_c, an, ae, bn);
+  k_ring_edges<<<nb(t.E), BS, 0, s>>>(t.E, n, t.e_c, t.e_v, t.t_e, an, ae, be);
   HIPCHK(hipGetLastError());
 }
 
@@ -624,9 +653,9 @@ __global__ __launch_bounds__(BS) void k_inv_keep(DevPair P, const uint8_t* __res
 }
 
 __global__ __launch_bounds__(BS) void k_inv_even(DevPair P, const double* __restrict__ dk,
-                                                 const double* __restrict__ hc, double* __restrict__ hf) {
-  int64_t k = TID;
-  if (k >= P.Nc) return;
+                                                 const double* __restrict__ hc, double* __restrict__ hf,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(k, cnt, lst)
   double s = hc[k];
   for (int q = 0; q < MK_MAX; ++q) {
     int32_t ec = P.mk[MK_MAX * k + q];
@@ -642,9 +671,9 @@ __global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* _
                                                      const double* __restrict__ dk,
                                                      const double* __restrict__ dp,
                                                      const double* __restrict__ uc, double* __restrict__ hf,
-                                                     double* __restrict__ uf) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
+                                                     double* __restrict__ uf,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(e, cnt, lst)
   double s = dk[e];
 #pragma unroll
   for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
@@ -659,9 +688,9 @@ __global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* _
 __global__ __launch_bounds__(BS) void k_inv_int(DevPair P, const uint8_t* __restrict__ ea_old,
                                                 const uint8_t* __restrict__ ea_new,
                                                 const double* __restrict__ di, const double* __restrict__ uc,
-                                                double* __restrict__ uf) {
-  int64_t t = TID;
-  if (t >= P.Tc) return;
+                                                double* __restrict__ uf,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(t, cnt, lst)
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     int32_t f = P.int_e[3 * t + s];
@@ -673,11 +702,13 @@ __global__ __launch_bounds__(BS) void k_inv_int(DevPair P, const uint8_t* __rest
 void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, const uint8_t* na_new,
                 const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
                 const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
-                hipStream_t s) {
+                hipStream_t s, Span ln, Span le, Span lt) {
+  // the kept details of every coarse edge (an even node's update reads up to 12 of them)
   k_inv_keep<<<nb(P.Ec), BS, 0, s>>>(P, na_old, na_new, dh, dk);
-  k_inv_even<<<nb(P.Nc), BS, 0, s>>>(P, dk, hc, hf);
-  k_inv_odd_pair<<<nb(P.Ec), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf);
-  k_inv_int<<<nb(P.Tc), BS, 0, s>>>(P, ea_old, ea_new, di, uc, uf);
+  const int64_t nn = span_n(ln, P.Nc), ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
+  if (nn) k_inv_even<<<nb(nn), BS, 0, s>>>(P, dk, hc, hf, ln.idx, nn);
+  if (ne) k_inv_odd_pair<<<nb(ne), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf, le.idx, ne);
+  if (nt) k_inv_int<<<nb(nt), BS, 0, s>>>(P, ea_old, ea_new, di, uc, uf, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 

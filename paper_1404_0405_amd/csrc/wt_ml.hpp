@@ -48,7 +48,9 @@ void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, co
                     hipStream_t s);
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
 // (bn, be) = (an, ae) grown by one ring of same-level neighbours (the R2 relation, gather form)
-void ml_ring(const DevTables& t, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be, hipStream_t s);
+// (n = lattice size 2^level)
+void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
+             hipStream_t s);
 // allow (optional): learned gate per quadrant of the 8 x 8 patches of the coarse level (lattice size nc)
 void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
            uint8_t* nef, hipStream_t s, const uint8_t* allow = nullptr, int nc = 0);
@@ -58,7 +60,7 @@ void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint
 void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, const uint8_t* na_new,
                 const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
                 const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
-                hipStream_t s);
+                hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
 void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
                    hipStream_t s);
 void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipStream_t s);
