@@ -84,6 +84,7 @@ struct wt_grid {
   int64_t redo = 0;
   bool use_lists = true;      // adaptive stage over work lists (false: whole levels)
   bool lists_ok = false;      // the lists match the current masks
+  bool details_partial = false;   // the stored details cover only the work-list support
   uint64_t epoch = 0;         // bumped whenever the work lists (and so the launches of a step) change
   CompactScratch csc;
   CompactBatch cb;
@@ -197,24 +198,33 @@ static void uniform_step(wt_grid* g, LevelState& ls, double dt) {
 
 // ---------------------------------------------------------------- multilevel operations
 // Fill inactive points of every level above jmin from the level below (top-down).
-static void prolong_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u) {
+static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
+
+// listed: only the work-list support of the current masks (the rest keeps stale values)
+static void prolong_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
+                        bool listed = false) {
+  const bool L = listed && g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
     LevelState& F = g->L(j + 1);
-    ml_prolong(g->P(j).dev, g->L(j).tab, F.na, F.ea, dh[j - g->jmin], u[j - g->jmin],
-               dh[j + 1 - g->jmin], u[j + 1 - g->jmin], g->stream);
+    PairState& P = g->P(j);
+    ml_prolong(P.dev, g->L(j).tab, F.na, F.ea, dh[j - g->jmin], u[j - g->jmin], dh[j + 1 - g->jmin],
+               u[j + 1 - g->jmin], g->stream, L ? span(P.l_cn) : Span{}, L ? span(P.l_ce) : Span{},
+               L ? span(P.l_ct) : Span{});
   }
 }
 
-static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u) {
+static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
+                        bool listed = false) {
+  const bool L = listed && g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     ml_details(P.dev, g->L(j).tab, dh[j + 1 - g->jmin], u[j + 1 - g->jmin], u[j - g->jmin], P.d_h, P.d_p,
-               P.d_i, g->stream);
+               P.d_i, g->stream, L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
+  g->details_partial = L;
 }
 
 // Inverse transform top-down with the details kept where (old & new) activity holds.
-static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
 
 // swapped: the new masks are already in na/ea and the old ones in nn/ne (adapt); listed: only
 // the fine points of the current work-list support are rewritten (the others are inactive, and
@@ -264,6 +274,7 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
       std::swap(ps->d_i, ps->r_i);
     }
   };
+  const bool partial = g->details_partial;   // describes the stored (swapped-out) details
   swap_details();
   try {
     prolong_all(g, rdh, ru);
@@ -271,9 +282,11 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
     inverse_all(g, rdh, ru, false);
   } catch (...) {
     swap_details();
+    g->details_partial = partial;
     throw;
   }
   swap_details();
+  g->details_partial = partial;
 }
 
 // ---------------------------------------------------------------- work lists
@@ -532,18 +545,22 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
 // eps and the new maxima) must not fall in a quadrant whose children the gate dropped.  Returns
 // the number of such quadrants.
 static int64_t judge_gated_step(wt_grid* g) {
+  // only the significance of active points matters here: prolongation, details and the test
+  // run over the work lists
   std::vector<double*> dh = state_dh(g), u = state_u(g);
-  prolong_all(g, dh, u);
-  details_all(g, dh, u);
+  prolong_all(g, dh, u, true);
+  details_all(g, dh, u, true);
   const double eh = g->last_eps * masked_max_all(g, true), eu = g->last_eps * masked_max_all(g, false);
   for (auto& l : g->lev) {
     HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
     HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
   }
+  const bool L = g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);
-    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream);
+    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
+                   L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
   g->last_eh = eh;
   g->last_eu = eu;
@@ -863,12 +880,21 @@ int64_t wt_patch_count(const wt_grid* g, int level) {
   return 10 * m * m;
 }
 
+// Details of every point of the current state (after a listed pass only the support was fresh).
+static void dense_details(wt_grid* g) {
+  if (!g->details_partial) return;
+  std::vector<double*> dh = state_dh(g), u = state_u(g);
+  prolong_all(g, dh, u);
+  details_all(g, dh, u);
+}
+
 static int patch_data(wt_grid* g, int level, float* out, bool labels, const char* who) {
   if (!g || !out) return fail(WT_EINVAL, std::string(who) + ": null argument");
   if (!g->have_state) return fail(WT_ESTATE, std::string(who) + ": call wt_set_state first");
   if (level < g->jmin || level > g->jmax || !learnable(g, level))
     return fail(WT_EINVAL, std::string(who) + ": level has no patches (needs jmin < level < jmax, level >= 3)");
   try {
+    dense_details(g);
     learn_stats_all(g, g->last_eh, g->last_eu);
     LevelState& l = g->L(level);
     if (labels) learn_labels(l.npatch, l.stats, out, g->stream);
@@ -920,6 +946,7 @@ int wt_inverse(wt_grid* g) {
 int wt_get_details(wt_grid* g, int level, double* dh, double* dpair, double* dint) {
   if (!g || level <= g->jmin || level > g->jmax) return fail(WT_EINVAL, "wt_get_details: bad level");
   try {
+    if (g->have_state) dense_details(g);
     PairState& P = g->P(level - 1);
     const LevelState& C = g->L(level - 1);
     if (dh) HIPCHK(hipMemcpyAsync(dh, P.d_h, C.tab.E * sizeof(double), hipMemcpyDeviceToHost, g->stream));

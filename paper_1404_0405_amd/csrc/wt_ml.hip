@@ -350,25 +350,26 @@ __global__ __launch_bounds__(BS) void k_details_edge(DevPair P, const int32_t* _
                                                      const double* __restrict__ hf,
                                                      const double* __restrict__ uf,
                                                      const double* __restrict__ uc,
-                                                     double* __restrict__ dh, double* __restrict__ dp) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
+                                                     double* __restrict__ dh, double* __restrict__ dp,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(e, cnt, lst)
   dh[e] = h_detail(P, e, hf);
   dp[e] = (uf[P.h1[e]] - uf[P.h2[e]]) - pair_pred(P, e, e_v_c, uc);
 }
 
 __global__ __launch_bounds__(BS) void k_details_int(DevPair P, const double* __restrict__ uf,
-                                                    const double* __restrict__ uc, double* __restrict__ di) {
-  int64_t t = TID;
-  if (t >= P.Tc) return;
+                                                    const double* __restrict__ uc, double* __restrict__ di,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(t, cnt, lst)
 #pragma unroll
   for (int s = 0; s < 3; ++s) di[3 * t + s] = uf[P.int_e[3 * t + s]] - int_pred(P, t, s, uc);
 }
 
 void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
-                const double* uc, double* dh, double* dp, double* di, hipStream_t s) {
-  k_details_edge<<<nb(P.Ec), BS, 0, s>>>(P, tc.e_v, hf, uf, uc, dh, dp);
-  k_details_int<<<nb(P.Tc), BS, 0, s>>>(P, uf, uc, di);
+                const double* uc, double* dh, double* dp, double* di, hipStream_t s, Span le, Span lt) {
+  const int64_t ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
+  if (ne) k_details_edge<<<nb(ne), BS, 0, s>>>(P, tc.e_v, hf, uf, uc, dh, dp, le.idx, ne);
+  if (nt) k_details_int<<<nb(nt), BS, 0, s>>>(P, uf, uc, di, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 
@@ -378,9 +379,9 @@ __global__ __launch_bounds__(BS) void k_sig_edge(DevPair P, const uint8_t* __res
                                                  const uint8_t* __restrict__ eaf,
                                                  const double* __restrict__ dh, const double* __restrict__ dp,
                                                  double eh, double eu, uint8_t* __restrict__ sn,
-                                                 uint8_t* __restrict__ se) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
+                                                 uint8_t* __restrict__ se,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(e, cnt, lst)
   int32_t m = P.mid[e];
   if (naf[m] && fabs(dh[e]) >= eh) sn[m] = 1;
   int32_t h1 = P.h1[e], h2 = P.h2[e];
@@ -392,9 +393,9 @@ __global__ __launch_bounds__(BS) void k_sig_edge(DevPair P, const uint8_t* __res
 
 __global__ __launch_bounds__(BS) void k_sig_int(DevPair P, const uint8_t* __restrict__ eaf,
                                                 const double* __restrict__ di, double eu,
-                                                uint8_t* __restrict__ se) {
-  int64_t t = TID;
-  if (t >= P.Tc) return;
+                                                uint8_t* __restrict__ se,
+    const int32_t* __restrict__ lst, int64_t cnt) {
+  LISTED(t, cnt, lst)
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     int32_t f = P.int_e[3 * t + s];
@@ -404,9 +405,10 @@ __global__ __launch_bounds__(BS) void k_sig_int(DevPair P, const uint8_t* __rest
 
 void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
                     const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
-                    hipStream_t s) {
-  k_sig_edge<<<nb(P.Ec), BS, 0, s>>>(P, naf, eaf, dh, dp, eh, eu, sn, se);
-  k_sig_int<<<nb(P.Tc), BS, 0, s>>>(P, eaf, di, eu, se);
+                    hipStream_t s, Span le, Span lt) {
+  const int64_t ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
+  if (ne) k_sig_edge<<<nb(ne), BS, 0, s>>>(P, naf, eaf, dh, dp, eh, eu, sn, se, le.idx, ne);
+  if (nt) k_sig_int<<<nb(nt), BS, 0, s>>>(P, eaf, di, eu, se, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 

@@ -42,10 +42,10 @@ void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, dou
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
                   const uint8_t* eaf, const double* hf, double* hc, hipStream_t s, Span lcn = {});
 void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
-                const double* uc, double* dh, double* dp, double* di, hipStream_t s);
+                const double* uc, double* dh, double* dp, double* di, hipStream_t s, Span le = {}, Span lt = {});
 void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
                     const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
-                    hipStream_t s);
+                    hipStream_t s, Span le = {}, Span lt = {});
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
 // (bn, be) = (an, ae) grown by one ring of same-level neighbours (the R2 relation, gather form)
 // (n = lattice size 2^level)
