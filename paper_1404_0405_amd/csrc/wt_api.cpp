@@ -389,20 +389,27 @@ static void ml_step(wt_grid* g, double dt) {
   }
 }
 
-static double masked_max_all(wt_grid* g, bool nodes) {
+// max |dh| over the active nodes and max |u| over the active edges of all levels: one batched
+// reduction and one read-back
+static void masked_max_all(wt_grid* g, double* mh, double* mu) {
   if (!g->host_val) HIPCHK(hipHostMalloc(&g->host_val, wt_grid::kSlots * sizeof(double), hipHostMallocDefault));
+  MaxJobs jobs{};
   int k = 0;
-  for (auto& l : g->lev) {
-    double* scratch = l->work.red;
-    double* out = l->work.red + 4096;
-    if (nodes) ml_masked_max(l->tab.N, l->work.dh, l->na, scratch, out, g->stream);
-    else ml_masked_max(l->tab.E, l->work.u, l->ea, scratch, out, g->stream);
-    HIPCHK(hipMemcpyAsync(g->host_val + k++, out, sizeof(double), hipMemcpyDeviceToHost, g->stream));
-  }
+  for (auto& l : g->lev) jobs.j[k++] = MaxJob{l->work.dh, l->na, l->tab.N};
+  for (auto& l : g->lev) jobs.j[k++] = MaxJob{l->work.u, l->ea, l->tab.E};
+  double* red = g->lev.front()->work.red;   // MAX_JOBS * MAX_BLOCKS partials, then the results
+  ml_masked_max_batch(jobs, k, red, red + MAX_JOBS * MAX_BLOCKS, g->stream);
+  HIPCHK(hipMemcpyAsync(g->host_val, red + MAX_JOBS * MAX_BLOCKS, k * sizeof(double), hipMemcpyDeviceToHost,
+                        g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
-  double best = 0.0;
-  for (int q = 0; q < k; ++q) best = std::fmax(best, g->host_val[q]);
-  return best;
+  const int nl = k / 2;
+  double bh = 0.0, bu = 0.0;
+  for (int q = 0; q < nl; ++q) {
+    bh = std::fmax(bh, g->host_val[q]);
+    bu = std::fmax(bu, g->host_val[nl + q]);
+  }
+  *mh = bh;
+  *mu = bu;
 }
 
 // ---------------------------------------------------------------- learned adjacent zone
@@ -449,6 +456,7 @@ static void learn_stats_all(wt_grid* g, double eh, double eu) {
 static float level_pos(const wt_grid* g, int j) { return float(j - g->jmin) / float(g->jmax - g->jmin); }
 
 static void snapshot(wt_grid* g, bool restore) {
+  if (restore) g->lists_ok = false;   // the work lists describe the masks being discarded
   for (auto& lp : g->lev) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E;
@@ -476,19 +484,26 @@ static void snapshot(wt_grid* g, bool restore) {
 }
 
 static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, bool gate = false) {
+  // The threshold test reads the details of active points only, whose prolongation and
+  // prediction stencils lie in the work-list support; the learned gate's patch features read
+  // every point's detail, so a gated adapt runs the transform on whole levels.
   std::vector<double*> dh = state_dh(g), u = state_u(g);
-  prolong_all(g, dh, u);
-  details_all(g, dh, u);
-  double eh = eps * masked_max_all(g, true), eu = eps * masked_max_all(g, false);
+  prolong_all(g, dh, u, !gate);
+  details_all(g, dh, u, !gate);
+  double mh, mu;
+  masked_max_all(g, &mh, &mu);
+  const double eh = eps * mh, eu = eps * mu;
   for (auto& l : g->lev) {
     HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
     HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
   }
   // R1: significant points
+  const bool listed = !gate && g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);
-    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream);
+    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
+                   listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
   }
   for (auto& l : g->lev) {
     HIPCHK(hipMemcpyAsync(l->nn, l->sn, l->tab.N, hipMemcpyDeviceToDevice, g->stream));
@@ -550,7 +565,9 @@ static int64_t judge_gated_step(wt_grid* g) {
   std::vector<double*> dh = state_dh(g), u = state_u(g);
   prolong_all(g, dh, u, true);
   details_all(g, dh, u, true);
-  const double eh = g->last_eps * masked_max_all(g, true), eu = g->last_eps * masked_max_all(g, false);
+  double mh, mu;
+  masked_max_all(g, &mh, &mu);
+  const double eh = g->last_eps * mh, eu = g->last_eps * mu;
   for (auto& l : g->lev) {
     HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
     HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
@@ -565,17 +582,17 @@ static int64_t judge_gated_step(wt_grid* g) {
   g->last_eh = eh;
   g->last_eu = eu;
   learn_stats_all(g, eh, eu);
-  int64_t total = 0;
+  int k = 0;
   for (int j = g->jmin + 1; j < g->jmax; ++j) {
     if (!learnable(g, j)) continue;
     LevelState& l = g->L(j);
     learn_violations(l.npatch, l.stats, l.dropped, l.viol, g->stream);
     ml_count(4 * l.npatch, l.viol, l.work.red, l.work.red + 4096, g->stream);
-    double c = 0;
-    HIPCHK(hipMemcpyAsync(&c, l.work.red + 4096, sizeof(double), hipMemcpyDeviceToHost, g->stream));
-    HIPCHK(hipStreamSynchronize(g->stream));
-    total += int64_t(c);
+    HIPCHK(hipMemcpyAsync(g->host_val + k++, l.work.red + 4096, sizeof(double), hipMemcpyDeviceToHost, g->stream));
   }
+  HIPCHK(hipStreamSynchronize(g->stream));
+  int64_t total = 0;
+  for (int q = 0; q < k; ++q) total += int64_t(g->host_val[q]);
   return total;
 }
 
@@ -1024,8 +1041,7 @@ int wt_diagnostics(wt_grid* g, wt_diag* d) {
       launch_diagnostics(l0.tab, l0.work, phys(g), g->stream, r0);
       d->mass = r0[0];
       nonfinite += r0[4];
-      d->max_abs_dh = masked_max_all(g, true);
-      d->max_abs_u = masked_max_all(g, false);
+      masked_max_all(g, &d->max_abs_dh, &d->max_abs_u);
     } else {
       d->mass = r[0];
       d->max_abs_dh = r[2];

@@ -451,16 +451,17 @@ __global__ __launch_bounds__(BS) void k_r2_edges(int64_t E, const int32_t* __res
 // lozenge sides find their neighbours by lattice index arithmetic (only mask bytes are read);
 // the others, and the poles, through the level's tables (a padded pentagon slot repeats an edge
 // of the cell, which changes nothing here).
-__global__ __launch_bounds__(BS) void k_ring_nodes(int64_t N, int n, const int32_t* __restrict__ c_e,
-                                                   const int32_t* __restrict__ e_c, const uint8_t* __restrict__ an,
-                                                   const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn) {
-  const int64_t id = TID;
-  if (id >= N) return;
-  const int64_t nn = int64_t(n) * n;
+// One ring of same-level neighbours of the (an, ae) points: threads [0, N) do the nodes, [N, N+E)
+// the edges.  Lattice-interior points use index arithmetic on the lozenge rows (n = 2^sh, ids fit
+// in 32 bits up to level 11); the rest go through the tables.
+__device__ __forceinline__ uint8_t ring_node(int32_t id, int sh, const int32_t* __restrict__ c_e,
+                                             const int32_t* __restrict__ e_c, const uint8_t* __restrict__ an,
+                                             const uint8_t* __restrict__ ae) {
+  const int n = 1 << sh, mk = n - 1;
   uint8_t m = an[id];
-  const int i = int((id / n) % n), j = int(id % n);
-  if (id < 10 * nn && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
-    const int64_t r = n;   // next row
+  const int i = (id >> sh) & mk, j = id & mk;
+  if ((id >> (2 * sh)) < 10 && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
+    const int32_t r = n;   // next row
     m |= an[id + r] | an[id + r + 1] | an[id + 1] | an[id - r] | an[id - r - 1] | an[id - 1];
     m |= ae[3 * id] | ae[3 * id + 1] | ae[3 * id + 2] | ae[3 * (id - r)] | ae[3 * (id - r - 1) + 1] |
          ae[3 * (id - 1) + 2];
@@ -470,21 +471,19 @@ __global__ __launch_bounds__(BS) void k_ring_nodes(int64_t N, int n, const int32
       m = ae[e] | an[e_c[2 * e]] | an[e_c[2 * e + 1]];
     }
   }
-  bn[id] = m ? 1 : 0;
+  return m;
 }
 
-__global__ __launch_bounds__(BS) void k_ring_edges(int64_t E, int n, const int32_t* __restrict__ e_c,
-                                                   const int32_t* __restrict__ e_v,
-                                                   const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
-                                                   const uint8_t* __restrict__ ae, uint8_t* __restrict__ be) {
-  const int64_t e = TID;
-  if (e >= E) return;
-  const int64_t id = e / 3;
-  const int d = int(e % 3);
-  const int i = int((id / n) % n), j = int(id % n);
+__device__ __forceinline__ uint8_t ring_edge(int32_t e, int sh, const int32_t* __restrict__ e_c,
+                                             const int32_t* __restrict__ e_v, const int32_t* __restrict__ t_e,
+                                             const uint8_t* __restrict__ an, const uint8_t* __restrict__ ae) {
+  const int n = 1 << sh, mk = n - 1;
+  const int32_t id = e / 3;
+  const int d = e - 3 * id;
+  const int i = (id >> sh) & mk, j = id & mk;
   uint8_t m;
   if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
-    const int64_t r = n;
+    const int32_t r = n;
     if (d == 0) {          // P -> P+(1,0): triangles (P, P+(1,0), P+(1,1)) and ((i,j-1), (i+1,j), P)
       m = an[id] | an[id + r] | ae[3 * id] | ae[3 * (id + r) + 2] | ae[3 * id + 1] | ae[3 * (id - 1) + 1] |
           ae[3 * (id - 1) + 2];
@@ -502,13 +501,29 @@ __global__ __launch_bounds__(BS) void k_ring_edges(int64_t E, int n, const int32
       m = ae[t_e[3 * t]] | ae[t_e[3 * t + 1]] | ae[t_e[3 * t + 2]];
     }
   }
-  be[e] = m ? 1 : 0;
+  return m;
+}
+
+__global__ __launch_bounds__(BS) void k_ring(int32_t N, int32_t E, int sh, const int32_t* __restrict__ c_e,
+                                             const int32_t* __restrict__ e_c, const int32_t* __restrict__ e_v,
+                                             const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
+                                             const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn,
+                                             uint8_t* __restrict__ be) {
+  const int32_t k = int32_t(blockIdx.x) * BS + int32_t(threadIdx.x);
+  if (k < N) {
+    bn[k] = ring_node(k, sh, c_e, e_c, an, ae) ? 1 : 0;
+  } else if (k - N < E) {
+    const int32_t e = k - N;
+    be[e] = ring_edge(e, sh, e_c, e_v, t_e, an, ae) ? 1 : 0;
+  }
 }
 
 void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
              hipStream_t s) {
-  k_ring_nodes<<<nb(t.N), BS, 0, s>>>(t.N, n, t.c_e, t.e_c, an, ae, bn);
-  k_ring_edges<<<nb(t.E), BS, 0, s>>>(t.E, n, t.e_c, t.e_v, t.t_e, an, ae, be);
+  if (n <= 0 || (n & (n - 1)) != 0) throw std::runtime_error("ml_ring: lozenge side must be a power of two");
+  if (t.N + t.E >= (int64_t(1) << 31)) throw std::runtime_error("ml_ring: level too large for 32-bit ids");
+  const int sh = __builtin_ctz(unsigned(n));
+  k_ring<<<nb(t.N + t.E), BS, 0, s>>>(int32_t(t.N), int32_t(t.E), sh, t.c_e, t.e_c, t.e_v, t.t_e, an, ae, bn, be);
   HIPCHK(hipGetLastError());
 }
 
@@ -748,6 +763,44 @@ void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scrat
   const int nblk = 512;
   k_masked_max<<<nblk, BS, 0, s>>>(n, v, act, scratch);
   k_max_final<<<1, BS, 0, s>>>(nblk, scratch, out);
+  HIPCHK(hipGetLastError());
+}
+
+// Several masked maxima in one launch: blockIdx.y picks the job, gridDim.x blocks share its range.
+__global__ __launch_bounds__(BS) void k_masked_max_b(MaxJobs J, double* __restrict__ part) {
+  __shared__ double sh[BS];
+  const MaxJob jb = J.j[blockIdx.y];
+  double m = 0.0;
+  for (int64_t i = TID; i < jb.n; i += int64_t(gridDim.x) * BS)
+    if (jb.act[i]) m = fmax(m, fabs(jb.v[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(BS) void k_max_final_b(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[BS];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += BS) m = fmax(m, part[int64_t(blockIdx.x) * nblk + i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = BS / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+void ml_masked_max_batch(const MaxJobs& jobs, int njobs, double* scratch, double* out, hipStream_t s) {
+  if (njobs <= 0) return;
+  if (njobs > MAX_JOBS) throw std::runtime_error("ml_masked_max_batch: too many jobs");
+  k_masked_max_b<<<dim3(MAX_BLOCKS, njobs), BS, 0, s>>>(jobs, scratch);
+  k_max_final_b<<<njobs, BS, 0, s>>>(MAX_BLOCKS, scratch, out);
   HIPCHK(hipGetLastError());
 }
 

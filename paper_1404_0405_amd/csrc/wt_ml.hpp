@@ -61,6 +61,18 @@ void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, co
                 const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
                 const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
                 hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
+// max |v[i]| over act[i] != 0 for up to MAX_JOBS arrays at once; scratch holds
+// MAX_JOBS * MAX_BLOCKS doubles, out[k] receives job k's maximum (0 when nothing is active)
+constexpr int MAX_JOBS = 32, MAX_BLOCKS = 128;
+struct MaxJob {
+  const double* v;
+  const uint8_t* act;
+  int64_t n;
+};
+struct MaxJobs {
+  MaxJob j[MAX_JOBS];
+};
+void ml_masked_max_batch(const MaxJobs& jobs, int njobs, double* scratch, double* out, hipStream_t s);
 void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
                    hipStream_t s);
 void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipStream_t s);
