@@ -57,6 +57,8 @@ struct LevelState {
   // stage intermediates are computed; 5 rings: where inactive points are prolonged)
   uint8_t *s3n = nullptr, *s3e = nullptr, *s5n = nullptr, *s5e = nullptr, *rn_ = nullptr, *re_ = nullptr;
   uint8_t *pred_t = nullptr, *pred_e = nullptr, *pred_a = nullptr;   // triangles, support / active elements
+  uint8_t* pf = nullptr;        // 8 x 8 patch flags of the ring dilation
+  int32_t* plist = nullptr;     // patches the ring dilation visits (count after the list)
   WorkList l_tri, l_elem, l_edge, l_node, l_tend;
 };
 
@@ -130,7 +132,7 @@ static void free_work(LevelState& ls) {
                 ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
                 ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
                 ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.rn_, ls.re_, ls.pred_t,
-                ls.pred_e, ls.pred_a};
+                ls.pred_e, ls.pred_a, ls.pf, ls.plist};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   w = DevWork{};
@@ -313,13 +315,27 @@ static void build_work_lists(wt_grid* g) {
       HIPCHK(hipMalloc(&l.pred_e, N));
       HIPCHK(hipMalloc(&l.pred_a, N));
     }
-    // rings of same-level neighbours: 1, 2 (scratch), 3 (kept), 4, 5 (kept)
+    // rings of same-level neighbours: 1, 2 (scratch), 3 (kept), 4, 5 (kept); patches far from
+    // every active point skip the gathers
     const int nl = 1 << l.geo.J;
-    ml_ring(l.tab, nl, l.na, l.ea, l.rn_, l.re_, s);
-    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s);
-    ml_ring(l.tab, nl, l.s5n, l.s5e, l.s3n, l.s3e, s);
-    ml_ring(l.tab, nl, l.s3n, l.s3e, l.rn_, l.re_, s);
-    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s);
+    const int32_t* pl = nullptr;
+    if (nl >= 8) {
+      const int64_t np = 10 * int64_t(nl / 8) * (nl / 8);
+      if (!l.pf) {
+        HIPCHK(hipMalloc(&l.pf, np));
+        HIPCHK(hipMalloc(&l.plist, (np + 1) * sizeof(int32_t)));
+      }
+      ml_patch_list(nl, l.na, l.ea, l.pf, l.plist, s);
+      pl = l.plist;
+      const ByteJob clr[] = {{l.rn_, nullptr, N, 0}, {l.re_, nullptr, E, 0}, {l.s5n, nullptr, N, 0},
+                             {l.s5e, nullptr, E, 0}, {l.s3n, nullptr, N, 0}, {l.s3e, nullptr, E, 0}};
+      ml_bytes_batch(clr, 6, s);
+    }
+    ml_ring(l.tab, nl, l.na, l.ea, l.rn_, l.re_, s, pl);
+    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s, pl);
+    ml_ring(l.tab, nl, l.s5n, l.s5e, l.s3n, l.s3e, s, pl);
+    ml_ring(l.tab, nl, l.s3n, l.s3e, l.rn_, l.re_, s, pl);
+    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s, pl);
     pred_tri(T, l.tab.t_e, l.s3e, l.pred_t, s);
     pred_elem(N, l.tab.n_elem, l.s3n, l.s3e, l.pred_e, s);
     pred_elem(N, l.tab.n_elem, l.na, l.ea, l.pred_a, s);
@@ -483,6 +499,15 @@ static void snapshot(wt_grid* g, bool restore) {
   }
 }
 
+static void clear_significant(wt_grid* g) {
+  std::vector<ByteJob> clr;
+  for (auto& l : g->lev) {
+    clr.push_back({l->sn, nullptr, l->tab.N, 0});
+    clr.push_back({l->se, nullptr, l->tab.E, 0});
+  }
+  ml_bytes_batch(clr.data(), int(clr.size()), g->stream);
+}
+
 static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, bool gate = false) {
   // The threshold test reads the details of active points only, whose prolongation and
   // prediction stencils lie in the work-list support; the learned gate's patch features read
@@ -493,10 +518,7 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
   double mh, mu;
   masked_max_all(g, &mh, &mu);
   const double eh = eps * mh, eu = eps * mu;
-  for (auto& l : g->lev) {
-    HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
-    HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
-  }
+  clear_significant(g);
   // R1: significant points
   const bool listed = !gate && g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
@@ -505,9 +527,13 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
                    listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
   }
-  for (auto& l : g->lev) {
-    HIPCHK(hipMemcpyAsync(l->nn, l->sn, l->tab.N, hipMemcpyDeviceToDevice, g->stream));
-    HIPCHK(hipMemcpyAsync(l->ne, l->se, l->tab.E, hipMemcpyDeviceToDevice, g->stream));
+  {
+    std::vector<ByteJob> cp;
+    for (auto& l : g->lev) {
+      cp.push_back({l->nn, l->sn, l->tab.N, 0});
+      cp.push_back({l->ne, l->se, l->tab.E, 0});
+    }
+    ml_bytes_batch(cp.data(), int(cp.size()), g->stream);
   }
   g->last_eh = eh;
   g->last_eu = eu;
@@ -533,8 +559,8 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     }
   }
   LevelState& L0 = g->L(g->jmin);
-  HIPCHK(hipMemsetAsync(L0.nn, 1, L0.tab.N, g->stream));
-  HIPCHK(hipMemsetAsync(L0.ne, 1, L0.tab.E, g->stream));
+  const ByteJob all0[] = {{L0.nn, nullptr, L0.tab.N, 1}, {L0.ne, nullptr, L0.tab.E, 1}};
+  ml_bytes_batch(all0, 2, g->stream);
   // R4 consistency and R5 prediction stencils, top-down
   for (int j = g->jmax; j >= g->jmin; --j) {
     LevelState& l = g->L(j);
@@ -568,10 +594,7 @@ static int64_t judge_gated_step(wt_grid* g) {
   double mh, mu;
   masked_max_all(g, &mh, &mu);
   const double eh = g->last_eps * mh, eu = g->last_eps * mu;
-  for (auto& l : g->lev) {
-    HIPCHK(hipMemsetAsync(l->sn, 0, l->tab.N, g->stream));
-    HIPCHK(hipMemsetAsync(l->se, 0, l->tab.E, g->stream));
-  }
+  clear_significant(g);
   const bool L = g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);

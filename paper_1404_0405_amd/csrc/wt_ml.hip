@@ -504,26 +504,118 @@ __device__ __forceinline__ uint8_t ring_edge(int32_t e, int sh, const int32_t* _
   return m;
 }
 
-__global__ __launch_bounds__(BS) void k_ring(int32_t N, int32_t E, int sh, const int32_t* __restrict__ c_e,
+// Ring over the listed 8 x 8 node patches: one block per patch (threads 0..63 the nodes, 64..255
+// their 192 edges), blocks striding over the device-side list; block 0 also does the poles.  The
+// points of unlisted patches are not written (the caller cleared them).
+__global__ __launch_bounds__(BS) void k_ring(int32_t N, int sh, const int32_t* __restrict__ plist,
+                                             const int32_t* __restrict__ pcount, const int32_t* __restrict__ c_e,
                                              const int32_t* __restrict__ e_c, const int32_t* __restrict__ e_v,
                                              const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
                                              const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn,
                                              uint8_t* __restrict__ be) {
-  const int32_t k = int32_t(blockIdx.x) * BS + int32_t(threadIdx.x);
-  if (k < N) {
-    bn[k] = ring_node(k, sh, c_e, e_c, an, ae) ? 1 : 0;
-  } else if (k - N < E) {
-    const int32_t e = k - N;
-    be[e] = ring_edge(e, sh, e_c, e_v, t_e, an, ae) ? 1 : 0;
+  static_assert(BS == 256, "one block covers the 64 nodes and 192 edges of a patch");
+  const int ps = sh - 3, m = 1 << ps;
+  const int tid = threadIdx.x;
+  const int32_t cnt = *pcount;
+  for (int32_t b = blockIdx.x; b < cnt; b += gridDim.x) {
+    const int32_t p = plist[b];
+    const int32_t L = p >> (2 * ps);
+    const int pi = (p >> ps) & (m - 1), pj = p & (m - 1);
+    if (tid < 64) {
+      const int32_t id = (((L << sh) + 8 * pi + (tid >> 3)) << sh) + 8 * pj + (tid & 7);
+      bn[id] = ring_node(id, sh, c_e, e_c, an, ae) ? 1 : 0;
+    } else {
+      const int q = (tid - 64) / 3, d = (tid - 64) - 3 * q;
+      const int32_t id = (((L << sh) + 8 * pi + (q >> 3)) << sh) + 8 * pj + (q & 7);
+      const int32_t e = 3 * id + d;
+      be[e] = ring_edge(e, sh, e_c, e_v, t_e, an, ae) ? 1 : 0;
+    }
   }
+  const int32_t pole = (10 << (2 * sh)) + tid;
+  if (blockIdx.x == 0 && pole < N) bn[pole] = ring_node(pole, sh, c_e, e_c, an, ae) ? 1 : 0;
+}
+
+// Levels with lozenge side below 8: one thread per node, then one per edge.
+__global__ __launch_bounds__(BS) void k_ring_small(int32_t N, int32_t E, int sh, const int32_t* __restrict__ c_e,
+                                                   const int32_t* __restrict__ e_c, const int32_t* __restrict__ e_v,
+                                                   const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
+                                                   const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn,
+                                                   uint8_t* __restrict__ be) {
+  const int32_t k = int32_t(blockIdx.x) * BS + int32_t(threadIdx.x);
+  if (k < N) bn[k] = ring_node(k, sh, c_e, e_c, an, ae) ? 1 : 0;
+  else if (k - N < E) be[k - N] = ring_edge(k - N, sh, e_c, e_v, t_e, an, ae) ? 1 : 0;
 }
 
 void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
-             hipStream_t s) {
+             hipStream_t s, const int32_t* plist) {
   if (n <= 0 || (n & (n - 1)) != 0) throw std::runtime_error("ml_ring: lozenge side must be a power of two");
   if (t.N + t.E >= (int64_t(1) << 31)) throw std::runtime_error("ml_ring: level too large for 32-bit ids");
+  const int64_t lat = int64_t(10) * n * n;
+  if (t.E != 3 * lat || t.N < lat || t.N - lat > BS)
+    throw std::runtime_error("ml_ring: tables do not match the lattice size");
   const int sh = __builtin_ctz(unsigned(n));
-  k_ring<<<nb(t.N + t.E), BS, 0, s>>>(int32_t(t.N), int32_t(t.E), sh, t.c_e, t.e_c, t.e_v, t.t_e, an, ae, bn, be);
+  if (!plist) {
+    k_ring_small<<<nb(t.N + t.E), BS, 0, s>>>(int32_t(t.N), int32_t(t.E), sh, t.c_e, t.e_c, t.e_v, t.t_e, an, ae,
+                                              bn, be);
+  } else {
+    if (n < 8) throw std::runtime_error("ml_ring: a patch list needs a lozenge side of at least 8");
+    const int64_t np = lat / 64;
+    const unsigned grid = unsigned(np < 1024 ? np : 1024);
+    k_ring<<<grid, BS, 0, s>>>(int32_t(t.N), sh, plist, plist + np, t.c_e, t.e_c, t.e_v, t.t_e, an, ae, bn, be);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// Patch list for the ring dilation: pf[p] = the 8 x 8 node patch p (patch (L, pi, pj) ->
+// (L m + pi) m + pj, m = n / 8) holds an active node or an active edge of its nodes; p is listed
+// when some patch of its 3 x 3 neighbourhood in the lozenge is flagged, or p touches the lozenge
+// border.  A node of an unlisted patch is more than 7 lattice steps from every active point (a
+// path from another lozenge crosses the border, 8 steps away), so up to 7 rings leave it and its
+// edges inactive.  The list order is the order of the appends (the ring does not depend on it).
+// One thread per row of a patch (t = ((L m + pi) m + pj) 8 + r): the 8 mask bytes of its nodes and
+// the 24 of their edges; the 8 lanes of a patch are combined by a wavefront ballot.
+__global__ __launch_bounds__(BS) void k_patch_any(int sh, const uint8_t* __restrict__ an,
+                                                  const uint8_t* __restrict__ ae, uint8_t* __restrict__ pf,
+                                                  int32_t* __restrict__ pcount) {
+  const int ps = sh - 3;
+  const int64_t t = TID;
+  if (t == 0) *pcount = 0;
+  const bool valid = t < (int64_t(10) << (2 * sh - 3));
+  bool any = false;
+  if (valid) {
+    const int64_t p = t >> 3;
+    const int m = 1 << ps, r = int(t & 7);
+    const int64_t L = p >> (2 * ps);
+    const int pi = int((p >> ps) & (m - 1)), pj = int(p & (m - 1));
+    const int64_t id0 = ((L << sh) + 8 * pi + r) * (int64_t(1) << sh) + 8 * pj;
+    const uint64_t a = *reinterpret_cast<const uint64_t*>(an + id0);
+    const uint64_t* ew = reinterpret_cast<const uint64_t*>(ae + 3 * id0);
+    any = (a | ew[0] | ew[1] | ew[2]) != 0;
+  }
+  const uint64_t bal = __ballot(any);
+  const int lane = threadIdx.x & 63;
+  if (valid && (lane & 7) == 0) pf[t >> 3] = ((bal >> lane) & 0xffu) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(BS) void k_patch_list(int ps, const uint8_t* __restrict__ pf,
+                                                   int32_t* __restrict__ plist, int32_t* __restrict__ pcount) {
+  const int m = 1 << ps;
+  const int64_t p = TID;
+  if (p >= int64_t(10) << (2 * ps)) return;
+  const int64_t L = p >> (2 * ps);
+  const int pi = int((p >> ps) & (m - 1)), pj = int(p & (m - 1));
+  uint8_t v = (pi == 0 || pj == 0 || pi == m - 1 || pj == m - 1) ? 1 : 0;
+  for (int di = -1; di <= 1 && !v; ++di)
+    for (int dj = -1; dj <= 1 && !v; ++dj) v = pf[((L << ps) + pi + di) * m + pj + dj];
+  if (v) plist[atomicAdd(pcount, 1)] = int32_t(p);
+}
+
+void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int32_t* plist, hipStream_t s) {
+  if (n < 8 || (n & (n - 1)) != 0) throw std::runtime_error("ml_patch_list: lozenge side must be 2^k >= 8");
+  const int sh = __builtin_ctz(unsigned(n)), ps = sh - 3;
+  const int64_t np = int64_t(10) << (2 * ps);
+  k_patch_any<<<nb(np * 8), BS, 0, s>>>(sh, an, ae, pf, plist + np);
+  k_patch_list<<<nb(np), BS, 0, s>>>(ps, pf, plist, plist + np);
   HIPCHK(hipGetLastError());
 }
 
@@ -802,6 +894,34 @@ void ml_masked_max_batch(const MaxJobs& jobs, int njobs, double* scratch, double
   k_masked_max_b<<<dim3(MAX_BLOCKS, njobs), BS, 0, s>>>(jobs, scratch);
   k_max_final_b<<<njobs, BS, 0, s>>>(MAX_BLOCKS, scratch, out);
   HIPCHK(hipGetLastError());
+}
+
+// Byte fills and copies of up to MAX_JOBS buffers in one launch (blockIdx.y = job); 16-byte
+// vector stores over the aligned body, bytes over the tail.
+__global__ __launch_bounds__(BS) void k_bytes_b(ByteJobs J) {
+  const ByteJob jb = J.j[blockIdx.y];
+  const int64_t n16 = jb.n >> 4, stride = int64_t(gridDim.x) * BS;
+  const uint32_t w = 0x01010101u * uint32_t(jb.val & 0xff);
+  for (int64_t i = TID; i < n16; i += stride) {
+    const uint4 v = jb.src ? reinterpret_cast<const uint4*>(jb.src)[i] : make_uint4(w, w, w, w);
+    reinterpret_cast<uint4*>(jb.dst)[i] = v;
+  }
+  for (int64_t i = (n16 << 4) + TID; i < jb.n; i += stride) jb.dst[i] = jb.src ? jb.src[i] : uint8_t(jb.val);
+}
+
+void ml_bytes_batch(const ByteJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_JOBS) {
+    ByteJobs J{};
+    const int nk = njobs - k0 < MAX_JOBS ? njobs - k0 : MAX_JOBS;
+    for (int k = 0; k < nk; ++k) {
+      const ByteJob& jb = jobs[k0 + k];
+      if ((reinterpret_cast<uintptr_t>(jb.dst) | reinterpret_cast<uintptr_t>(jb.src)) & 15)
+        throw std::runtime_error("ml_bytes_batch: buffers must be 16-byte aligned");
+      J.j[k] = jb;
+    }
+    k_bytes_b<<<dim3(256, nk), BS, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
 }
 
 // ------------------------------------------------------------------ active counts

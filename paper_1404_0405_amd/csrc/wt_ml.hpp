@@ -48,9 +48,15 @@ void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, co
                     hipStream_t s, Span le = {}, Span lt = {});
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
 // (bn, be) = (an, ae) grown by one ring of same-level neighbours (the R2 relation, gather form)
-// (n = lattice size 2^level)
+// (n = lattice size 2^level).  With plist (from ml_patch_list of the set the ring chain starts
+// from, at most 7 rings ago) only the listed patches and the poles are written: the caller clears
+// (bn, be) once before the chain.
 void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
-             hipStream_t s);
+             hipStream_t s, const int32_t* plist = nullptr);
+// 8 x 8 node patches within one patch of an active point of (an, ae) or on a lozenge border:
+// plist[0..count) with count = plist[np], np = 10 (n/8)^2 (plist holds np + 1 ints, pf np
+// bytes of scratch; n >= 8)
+void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int32_t* plist, hipStream_t s);
 // allow (optional): learned gate per quadrant of the 8 x 8 patches of the coarse level (lattice size nc)
 void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
            uint8_t* nef, hipStream_t s, const uint8_t* allow = nullptr, int nc = 0);
@@ -73,6 +79,18 @@ struct MaxJobs {
   MaxJob j[MAX_JOBS];
 };
 void ml_masked_max_batch(const MaxJobs& jobs, int njobs, double* scratch, double* out, hipStream_t s);
+// dst[0..n) = src[0..n) (src non-null) or the byte val, for any number of 16-byte aligned
+// buffers, MAX_JOBS per launch
+struct ByteJob {
+  uint8_t* dst;
+  const uint8_t* src;
+  int64_t n;
+  int val;
+};
+struct ByteJobs {
+  ByteJob j[MAX_JOBS];
+};
+void ml_bytes_batch(const ByteJob* jobs, int njobs, hipStream_t s);
 void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
                    hipStream_t s);
 void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipStream_t s);

@@ -191,7 +191,8 @@ def test_tc2_adaptive_levels_4_to_6(precision):
 
 
 @pytest.mark.parametrize("case,jmin,jmax,eps,prec", [("jet", 4, 7, 5e-3, "fp64"), ("tc2p", 3, 6, 1e-3, "fp64"),
-                                                     ("jet", 5, 8, 5e-3, "fp32")])
+                                                     ("jet", 5, 8, 5e-3, "fp32"), ("tc2p", 2, 5, 1e-3, "fp64"),
+                                                     ("jet", 5, 9, 5e-3, "fp64")])
 def test_work_lists_equal_whole_levels(case, jmin, jmax, eps, prec):
     """The adaptive stage over ballot/prefix-scan work lists (support rings of the active
     points) gives bitwise the same states, masks and diagnostics as the stage over whole
