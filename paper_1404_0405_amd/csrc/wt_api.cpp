@@ -87,7 +87,8 @@ struct wt_grid {
   bool use_lists = true;      // adaptive stage over work lists (false: whole levels)
   bool lists_ok = false;      // the lists match the current masks
   bool details_partial = false;   // the stored details cover only the work-list support
-  uint64_t epoch = 0;         // bumped whenever the work lists (and so the launches of a step) change
+  uint64_t epoch = 0;         // bumped whenever the launches of a step change (see touch_epoch)
+  std::vector<int64_t> step_sig;   // what the launches of a step depend on, as of the last bump
   CompactScratch csc;
   CompactBatch cb;
   // batched read-backs of per-level maxima (pinned)
@@ -200,7 +201,8 @@ static void uniform_step(wt_grid* g, LevelState& ls, double dt) {
 
 // ---------------------------------------------------------------- multilevel operations
 // Fill inactive points of every level above jmin from the level below (top-down).
-static Span span(const WorkList& L) { return Span{L.idx, L.n}; }
+// launches over a work list cover its padded bound (padding entries are -1)
+static Span span(const WorkList& L) { return Span{L.idx, L.bound}; }
 
 // listed: only the work-list support of the current masks (the rest keeps stale values)
 static void prolong_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
@@ -293,12 +295,44 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
 
 // ---------------------------------------------------------------- work lists
 
+// The launches of a multilevel step depend on whether the work lists are used, on the lists'
+// addresses and padded bounds, and on the mask addresses; a captured step stays valid while
+// none of these change.
+static void touch_epoch(wt_grid* g) {
+  std::vector<int64_t> sig;
+  sig.push_back(g->use_lists && g->lists_ok);
+  auto add = [&](const WorkList& L) {
+    sig.push_back(reinterpret_cast<int64_t>(L.idx));
+    sig.push_back(L.bound);
+  };
+  for (auto& l : g->lev) {
+    sig.push_back(reinterpret_cast<int64_t>(l->na));
+    sig.push_back(reinterpret_cast<int64_t>(l->ea));
+    add(l->l_tri);
+    add(l->l_elem);
+    add(l->l_edge);
+    add(l->l_node);
+    add(l->l_tend);
+  }
+  for (auto& p : g->pairs) {
+    add(p->l_cn);
+    add(p->l_ce);
+    add(p->l_ct);
+  }
+  if (sig != g->step_sig) {
+    g->step_sig.swap(sig);
+    ++g->epoch;
+  }
+}
+
 // Support rings of the active points of every level and the index lists of the adaptive stage
 // (ballot / prefix-scan compaction).  Called whenever the masks change.
-static void build_work_lists(wt_grid* g) {
+static void build_work_lists(wt_grid* g, bool touch = true) {
   g->lists_ok = false;
-  ++g->epoch;
-  if (!g->multi() || !g->use_lists) return;
+  if (!g->multi() || !g->use_lists) {
+    if (touch) touch_epoch(g);
+    return;
+  }
   hipStream_t s = g->stream;
   CompactBatch& cb = g->cb;
   for (auto& lp : g->lev) {
@@ -358,7 +392,7 @@ static void build_work_lists(wt_grid* g) {
   }
   cb.run(s);
   g->lists_ok = true;
-  ++g->epoch;
+  if (touch) touch_epoch(g);
 }
 
 static void ml_step(wt_grid* g, double dt) {
@@ -472,7 +506,9 @@ static void learn_stats_all(wt_grid* g, double eh, double eu) {
 static float level_pos(const wt_grid* g, int j) { return float(j - g->jmin) / float(g->jmax - g->jmin); }
 
 static void snapshot(wt_grid* g, bool restore) {
-  if (restore) g->lists_ok = false;   // the work lists describe the masks being discarded
+  // the work lists describe the masks being discarded; the adapt that follows a restore builds
+  // them again (and bumps the epoch if the launches change)
+  if (restore) g->lists_ok = false;
   for (auto& lp : g->lev) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E;
@@ -576,8 +612,23 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
   }
   // the new masks' work lists first: the inverse then rewrites only the support (the old masks
   // stay in nn/ne for it)
-  build_work_lists(g);
+  build_work_lists(g, false);
   inverse_all(g, dh, u, true, true, true);
+  // the new masks go back into the buffers that held the old ones, so the mask addresses a
+  // recorded step uses stay the same from one adapt to the next
+  {
+    std::vector<ByteJob> cp;
+    for (auto& l : g->lev) {
+      cp.push_back({l->nn, l->na, l->tab.N, 0});
+      cp.push_back({l->ne, l->ea, l->tab.E, 0});
+    }
+    ml_bytes_batch(cp.data(), int(cp.size()), g->stream);
+    for (auto& l : g->lev) {
+      std::swap(l->na, l->nn);
+      std::swap(l->ea, l->ne);
+    }
+  }
+  touch_epoch(g);
   if (eh_out) *eh_out = eh;
   if (eu_out) *eu_out = eu;
 }

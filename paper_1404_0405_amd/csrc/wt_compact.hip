@@ -121,6 +121,7 @@ void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hi
   }
   if (n == 0) {
     L.n = 0;
+    L.bound = 0;
     if (total_dev) HIPCHK(hipMemsetAsync(total_dev, 0, sizeof(int64_t), s));
     return;
   }
@@ -138,6 +139,7 @@ void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hi
   HIPCHK(hipMemcpyAsync(&total, sc.off + nchunk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   L.n = total;
+  L.bound = total;
 }
 
 // ------------------------------------------------------------------ batched compaction
@@ -231,6 +233,32 @@ __global__ __launch_bounds__(CB) void k_scatter_b(const CJob* __restrict__ jobs,
   }
 }
 
+// -1 over idx[from, to) of up to PAD_JOBS lists (blockIdx.y = list)
+constexpr int PAD_JOBS = 64;
+struct PadJob {
+  int32_t* idx;
+  int64_t from, to;
+};
+struct PadJobs {
+  PadJob j[PAD_JOBS];
+};
+__global__ __launch_bounds__(CB) void k_pad_b(PadJobs J) {
+  const PadJob jb = J.j[blockIdx.y];
+  for (int64_t i = jb.from + int64_t(blockIdx.x) * CB + threadIdx.x; i < jb.to; i += int64_t(gridDim.x) * CB)
+    jb.idx[i] = -1;
+}
+
+// The padded bound of a list of n entries: kept while n <= bound <= 8 max(n, 256); otherwise the
+// power of two at or above 2 max(n, 256) (capped by cap), so small drifts of n between adapts do
+// not change the launches.
+static int64_t list_bound(int64_t prev, int64_t n, int64_t cap) {
+  const int64_t m = n > 256 ? n : 256;
+  if (prev >= n && prev <= cap && prev <= 8 * m) return prev;
+  int64_t b = 256;
+  while (b < 2 * m) b <<= 1;
+  return b < cap ? b : cap;
+}
+
 void CompactBatch::add(const uint8_t* pred, int64_t n, WorkList& L) {
   if (!L.idx || L.cap < n) {
     // the list may still be read by queued work: let it drain before freeing
@@ -276,7 +304,20 @@ void CompactBatch::run(hipStream_t s) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(h_tot, d_tot, njob * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  for (int k = 0; k < njob; ++k) jobs[k].list->n = h_tot[k];
+  std::vector<PadJob> pads;
+  for (int k = 0; k < njob; ++k) {
+    WorkList& L = *jobs[k].list;
+    L.n = h_tot[k];
+    L.bound = list_bound(L.bound, L.n, L.cap);
+    if (L.bound > L.n) pads.push_back(PadJob{L.idx, L.n, L.bound});
+  }
+  for (size_t k0 = 0; k0 < pads.size(); k0 += PAD_JOBS) {
+    PadJobs J{};
+    const size_t nk = std::min<size_t>(PAD_JOBS, pads.size() - k0);
+    for (size_t k = 0; k < nk; ++k) J.j[k] = pads[k0 + k];
+    k_pad_b<<<dim3(8, unsigned(nk)), CB, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
   jobs.clear();
 }
 

@@ -9,9 +9,12 @@
 
 namespace wt {
 
+// idx[0..n) the listed indices in increasing order, idx[n..bound) = -1: launches cover `bound`
+// entries (a power of two with room to grow, kept while the count stays within it), so a launch
+// sequence recorded for one list stays valid while later lists of the same predicate fit.
 struct WorkList {
-  int32_t* idx = nullptr;   // device, increasing indices
-  int64_t n = 0, cap = 0;
+  int32_t* idx = nullptr;   // device
+  int64_t n = 0, cap = 0, bound = 0;
 };
 
 struct CompactScratch {
@@ -43,7 +46,7 @@ struct CompactBatch {
   int64_t chunk_cap = 0;
 
   void add(const uint8_t* pred, int64_t n, WorkList& L);   // sizes L for n indices
-  void run(hipStream_t s);                                  // compacts every job, sets the counts
+  void run(hipStream_t s);   // compacts every job, sets the counts and bounds, pads with -1
   void release();
 };
 void free_scratch(CompactScratch& sc);

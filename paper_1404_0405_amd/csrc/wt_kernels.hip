@@ -42,7 +42,10 @@ __global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __r
                                                T* __restrict__ qv) {
   int64_t t = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (t >= n_tri) return;
-  if (list) t = list[t];
+  if (list) {
+    t = list[t];
+    if (t < 0) return;   // padding of a work list
+  }
   T z = T(0), hv = T(0);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -66,7 +69,10 @@ __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
                                                   T* __restrict__ qe) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
-  if (list) id = list[id];
+  if (list) {
+    id = list[id];
+    if (id < 0) return;   // padding of a work list
+  }
   T K = T(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -116,7 +122,10 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
                                              StageOut c) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
-  if (list) id = list[id];
+  if (list) {
+    id = list[id];
+    if (id < 0) return;   // padding of a work list
+  }
   double div = 0.0;  // divergence sums stay in double in both precisions
 #pragma unroll
   for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * F[c_e[6 * id + k]];

@@ -21,11 +21,15 @@ namespace wt {
 constexpr int BS = 256;
 static inline unsigned nb(int64_t n) { return unsigned((n + BS - 1) / BS); }
 #define TID (int64_t(blockIdx.x) * BS + threadIdx.x)
-// thread index into an optional work list: the i-th listed index, or i itself
+// thread index into an optional work list: the i-th listed index (padding entries are -1), or
+// i itself
 #define LISTED(var, count, lst)            \
   int64_t var = TID;                       \
   if (var >= (count)) return;              \
-  if (lst) var = (lst)[var];
+  if (lst) {                               \
+    var = (lst)[var];                      \
+    if (var < 0) return;                   \
+  }
 static inline int64_t span_n(const Span& sp, int64_t dense) { return sp.idx ? sp.n : dense; }
 
 // ------------------------------------------------------------------ shared device helpers
