@@ -81,8 +81,12 @@ typedef struct {
 /* Create a grid with levels jmin..jmax (0 <= jmin <= jmax <= 12) and adaptivity patch size
  * patch in {4, 8, 16} (Sec. 5.2: patches are the smallest unit of the adapted structure;
  * results do not depend on it).  Builds the geometry of every level on the host (Sec. 4.1)
- * and uploads it; selects HIP device 0 unless one is current.  Returns NULL on error. */
+ * and uploads it; selects HIP device 0 unless one is current.  Returns NULL on error.
+ * The geometry-only host tables of each level and level pair (those not depending on the
+ * effective areas, Sec. 4.2) are kept in a process-wide cache and shared by later grids. */
 wt_grid* wt_grid_create(int jmin, int jmax, int patch);
+/* Frees the host table cache of wt_grid_create (existing grids are not affected). */
+void wt_table_cache_clear(void);
 
 /* Frees all host and device memory of the grid.  NULL is accepted. */
 void wt_grid_destroy(wt_grid* g);

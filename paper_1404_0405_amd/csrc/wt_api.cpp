@@ -5,9 +5,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/wt.h"
@@ -670,9 +673,50 @@ static int64_t judge_gated_step(wt_grid* g) {
   return total;
 }
 
+// Host tables are expensive to build (seconds at level 9) and depend only on the level (pairs:
+// on the coarse level) and the sphere's radius and rotation rate: grids built in one process share
+// the geometry-only parts through this cache; effective areas are applied per grid.
+namespace {
+std::mutex g_cache_mu;
+std::map<std::tuple<int, double, double>, std::shared_ptr<const Level>> g_level_cache;
+std::map<std::tuple<int, double, double>, std::shared_ptr<const PairTables>> g_pair_cache;
+}  // namespace
+
+static std::shared_ptr<const Level> cached_level(int j, double radius, double omega) {
+  const auto key = std::make_tuple(j, radius, omega);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_level_cache.find(key);
+    if (it != g_level_cache.end()) return it->second;
+  }
+  auto L = std::make_shared<Level>();
+  build_level(j, radius, omega, *L);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return g_level_cache.emplace(key, std::move(L)).first->second;
+}
+
+static std::shared_ptr<const PairTables> cached_pair(const Level& C, const Level& F) {
+  const auto key = std::make_tuple(C.J, C.radius, C.omega);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_pair_cache.find(key);
+    if (it != g_pair_cache.end()) return it->second;
+  }
+  auto P = std::make_shared<PairTables>();
+  build_pair(C, F, *P);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return g_pair_cache.emplace(key, std::move(P)).first->second;
+}
+
 extern "C" {
 
 const char* wt_last_error(void) { return g_err.c_str(); }
+
+void wt_table_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_level_cache.clear();
+  g_pair_cache.clear();
+}
 
 const char* wt_kernel_names(void) { return "trisk_vertex,trisk_edge_cell,trisk_tend,trisk_lattice"; }
 
@@ -713,31 +757,39 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
     g->prm.precision = WT_FP64;
     HIPCHK(hipStreamCreate(&g->own));
     g->stream = g->own;
-    for (int j = jmin; j <= jmax; ++j) {
-      auto ls = std::make_unique<LevelState>();
-      build_level(j, g->prm.radius, g->prm.omega, ls->geo);
-      g->lev.push_back(std::move(ls));
-    }
+    std::vector<std::shared_ptr<const Level>> raw;
+    for (int j = jmin; j <= jmax; ++j) raw.push_back(cached_level(j, g->prm.radius, g->prm.omega));
     for (int j = jmin; j < jmax; ++j) {
       auto ps = std::make_unique<PairState>();
-      build_pair(g->L(j).geo, g->L(j + 1).geo, ps->host);
+      ps->host = *cached_pair(*raw[j - jmin], *raw[j + 1 - jmin]);
       g->pairs.push_back(std::move(ps));
     }
     // effective areas, bottom-up from the geometric areas of jmax (area conditions, Sec. 4.2)
-    std::vector<double> A = g->L(jmax).geo.A_i, Ac;
-    for (int j = jmax - 1; j >= jmin; --j) {
-      finish_pair(g->L(j).geo, g->L(j + 1).geo, A, g->P(j).host, Ac);
-      g->L(j).geo.A_i = Ac;
-      A = Ac;
-    }
-    for (auto& ls : g->lev) {
-      upload_tables(ls->geo, ls->tab);
-      alloc_work(*ls);
+    const int nl = jmax - jmin + 1;
+    std::vector<std::vector<double>> Aeff(nl);
+    Aeff[nl - 1] = raw[nl - 1]->A_i;
+    for (int j = jmax - 1; j >= jmin; --j)
+      finish_pair(*raw[j - jmin], *raw[j + 1 - jmin], Aeff[j + 1 - jmin], g->P(j).host, Aeff[j - jmin]);
+    for (int q = 0; q < nl; ++q) {
+      const Level& R = *raw[q];
+      auto ls = std::make_unique<LevelState>();
+      upload_tables(R, Aeff[q], ls->tab);
+      // the host keeps what coordinates, counts and diagnostics read
+      Level& L = ls->geo;
+      L.J = R.J;
+      L.n = R.n; L.N = R.N; L.E = R.E; L.T = R.T;
+      L.radius = R.radius; L.omega = R.omega;
+      L.pos = R.pos;
+      L.e_c = R.e_c;
+      L.A_i = std::move(Aeff[q]);
+      g->lev.push_back(std::move(ls));
+      alloc_work(*g->lev.back());
     }
     if (!g->multi()) {
       LatticeHost lh;
-      if (build_lattice(g->L(jmax).geo, lh)) upload_lattice(lh, g->L(jmax).lat);
+      if (build_lattice(*raw[nl - 1], lh)) upload_lattice(lh, g->L(jmax).lat);
     }
+    raw.clear();
     for (auto& ps : g->pairs) {
       upload_pair(ps->host, ps->dev);
       auto A2 = [](double** q, int64_t n) { HIPCHK(hipMalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };

@@ -73,7 +73,8 @@ struct Timer {
   std::vector<Rec> recs;
 };
 
-void upload_tables(const Level& L, DevTables& t);
+// device tables of level L with cell areas A_i (the effective areas below jmax)
+void upload_tables(const Level& L, const std::vector<double>& A_i, DevTables& t);
 void free_tables(DevTables& t);
 
 struct DevLattice;

@@ -376,7 +376,8 @@ static X* dev_upload(const std::vector<X>& v) {
   return p;
 }
 
-void upload_tables(const Level& L, DevTables& t) {
+void upload_tables(const Level& L, const std::vector<double>& A_i, DevTables& t) {
+  if (int64_t(A_i.size()) != L.N) throw std::runtime_error("upload_tables: cell areas do not match the level");
   const int64_t N = L.N, E = L.E, T = L.T;
   t.N = N; t.E = E; t.T = T; t.n_elem = 10 * L.n * L.n;
   std::vector<int32_t> c_e(6 * N);
@@ -386,8 +387,8 @@ void upload_tables(const Level& L, DevTables& t) {
       bool ok = k < L.c_deg[i];
       int32_t e = L.c_e[6 * i + (ok ? k : 0)];
       c_e[6 * i + k] = e;
-      c_div[6 * i + k] = ok ? L.c_s[6 * i + k] * L.l_e[e] / L.A_i[i] : 0.0;
-      c_ke[6 * i + k] = ok ? L.l_e[e] * L.d_e[e] / (4.0 * L.A_i[i]) : 0.0;
+      c_div[6 * i + k] = ok ? L.c_s[6 * i + k] * L.l_e[e] / A_i[i] : 0.0;
+      c_ke[6 * i + k] = ok ? L.l_e[e] * L.d_e[e] / (4.0 * A_i[i]) : 0.0;
     }
   std::vector<double> inv_d(E), wl(10 * E);
   for (int64_t e = 0; e < E; ++e) {
@@ -413,7 +414,7 @@ void upload_tables(const Level& L, DevTables& t) {
   t.t_curl = dev_upload(t_curl);
   t.t_R = dev_upload(t_R);
   t.f_v = dev_upload(L.f_v);
-  t.A_i = dev_upload(L.A_i);
+  t.A_i = dev_upload(A_i);
   t.l_e = dev_upload(L.l_e);
   t.d_e = dev_upload(L.d_e);
 }

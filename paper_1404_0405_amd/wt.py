@@ -68,6 +68,7 @@ SIGNATURES = [
     ("wt_timing_reset", C.c_int, [_P]),
     ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64, _D]),
     ("wt_kernel_names", C.c_char_p, []),
+    ("wt_table_cache_clear", None, []),
     ("wt_host_level_tables", C.c_int, [C.c_int, C.c_double, C.c_double, _D, _D, _D, _D, _I32, _I32, _D]),
     ("wt_host_pair_tables", C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, _I32, _D, _D, _D, _I32, _D,
                                       _D, _D, _I32, _D, _I32, _D]),
@@ -126,6 +127,11 @@ def _ptr(a, ct):
 def _check(code, what=""):
     if code != WT_OK:
         raise WtError(code, load().wt_last_error().decode() or what)
+
+
+def table_cache_clear():
+    """Free the host geometry tables that grid creation caches per level and level pair."""
+    load().wt_table_cache_clear()
 
 
 def host_level_tables(level, radius=6.371e6, omega=7.292e-5):
