@@ -494,10 +494,12 @@ static void ensure_learn_buffers(wt_grid* g) {
 // the current significant points.
 static void learn_stats_all(wt_grid* g, double eh, double eu) {
   ensure_learn_buffers(g);
+  const bool L = g->details_partial;   // then only the work lists' details are current
   for (int j = g->jmin + 1; j <= g->jmax; ++j) {
     PairState& P = g->P(j - 1);
     LevelState& l = g->L(j);
-    learn_point_r(P.dev, P.d_h, P.d_p, P.d_i, eh, eu, l.rn, l.re, g->stream);
+    learn_point_r(P.dev, P.d_h, P.d_p, P.d_i, eh, eu, l.rn, l.re, g->stream, L ? span(P.l_ce) : Span{},
+                  L ? span(P.l_ct) : Span{});
   }
   for (int j = g->jmin + 1; j < g->jmax; ++j) {
     if (!learnable(g, j)) continue;
@@ -550,16 +552,17 @@ static void clear_significant(wt_grid* g) {
 static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, bool gate = false) {
   // The threshold test reads the details of active points only, whose prolongation and
   // prediction stencils lie in the work-list support; the learned gate's patch features read
-  // every point's detail, so a gated adapt runs the transform on whole levels.
+  // every point's detail, but outside the support the points are inactive with prolonged values
+  // and their details vanish, so the transform runs over the work lists in both cases.
   std::vector<double*> dh = state_dh(g), u = state_u(g);
-  prolong_all(g, dh, u, !gate);
-  details_all(g, dh, u, !gate);
+  prolong_all(g, dh, u, true);
+  details_all(g, dh, u, true);
   double mh, mu;
   masked_max_all(g, &mh, &mu);
   const double eh = eps * mh, eu = eps * mu;
   clear_significant(g);
   // R1: significant points
-  const bool listed = !gate && g->lists_ok;
+  const bool listed = g->lists_ok;
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);

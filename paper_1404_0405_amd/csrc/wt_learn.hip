@@ -42,9 +42,14 @@ __global__ __launch_bounds__(LB) void k_fill_f(float* __restrict__ a, int64_t n,
 // Detail size of every fine point of a pair (each fine point carries at most one detail).
 __global__ __launch_bounds__(LB) void k_point_r_edge(DevPair P, const double* __restrict__ dh,
                                                      const double* __restrict__ dp, double eh, double eu,
-                                                     float* __restrict__ rn, float* __restrict__ re) {
-  const int64_t e = TID;
-  if (e >= P.Ec) return;
+                                                     float* __restrict__ rn, float* __restrict__ re,
+                                                     const int32_t* __restrict__ lst, int64_t cnt) {
+  int64_t e = TID;
+  if (e >= cnt) return;
+  if (lst) {
+    e = lst[e];
+    if (e < 0) return;   // padding of a work list
+  }
   rn[P.mid[e]] = rlog(dh[e], eh);
   const float ru = rlog(dp[e], eu);
   re[P.h1[e]] = ru;
@@ -52,19 +57,25 @@ __global__ __launch_bounds__(LB) void k_point_r_edge(DevPair P, const double* __
 }
 
 __global__ __launch_bounds__(LB) void k_point_r_int(DevPair P, const double* __restrict__ di, double eu,
-                                                    float* __restrict__ re) {
-  const int64_t t = TID;
-  if (t >= P.Tc) return;
+                                                    float* __restrict__ re, const int32_t* __restrict__ lst,
+                                                    int64_t cnt) {
+  int64_t t = TID;
+  if (t >= cnt) return;
+  if (lst) {
+    t = lst[t];
+    if (t < 0) return;   // padding of a work list
+  }
 #pragma unroll
   for (int s = 0; s < 3; ++s) re[P.int_e[3 * t + s]] = rlog(di[3 * t + s], eu);
 }
 
 void learn_point_r(const DevPair& P, const double* dh, const double* dp, const double* di, double eh, double eu,
-                   float* rn, float* re, hipStream_t s) {
+                   float* rn, float* re, hipStream_t s, Span le, Span lt) {
   k_fill_f<<<nb(P.Nf), LB, 0, s>>>(rn, P.Nf, -2.f);
   k_fill_f<<<nb(P.Ef), LB, 0, s>>>(re, P.Ef, -2.f);
-  k_point_r_edge<<<nb(P.Ec), LB, 0, s>>>(P, dh, dp, eh, eu, rn, re);
-  k_point_r_int<<<nb(P.Tc), LB, 0, s>>>(P, di, eu, re);
+  const int64_t ne = le.idx ? le.n : P.Ec, nt = lt.idx ? lt.n : P.Tc;
+  if (ne) k_point_r_edge<<<nb(ne), LB, 0, s>>>(P, dh, dp, eh, eu, rn, re, le.idx, ne);
+  if (nt) k_point_r_int<<<nb(nt), LB, 0, s>>>(P, di, eu, re, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 

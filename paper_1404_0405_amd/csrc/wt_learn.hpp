@@ -10,9 +10,12 @@ namespace wt {
 
 constexpr int LEARN_STATS = 32;   // statistics per patch (layout in wt_learn.hip)
 
-// rn[Nf], re[Ef]: detail size of every fine point of the pair (floor where there is none)
+// rn[Nf], re[Ef]: detail size of every fine point of the pair (floor where there is none).
+// With work lists (le: coarse edges, lt: coarse triangles) only the listed points are read and
+// every other point gets the floor: the points outside the lists are inactive with prolonged
+// values, whose details vanish (up to rounding, far below the floor).
 void learn_point_r(const DevPair& P, const double* dh, const double* dp, const double* di, double eh, double eu,
-                   float* rn, float* re, hipStream_t s);
+                   float* rn, float* re, hipStream_t s, Span le = {}, Span lt = {});
 // statistics of the npatch = 10 (n/8)^2 patches of a level with lattice size n: rn, re of the
 // level (details of the pair below), rnf, ref of the level above, masks na (level), naf
 // (level above), significant points sn, se of the level

@@ -276,3 +276,27 @@ def test_trained_predictor_against_plain_zone():
     assert err < 1e-4
     m0, m1 = lrn["mass"]
     assert abs(m1 / m0 - 1) < 1e-13
+
+
+def test_learned_zone_over_work_lists_equals_whole_levels():
+    """The gated adapt, its patch features and the threshold test run over the work lists: with
+    an untrained network at threshold 0.5 (a mix of proposed and dropped quadrants) the run
+    equals, bitwise, the same run over whole levels, redo count included."""
+    jmin, jmax, eps, nsteps = 4, 7, 5e-3, 6
+    out = []
+    for lists in (True, False):
+        g = _grid(jmin, jmax, seed_bump=30.0)
+        with g:
+            g.set_work_lists(lists)
+            dt = g.suggest_dt(0.8)
+            m = wt.Mlp(inputs.mlp_init())
+            g.set_predictor(m, 0.5)
+            act = _run(g, eps, dt, nsteps)
+            out.append(([g.get_state(j) for j in range(jmin, jmax + 1)], act, g.redo_count()))
+            m.close()
+    (sa, aa, ra), (sb, ab, rb) = out
+    _say(f"lists vs whole levels: active {aa} / {ab}, redo {ra} / {rb}")
+    assert aa == ab and ra == rb
+    for a, b in zip(sa, sb):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
