@@ -248,10 +248,11 @@ __global__ __launch_bounds__(CB) void k_pad_b(PadJobs J) {
     jb.idx[i] = -1;
 }
 
-// The padded bound of a list of n entries: kept while n <= bound <= 8 max(n, 256); otherwise the
-// power of two at or above 2 max(n, 256) (capped by cap), so small drifts of n between adapts do
-// not change the launches.
+// The padded bound of a list of n entries: 0 for an empty list (nothing is launched); kept while
+// n <= bound <= 8 max(n, 256); otherwise the power of two at or above 2 max(n, 256) (capped by
+// cap), so small drifts of n between adapts do not change the launches.
 static int64_t list_bound(int64_t prev, int64_t n, int64_t cap) {
+  if (n == 0) return 0;
   const int64_t m = n > 256 ? n : 256;
   if (prev >= n && prev <= cap && prev <= 8 * m) return prev;
   int64_t b = 256;

@@ -10,8 +10,9 @@
 namespace wt {
 
 // idx[0..n) the listed indices in increasing order, idx[n..bound) = -1: launches cover `bound`
-// entries (a power of two with room to grow, kept while the count stays within it), so a launch
-// sequence recorded for one list stays valid while later lists of the same predicate fit.
+// entries (0 for an empty list, else a power of two with room to grow, kept while the count stays
+// within it), so a launch sequence recorded for one list stays valid while later lists of the
+// same predicate fit.
 struct WorkList {
   int32_t* idx = nullptr;   // device
   int64_t n = 0, cap = 0, bound = 0;
