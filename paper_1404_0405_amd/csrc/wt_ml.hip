@@ -289,10 +289,10 @@ __global__ __launch_bounds__(BS) void k_restrict_h(DevPair P, const double* __re
   int64_t k = TID;
   if (k >= P.Nc) return;
   double s = hf[P.even[k]];
-  for (int q = 0; q < MK_MAX; ++q) {
-    int32_t ec = P.mk[MK_MAX * k + q];
-    if (ec < 0) break;
-    s += P.s_upd[ec] * h_detail(P, ec >> 2, hf);
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q) {   // valid entries first, then -1: same order as a break
+    const int32_t ec = P.mk[MK_MAX * k + q];
+    if (ec >= 0) s += P.s_upd[ec] * h_detail(P, ec >> 2, hf);
   }
   hc[k] = s;
 }
@@ -320,25 +320,31 @@ __global__ __launch_bounds__(BS) void k_partial_h(DevPair P, const int32_t* __re
                                                   const double* __restrict__ hf, double* __restrict__ hc,
                                                   const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(k, cnt, lst)
-  if (!nac[k] || !naf[P.even[k]]) return;
+  // the conditions combine mask bytes (0 / 1) without early exits, so their loads are issued
+  // together rather than one dependent round trip after another
+  const int32_t ev = P.even[k];
+  int32_t ecs[MK_MAX];
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q) ecs[q] = P.mk[MK_MAX * k + q];   // valid entries first, then -1
+  uint32_t ok = nac[k] & naf[ev];
+#pragma unroll
   for (int q = 0; q < MK_MAX; ++q) {
-    int32_t ec = P.mk[MK_MAX * k + q];
-    if (ec < 0) break;
-    int64_t e = ec >> 2;
-    if (!naf[P.mid[e]]) return;
-    for (int c = 0; c < 4; ++c)
-      if (!naf[P.even[P.cells[4 * e + c]]]) return;
+    if (ecs[q] >= 0) {
+      const int64_t e = ecs[q] >> 2;
+      ok &= naf[P.mid[e]] & naf[P.even[P.cells[4 * e]]] & naf[P.even[P.cells[4 * e + 1]]] &
+            naf[P.even[P.cells[4 * e + 2]]] & naf[P.even[P.cells[4 * e + 3]]];
+    }
   }
+#pragma unroll
   for (int q = 0; q < 6; ++q) {
-    int32_t e = c_e_c[6 * k + q];
-    if (!(eaf[P.h1[e]] && eaf[P.h2[e]])) return;
+    const int32_t e = c_e_c[6 * k + q];
+    ok &= eaf[P.h1[e]] & eaf[P.h2[e]];
   }
-  double s = hf[P.even[k]];
-  for (int q = 0; q < MK_MAX; ++q) {
-    int32_t ec = P.mk[MK_MAX * k + q];
-    if (ec < 0) break;
-    s += P.s_upd[ec] * h_detail(P, ec >> 2, hf);
-  }
+  if (!ok) return;
+  double s = hf[ev];
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q)
+    if (ecs[q] >= 0) s += P.s_upd[ecs[q]] * h_detail(P, ecs[q] >> 2, hf);
   hc[k] = s;
 }
 
@@ -770,10 +776,10 @@ __global__ __launch_bounds__(BS) void k_inv_even(DevPair P, const double* __rest
     const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(k, cnt, lst)
   double s = hc[k];
-  for (int q = 0; q < MK_MAX; ++q) {
-    int32_t ec = P.mk[MK_MAX * k + q];
-    if (ec < 0) break;
-    s -= P.s_upd[ec] * dk[ec >> 2];
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q) {   // valid entries first, then -1: same order as a break
+    const int32_t ec = P.mk[MK_MAX * k + q];
+    if (ec >= 0) s -= P.s_upd[ec] * dk[ec >> 2];
   }
   hf[P.even[k]] = s;
 }
