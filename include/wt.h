@@ -325,10 +325,26 @@ wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n);
 void wt_ensemble_destroy(wt_ensemble* e);
 /* wt_adapt of every member with eps_host[k]. */
 int wt_ensemble_adapt(wt_ensemble* e, const double* eps_host);
-/* One step of every member with dt_host[k] as one graph launch; synchronises. */
+/* One step of every member with dt_host[k] as one graph launch (or, batched, one persistent
+ * launch); synchronises. */
 int wt_ensemble_step(wt_ensemble* e, const double* dt_host);
-/* Number of graph captures and launches so far. */
+/* Number of graph captures (batched: step plans built) and launches so far. */
 int wt_ensemble_stats(const wt_ensemble* e, int64_t* captures, int64_t* launches);
+/* on != 0: later steps run batched -- ONE persistent cooperative launch covers every member's
+ * whole multilevel step.  The step's phases (prolongation pair by pair upwards, intermediates,
+ * restriction pair by pair downwards, tendencies, per stage; then the partial height transform)
+ * follow one another with a grid-wide barrier; within a phase, the jobs of all members (one per
+ * member, level or pair and kernel) are cut into chunks of consecutive work-list entries that the
+ * workgroups take from a global work queue (an atomic counter per phase).  Every entry runs the
+ * same per-point code as the unbatched step, so results are bitwise those of stepping the members
+ * one by one.  The launch shape (workgroups per CU, entries per chunk) is tuned on line: the first
+ * steps each try one candidate, timed with events on the ensemble's stream, and the fastest is
+ * kept.  Every member must be multilevel (jmin < jmax); WT_EINVAL otherwise.  on = 0 returns to
+ * the graph step. */
+int wt_ensemble_set_batched(wt_ensemble* e, int on);
+/* Launch shape in use (workgroups per CU, entries per chunk; 0 before the first batched step)
+ * and whether tuning has finished (*tuned = 1).  Any pointer may be NULL. */
+int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* tuned);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);

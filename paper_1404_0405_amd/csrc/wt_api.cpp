@@ -16,6 +16,7 @@
 #include "../../include/wt.h"
 #include "wt_grid.hpp"
 #include "wt_internal.hpp"
+#include "wt_batch.hpp"
 #include "wt_compact.hpp"
 #include "wt_lattice_dev.hpp"
 #include "wt_learn.hpp"
@@ -1349,10 +1350,198 @@ struct wt_ensemble {
   std::vector<hipEvent_t> join;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<uint64_t> epochs;   // member epochs the graph was captured with
+  std::vector<uint64_t> epochs;   // member epochs the graph (or the batch plan) was built with
   std::vector<double> dts;
   int64_t captures = 0, launches = 0;
+  // batched persistent step
+  bool batched = false;
+  bool plan_ok = false;
+  wt::BatchPlan plan;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  // launch-shape tuning: each candidate (workgroups per CU, chunk entries) runs one step, the
+  // fastest is kept
+  std::vector<std::pair<int, int>> cand;
+  std::vector<float> cand_ms;
+  int bpc = 0, chunk = 0;
+  bool tuned = false;
 };
+
+// The batched step replays the phases of ml_step for every member at once (same per-point code
+// and the same dependencies: prolongation pair by pair upwards, intermediates, restriction pair
+// by pair downwards, tendencies, per stage; then the partial height transform downwards).
+static void build_batch_plan(wt_ensemble* e, const double* dt) {
+  BatchPlan& pl = e->plan;
+  pl.levels.clear();
+  pl.pairs.clear();
+  pl.jobs.clear();
+  pl.phase_jobs.clear();
+  struct MInfo {
+    int lev0, pair0, jmin, jmax;
+    bool wl, fp32;
+  };
+  std::vector<MInfo> mi;
+  int J0 = 1 << 30, J1 = -1;
+  for (size_t k = 0; k < e->m.size(); ++k) {
+    wt_grid* g = e->m[k];
+    if (!g->multi()) throw std::runtime_error("the batched step needs multilevel members");
+    MInfo x{int(pl.levels.size()), int(pl.pairs.size()), g->jmin, g->jmax, g->use_lists && g->lists_ok,
+            g->prm.precision == WT_FP32_TENDENCY};
+    const PhysParams p = phys(g);
+    for (auto& lp : g->lev) {
+      LevelState& l = *lp;
+      BatchLevel bl{};
+      bl.t = l.tab;
+      bl.na = l.na;
+      bl.ea = l.ea;
+      bl.qv = l.work.qv;
+      bl.B = l.work.B;
+      bl.F = l.work.F;
+      bl.qe = l.work.qe;
+      bl.Q = l.work.Q;
+      bl.c = l.work.c;
+      bl.dh = l.work.dh;
+      bl.g = p.g;
+      bl.H = p.H;
+      bl.fp32 = x.fp32;
+      for (int st = 0; st < 4; ++st) {
+        const StageSpec sp = rk_stage(g->prm.rk, st, l.work, dt[k]);
+        bl.pdh[st] = sp.pdh;
+        bl.pu[st] = sp.pu;
+        bl.so[st] = sp.c;
+      }
+      pl.levels.push_back(bl);
+    }
+    for (int j = g->jmin; j < g->jmax; ++j)
+      pl.pairs.push_back(BatchPair{g->P(j).dev, x.lev0 + (j - g->jmin), x.lev0 + (j + 1 - g->jmin)});
+    J0 = std::min(J0, g->jmin);
+    J1 = std::max(J1, g->jmax);
+    mi.push_back(x);
+  }
+  std::vector<int32_t> cur;
+  auto job = [&](int kind, int a, int st, const MInfo& x, const WorkList& L, int64_t dense) {
+    const int64_t cnt = x.wl ? L.bound : dense;
+    if (cnt <= 0) return;
+    pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, x.wl ? L.idx : nullptr, cnt});
+    cur.push_back(int32_t(pl.jobs.size() - 1));
+  };
+  auto flush = [&]() {
+    if (!cur.empty()) pl.phase_jobs.push_back(cur);
+    cur.clear();
+  };
+  for (int st = 0; st < 4; ++st) {
+    for (int j = J0; j < J1; ++j) {
+      for (size_t k = 0; k < mi.size(); ++k)
+        if (mi[k].jmin <= j && j < mi[k].jmax) {
+          const PairState& P = e->m[k]->P(j);
+          job(BK_PRO_EVEN, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_cn, P.dev.Nc);
+        }
+      flush();
+      for (size_t k = 0; k < mi.size(); ++k)
+        if (mi[k].jmin <= j && j < mi[k].jmax) {
+          const PairState& P = e->m[k]->P(j);
+          job(BK_PRO_ODD, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_ce, P.dev.Ec);
+          job(BK_PRO_INT, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_ct, P.dev.Tc);
+        }
+      flush();
+    }
+    const int kinds[3] = {BK_VERTEX, BK_EDGE_CELL, BK_Q};
+    for (int kind : kinds) {
+      for (size_t k = 0; k < mi.size(); ++k) {
+        wt_grid* g = e->m[k];
+        for (int q = 0; q < int(g->lev.size()); ++q) {
+          const LevelState& l = *g->lev[q];
+          if (kind == BK_VERTEX) job(kind, mi[k].lev0 + q, st, mi[k], l.l_tri, l.tab.T);
+          else if (kind == BK_EDGE_CELL) job(kind, mi[k].lev0 + q, st, mi[k], l.l_elem, l.tab.N);
+          else job(kind, mi[k].lev0 + q, st, mi[k], l.l_edge, l.tab.E);
+        }
+      }
+      flush();
+    }
+    for (int j = J1 - 1; j >= J0; --j) {
+      for (size_t k = 0; k < mi.size(); ++k)
+        if (mi[k].jmin <= j && j < mi[k].jmax) {
+          const LevelState& F = e->m[k]->L(j + 1);
+          job(BK_DIV, mi[k].lev0 + (j + 1 - mi[k].jmin), st, mi[k], F.l_node, F.tab.N);
+        }
+      flush();
+      for (size_t k = 0; k < mi.size(); ++k)
+        if (mi[k].jmin <= j && j < mi[k].jmax) {
+          const PairState& P = e->m[k]->P(j);
+          job(BK_RES_E, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_ce, P.dev.Ec);
+          job(BK_RES_B, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_cn, P.dev.Nc);
+        }
+      flush();
+    }
+    for (size_t k = 0; k < mi.size(); ++k) {
+      wt_grid* g = e->m[k];
+      for (int q = 0; q < int(g->lev.size()); ++q)
+        job(BK_TEND, mi[k].lev0 + q, st, mi[k], g->lev[q]->l_tend, g->lev[q]->tab.N);
+    }
+    flush();
+  }
+  for (int j = J1 - 1; j >= J0; --j) {
+    for (size_t k = 0; k < mi.size(); ++k)
+      if (mi[k].jmin <= j && j < mi[k].jmax) {
+        const PairState& P = e->m[k]->P(j);
+        job(BK_PARTIAL_H, mi[k].pair0 + j - mi[k].jmin, 0, mi[k], P.l_cn, P.dev.Nc);
+      }
+    flush();
+  }
+}
+
+static void batched_step(wt_ensemble* e, const double* dt) {
+  const size_t n = e->m.size();
+  if (e->cand.empty()) {
+    const int maxb = batch_max_blocks_per_cu();
+    if (maxb < 1) throw std::runtime_error("the batch kernel does not fit on a CU");
+    for (int b : {1, 2, 4, 8})
+      if (b <= maxb)
+        for (int c : {256, 1024}) e->cand.push_back({b, c});
+    e->bpc = e->cand[0].first;
+    e->chunk = e->cand[0].second;
+  }
+  // launch shape of this step: the next untried candidate while tuning
+  int bpc = e->bpc, chunk = e->chunk;
+  const size_t tried = e->cand_ms.size();
+  if (!e->tuned) {
+    bpc = e->cand[tried].first;
+    chunk = e->cand[tried].second;
+  }
+  bool stale = !e->plan_ok || e->dts.size() != n;
+  for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
+  if (stale) {
+    build_batch_plan(e, dt);
+    e->plan.upload(chunk, e->s0);
+    e->plan_ok = true;
+    e->epochs.resize(n);
+    for (size_t k = 0; k < n; ++k) e->epochs[k] = e->m[k]->epoch;
+    e->dts.assign(dt, dt + n);
+    ++e->captures;
+  } else if (e->plan.chunk != chunk) {
+    e->plan.upload(chunk, e->s0);
+  }
+  // members' own streams are idle here (their adapts synchronise)
+  if (!e->t0) {
+    HIPCHK(hipEventCreate(&e->t0));
+    HIPCHK(hipEventCreate(&e->t1));
+  }
+  HIPCHK(hipEventRecord(e->t0, e->s0));
+  batch_launch(e->plan, bpc, e->s0);
+  HIPCHK(hipEventRecord(e->t1, e->s0));
+  HIPCHK(hipStreamSynchronize(e->s0));
+  ++e->launches;
+  if (!e->tuned) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e->t0, e->t1));
+    e->cand_ms.push_back(ms);
+    if (e->cand_ms.size() == e->cand.size()) {
+      const size_t best = size_t(std::min_element(e->cand_ms.begin(), e->cand_ms.end()) - e->cand_ms.begin());
+      e->bpc = e->cand[best].first;
+      e->chunk = e->cand[best].second;
+      e->tuned = true;
+    }
+  }
+}
 
 wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n) {
   if (!members || n < 1) {
@@ -1387,6 +1576,9 @@ wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n) {
 void wt_ensemble_destroy(wt_ensemble* e) {
   if (!e) return;
   if (e->s0) (void)hipStreamSynchronize(e->s0);
+  e->plan.release();
+  if (e->t0) (void)hipEventDestroy(e->t0);
+  if (e->t1) (void)hipEventDestroy(e->t1);
   if (e->exec) (void)hipGraphExecDestroy(e->exec);
   if (e->graph) (void)hipGraphDestroy(e->graph);
   for (auto& j : e->join)
@@ -1415,7 +1607,9 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
   try {
     bool stale = !e->exec || e->dts.size() != n;
     for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
-    if (stale) {
+    if (e->batched) {
+      batched_step(e, dt);
+    } else if (stale) {
       // capture every member's step on its own stream, forked from and joined into s0
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed));
@@ -1455,9 +1649,11 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
       e->dts.assign(dt, dt + n);
       ++e->captures;
     }
-    HIPCHK(hipGraphLaunch(e->exec, e->s0));
-    HIPCHK(hipStreamSynchronize(e->s0));
-    ++e->launches;
+    if (!e->batched) {
+      HIPCHK(hipGraphLaunch(e->exec, e->s0));
+      HIPCHK(hipStreamSynchronize(e->s0));
+      ++e->launches;
+    }
     // the threshold test of the learned zone needs the host: members judged one by one
     for (size_t k = 0; k < n; ++k) {
       wt_grid* m = e->m[k];
@@ -1474,6 +1670,35 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
   } catch (const std::exception& x) {
     return fail(WT_EDEVICE, std::string("wt_ensemble_step: ") + x.what());
   }
+  return WT_OK;
+}
+
+int wt_ensemble_set_batched(wt_ensemble* e, int on) {
+  if (!e) return fail(WT_EINVAL, "wt_ensemble_set_batched: null ensemble");
+  if (on) {
+    for (auto* g : e->m)
+      if (!g->multi()) return fail(WT_EINVAL, "wt_ensemble_set_batched: every member must have jmin < jmax");
+  }
+  try {
+    HIPCHK(hipStreamSynchronize(e->s0));
+  } catch (const std::exception& x) {
+    return fail(WT_EDEVICE, std::string("wt_ensemble_set_batched: ") + x.what());
+  }
+  e->batched = on != 0;
+  // the next step rebuilds what the mode launches
+  e->plan_ok = false;
+  if (e->exec) {
+    (void)hipGraphExecDestroy(e->exec);
+    e->exec = nullptr;
+  }
+  return WT_OK;
+}
+
+int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* tuned) {
+  if (!e) return fail(WT_EINVAL, "wt_ensemble_tuning: null ensemble");
+  if (blocks_per_cu) *blocks_per_cu = e->bpc;
+  if (chunk) *chunk = e->chunk;
+  if (tuned) *tuned = e->tuned ? 1 : 0;
   return WT_OK;
 }
 

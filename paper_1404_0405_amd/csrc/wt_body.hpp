@@ -1,0 +1,251 @@
+// Per-point bodies of the adaptive stage (Sec. 3.1, 4.1-4.4): one function per kernel of the
+// multilevel Runge-Kutta step, evaluated at one node, edge or triangle.  The one-launch-per-kernel
+// path (wt_ml.hip, wt_kernels.hip) and the batched ensemble step (wt_batch.hip) both call these,
+// so the two give identical results.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wt_ml.hpp"
+
+namespace wt {
+
+// ------------------------------------------------------------------ inter-scale predictions
+// velocity difference of the two half-edges of coarse edge e predicted from the coarse
+// velocities of its two triangles' stencils
+__device__ __forceinline__ double pair_pred(const DevPair& P, int64_t e, const int32_t* __restrict__ e_v,
+                                            const double* __restrict__ uc) {
+  int32_t tl = e_v[2 * e], tr = e_v[2 * e + 1];
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s += P.w_pl[9 * e + k] * uc[P.v_sten[9 * tl + k]];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s += P.w_pr[9 * e + k] * uc[P.v_sten[9 * tr + k]];
+  return s;
+}
+
+// interior fine edge s of coarse triangle t predicted from the triangle's coarse stencil
+__device__ __forceinline__ double int_pred(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v += P.w_int[27 * t + 9 * s + k] * uc[P.v_sten[9 * t + k]];
+  return v;
+}
+
+// height detail at the midpoint of coarse edge e: fine value minus the s~-weighted mean of the
+// four even fine neighbours
+__device__ __forceinline__ double h_detail(const DevPair& P, int64_t e, const double* __restrict__ hf) {
+  double s = hf[P.mid[e]];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s -= P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
+  return s;
+}
+
+// ------------------------------------------------------------------ prolongation (one pair)
+// Inactive even node: the coarse value; inactive odd node: s~-weighted mean of its four even
+// fine neighbours; inactive half-edges: u^j -+ (p1-p2)/2; inactive interior edges: prediction.
+__device__ __forceinline__ void body_prolong_even(int64_t k, const DevPair& P, const uint8_t* __restrict__ naf,
+                                                  const double* __restrict__ hc, double* __restrict__ hf) {
+  int32_t f = P.even[k];
+  if (!naf[f]) hf[f] = hc[k];
+}
+
+__device__ __forceinline__ void body_prolong_odd_pair(int64_t e, const DevPair& P, const uint8_t* __restrict__ naf,
+                                                      const uint8_t* __restrict__ eaf,
+                                                      const int32_t* __restrict__ e_v_c,
+                                                      const double* __restrict__ uc, double* __restrict__ hf,
+                                                      double* __restrict__ uf) {
+  int32_t m = P.mid[e];
+  if (!naf[m]) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
+    hf[m] = s;
+  }
+  int32_t h1 = P.h1[e], h2 = P.h2[e];
+  bool a1 = eaf[h1], a2 = eaf[h2];
+  if (!a1 || !a2) {
+    double half = 0.5 * pair_pred(P, e, e_v_c, uc);
+    if (!a1) uf[h1] = uc[e] + half;
+    if (!a2) uf[h2] = uc[e] - half;
+  }
+}
+
+__device__ __forceinline__ void body_prolong_int(int64_t t, const DevPair& P, const uint8_t* __restrict__ eaf,
+                                                 const double* __restrict__ uc, double* __restrict__ uf) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    int32_t f = P.int_e[3 * t + s];
+    if (!eaf[f]) uf[f] = int_pred(P, t, s, uc);
+  }
+}
+
+// ------------------------------------------------------------------ TRiSK intermediates (one level)
+// q_v = (zeta_v + f_v) / h_v at triangle t
+template <typename T>
+__device__ __forceinline__ void body_vertex(int64_t t, const DevTables& tb, const double* __restrict__ dh,
+                                            const double* __restrict__ u, double H, T* __restrict__ qv) {
+  T z = T(0), hv = T(0);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    z += T(tb.t_curl[3 * t + s]) * T(u[tb.t_e[3 * t + s]]);
+    hv += T(tb.t_R[3 * t + s]) * (T(H) + T(dh[tb.t_n[3 * t + s]]));
+  }
+  qv[t] = (z + T(tb.f_v[t])) / hv;
+}
+
+// B_i = g dh_i + K_i at node id; F_e = h_e u_e and q_e at its three edges
+template <typename T>
+__device__ __forceinline__ void body_edge_cell(int64_t id, const DevTables& tb, const double* __restrict__ dh,
+                                               const double* __restrict__ u, const T* __restrict__ qv, double g,
+                                               double H, T* __restrict__ B, double* __restrict__ F,
+                                               T* __restrict__ qe) {
+  T K = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    T ue = T(u[tb.c_e[6 * id + k]]);
+    K += T(tb.c_ke[6 * id + k]) * ue * ue;
+  }
+  B[id] = T(g) * T(dh[id]) + K;
+  if (id >= tb.n_elem) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int64_t e = 3 * id + d;
+    T he = T(0.5) * ((T(H) + T(dh[tb.e_c[2 * e]])) + (T(H) + T(dh[tb.e_c[2 * e + 1]])));
+    F[e] = double(he * T(u[e]));  // the mass flux is stored in double in both precisions
+    qe[e] = T(0.5) * (qv[tb.e_v[2 * e]] + qv[tb.e_v[2 * e + 1]]);
+  }
+}
+
+// Q_e = sum over the perpendicular-flux stencil of w l'/d F' (q_e + q_e')/2
+template <typename T>
+__device__ __forceinline__ void body_Q(int64_t e, const DevTables& tb, const double* __restrict__ F,
+                                       const T* __restrict__ qe, T* __restrict__ Q) {
+  T q0 = qe[e], s = T(0);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    int32_t ep = tb.ecp[10 * e + k];
+    s += T(tb.wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
+  }
+  Q[e] = s;
+}
+
+// ------------------------------------------------------------------ restriction (one pair)
+// fine divergence c_i (integrated form, used by the flux restriction)
+__device__ __forceinline__ void body_div(int64_t i, const DevTables& tf, const double* __restrict__ F,
+                                         double* __restrict__ c) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s += tf.c_div[6 * i + k] * F[tf.c_e[6 * i + k]];
+  c[i] = s;
+}
+
+// F^j = R_F(F^{j+1}, c^{j+1}) and Q^j = mean of the half-edges at non-leaf coarse edge e
+template <typename T>
+__device__ __forceinline__ void body_restrict_edges(int64_t e, const DevPair& P, const uint8_t* __restrict__ eaf,
+                                                    const double* __restrict__ l_f, const double* __restrict__ l_c,
+                                                    const double* __restrict__ Ff, const double* __restrict__ cf,
+                                                    const T* __restrict__ Qf, double* __restrict__ Fc,
+                                                    T* __restrict__ Qc) {
+  int32_t h1 = P.h1[e], h2 = P.h2[e];
+  if (!(eaf[h1] && eaf[h2])) return;
+  double phi = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int32_t f = P.rf_f[3 * e + k];
+    phi += P.rf_fw[3 * e + k] * (l_f[f] * Ff[f]);
+  }
+#pragma unroll
+  for (int k = 0; k < RF_NC; ++k) phi += P.rf_cw[RF_NC * e + k] * cf[P.rf_c[RF_NC * e + k]];
+  Fc[e] = phi / l_c[e];
+  Qc[e] = T(0.5) * (Qf[h1] + Qf[h2]);
+}
+
+// B^j = B^{j+1} at non-leaf coarse node k
+template <typename T>
+__device__ __forceinline__ void body_restrict_B(int64_t k, const DevPair& P, const uint8_t* __restrict__ naf,
+                                                const T* __restrict__ Bf, T* __restrict__ Bc) {
+  int32_t f = P.even[k];
+  if (naf[f]) Bc[k] = Bf[f];
+}
+
+// ------------------------------------------------------------------ tendencies (one level)
+// Runge-Kutta stage combination at point i after the tendency k
+__device__ __forceinline__ void rk_out(int64_t i, double k, const StagePtrs& p, const StageOut& c) {
+  if (p.o1) {
+    double v = c.d1 * k;
+    if (c.a1 != 0.0) v += c.a1 * p.y[i];
+    if (c.b1 != 0.0) v += c.b1 * p.acc[i];
+    if (c.c1 != 0.0) v += c.c1 * p.x[i];
+    p.o1[i] = v;
+  }
+  if (p.o2) {
+    double v = c.d2 * k;
+    if (c.a2 != 0.0) v += c.a2 * p.y[i];
+    if (c.b2 != 0.0) v += c.b2 * p.acc[i];
+    if (c.c2 != 0.0) v += c.c2 * p.x[i];
+    p.o2[i] = v;
+  }
+}
+
+// Tendencies at node id and its edges with the level's (possibly restricted) F, Q, B, zero at
+// inactive points, then the stage combination.
+template <typename T>
+__device__ __forceinline__ void body_tend_ml(int64_t id, const DevTables& tb, const uint8_t* __restrict__ na,
+                                             const uint8_t* __restrict__ ea, const T* __restrict__ B,
+                                             const double* __restrict__ F, const T* __restrict__ Q,
+                                             const StagePtrs& pdh, const StagePtrs& pu, const StageOut& c) {
+  double k = 0.0;
+  if (na[id]) {
+    double div = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) div += tb.c_div[6 * id + q] * F[tb.c_e[6 * id + q]];
+    k = -div;
+  }
+  rk_out(id, k, pdh, c);
+  if (id >= tb.n_elem) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int64_t e = 3 * id + d;
+    double ku = 0.0;
+    if (ea[e]) ku = double(-Q[e] - (B[tb.e_c[2 * e + 1]] - B[tb.e_c[2 * e]]) * T(tb.inv_d[e]));
+    rk_out(e, ku, pu, c);
+  }
+}
+
+// ------------------------------------------------------------------ partial height transform
+// h^j_k <- R_h(h^{j+1})_k at complete coarse node k: the whole height-restriction stencil is
+// active and every coarse edge of the node is non-leaf.  The conditions combine mask bytes (0 / 1)
+// without early exits, so their loads are issued together.
+__device__ __forceinline__ void body_partial_h(int64_t k, const DevPair& P, const int32_t* __restrict__ c_e_c,
+                                               const uint8_t* __restrict__ nac, const uint8_t* __restrict__ naf,
+                                               const uint8_t* __restrict__ eaf, const double* __restrict__ hf,
+                                               double* __restrict__ hc) {
+  const int32_t ev = P.even[k];
+  int32_t ecs[MK_MAX];
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q) ecs[q] = P.mk[MK_MAX * k + q];   // valid entries first, then -1
+  uint32_t ok = nac[k] & naf[ev];
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q) {
+    if (ecs[q] >= 0) {
+      const int64_t e = ecs[q] >> 2;
+      ok &= naf[P.mid[e]] & naf[P.even[P.cells[4 * e]]] & naf[P.even[P.cells[4 * e + 1]]] &
+            naf[P.even[P.cells[4 * e + 2]]] & naf[P.even[P.cells[4 * e + 3]]];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int32_t e = c_e_c[6 * k + q];
+    ok &= eaf[P.h1[e]] & eaf[P.h2[e]];
+  }
+  if (!ok) return;
+  double s = hf[ev];
+#pragma unroll
+  for (int q = 0; q < MK_MAX; ++q)
+    if (ecs[q] >= 0) s += P.s_upd[ecs[q]] * h_detail(P, ecs[q] >> 2, hf);
+  hc[k] = s;
+}
+
+}  // namespace wt

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <stdexcept>
 
+#include "wt_body.hpp"
 #include "wt_internal.hpp"
 #include "wt_lattice_dev.hpp"
 
@@ -31,63 +32,30 @@ const char* const kKernelNames[K_COUNT] = {"trisk_vertex", "trisk_edge_cell", "t
 constexpr int BS = 256;
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __restrict__ list,
-                                               const int32_t* __restrict__ t_n,
-                                               const int32_t* __restrict__ t_e,
-                                               const double* __restrict__ t_curl,
-                                               const double* __restrict__ t_R,
-                                               const double* __restrict__ f_v,
-                                               const double* __restrict__ dh,
-                                               const double* __restrict__ u, double H,
-                                               T* __restrict__ qv) {
+__global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __restrict__ list, DevTables tb,
+                                               const double* __restrict__ dh, const double* __restrict__ u,
+                                               double H, T* __restrict__ qv) {
   int64_t t = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (t >= n_tri) return;
   if (list) {
     t = list[t];
     if (t < 0) return;   // padding of a work list
   }
-  T z = T(0), hv = T(0);
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    z += T(t_curl[3 * t + s]) * T(u[t_e[3 * t + s]]);
-    hv += T(t_R[3 * t + s]) * (T(H) + T(dh[t_n[3 * t + s]]));
-  }
-  qv[t] = (z + T(f_v[t])) / hv;
+  body_vertex<T>(t, tb, dh, u, H, qv);
 }
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, int64_t n_elem,
-                                                  const int32_t* __restrict__ list,
-                                                  const int32_t* __restrict__ c_e,
-                                                  const double* __restrict__ c_ke,
-                                                  const int32_t* __restrict__ e_c,
-                                                  const int32_t* __restrict__ e_v,
-                                                  const double* __restrict__ dh,
-                                                  const double* __restrict__ u,
-                                                  const T* __restrict__ qv, double g, double H,
-                                                  T* __restrict__ B, double* __restrict__ F,
-                                                  T* __restrict__ qe) {
+__global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, const int32_t* __restrict__ list, DevTables tb,
+                                                  const double* __restrict__ dh, const double* __restrict__ u,
+                                                  const T* __restrict__ qv, double g, double H, T* __restrict__ B,
+                                                  double* __restrict__ F, T* __restrict__ qe) {
   int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (id >= N) return;
   if (list) {
     id = list[id];
     if (id < 0) return;   // padding of a work list
   }
-  T K = T(0);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    T ue = T(u[c_e[6 * id + k]]);
-    K += T(c_ke[6 * id + k]) * ue * ue;
-  }
-  B[id] = T(g) * T(dh[id]) + K;
-  if (id >= n_elem) return;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int64_t e = 3 * id + d;
-    T he = T(0.5) * ((T(H) + T(dh[e_c[2 * e]])) + (T(H) + T(dh[e_c[2 * e + 1]])));
-    F[e] = double(he * T(u[e]));  // the mass flux is stored in double in both precisions
-    qe[e] = T(0.5) * (qv[e_v[2 * e]] + qv[e_v[2 * e + 1]]);
-  }
+  body_edge_cell<T>(id, tb, dh, u, qv, g, H, B, F, qe);
 }
 
 __device__ __forceinline__ void rk_epilogue(int64_t i, double k, const StagePtrs& p,
@@ -213,12 +181,11 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
   const double e_dof = epi(c, sdh, true);
   {
     TimedLaunch tl_(tm, K_VERTEX, s, double(nt) * (80.0 + 16.0 + sz));
-    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tl, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
+    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tl, t, sdh.x, su.x, p.H, qv);
   }
   {
     TimedLaunch tl_(tm, K_EDGE_CELL, s, double(ne) * (120.0 + 32.0 + 24.0 + 6.0 * sz));
-    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, t.n_elem, el, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv,
-                                           p.g, p.H, B, F, qe);
+    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, el, t, sdh.x, su.x, qv, p.g, p.H, B, F, qe);
   }
   {
     TimedLaunch tl_(tm, K_TEND, s, double(nr) * (480.0 + 24.0 + 4.0 * sz + 4.0 * e_dof));
@@ -244,11 +211,10 @@ static void intermediates_impl(const DevTables& t, DevWork& w, const PhysParams&
                                const int32_t* elem_list, int64_t ne) {
   T* qv = static_cast<T*>(w.qv);
   if (nt)
-    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tri_list, t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, sdh.x, su.x, p.H, qv);
+    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tri_list, t, sdh.x, su.x, p.H, qv);
   if (ne)
-    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, t.n_elem, elem_list, t.c_e, t.c_ke, t.e_c, t.e_v, sdh.x, su.x, qv,
-                                           p.g, p.H, static_cast<T*>(w.B), static_cast<double*>(w.F),
-                                           static_cast<T*>(w.qe));
+    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, elem_list, t, sdh.x, su.x, qv, p.g, p.H, static_cast<T*>(w.B),
+                                           static_cast<double*>(w.F), static_cast<T*>(w.qe));
   HIPCHK(hipGetLastError());
 }
 

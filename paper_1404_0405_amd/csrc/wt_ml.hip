@@ -8,6 +8,7 @@
 #include <stdexcept>
 #include <string>
 
+#include "wt_body.hpp"
 #include "wt_ml.hpp"
 
 namespace wt {
@@ -32,41 +33,12 @@ static inline unsigned nb(int64_t n) { return unsigned((n + BS - 1) / BS); }
   }
 static inline int64_t span_n(const Span& sp, int64_t dense) { return sp.idx ? sp.n : dense; }
 
-// ------------------------------------------------------------------ shared device helpers
-__device__ __forceinline__ double pair_pred(const DevPair& P, int64_t e, const int32_t* __restrict__ e_v,
-                                            const double* __restrict__ uc) {
-  int32_t tl = e_v[2 * e], tr = e_v[2 * e + 1];
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) s += P.w_pl[9 * e + k] * uc[P.v_sten[9 * tl + k]];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) s += P.w_pr[9 * e + k] * uc[P.v_sten[9 * tr + k]];
-  return s;
-}
-
-__device__ __forceinline__ double int_pred(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
-  double v = 0.0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) v += P.w_int[27 * t + 9 * s + k] * uc[P.v_sten[9 * t + k]];
-  return v;
-}
-
-__device__ __forceinline__ double h_detail(const DevPair& P, int64_t e, const double* __restrict__ hf) {
-  double s = hf[P.mid[e]];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) s -= P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
-  return s;
-}
-
 // ------------------------------------------------------------------ prolongation
-// Inactive even node: the coarse value; inactive odd node: s~-weighted mean of its four even
-// fine neighbours; inactive half-edges: u^j -+ (p1-p2)/2; inactive interior edges: prediction.
 __global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* __restrict__ naf,
                                                      const double* __restrict__ hc, double* __restrict__ hf,
                                                      const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(k, cnt, lst)
-  int32_t f = P.even[k];
-  if (!naf[f]) hf[f] = hc[k];
+  body_prolong_even(k, P, naf, hc, hf);
 }
 
 __global__ __launch_bounds__(BS) void k_prolong_odd_pair(DevPair P, const uint8_t* __restrict__ naf,
@@ -76,31 +48,14 @@ __global__ __launch_bounds__(BS) void k_prolong_odd_pair(DevPair P, const uint8_
                                                          double* __restrict__ hf, double* __restrict__ uf,
                                                          const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(e, cnt, lst)
-  int32_t m = P.mid[e];
-  if (!naf[m]) {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
-    hf[m] = s;
-  }
-  int32_t h1 = P.h1[e], h2 = P.h2[e];
-  bool a1 = eaf[h1], a2 = eaf[h2];
-  if (!a1 || !a2) {
-    double half = 0.5 * pair_pred(P, e, e_v_c, uc);
-    if (!a1) uf[h1] = uc[e] + half;
-    if (!a2) uf[h2] = uc[e] - half;
-  }
+  body_prolong_odd_pair(e, P, naf, eaf, e_v_c, uc, hf, uf);
 }
 
 __global__ __launch_bounds__(BS) void k_prolong_int(DevPair P, const uint8_t* __restrict__ eaf,
                                                     const double* __restrict__ uc, double* __restrict__ uf,
                                                     const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(t, cnt, lst)
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    int32_t f = P.int_e[3 * t + s];
-    if (!eaf[f]) uf[f] = int_pred(P, t, s, uc);
-  }
+  body_prolong_int(t, P, eaf, uc, uf);
 }
 
 void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
@@ -115,33 +70,19 @@ void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const
 
 // ------------------------------------------------------------------ Q, divergence, restriction
 template <typename T>
-__global__ __launch_bounds__(BS) void k_Q(int64_t E, const int32_t* __restrict__ ecp,
-                                          const double* __restrict__ wl, const double* __restrict__ F,
+__global__ __launch_bounds__(BS) void k_Q(int64_t E, DevTables tb, const double* __restrict__ F,
                                           const T* __restrict__ qe, T* __restrict__ Q,
                                           const int32_t* __restrict__ lst) {
   LISTED(e, E, lst)
-  T q0 = qe[e], s = T(0);
-#pragma unroll
-  for (int k = 0; k < 10; ++k) {
-    int32_t ep = ecp[10 * e + k];
-    s += T(wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
-  }
-  Q[e] = s;
+  body_Q<T>(e, tb, F, qe, Q);
 }
 
-template <typename T>
-__global__ __launch_bounds__(BS) void k_div(int64_t N, const int32_t* __restrict__ c_e,
-                                            const double* __restrict__ c_div, const double* __restrict__ F,
+__global__ __launch_bounds__(BS) void k_div(int64_t N, DevTables tf, const double* __restrict__ F,
                                             double* __restrict__ c, const int32_t* __restrict__ lst) {
   LISTED(i, N, lst)
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) s += c_div[6 * i + k] * F[c_e[6 * i + k]];
-  c[i] = s;
+  body_div(i, tf, F, c);
 }
 
-// F^j = R_F(F^{j+1}, c^{j+1}) and Q^j = mean of the half-edges at non-leaf edges;
-// B^j = B^{j+1} at non-leaf nodes.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict_edges(DevPair P, const uint8_t* __restrict__ eaf,
                                                        const double* __restrict__ l_f,
@@ -151,18 +92,7 @@ __global__ __launch_bounds__(BS) void k_restrict_edges(DevPair P, const uint8_t*
                                                        T* __restrict__ Qc, const int32_t* __restrict__ lst,
                                                        int64_t cnt) {
   LISTED(e, cnt, lst)
-  int32_t h1 = P.h1[e], h2 = P.h2[e];
-  if (!(eaf[h1] && eaf[h2])) return;
-  double phi = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    int32_t f = P.rf_f[3 * e + k];
-    phi += P.rf_fw[3 * e + k] * (l_f[f] * Ff[f]);
-  }
-#pragma unroll
-  for (int k = 0; k < RF_NC; ++k) phi += P.rf_cw[RF_NC * e + k] * cf[P.rf_c[RF_NC * e + k]];
-  Fc[e] = phi / l_c[e];
-  Qc[e] = T(0.5) * (Qf[h1] + Qf[h2]);
+  body_restrict_edges<T>(e, P, eaf, l_f, l_c, Ff, cf, Qf, Fc, Qc);
 }
 
 template <typename T>
@@ -170,56 +100,19 @@ __global__ __launch_bounds__(BS) void k_restrict_B(DevPair P, const uint8_t* __r
                                                    const T* __restrict__ Bf, T* __restrict__ Bc,
                                                    const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(k, cnt, lst)
-  int32_t f = P.even[k];
-  if (naf[f]) Bc[k] = Bf[f];
-}
-
-__device__ __forceinline__ void rk_out(int64_t i, double k, const StagePtrs& p, const StageOut& c) {
-  if (p.o1) {
-    double v = c.d1 * k;
-    if (c.a1 != 0.0) v += c.a1 * p.y[i];
-    if (c.b1 != 0.0) v += c.b1 * p.acc[i];
-    if (c.c1 != 0.0) v += c.c1 * p.x[i];
-    p.o1[i] = v;
-  }
-  if (p.o2) {
-    double v = c.d2 * k;
-    if (c.a2 != 0.0) v += c.a2 * p.y[i];
-    if (c.b2 != 0.0) v += c.b2 * p.acc[i];
-    if (c.c2 != 0.0) v += c.c2 * p.x[i];
-    p.o2[i] = v;
-  }
+  body_restrict_B<T>(k, P, naf, Bf, Bc);
 }
 
 // Tendencies at active points of one level with that level's (possibly restricted) F, Q, B,
 // zero elsewhere, followed by the Runge-Kutta stage combination.
 template <typename T>
-__global__ __launch_bounds__(BS) void k_tend_ml(int64_t N, int64_t n_elem, const int32_t* __restrict__ c_e,
-                                                const double* __restrict__ c_div,
-                                                const int32_t* __restrict__ e_c,
-                                                const double* __restrict__ inv_d,
-                                                const uint8_t* __restrict__ na,
+__global__ __launch_bounds__(BS) void k_tend_ml(int64_t N, DevTables tb, const uint8_t* __restrict__ na,
                                                 const uint8_t* __restrict__ ea, const T* __restrict__ B,
                                                 const double* __restrict__ F, const T* __restrict__ Q,
                                                 StagePtrs pdh, StagePtrs pu, StageOut c,
                                                 const int32_t* __restrict__ lst) {
   LISTED(id, N, lst)
-  double k = 0.0;
-  if (na[id]) {
-    double div = 0.0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) div += c_div[6 * id + q] * F[c_e[6 * id + q]];
-    k = -div;
-  }
-  rk_out(id, k, pdh, c);
-  if (id >= n_elem) return;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int64_t e = 3 * id + d;
-    double ku = 0.0;
-    if (ea[e]) ku = double(-Q[e] - (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * T(inv_d[e]));
-    rk_out(e, ku, pu, c);
-  }
+  body_tend_ml<T>(id, tb, na, ea, B, F, Q, pdh, pu, c);
 }
 
 template <typename T>
@@ -235,10 +128,10 @@ void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p,
   const int64_t ne = span_n(led, t.E);
   if (ne == 0) return;
   if (fp32)
-    k_Q<float><<<nb(ne), BS, 0, s>>>(ne, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<float*>(w.qe),
+    k_Q<float><<<nb(ne), BS, 0, s>>>(ne, t, static_cast<double*>(w.F), static_cast<float*>(w.qe),
                                      static_cast<float*>(w.Q), led.idx);
   else
-    k_Q<double><<<nb(ne), BS, 0, s>>>(ne, t.ecp, t.wl, static_cast<double*>(w.F), static_cast<double*>(w.qe),
+    k_Q<double><<<nb(ne), BS, 0, s>>>(ne, t, static_cast<double*>(w.F), static_cast<double*>(w.qe),
                                       static_cast<double*>(w.Q), led.idx);
   HIPCHK(hipGetLastError());
 }
@@ -247,7 +140,7 @@ void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, Dev
                  const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s, Span lfn, Span lce, Span lcn) {
   const int64_t nf = span_n(lfn, tf.N), ne = span_n(lce, P.Ec), nn = span_n(lcn, P.Nc);
   if (fp32) {
-    if (nf) k_div<float><<<nb(nf), BS, 0, s>>>(nf, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c, lfn.idx);
+    if (nf) k_div<<<nb(nf), BS, 0, s>>>(nf, tf, static_cast<double*>(wf.F), wf.c, lfn.idx);
     if (ne)
       k_restrict_edges<float><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
                                                     static_cast<float*>(wf.Q), static_cast<double*>(wc.F),
@@ -256,7 +149,7 @@ void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, Dev
       k_restrict_B<float><<<nb(nn), BS, 0, s>>>(P, naf, static_cast<float*>(wf.B), static_cast<float*>(wc.B),
                                                 lcn.idx, nn);
   } else {
-    if (nf) k_div<double><<<nb(nf), BS, 0, s>>>(nf, tf.c_e, tf.c_div, static_cast<double*>(wf.F), wf.c, lfn.idx);
+    if (nf) k_div<<<nb(nf), BS, 0, s>>>(nf, tf, static_cast<double*>(wf.F), wf.c, lfn.idx);
     if (ne)
       k_restrict_edges<double><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
                                                      static_cast<double*>(wf.Q), static_cast<double*>(wc.F),
@@ -273,11 +166,11 @@ void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* e
   const int64_t n = span_n(lel, t.N);
   if (n == 0) return;
   if (fp32)
-    k_tend_ml<float><<<nb(n), BS, 0, s>>>(n, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
+    k_tend_ml<float><<<nb(n), BS, 0, s>>>(n, t, na, ea,
                                           static_cast<float*>(w.B), static_cast<double*>(w.F),
                                           static_cast<float*>(w.Q), sdh, su, c, lel.idx);
   else
-    k_tend_ml<double><<<nb(n), BS, 0, s>>>(n, t.n_elem, t.c_e, t.c_div, t.e_c, t.inv_d, na, ea,
+    k_tend_ml<double><<<nb(n), BS, 0, s>>>(n, t, na, ea,
                                            static_cast<double*>(w.B), static_cast<double*>(w.F),
                                            static_cast<double*>(w.Q), sdh, su, c, lel.idx);
   HIPCHK(hipGetLastError());
@@ -320,32 +213,7 @@ __global__ __launch_bounds__(BS) void k_partial_h(DevPair P, const int32_t* __re
                                                   const double* __restrict__ hf, double* __restrict__ hc,
                                                   const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(k, cnt, lst)
-  // the conditions combine mask bytes (0 / 1) without early exits, so their loads are issued
-  // together rather than one dependent round trip after another
-  const int32_t ev = P.even[k];
-  int32_t ecs[MK_MAX];
-#pragma unroll
-  for (int q = 0; q < MK_MAX; ++q) ecs[q] = P.mk[MK_MAX * k + q];   // valid entries first, then -1
-  uint32_t ok = nac[k] & naf[ev];
-#pragma unroll
-  for (int q = 0; q < MK_MAX; ++q) {
-    if (ecs[q] >= 0) {
-      const int64_t e = ecs[q] >> 2;
-      ok &= naf[P.mid[e]] & naf[P.even[P.cells[4 * e]]] & naf[P.even[P.cells[4 * e + 1]]] &
-            naf[P.even[P.cells[4 * e + 2]]] & naf[P.even[P.cells[4 * e + 3]]];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const int32_t e = c_e_c[6 * k + q];
-    ok &= eaf[P.h1[e]] & eaf[P.h2[e]];
-  }
-  if (!ok) return;
-  double s = hf[ev];
-#pragma unroll
-  for (int q = 0; q < MK_MAX; ++q)
-    if (ecs[q] >= 0) s += P.s_upd[ecs[q]] * h_detail(P, ecs[q] >> 2, hf);
-  hc[k] = s;
+  body_partial_h(k, P, c_e_c, nac, naf, eaf, hf, hc);
 }
 
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,

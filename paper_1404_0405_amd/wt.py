@@ -91,6 +91,8 @@ SIGNATURES = [
     ("wt_ensemble_adapt", C.c_int, [_P, _D]),
     ("wt_ensemble_step", C.c_int, [_P, _D]),
     ("wt_ensemble_stats", C.c_int, [_P, _I64, _I64]),
+    ("wt_ensemble_set_batched", C.c_int, [_P, C.c_int]),
+    ("wt_ensemble_tuning", C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -402,7 +404,8 @@ class Mlp:
 
 
 class Ensemble:
-    """Members advanced together: one HIP graph launch per ensemble step (wt_ensemble_*)."""
+    """Members advanced together: one HIP graph launch, or one persistent batched launch, per
+    ensemble step (wt_ensemble_*)."""
 
     def __init__(self, grids):
         self._grids = list(grids)   # keeps the members alive
@@ -438,3 +441,13 @@ class Ensemble:
         c, l = C.c_int64(), C.c_int64()
         _check(load().wt_ensemble_stats(self._h, C.byref(c), C.byref(l)))
         return c.value, l.value
+
+    def set_batched(self, on=True):
+        """Later steps as one persistent launch over a work queue (True) or one graph (False)."""
+        _check(load().wt_ensemble_set_batched(self._h, 1 if on else 0))
+
+    def tuning(self):
+        """(workgroups per CU, entries per chunk, tuning finished) of the batched step."""
+        b, c, t = C.c_int(), C.c_int(), C.c_int()
+        _check(load().wt_ensemble_tuning(self._h, C.byref(b), C.byref(c), C.byref(t)))
+        return b.value, c.value, bool(t.value)

@@ -1,5 +1,6 @@
-"""Ensembles on the GPU: one graph launch per ensemble step gives bitwise the states of the
-members stepped one by one, with the blanket zone and with the learned zone."""
+"""Ensembles on the GPU: one graph launch, or one persistent batched launch over a work queue,
+per ensemble step gives bitwise the states of the members stepped one by one, with the blanket
+zone and with the learned zone, in FP64 and with FP32 tendencies."""
 import numpy as np
 import pytest
 
@@ -21,16 +22,18 @@ def _member(p, jmin=4, prec=wt.WT_FP64):
     return g
 
 
-@pytest.mark.parametrize("learned", [False, True])
-def test_ensemble_graph_equals_members_one_by_one(learned):
+@pytest.mark.parametrize("learned,batched", [(False, False), (True, False), (False, True), (True, True)])
+def test_ensemble_graph_equals_members_one_by_one(learned, batched):
     params = inputs.ensemble_members(4, jmax_choices=(5, 6, 7))
-    _say(f"members {[(p['jmax'], p['eps']) for p in params]} learned={learned}")
+    # batched: members of both precisions in one launch
+    precs = [wt.WT_FP32_TENDENCY if (batched and k % 2) else wt.WT_FP64 for k in range(len(params))]
+    _say(f"members {[(p['jmax'], p['eps']) for p in params]} learned={learned} batched={batched}")
     nsteps = 5
     mlp = wt.Mlp(inputs.mlp_init()) if learned else None
     # one by one
     ref = []
-    for p in params:
-        g = _member(p)
+    for p, prec in zip(params, precs):
+        g = _member(p, prec=prec)
         with g:
             if learned:
                 g.set_predictor(mlp, 0.5)
@@ -40,16 +43,22 @@ def test_ensemble_graph_equals_members_one_by_one(learned):
                 g.step(dt)
             ref.append(([g.get_state(j) for j in range(g.jmin, g.jmax + 1)], g.redo_count(), dt))
     # ensemble
-    grids = [_member(p) for p in params]
+    grids = [_member(p, prec=prec) for p, prec in zip(params, precs)]
     if learned:
         for g in grids:
             g.set_predictor(mlp, 0.5)
     dts = [r[2] for r in ref]
     with wt.Ensemble(grids) as ens:
+        if batched:
+            ens.set_batched(True)
         for _ in range(nsteps):
             ens.adapt([p["eps"] for p in params])
             ens.step(dts)
         captures, launches = ens.stats()
+        if batched:
+            bpc, chunk, tuned = ens.tuning()
+            _say(f"batched launch shape {bpc} workgroups/CU, {chunk} entries/chunk, tuned={tuned}")
+            assert bpc >= 1 and chunk >= 256
     assert launches == nsteps and 1 <= captures <= nsteps
     for g, (states, redo, _) in zip(grids, ref):
         got = [g.get_state(j) for j in range(g.jmin, g.jmax + 1)]
@@ -68,3 +77,11 @@ def test_ensemble_rejects_shared_grid():
     with g:
         with pytest.raises(wt.WtError):
             wt.Ensemble([g, g])
+
+
+def test_batched_ensemble_rejects_single_level_member():
+    g1, g2 = wt.Grid(3, 4, 8), wt.Grid(4, 4, 8)
+    with g1, g2:
+        with wt.Ensemble([g1, g2]) as ens:
+            with pytest.raises(wt.WtError):
+                ens.set_batched(True)

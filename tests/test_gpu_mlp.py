@@ -105,7 +105,8 @@ def test_training_lowers_loss():
             m.train_step(x, y, 3e-3, want_loss=False)
         l1 = m.gradient(x, y)[1]
         p = torch.empty((n, 4), dtype=torch.float32, device="cuda")
-        m.forward(x, p)
+        m.forward(x, p)   # asynchronous on the network's stream
+        torch.cuda.synchronize()
         acc = float(((p.cpu().numpy() > 0.5) == (Y > 0.5)).mean())
     _say(f"loss {l0:.4f} -> {l1:.4f}, accuracy {acc:.4f}")
     assert l1 < 0.35 * l0
