@@ -216,10 +216,11 @@ def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, warmup=2, ensemble_members=
     return out
 
 
-def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=6, mlp=None):
+def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=10, mlp=None):
     """Ensemble of jet members (seeded bump amplitude/position, Jmax and eps drawn per member),
     FP32 tendencies / FP64 state, learned zone when a network is given: one graph launch per
-    ensemble step, against the same members stepped one after another (same grids, state set
+    ensemble step, and one persistent batched launch per step (its launch shape tuned during the
+    first steps), against the same members stepped one after another (same grids, state set
     again in between)."""
     import torch
     from paper_1404_0405_amd import inputs, wt
@@ -235,17 +236,16 @@ def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=6, mlp=None):
         init.append((p["jmax"], dh, u))
     build_s = time.perf_counter() - t0
 
-    def reset():
+    def reset(net):
         for g, (j, dh, u) in zip(grids, init):
             g.set_state(j, dh, u)
-            if mlp is not None:
-                g.set_predictor(mlp, 0.5)
+            g.set_predictor(net, 0.5)
 
-    reset()
+    reset(None)
     dts = [g.suggest_dt(0.8) for g in grids]
     eps = [p["eps"] for p in params]
     out = {"members": members, "jmin": jmin, "jmax": [p["jmax"] for p in params], "eps": eps,
-           "grid_build_s": build_s, "learned": mlp is not None}
+           "grid_build_s": build_s, "steps": steps}
 
     def active():
         tot = 0
@@ -254,39 +254,57 @@ def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=6, mlp=None):
             tot += sum(d.active_nodes) + sum(d.active_edges)
         return tot
 
-    # one by one
-    wall, act = 0.0, 0
-    for _ in range(steps):
-        for g, e, dt in zip(grids, eps, dts):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            g.adapt(e)
-            g.step(dt)
-            torch.cuda.synchronize()
-            wall += time.perf_counter() - t1
-        act += active()
-    redo0 = sum(g.redo_count() for g in grids)
-    out["one_by_one"] = {"value": act * 4 / wall, "ms_per_step": wall * 1e3 / steps, "redo": redo0}
-    reset()
-    wall, wall_step, act = 0.0, 0.0, 0
-    with wt.Ensemble(grids) as ens:
+    def redos():
+        return sum(g.redo_count() for g in grids)
+
+    def one_by_one(net):
+        reset(net)
+        wall, act, r0 = 0.0, 0, redos()
         for _ in range(steps):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            ens.adapt(eps)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            ens.step(dts)
-            t3 = time.perf_counter()
-            wall += t3 - t1
-            wall_step += t3 - t2
+            for g, e, dt in zip(grids, eps, dts):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                g.adapt(e)
+                g.step(dt)
+                torch.cuda.synchronize()
+                wall += time.perf_counter() - t1
             act += active()
-        caps, launches = ens.stats()
-    out["graph"] = {"value": act * 4 / wall, "ms_per_step": wall * 1e3 / steps,
-                    "ms_graph_step": wall_step * 1e3 / steps, "captures": caps, "launches": launches,
-                    "redo": sum(g.redo_count() for g in grids) - redo0}
-    out["active_dof_per_step"] = act / steps
-    out["speedup_graph_over_one_by_one"] = out["graph"]["value"] / out["one_by_one"]["value"]
+        return {"value": act * 4 / wall, "ms_per_step": wall * 1e3 / steps, "redo": redos() - r0}, act
+
+    def run_ens(net, batched):
+        reset(net)
+        wall, wall_step, act, r0 = 0.0, 0.0, 0, redos()
+        with wt.Ensemble(grids) as ens:
+            if batched:
+                ens.set_batched(True)
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ens.adapt(eps)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                ens.step(dts)
+                t3 = time.perf_counter()
+                wall += t3 - t1
+                wall_step += t3 - t2
+                act += active()
+            caps, launches = ens.stats()
+            shape = ens.tuning() if batched else None
+        r = {"value": act * 4 / wall, "ms_per_step": wall * 1e3 / steps, "ms_step_call": wall_step * 1e3 / steps,
+             "captures": caps, "launches": launches, "redo": redos() - r0}
+        if shape:
+            r["launch_shape"] = shape
+        return r
+
+    for name, net in (("plain", None), ("learned", mlp)):
+        if name == "learned" and mlp is None:
+            continue
+        res, act = one_by_one(net)
+        res = {"one_by_one": res, "graph": run_ens(net, False), "batched": run_ens(net, True),
+               "active_dof_per_step": act / steps}
+        res["speedup_graph_over_one_by_one"] = res["graph"]["value"] / res["one_by_one"]["value"]
+        res["speedup_batched_over_one_by_one"] = res["batched"]["value"] / res["one_by_one"]["value"]
+        out[name] = res
     for g in grids:
         g.close()
     return out

@@ -337,14 +337,16 @@ int wt_ensemble_stats(const wt_ensemble* e, int64_t* captures, int64_t* launches
  * member, level or pair and kernel) are cut into chunks of consecutive work-list entries that the
  * workgroups take from a global work queue (an atomic counter per phase).  Every entry runs the
  * same per-point code as the unbatched step, so results are bitwise those of stepping the members
- * one by one.  The launch shape (workgroups per CU, entries per chunk) is tuned on line: the first
- * steps each try one candidate, timed with events on the ensemble's stream, and the fastest is
- * kept.  Every member must be multilevel (jmin < jmax); WT_EINVAL otherwise.  on = 0 returns to
+ * one by one.  The launch shape (workgroups per CU, entries per chunk, work queue or a fixed
+ * round-robin deal of the chunks) is tuned on line: the first steps each try one candidate, timed
+ * with events on the ensemble's stream, and the fastest is kept.  Every member must be multilevel (jmin < jmax); WT_EINVAL otherwise.  on = 0 returns to
  * the graph step. */
 int wt_ensemble_set_batched(wt_ensemble* e, int on);
-/* Launch shape in use (workgroups per CU, entries per chunk; 0 before the first batched step)
- * and whether tuning has finished (*tuned = 1).  Any pointer may be NULL. */
-int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* tuned);
+/* Launch shape in use (workgroups per CU, entries per chunk, *queue = 1: chunks from the work
+ * queue, 0: dealt round-robin; zeros before the first batched step), whether tuning has finished
+ * (*tuned = 1) and the device time of the last batched launch in ms.  Any pointer may be NULL. */
+int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* queue, int* tuned,
+                       float* last_ms);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);

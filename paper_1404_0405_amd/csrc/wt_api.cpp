@@ -1358,12 +1358,18 @@ struct wt_ensemble {
   bool plan_ok = false;
   wt::BatchPlan plan;
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  // launch-shape tuning: each candidate (workgroups per CU, chunk entries) runs one step, the
-  // fastest is kept
-  std::vector<std::pair<int, int>> cand;
+  // launch-shape tuning: each candidate (workgroups per CU, chunk entries, work queue or
+  // round-robin deal) runs one step, the fastest is kept
+  struct Shape {
+    int bpc, chunk;
+    bool queue;
+  };
+  std::vector<Shape> cand;
   std::vector<float> cand_ms;
   int bpc = 0, chunk = 0;
+  bool queue = false;
   bool tuned = false;
+  float last_ms = 0.f;   // device time of the last batched launch
 };
 
 // The batched step replays the phases of ml_step for every member at once (same per-point code
@@ -1494,18 +1500,22 @@ static void batched_step(wt_ensemble* e, const double* dt) {
   if (e->cand.empty()) {
     const int maxb = batch_max_blocks_per_cu();
     if (maxb < 1) throw std::runtime_error("the batch kernel does not fit on a CU");
-    for (int b : {1, 2, 4, 8})
+    for (int b : {1, 2})
       if (b <= maxb)
-        for (int c : {256, 1024}) e->cand.push_back({b, c});
-    e->bpc = e->cand[0].first;
-    e->chunk = e->cand[0].second;
+        for (int c : {256, 1024})
+          for (bool q : {false, true}) e->cand.push_back({b, c, q});
+    e->bpc = e->cand[0].bpc;
+    e->chunk = e->cand[0].chunk;
+    e->queue = e->cand[0].queue;
   }
   // launch shape of this step: the next untried candidate while tuning
   int bpc = e->bpc, chunk = e->chunk;
+  bool queue = e->queue;
   const size_t tried = e->cand_ms.size();
   if (!e->tuned) {
-    bpc = e->cand[tried].first;
-    chunk = e->cand[tried].second;
+    bpc = e->cand[tried].bpc;
+    chunk = e->cand[tried].chunk;
+    queue = e->cand[tried].queue;
   }
   bool stale = !e->plan_ok || e->dts.size() != n;
   for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
@@ -1526,18 +1536,20 @@ static void batched_step(wt_ensemble* e, const double* dt) {
     HIPCHK(hipEventCreate(&e->t1));
   }
   HIPCHK(hipEventRecord(e->t0, e->s0));
-  batch_launch(e->plan, bpc, e->s0);
+  batch_launch(e->plan, bpc, queue, e->s0);
   HIPCHK(hipEventRecord(e->t1, e->s0));
-  HIPCHK(hipStreamSynchronize(e->s0));
+  batch_check(e->plan, e->s0);
   ++e->launches;
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e->t0, e->t1));
+  e->last_ms = ms;
   if (!e->tuned) {
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, e->t0, e->t1));
     e->cand_ms.push_back(ms);
     if (e->cand_ms.size() == e->cand.size()) {
       const size_t best = size_t(std::min_element(e->cand_ms.begin(), e->cand_ms.end()) - e->cand_ms.begin());
-      e->bpc = e->cand[best].first;
-      e->chunk = e->cand[best].second;
+      e->bpc = e->cand[best].bpc;
+      e->chunk = e->cand[best].chunk;
+      e->queue = e->cand[best].queue;
       e->tuned = true;
     }
   }
@@ -1694,11 +1706,14 @@ int wt_ensemble_set_batched(wt_ensemble* e, int on) {
   return WT_OK;
 }
 
-int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* tuned) {
+int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* queue, int* tuned,
+                       float* last_ms) {
   if (!e) return fail(WT_EINVAL, "wt_ensemble_tuning: null ensemble");
   if (blocks_per_cu) *blocks_per_cu = e->bpc;
   if (chunk) *chunk = e->chunk;
+  if (queue) *queue = e->queue ? 1 : 0;
   if (tuned) *tuned = e->tuned ? 1 : 0;
+  if (last_ms) *last_ms = e->last_ms;
   return WT_OK;
 }
 

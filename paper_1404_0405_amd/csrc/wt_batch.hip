@@ -1,7 +1,6 @@
 // Batched persistent Runge-Kutta step of an ensemble (the phases and the work queue are
 // described in wt_batch.hpp).
 #include <hip/hip_runtime.h>
-#include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
 #include <stdexcept>
@@ -11,8 +10,6 @@
 #include "wt_body.hpp"
 
 namespace wt {
-
-namespace cg = cooperative_groups;
 
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
@@ -98,22 +95,76 @@ __device__ __forceinline__ void batch_entry(const BatchJob& jb, int64_t i, const
   }
 }
 
-// Every workgroup takes chunks of the current phase from the phase's counter until none is left;
-// the grid synchronises (with device-wide visibility of the writes) before the next phase.  The
-// loop exits are uniform per workgroup, so every workgroup reaches every grid barrier.
+// Grid barrier of phase p, a two-level tree: workgroups arrive on the counter of their group
+// (blockIdx mod BAR_GROUPS), the last of a group on the phase's top counter, the last group sets
+// the phase's done flag that every workgroup waits for.  Each phase has its own counters (zeroed
+// before the launch), so nothing is reused.  The wait is bounded: past the limit the workgroup
+// records the failure in *err and goes on (the host turns it into an error), and a workgroup
+// that finds *err set does not wait at all, so the kernel always ends.
+constexpr int BAR_GROUPS = 8, BAR_STRIDE = 32;   // counters one 128-byte line apart
+constexpr int BAR_SLOTS = BAR_GROUPS + 2;        // group counters, top counter, done flag
+constexpr uint32_t BAR_SPIN_LIMIT = 1u << 20;
+
+__device__ __forceinline__ void batch_barrier(uint32_t* __restrict__ bar, int p, uint32_t* __restrict__ err) {
+  // every wave waits for its own outstanding memory operations (all counters zero), so once the
+  // workgroup barrier is passed the workgroup's stores sit in the caches, and one device-scope
+  // release by the arriving thread (a write-back of its cache) covers them all
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // release of this workgroup's writes; the counters themselves are relaxed, with acquire
+    // fences where a thread learns that others have arrived and a release before it passes that on
+    __threadfence();
+    const uint32_t nwg = gridDim.x, g = blockIdx.x % BAR_GROUPS;
+    const uint32_t gsize = nwg / BAR_GROUPS + (g < nwg % BAR_GROUPS ? 1u : 0u);
+    const uint32_t ngroups = nwg < uint32_t(BAR_GROUPS) ? nwg : uint32_t(BAR_GROUPS);
+    uint32_t* base = bar + size_t(p) * BAR_SLOTS * BAR_STRIDE;
+    uint32_t* done = base + (BAR_GROUPS + 1) * BAR_STRIDE;
+    if (__hip_atomic_fetch_add(base + g * BAR_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");   // the group's writes, passed on
+      if (__hip_atomic_fetch_add(base + BAR_GROUPS * BAR_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+          ngroups - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    // poll without cache maintenance; one acquire fence once the flag is seen
+    uint32_t spins = 0;
+    while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      if (++spins > BAR_SPIN_LIMIT) {
+        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the caches this workgroup reads drop stale lines
+  }
+  __syncthreads();
+}
+
+// Every workgroup takes chunks of the current phase until none is left -- from the phase's counter
+// (dynamic, queue != 0) or every gridDim-th chunk from its own index (static) -- then waits at the
+// phase's grid barrier.  The loop exits are uniform per workgroup, so every workgroup reaches
+// every barrier.
 __global__ __launch_bounds__(BB) void k_batch(const BatchLevel* __restrict__ LV, const BatchPair* __restrict__ PR,
                                               const BatchJob* __restrict__ JB, const BatchChunk* __restrict__ CH,
-                                              const BatchPhase* __restrict__ PH, int nphase, int chunk,
-                                              int32_t* __restrict__ ctr) {
-  cg::grid_group grid = cg::this_grid();
+                                              const BatchPhase* __restrict__ PH, int nphase, int chunk, int queue,
+                                              int32_t* __restrict__ ctr, uint32_t* __restrict__ bar,
+                                              uint32_t* __restrict__ err) {
   __shared__ int32_t s_c;
   for (int p = 0; p < nphase; ++p) {
     const BatchPhase ph = PH[p];
-    for (;;) {
-      if (threadIdx.x == 0) s_c = ph.c0 + atomicAdd(&ctr[p], 1);
-      __syncthreads();
-      const int32_t c = __builtin_amdgcn_readfirstlane(s_c);
-      __syncthreads();   // the next grab rewrites s_c
+    for (int32_t k = 0;; ++k) {
+      int32_t c;
+      if (queue) {
+        if (threadIdx.x == 0) s_c = ph.c0 + atomicAdd(&ctr[p], 1);
+        __syncthreads();
+        c = __builtin_amdgcn_readfirstlane(s_c);
+        __syncthreads();   // the next grab rewrites s_c
+      } else {
+        c = ph.c0 + int32_t(blockIdx.x) + k * int32_t(gridDim.x);
+      }
       if (c >= ph.c1) break;
       const BatchChunk ck = CH[c];
       const BatchJob jb = JB[ck.job];
@@ -128,18 +179,26 @@ __global__ __launch_bounds__(BB) void k_batch(const BatchLevel* __restrict__ LV,
         else batch_entry<double>(jb, i, LV, PR);
       }
     }
-    __threadfence();
-    grid.sync();
+    batch_barrier(bar, p, err);
   }
 }
 
+// device words of a plan's counters: one work-queue counter per phase, BAR_SLOTS barrier lines
+// per phase, the error flag
+static size_t ctr_words(size_t nphase) {
+  return ((nphase + BAR_STRIDE - 1) / BAR_STRIDE) * BAR_STRIDE + nphase * BAR_SLOTS * BAR_STRIDE + BAR_STRIDE;
+}
+static size_t ctr_bytes(size_t nphase) { return std::max<size_t>(1, ctr_words(nphase)) * sizeof(uint32_t); }
+
+// copies v to the device buffer d (grown when too small; cap counts elements)
 template <typename X>
-static X* upload_vec(const std::vector<X>& v, X* old, hipStream_t s) {
-  if (old) HIPCHK(hipFree(old));
-  X* d = nullptr;
-  HIPCHK(hipMalloc(&d, std::max<size_t>(1, v.size()) * sizeof(X)));
+static void upload_vec(const std::vector<X>& v, X*& d, size_t& cap, hipStream_t s) {
+  if (!d || cap < v.size()) {
+    if (d) HIPCHK(hipFree(d));
+    cap = std::max<size_t>(1, v.size() + v.size() / 2);
+    HIPCHK(hipMalloc(&d, cap * sizeof(X)));
+  }
   if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s));
-  return d;
 }
 
 void BatchPlan::upload(int chunk_entries, hipStream_t s) {
@@ -156,13 +215,17 @@ void BatchPlan::upload(int chunk_entries, hipStream_t s) {
   if (ch.size() >= size_t(1) << 30) throw std::runtime_error("batch plan: too many chunks");
   // the previous tables may still be read by a queued launch
   HIPCHK(hipStreamSynchronize(s));
-  d_levels = upload_vec(levels, d_levels, s);
-  d_pairs = upload_vec(pairs, d_pairs, s);
-  d_jobs = upload_vec(jobs, d_jobs, s);
-  d_chunks = upload_vec(ch, d_chunks, s);
-  d_phases = upload_vec(ph, d_phases, s);
-  if (d_ctr) HIPCHK(hipFree(d_ctr));
-  HIPCHK(hipMalloc(&d_ctr, std::max<size_t>(1, ph.size()) * sizeof(int32_t)));
+  upload_vec(levels, d_levels, cap[0], s);
+  upload_vec(pairs, d_pairs, cap[1], s);
+  upload_vec(jobs, d_jobs, cap[2], s);
+  upload_vec(ch, d_chunks, cap[3], s);
+  upload_vec(ph, d_phases, cap[4], s);
+  // work-queue counters, then the barrier slots of every phase, then the error flag
+  if (!d_ctr || cap[5] < ctr_bytes(ph.size())) {
+    if (d_ctr) HIPCHK(hipFree(d_ctr));
+    cap[5] = ctr_bytes(ph.size() + ph.size() / 2);
+    HIPCHK(hipMalloc(&d_ctr, cap[5]));
+  }
   HIPCHK(hipStreamSynchronize(s));   // the host vectors of the copies are temporaries
   chunk = chunk_entries;
   nphase = int(ph.size());
@@ -173,6 +236,7 @@ void BatchPlan::release() {
   void* ps[] = {d_levels, d_pairs, d_jobs, d_chunks, d_phases, d_ctr};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  for (auto& c : cap) c = 0;
   d_levels = nullptr;
   d_pairs = nullptr;
   d_jobs = nullptr;
@@ -198,23 +262,38 @@ int batch_cu_count() {
   return cus;
 }
 
-void batch_launch(BatchPlan& plan, int blocks_per_cu, hipStream_t s) {
+void batch_launch(BatchPlan& plan, int blocks_per_cu, bool queue, hipStream_t s) {
   if (plan.nphase == 0) return;
   const int maxb = batch_max_blocks_per_cu();
   if (blocks_per_cu < 1 || blocks_per_cu > maxb)
     throw std::runtime_error("batch step: " + std::to_string(blocks_per_cu) + " workgroups per CU, at most " +
                              std::to_string(maxb) + " fit");
-  HIPCHK(hipMemsetAsync(plan.d_ctr, 0, size_t(plan.nphase) * sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(plan.d_ctr, 0, ctr_bytes(size_t(plan.nphase)), s));
   const BatchLevel* lv = plan.d_levels;
   const BatchPair* pr = plan.d_pairs;
   const BatchJob* jb = plan.d_jobs;
   const BatchChunk* ch = plan.d_chunks;
   const BatchPhase* ph = plan.d_phases;
-  int nphase = plan.nphase, chunk = plan.chunk;
+  int nphase = plan.nphase, chunk = plan.chunk, use_queue = queue ? 1 : 0;
+  const size_t q0 = ((size_t(nphase) + BAR_STRIDE - 1) / BAR_STRIDE) * BAR_STRIDE;
   int32_t* ctr = plan.d_ctr;
-  void* args[] = {&lv, &pr, &jb, &ch, &ph, &nphase, &chunk, &ctr};
+  uint32_t* bar = reinterpret_cast<uint32_t*>(plan.d_ctr) + q0;
+  uint32_t* err = bar + size_t(nphase) * BAR_SLOTS * BAR_STRIDE;
+  void* args[] = {&lv, &pr, &jb, &ch, &ph, &nphase, &chunk, &use_queue, &ctr, &bar, &err};
   const dim3 grid(unsigned(blocks_per_cu * batch_cu_count()));
+  // cooperative: the runtime refuses a grid whose workgroups cannot all be resident at once,
+  // which the barriers need
   HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batch), grid, dim3(BB), args, 0, s));
+}
+
+void batch_check(const BatchPlan& plan, hipStream_t s) {
+  if (plan.nphase == 0) return;
+  const size_t q0 = ((size_t(plan.nphase) + BAR_STRIDE - 1) / BAR_STRIDE) * BAR_STRIDE;
+  const uint32_t* err = reinterpret_cast<const uint32_t*>(plan.d_ctr) + q0 + size_t(plan.nphase) * BAR_SLOTS * BAR_STRIDE;
+  uint32_t h = 0;
+  HIPCHK(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h) throw std::runtime_error("batch step: a grid barrier timed out (results of this step are invalid)");
 }
 
 }  // namespace wt

@@ -5,7 +5,8 @@
 // intermediates of all levels, the restriction chain bottom-up, the tendencies, per stage; then the
 // partial height transform).  A phase holds the (member, level or pair) jobs that can run at the
 // same time; its work is cut into chunks of consecutive list entries of one job, handed out by an
-// atomic counter, and the whole grid synchronises between phases.  Each entry is evaluated by the
+// atomic counter (a work queue) or dealt round-robin, and the whole grid meets at a barrier
+// between phases.  Each entry is evaluated by the
 // same per-point code as the one-launch-per-kernel path, so results are identical.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -70,7 +71,8 @@ struct BatchPlan {
   BatchJob* d_jobs = nullptr;
   BatchChunk* d_chunks = nullptr;
   BatchPhase* d_phases = nullptr;
-  int32_t* d_ctr = nullptr;   // one work-queue counter per phase
+  int32_t* d_ctr = nullptr;   // work-queue counters, barrier slots and error flag of the phases
+  size_t cap[6] = {0, 0, 0, 0, 0, 0};   // allocated sizes of the six device buffers
   int chunk = 0;              // entries per chunk the tables were cut for
   int nphase = 0;
   int64_t nchunk = 0;
@@ -82,7 +84,10 @@ struct BatchPlan {
 // Largest cooperative grid (workgroups per CU x CUs) the device holds for the batch kernel.
 int batch_max_blocks_per_cu();
 int batch_cu_count();
-// One step: clears the counters and launches blocks_per_cu x CUs workgroups cooperatively.
-void batch_launch(BatchPlan& plan, int blocks_per_cu, hipStream_t s);
+// One step: clears the counters and launches blocks_per_cu x CUs workgroups cooperatively;
+// queue: chunks from the per-phase work queue, else a fixed round-robin deal of the chunks.
+void batch_launch(BatchPlan& plan, int blocks_per_cu, bool queue, hipStream_t s);
+// After a step: synchronises and throws if a grid barrier's bounded wait ran out.
+void batch_check(const BatchPlan& plan, hipStream_t s);
 
 }  // namespace wt

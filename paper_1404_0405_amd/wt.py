@@ -92,7 +92,8 @@ SIGNATURES = [
     ("wt_ensemble_step", C.c_int, [_P, _D]),
     ("wt_ensemble_stats", C.c_int, [_P, _I64, _I64]),
     ("wt_ensemble_set_batched", C.c_int, [_P, C.c_int]),
-    ("wt_ensemble_tuning", C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("wt_ensemble_tuning", C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     ("wt_last_error", C.c_char_p, []),
 ]
 
@@ -447,7 +448,9 @@ class Ensemble:
         _check(load().wt_ensemble_set_batched(self._h, 1 if on else 0))
 
     def tuning(self):
-        """(workgroups per CU, entries per chunk, tuning finished) of the batched step."""
-        b, c, t = C.c_int(), C.c_int(), C.c_int()
-        _check(load().wt_ensemble_tuning(self._h, C.byref(b), C.byref(c), C.byref(t)))
-        return b.value, c.value, bool(t.value)
+        """Launch shape of the batched step: dict of workgroups per CU, entries per chunk, work
+        queue (else round-robin), tuning finished, device ms of the last launch."""
+        b, c, q, t, ms = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_float()
+        _check(load().wt_ensemble_tuning(self._h, C.byref(b), C.byref(c), C.byref(q), C.byref(t), C.byref(ms)))
+        return {"workgroups_per_cu": b.value, "chunk_entries": c.value, "work_queue": bool(q.value),
+                "tuned": bool(t.value), "last_launch_ms": ms.value}

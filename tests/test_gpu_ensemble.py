@@ -56,9 +56,9 @@ def test_ensemble_graph_equals_members_one_by_one(learned, batched):
             ens.step(dts)
         captures, launches = ens.stats()
         if batched:
-            bpc, chunk, tuned = ens.tuning()
-            _say(f"batched launch shape {bpc} workgroups/CU, {chunk} entries/chunk, tuned={tuned}")
-            assert bpc >= 1 and chunk >= 256
+            shape = ens.tuning()
+            _say(f"batched launch shape {shape}")
+            assert shape["workgroups_per_cu"] >= 1 and shape["chunk_entries"] >= 256 and shape["last_launch_ms"] > 0
     assert launches == nsteps and 1 <= captures <= nsteps
     for g, (states, redo, _) in zip(grids, ref):
         got = [g.get_state(j) for j in range(g.jmin, g.jmax + 1)]
