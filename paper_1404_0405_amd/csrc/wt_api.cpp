@@ -10,6 +10,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -675,6 +676,33 @@ static int64_t judge_gated_step(wt_grid* g) {
   int64_t total = 0;
   for (int q = 0; q < k; ++q) total += int64_t(g->host_val[q]);
   return total;
+}
+
+// fn(k) for every member k, members spread over host threads (each member has its own stream,
+// so their kernels overlap on the device); the first failure (in member order) is returned with
+// its message.  fn returns WT_OK or an error code and leaves its message in g_err.
+template <typename Fn>
+static int for_members(size_t n, Fn fn) {
+  std::vector<int> rc(n, WT_OK);
+  std::vector<std::string> msg(n);
+  const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>({n, hw, size_t(16)});
+  auto work = [&](size_t t0) {
+    for (size_t k = t0; k < n; k += nt) {
+      rc[k] = fn(k);
+      if (rc[k] != WT_OK) msg[k] = g_err;
+    }
+  };
+  if (nt <= 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < nt; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+  for (size_t k = 0; k < n; ++k)
+    if (rc[k] != WT_OK) return fail(rc[k], msg[k]);
+  return WT_OK;
 }
 
 // Host tables are expensive to build (seconds at level 9) and depend only on the level (pairs:
@@ -1602,11 +1630,7 @@ void wt_ensemble_destroy(wt_ensemble* e) {
 
 int wt_ensemble_adapt(wt_ensemble* e, const double* eps) {
   if (!e || !eps) return fail(WT_EINVAL, "wt_ensemble_adapt: null argument");
-  for (size_t k = 0; k < e->m.size(); ++k) {
-    const int rc = wt_adapt(e->m[k], eps[k]);
-    if (rc != WT_OK) return rc;
-  }
-  return WT_OK;
+  return for_members(e->m.size(), [&](size_t k) { return wt_adapt(e->m[k], eps[k]); });
 }
 
 int wt_ensemble_step(wt_ensemble* e, const double* dt) {
@@ -1666,10 +1690,15 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
       HIPCHK(hipStreamSynchronize(e->s0));
       ++e->launches;
     }
-    // the threshold test of the learned zone needs the host: members judged one by one
-    for (size_t k = 0; k < n; ++k) {
-      wt_grid* m = e->m[k];
-      if (!m->multi() || !m->gated) continue;
+  } catch (const std::exception& x) {
+    return fail(WT_EDEVICE, std::string("wt_ensemble_step: ") + x.what());
+  }
+  // the threshold test of the learned zone needs the host: each member judged (and redone if
+  // needed) on its own stream, members spread over host threads
+  return for_members(n, [&](size_t k) {
+    wt_grid* m = e->m[k];
+    if (!m->multi() || !m->gated) return int(WT_OK);
+    try {
       m->gated = false;
       if (judge_gated_step(m) > 0) {
         snapshot(m, true);
@@ -1678,11 +1707,11 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
         ++m->redo;
       }
       HIPCHK(hipStreamSynchronize(m->stream));
+    } catch (const std::exception& x) {
+      return fail(WT_EDEVICE, std::string("wt_ensemble_step: ") + x.what());
     }
-  } catch (const std::exception& x) {
-    return fail(WT_EDEVICE, std::string("wt_ensemble_step: ") + x.what());
-  }
-  return WT_OK;
+    return int(WT_OK);
+  });
 }
 
 int wt_ensemble_set_batched(wt_ensemble* e, int on) {
