@@ -693,13 +693,16 @@ static int for_members(size_t n, Fn fn) {
       if (rc[k] != WT_OK) msg[k] = g_err;
     }
   };
-  if (nt <= 1) {
-    work(0);
-  } else {
-    std::vector<std::thread> th;
-    for (size_t t = 0; t < nt; ++t) th.emplace_back(work, t);
-    for (auto& x : th) x.join();
+  std::vector<std::thread> th;
+  size_t started = 0;
+  try {
+    for (size_t t = 1; t < nt; ++t, ++started) th.emplace_back(work, t);
+  } catch (const std::exception&) {
+    // no more threads: the calling thread takes the shares that were not started
   }
+  work(0);
+  for (size_t t = started + 1; t < nt; ++t) work(t);
+  for (auto& x : th) x.join();
   for (size_t k = 0; k < n; ++k)
     if (rc[k] != WT_OK) return fail(rc[k], msg[k]);
   return WT_OK;
