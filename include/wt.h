@@ -348,6 +348,19 @@ int wt_ensemble_set_batched(wt_ensemble* e, int on);
 int wt_ensemble_tuning(const wt_ensemble* e, int* blocks_per_cu, int* chunk, int* queue, int* tuned,
                        float* last_ms);
 
+/* Checkpoint / restart.  wt_save writes the grid's state to the file `path` (binary): levels,
+ * patch size, parameters, the thresholds of the last adapt and the redo count, then per level
+ * the raw state of every point (active or not) and the masks.  wt_load reads such a file into a
+ * grid created with the same jmin, jmax and patch (and the same radius and rotation rate; the
+ * other parameters are taken from the file), rebuilds the work lists and leaves the grid ready
+ * to step: continuing from a loaded checkpoint gives bitwise the states of continuing the saved
+ * run (a learned predictor is not part of the file; set it again).  Errors: WT_EINVAL for a
+ * null argument, an unreadable or unwritable path, or a file that is not a checkpoint of this
+ * grid's shape (the grid is then unchanged); WT_ESTATE for wt_save without a state;
+ * WT_EDEVICE for a device failure. */
+int wt_save(wt_grid* g, const char* path);
+int wt_load(wt_grid* g, const char* path);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* wt_last_error(void);
 

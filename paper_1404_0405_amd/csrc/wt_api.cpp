@@ -955,6 +955,120 @@ int wt_set_state_device(wt_grid* g, int level, const void* dh, const void* u) {
   return set_state_impl(g, level, dh, u, hipMemcpyDeviceToDevice);
 }
 
+// Checkpoint file: magic, the grid's shape and parameters, the learned-zone thresholds and redo
+// count, then per level the raw device state (every point, active or not) and the masks.
+static const char kCkptMagic[8] = {'W', 'T', 'C', 'K', 'P', 'T', '0', '1'};
+static const char kCkptEnd[8] = {'W', 'T', 'C', 'K', 'P', 'E', 'N', 'D'};
+
+int wt_save(wt_grid* g, const char* path) {
+  if (!g || !path) return fail(WT_EINVAL, "wt_save: null argument");
+  if (!g->have_state) return fail(WT_ESTATE, "wt_save: no state loaded");
+  std::FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(WT_EINVAL, std::string("wt_save: cannot open ") + path);
+  bool ok = true;
+  auto put = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
+  try {
+    const int32_t head[4] = {g->jmin, g->jmax, g->patch, int32_t(sizeof(wt_params))};
+    const double lasts[3] = {g->last_eps, g->last_eh, g->last_eu};
+    put(kCkptMagic, 8);
+    put(head, sizeof(head));
+    put(&g->prm, sizeof(wt_params));
+    put(lasts, sizeof(lasts));
+    put(&g->redo, sizeof(int64_t));
+    std::vector<double> hv;
+    std::vector<uint8_t> hm;
+    for (auto& lp : g->lev) {
+      LevelState& l = *lp;
+      const int64_t ne[2] = {l.tab.N, l.tab.E};
+      put(ne, sizeof(ne));
+      hv.resize(size_t(l.tab.N + l.tab.E));
+      hm.resize(size_t(l.tab.N + l.tab.E));
+      HIPCHK(hipMemcpyAsync(hv.data(), l.work.dh, l.tab.N * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+      HIPCHK(hipMemcpyAsync(hv.data() + l.tab.N, l.work.u, l.tab.E * sizeof(double), hipMemcpyDeviceToHost,
+                            g->stream));
+      HIPCHK(hipMemcpyAsync(hm.data(), l.na, l.tab.N, hipMemcpyDeviceToHost, g->stream));
+      HIPCHK(hipMemcpyAsync(hm.data() + l.tab.N, l.ea, l.tab.E, hipMemcpyDeviceToHost, g->stream));
+      HIPCHK(hipStreamSynchronize(g->stream));
+      put(hv.data(), hv.size() * sizeof(double));
+      put(hm.data(), hm.size());
+    }
+    put(kCkptEnd, 8);
+  } catch (const std::exception& e) {
+    std::fclose(f);
+    return fail(WT_EDEVICE, std::string("wt_save: ") + e.what());
+  }
+  if (std::fclose(f) != 0) ok = false;
+  if (!ok) return fail(WT_EINVAL, std::string("wt_save: write failed: ") + path);
+  return WT_OK;
+}
+
+int wt_load(wt_grid* g, const char* path) {
+  if (!g || !path) return fail(WT_EINVAL, "wt_load: null argument");
+  std::FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(WT_EINVAL, std::string("wt_load: cannot open ") + path);
+  bool ok = true;
+  auto get = [&](void* p, size_t n) { ok = ok && std::fread(p, 1, n, f) == n; };
+  auto bad = [&](const std::string& why) {
+    std::fclose(f);
+    return fail(WT_EINVAL, "wt_load: " + why + ": " + path);
+  };
+  char magic[8];
+  int32_t head[4];
+  wt_params prm{};
+  double lasts[3];
+  int64_t redo = 0;
+  get(magic, 8);
+  if (!ok || std::memcmp(magic, kCkptMagic, 8) != 0) return bad("not a checkpoint");
+  get(head, sizeof(head));
+  if (!ok || head[0] != g->jmin || head[1] != g->jmax || head[2] != g->patch || head[3] != int32_t(sizeof(wt_params)))
+    return bad("levels, patch size or format differ from the grid's");
+  get(&prm, sizeof(prm));
+  get(lasts, sizeof(lasts));
+  get(&redo, sizeof(redo));
+  if (!ok) return bad("truncated header");
+  if (prm.radius != g->prm.radius || prm.omega != g->prm.omega) return bad("radius or omega differ from the grid's");
+  std::vector<std::vector<double>> hv(g->lev.size());
+  std::vector<std::vector<uint8_t>> hm(g->lev.size());
+  for (size_t q = 0; q < g->lev.size(); ++q) {
+    const LevelState& l = *g->lev[q];
+    int64_t ne[2];
+    get(ne, sizeof(ne));
+    if (!ok || ne[0] != l.tab.N || ne[1] != l.tab.E) return bad("level sizes differ");
+    hv[q].resize(size_t(ne[0] + ne[1]));
+    hm[q].resize(size_t(ne[0] + ne[1]));
+    get(hv[q].data(), hv[q].size() * sizeof(double));
+    get(hm[q].data(), hm[q].size());
+    if (!ok) return bad("truncated level data");
+  }
+  get(magic, 8);
+  if (!ok || std::memcmp(magic, kCkptEnd, 8) != 0) return bad("missing end marker");
+  std::fclose(f);
+  try {
+    for (size_t q = 0; q < g->lev.size(); ++q) {
+      LevelState& l = *g->lev[q];
+      HIPCHK(hipMemcpyAsync(l.work.dh, hv[q].data(), l.tab.N * sizeof(double), hipMemcpyHostToDevice, g->stream));
+      HIPCHK(hipMemcpyAsync(l.work.u, hv[q].data() + l.tab.N, l.tab.E * sizeof(double), hipMemcpyHostToDevice,
+                            g->stream));
+      HIPCHK(hipMemcpyAsync(l.na, hm[q].data(), l.tab.N, hipMemcpyHostToDevice, g->stream));
+      HIPCHK(hipMemcpyAsync(l.ea, hm[q].data() + l.tab.N, l.tab.E, hipMemcpyHostToDevice, g->stream));
+    }
+    HIPCHK(hipStreamSynchronize(g->stream));   // the host vectors are released at return
+    g->prm = prm;
+    g->last_eps = lasts[0];
+    g->last_eh = lasts[1];
+    g->last_eu = lasts[2];
+    g->redo = redo;
+    g->gated = false;
+    g->details_partial = true;   // the stored details are recomputed when read
+    g->have_state = true;
+    build_work_lists(g);
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_load: ") + e.what());
+  }
+  return WT_OK;
+}
+
 int wt_get_state(wt_grid* g, int level, double* dh, double* u, uint8_t* na, uint8_t* ea) {
   if (bad_level(g, level)) return fail(WT_EINVAL, "wt_get_state: bad level");
   if (!g->have_state) return fail(WT_ESTATE, "wt_get_state: no state loaded");

@@ -69,6 +69,8 @@ SIGNATURES = [
     ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64, _D]),
     ("wt_kernel_names", C.c_char_p, []),
     ("wt_table_cache_clear", None, []),
+    ("wt_save", C.c_int, [_P, C.c_char_p]),
+    ("wt_load", C.c_int, [_P, C.c_char_p]),
     ("wt_host_level_tables", C.c_int, [C.c_int, C.c_double, C.c_double, _D, _D, _D, _D, _I32, _I32, _D]),
     ("wt_host_pair_tables", C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, _I32, _D, _D, _D, _I32, _D,
                                       _D, _D, _I32, _D, _I32, _D]),
@@ -315,6 +317,14 @@ class Grid:
     def set_predictor(self, mlp, threshold=0.5):
         self._predictor = mlp   # keeps the network alive while the grid uses it
         _check(load().wt_set_predictor(self._h, mlp._h if mlp is not None else None, float(threshold)))
+
+    def save(self, path):
+        """Write the grid's state (every level, masks, parameters) to a checkpoint file."""
+        _check(load().wt_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Read a checkpoint written by save() of a grid with the same levels and patch size."""
+        _check(load().wt_load(self._h, os.fsencode(path)))
 
     def set_work_lists(self, enable):
         _check(load().wt_set_work_lists(self._h, 1 if enable else 0))

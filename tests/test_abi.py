@@ -39,6 +39,8 @@ def test_errors_without_device_are_reported():
     assert lib.wt_grid_create(2, 2, 5) is None
     assert b"patch" in lib.wt_last_error()
     assert lib.wt_step(None, 1.0) == wt.WT_EINVAL
+    assert lib.wt_save(None, b"/tmp/wt_none.ckpt") == wt.WT_EINVAL
+    assert lib.wt_load(None, b"/tmp/wt_none.ckpt") == wt.WT_EINVAL
 
 
 @pytest.mark.parametrize("J", [0, 1, 2, 3, 4])

@@ -221,3 +221,46 @@ def test_work_lists_equal_whole_levels(case, jmin, jmax, eps, prec):
             assert np.array_equal(x, y)
     assert ma == mb and ea_ == eb and an == bn and ae == be
     _say(f"active nodes per level {an[jmin:jmax + 1]}")
+
+
+def test_checkpoint_restart_is_bitwise(tmp_path):
+    """wt_save after 3 adaptive steps, then 3 more steps, against a fresh grid that loads the
+    checkpoint and takes the same 3 steps: identical states and masks; a checkpoint of another
+    grid shape, or a file that is not a checkpoint, is refused and leaves the grid usable."""
+    _say("checkpoint restart")
+    jmin, jmax, eps = 4, 7, 5e-3
+    path = str(tmp_path / "jet.ckpt")
+    g = wt.Grid(jmin, jmax, 8)
+    with g:
+        x, m, t = g.coords(jmax)
+        dh, u, Hd = _ic("jet", (x, m, t))
+        g.set_params(mean_depth=Hd, precision=wt.WT_FP32_TENDENCY)
+        g.set_state(jmax, dh, u)
+        dt = g.suggest_dt(0.8)
+        for _ in range(3):
+            g.adapt(eps)
+            g.step(dt)
+        g.save(path)
+        for _ in range(3):
+            g.adapt(eps)
+            g.step(dt)
+        ref = [g.get_state(j) for j in range(jmin, jmax + 1)]
+    h = wt.Grid(jmin, jmax, 8)
+    with h:
+        h.load(path)
+        assert h.get_params().precision == wt.WT_FP32_TENDENCY and h.get_params().mean_depth == Hd
+        for _ in range(3):
+            h.adapt(eps)
+            h.step(dt)
+        got = [h.get_state(j) for j in range(jmin, jmax + 1)]
+    for a, b in zip(ref, got):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    other = wt.Grid(jmin, jmax - 1, 8)
+    with other:
+        with pytest.raises(wt.WtError):
+            other.load(path)
+        junk = str(tmp_path / "junk.ckpt")
+        open(junk, "wb").write(b"not a checkpoint")
+        with pytest.raises(wt.WtError):
+            other.load(junk)
