@@ -85,3 +85,45 @@ def test_batched_ensemble_rejects_single_level_member():
         with wt.Ensemble([g1, g2]) as ens:
             with pytest.raises(wt.WtError):
                 ens.set_batched(True)
+
+
+def test_batched_ensemble_mixed_schemes_and_whole_levels():
+    """Batched step over members that differ in everything the step depends on: RK4 and SSPRK(4,3),
+    FP64 and FP32 tendencies, work lists on and off (a member stepped over whole levels), levels
+    3..5 to 4..7: bitwise equal to stepping the same members one by one."""
+    params = inputs.ensemble_members(4, jmax_choices=(5, 6, 7))
+    setup = [(wt.WT_RK4, wt.WT_FP64, True, 4), (wt.WT_SSPRK43, wt.WT_FP32_TENDENCY, True, 4),
+             (wt.WT_SSPRK43, wt.WT_FP64, False, 3), (wt.WT_RK4, wt.WT_FP32_TENDENCY, False, 4)]
+
+    def make(p, rk, prec, lists, jmin):
+        g = wt.Grid(jmin, p["jmax"], 8)
+        x, m, t = g.coords(p["jmax"])
+        dh, u, H = inputs.jet(x, m, t, bump=p["bump"], bump_lat=p["bump_lat"], bump_lon=p["bump_lon"])
+        g.set_params(mean_depth=H, rk=rk, precision=prec)
+        g.set_state(p["jmax"], dh, u)
+        g.set_work_lists(lists)
+        return g
+
+    nsteps = 4
+    ref, dts = [], []
+    for p, st in zip(params, setup):
+        g = make(p, *st)
+        with g:
+            dt = g.suggest_dt(0.8)
+            for _ in range(nsteps):
+                g.adapt(p["eps"])
+                g.step(dt)
+            ref.append([g.get_state(j) for j in range(g.jmin, g.jmax + 1)])
+            dts.append(dt)
+    grids = [make(p, *st) for p, st in zip(params, setup)]
+    with wt.Ensemble(grids) as ens:
+        ens.set_batched(True)
+        for _ in range(nsteps):
+            ens.adapt([p["eps"] for p in params])
+            ens.step(dts)
+    for g, states in zip(grids, ref):
+        got = [g.get_state(j) for j in range(g.jmin, g.jmax + 1)]
+        for a, b in zip(got, states):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        g.close()
