@@ -1502,6 +1502,7 @@ struct wt_ensemble {
   bool batched = false;
   bool plan_ok = false;
   wt::BatchPlan plan;
+  std::vector<int64_t> plan_sig;   // what the plan was built from
   hipEvent_t t0 = nullptr, t1 = nullptr;
   // launch-shape tuning: each candidate (workgroups per CU, chunk entries, work queue or
   // round-robin deal) runs one step, the fastest is kept
@@ -1525,7 +1526,7 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
   pl.levels.clear();
   pl.pairs.clear();
   pl.jobs.clear();
-  pl.phase_jobs.clear();
+  pl.phases.clear();
   struct MInfo {
     int lev0, pair0, jmin, jmax;
     bool wl, fp32;
@@ -1568,16 +1569,20 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
     J1 = std::max(J1, g->jmax);
     mi.push_back(x);
   }
-  std::vector<int32_t> cur;
+  // jobs are appended phase by phase; a listed job reads its length on the device
+  int32_t j0 = 0;
   auto job = [&](int kind, int a, int st, const MInfo& x, const WorkList& L, int64_t dense) {
-    const int64_t cnt = x.wl ? L.bound : dense;
-    if (cnt <= 0) return;
-    pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, x.wl ? L.idx : nullptr, cnt});
-    cur.push_back(int32_t(pl.jobs.size() - 1));
+    if (x.wl) {
+      if (!L.idx || !L.dn) throw std::runtime_error("batched step: a member's work lists are not built");
+      pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, L.idx, L.dn, 0});
+    } else if (dense > 0) {
+      pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, nullptr, nullptr, dense});
+    }
   };
   auto flush = [&]() {
-    if (!cur.empty()) pl.phase_jobs.push_back(cur);
-    cur.clear();
+    const int32_t j1 = int32_t(pl.jobs.size());
+    if (j1 > j0) pl.phases.push_back(BatchPhase{j0, j1});
+    j0 = j1;
   };
   for (int st = 0; st < 4; ++st) {
     for (int j = J0; j < J1; ++j) {
@@ -1662,18 +1667,39 @@ static void batched_step(wt_ensemble* e, const double* dt) {
     chunk = e->cand[tried].chunk;
     queue = e->cand[tried].queue;
   }
-  bool stale = !e->plan_ok || e->dts.size() != n;
-  for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
-  if (stale) {
+  // what the plan depends on: list use, list and mask addresses, levels, parameters, time steps
+  // (not the list lengths, which the kernel reads on the device)
+  std::vector<int64_t> sig;
+  for (size_t k = 0; k < n; ++k) {
+    wt_grid* g = e->m[k];
+    sig.push_back(g->use_lists && g->lists_ok);
+    sig.push_back(g->jmin);
+    sig.push_back(g->jmax);
+    sig.push_back(g->prm.rk);
+    sig.push_back(g->prm.precision);
+    int64_t bits = 0;
+    std::memcpy(&bits, &dt[k], sizeof(bits));
+    sig.push_back(bits);
+    for (auto& l : g->lev) {
+      for (const WorkList* L : {&l->l_tri, &l->l_elem, &l->l_edge, &l->l_node, &l->l_tend}) {
+        sig.push_back(reinterpret_cast<int64_t>(L->idx));
+        sig.push_back(reinterpret_cast<int64_t>(L->dn));
+      }
+      sig.push_back(reinterpret_cast<int64_t>(l->na));
+      sig.push_back(reinterpret_cast<int64_t>(l->ea));
+    }
+    for (auto& p : g->pairs)
+      for (const WorkList* L : {&p->l_cn, &p->l_ce, &p->l_ct}) {
+        sig.push_back(reinterpret_cast<int64_t>(L->idx));
+        sig.push_back(reinterpret_cast<int64_t>(L->dn));
+      }
+  }
+  if (!e->plan_ok || sig != e->plan_sig) {
     build_batch_plan(e, dt);
-    e->plan.upload(chunk, e->s0);
+    e->plan.upload(e->s0);
     e->plan_ok = true;
-    e->epochs.resize(n);
-    for (size_t k = 0; k < n; ++k) e->epochs[k] = e->m[k]->epoch;
-    e->dts.assign(dt, dt + n);
+    e->plan_sig.swap(sig);
     ++e->captures;
-  } else if (e->plan.chunk != chunk) {
-    e->plan.upload(chunk, e->s0);
   }
   // members' own streams are idle here (their adapts synchronise)
   if (!e->t0) {
@@ -1681,7 +1707,7 @@ static void batched_step(wt_ensemble* e, const double* dt) {
     HIPCHK(hipEventCreate(&e->t1));
   }
   HIPCHK(hipEventRecord(e->t0, e->s0));
-  batch_launch(e->plan, bpc, queue, e->s0);
+  batch_launch(e->plan, bpc, chunk, queue, e->s0);
   HIPCHK(hipEventRecord(e->t1, e->s0));
   batch_check(e->plan, e->s0);
   ++e->launches;

@@ -143,33 +143,82 @@ __device__ __forceinline__ void batch_barrier(uint32_t* __restrict__ bar, int p,
   __syncthreads();
 }
 
+// Block-wide chunk prefix of a phase's jobs: s_pre[j] = chunks of jobs 0..j-1 (s_pre[nj] = the
+// phase's total), from each job's entry count (a work list's device count, or a whole level).
+__device__ __forceinline__ int32_t phase_prefix(const BatchJob* __restrict__ JB, const BatchPhase& ph, int chunk,
+                                                int32_t* s_pre, int32_t* s_tmp) {
+  const int nj = ph.j1 - ph.j0, tid = threadIdx.x;
+  int32_t v[BATCH_MAX_JOBS / BB], tsum = 0;
+#pragma unroll
+  for (int q = 0; q < BATCH_MAX_JOBS / BB; ++q) {
+    const int j = (BATCH_MAX_JOBS / BB) * tid + q;
+    v[q] = 0;
+    if (j < nj) {
+      const BatchJob& jb = JB[ph.j0 + j];
+      const int64_t cnt = jb.dn ? *jb.dn : jb.cnt;
+      v[q] = int32_t((cnt + chunk - 1) / chunk);
+    }
+    tsum += v[q];
+  }
+  s_tmp[tid] = tsum;
+  __syncthreads();
+  for (int off = 1; off < BB; off <<= 1) {   // inclusive scan of the per-thread sums
+    const int32_t add = tid >= off ? s_tmp[tid - off] : 0;
+    __syncthreads();
+    s_tmp[tid] += add;
+    __syncthreads();
+  }
+  int32_t run = s_tmp[tid] - tsum;
+#pragma unroll
+  for (int q = 0; q < BATCH_MAX_JOBS / BB; ++q) {
+    const int j = (BATCH_MAX_JOBS / BB) * tid + q;
+    if (j < nj) {
+      run += v[q];
+      s_pre[j + 1] = run;
+    }
+  }
+  if (tid == 0) s_pre[0] = 0;
+  __syncthreads();
+  return s_pre[nj];
+}
+
 // Every workgroup takes chunks of the current phase until none is left -- from the phase's counter
-// (dynamic, queue != 0) or every gridDim-th chunk from its own index (static) -- then waits at the
-// phase's grid barrier.  The loop exits are uniform per workgroup, so every workgroup reaches
-// every barrier.
+// (queue != 0) or every gridDim-th chunk from its own index -- then waits at the phase's grid
+// barrier.  The loop exits are uniform per workgroup, so every workgroup reaches every barrier.
 __global__ __launch_bounds__(BB) void k_batch(const BatchLevel* __restrict__ LV, const BatchPair* __restrict__ PR,
-                                              const BatchJob* __restrict__ JB, const BatchChunk* __restrict__ CH,
-                                              const BatchPhase* __restrict__ PH, int nphase, int chunk, int queue,
-                                              int32_t* __restrict__ ctr, uint32_t* __restrict__ bar,
-                                              uint32_t* __restrict__ err) {
+                                              const BatchJob* __restrict__ JB, const BatchPhase* __restrict__ PH,
+                                              int nphase, int chunk, int queue, int32_t* __restrict__ ctr,
+                                              uint32_t* __restrict__ bar, uint32_t* __restrict__ err) {
+  __shared__ int32_t s_pre[BATCH_MAX_JOBS + 1], s_tmp[BB];
   __shared__ int32_t s_c;
   for (int p = 0; p < nphase; ++p) {
     const BatchPhase ph = PH[p];
+    const int nj = ph.j1 - ph.j0;
+    const int32_t total = phase_prefix(JB, ph, chunk, s_pre, s_tmp);
     for (int32_t k = 0;; ++k) {
       int32_t c;
       if (queue) {
-        if (threadIdx.x == 0) s_c = ph.c0 + atomicAdd(&ctr[p], 1);
+        if (threadIdx.x == 0) s_c = atomicAdd(&ctr[p], 1);
         __syncthreads();
         c = __builtin_amdgcn_readfirstlane(s_c);
         __syncthreads();   // the next grab rewrites s_c
       } else {
-        c = ph.c0 + int32_t(blockIdx.x) + k * int32_t(gridDim.x);
+        c = int32_t(blockIdx.x) + k * int32_t(gridDim.x);
       }
-      if (c >= ph.c1) break;
-      const BatchChunk ck = CH[c];
-      const BatchJob jb = JB[ck.job];
-      const int64_t end = std::min<int64_t>(int64_t(ck.start) + chunk, jb.cnt);
-      for (int64_t r = int64_t(ck.start) + threadIdx.x; r < end; r += BB) {
+      if (c >= total) break;
+      // the job of chunk c: the last j with s_pre[j] <= c (jobs without chunks are passed over)
+      int lo = 0, hi = nj - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= c) lo = mid;
+        else hi = mid - 1;
+      }
+      lo = __builtin_amdgcn_readfirstlane(lo);
+      const BatchJob jb = JB[ph.j0 + lo];
+      const int64_t cnt = jb.dn ? *jb.dn : jb.cnt;
+      const int64_t start = int64_t(c - s_pre[lo]) * chunk;
+      const int64_t end = std::min<int64_t>(start + chunk, cnt);
+      for (int64_t r = start + threadIdx.x; r < end; r += BB) {
         int64_t i = r;
         if (jb.lst) {
           i = jb.lst[r];
@@ -201,51 +250,36 @@ static void upload_vec(const std::vector<X>& v, X*& d, size_t& cap, hipStream_t 
   if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s));
 }
 
-void BatchPlan::upload(int chunk_entries, hipStream_t s) {
-  if (chunk_entries < BB || chunk_entries % BB) throw std::runtime_error("batch plan: chunk must be a multiple of 256");
-  std::vector<BatchChunk> ch;
-  std::vector<BatchPhase> ph;
-  for (const auto& pj : phase_jobs) {
-    BatchPhase p{int32_t(ch.size()), 0};
-    for (int32_t j : pj)
-      for (int64_t st = 0; st < jobs[j].cnt; st += chunk_entries) ch.push_back(BatchChunk{j, int32_t(st)});
-    p.c1 = int32_t(ch.size());
-    ph.push_back(p);
-  }
-  if (ch.size() >= size_t(1) << 30) throw std::runtime_error("batch plan: too many chunks");
+void BatchPlan::upload(hipStream_t s) {
+  for (const auto& ph : phases)
+    if (ph.j1 - ph.j0 > BATCH_MAX_JOBS) throw std::runtime_error("batch plan: too many jobs in one phase");
   // the previous tables may still be read by a queued launch
   HIPCHK(hipStreamSynchronize(s));
   upload_vec(levels, d_levels, cap[0], s);
   upload_vec(pairs, d_pairs, cap[1], s);
   upload_vec(jobs, d_jobs, cap[2], s);
-  upload_vec(ch, d_chunks, cap[3], s);
-  upload_vec(ph, d_phases, cap[4], s);
+  upload_vec(phases, d_phases, cap[3], s);
   // work-queue counters, then the barrier slots of every phase, then the error flag
-  if (!d_ctr || cap[5] < ctr_bytes(ph.size())) {
+  if (!d_ctr || cap[4] < ctr_bytes(phases.size())) {
     if (d_ctr) HIPCHK(hipFree(d_ctr));
-    cap[5] = ctr_bytes(ph.size() + ph.size() / 2);
-    HIPCHK(hipMalloc(&d_ctr, cap[5]));
+    cap[4] = ctr_bytes(phases.size() + phases.size() / 2);
+    HIPCHK(hipMalloc(&d_ctr, cap[4]));
   }
-  HIPCHK(hipStreamSynchronize(s));   // the host vectors of the copies are temporaries
-  chunk = chunk_entries;
-  nphase = int(ph.size());
-  nchunk = int64_t(ch.size());
+  HIPCHK(hipStreamSynchronize(s));   // the host vectors of the copies may change afterwards
+  nphase = int(phases.size());
 }
 
 void BatchPlan::release() {
-  void* ps[] = {d_levels, d_pairs, d_jobs, d_chunks, d_phases, d_ctr};
+  void* ps[] = {d_levels, d_pairs, d_jobs, d_phases, d_ctr};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& c : cap) c = 0;
   d_levels = nullptr;
   d_pairs = nullptr;
   d_jobs = nullptr;
-  d_chunks = nullptr;
   d_phases = nullptr;
   d_ctr = nullptr;
   nphase = 0;
-  nchunk = 0;
-  chunk = 0;
 }
 
 int batch_max_blocks_per_cu() {
@@ -262,24 +296,24 @@ int batch_cu_count() {
   return cus;
 }
 
-void batch_launch(BatchPlan& plan, int blocks_per_cu, bool queue, hipStream_t s) {
+void batch_launch(BatchPlan& plan, int blocks_per_cu, int chunk, bool queue, hipStream_t s) {
   if (plan.nphase == 0) return;
   const int maxb = batch_max_blocks_per_cu();
   if (blocks_per_cu < 1 || blocks_per_cu > maxb)
     throw std::runtime_error("batch step: " + std::to_string(blocks_per_cu) + " workgroups per CU, at most " +
                              std::to_string(maxb) + " fit");
+  if (chunk < BB || chunk % BB) throw std::runtime_error("batch step: chunk must be a multiple of 256");
   HIPCHK(hipMemsetAsync(plan.d_ctr, 0, ctr_bytes(size_t(plan.nphase)), s));
   const BatchLevel* lv = plan.d_levels;
   const BatchPair* pr = plan.d_pairs;
   const BatchJob* jb = plan.d_jobs;
-  const BatchChunk* ch = plan.d_chunks;
   const BatchPhase* ph = plan.d_phases;
-  int nphase = plan.nphase, chunk = plan.chunk, use_queue = queue ? 1 : 0;
+  int nphase = plan.nphase, use_queue = queue ? 1 : 0;
   const size_t q0 = ((size_t(nphase) + BAR_STRIDE - 1) / BAR_STRIDE) * BAR_STRIDE;
   int32_t* ctr = plan.d_ctr;
   uint32_t* bar = reinterpret_cast<uint32_t*>(plan.d_ctr) + q0;
   uint32_t* err = bar + size_t(nphase) * BAR_SLOTS * BAR_STRIDE;
-  void* args[] = {&lv, &pr, &jb, &ch, &ph, &nphase, &chunk, &use_queue, &ctr, &bar, &err};
+  void* args[] = {&lv, &pr, &jb, &ph, &nphase, &chunk, &use_queue, &ctr, &bar, &err};
   const dim3 grid(unsigned(blocks_per_cu * batch_cu_count()));
   // cooperative: the runtime refuses a grid whose workgroups cannot all be resident at once,
   // which the barriers need

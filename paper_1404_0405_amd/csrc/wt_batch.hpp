@@ -4,9 +4,9 @@
 // The step is a fixed sequence of phases (prolongation pair by pair top-down, the TRiSK
 // intermediates of all levels, the restriction chain bottom-up, the tendencies, per stage; then the
 // partial height transform).  A phase holds the (member, level or pair) jobs that can run at the
-// same time; its work is cut into chunks of consecutive list entries of one job, handed out by an
-// atomic counter (a work queue) or dealt round-robin, and the whole grid meets at a barrier
-// between phases.  Each entry is evaluated by the
+// same time; its work is cut into chunks of consecutive list entries of one job (the list lengths
+// read on the device at the phase's start), handed out by an atomic counter (a work queue) or
+// dealt round-robin, and the whole grid meets at a barrier between phases.  Each entry is evaluated by the
 // same per-point code as the one-launch-per-kernel path, so results are identical.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -42,42 +42,39 @@ struct BatchPair {
 };
 
 // a job: kind, the level (a) or pair (a) it works on, the stage, the member's tendency precision
-// and its entries lst[0..cnt) (-1 = padding) or 0..cnt
+// and its entries: lst[0..*dn) of a work list (its count as the compaction left it on the
+// device), or 0..cnt of a whole level (lst and dn null)
 struct BatchJob {
   int32_t kind, a, stage, fp32;
   const int32_t* lst;
+  const int64_t* dn;
   int64_t cnt;
 };
 
-struct BatchChunk {
-  int32_t job;
-  int32_t start;   // first entry of the chunk
-};
-
+// the jobs of a phase: JB[j0..j1)
 struct BatchPhase {
-  int32_t c0, c1;   // chunk range
+  int32_t j0, j1;
 };
 
-// Host-built description of one ensemble step, uploaded once and launched every step until the
-// members' launch arguments change.
+constexpr int BATCH_MAX_JOBS = 1024;   // jobs per phase (the kernel's chunk prefix lives in LDS)
+
+// Host-built description of one ensemble step, uploaded once and launched every step until a
+// member's levels, list or mask addresses, list use or time step change (the list lengths are
+// read on the device, so new lists of the same predicates need no new plan).
 struct BatchPlan {
   std::vector<BatchLevel> levels;
   std::vector<BatchPair> pairs;
-  std::vector<BatchJob> jobs;
-  std::vector<std::vector<int32_t>> phase_jobs;   // jobs of each phase
-  // device copies and the chunk tables for one chunk size
+  std::vector<BatchJob> jobs;     // phase by phase
+  std::vector<BatchPhase> phases;
   BatchLevel* d_levels = nullptr;
   BatchPair* d_pairs = nullptr;
   BatchJob* d_jobs = nullptr;
-  BatchChunk* d_chunks = nullptr;
   BatchPhase* d_phases = nullptr;
   int32_t* d_ctr = nullptr;   // work-queue counters, barrier slots and error flag of the phases
-  size_t cap[6] = {0, 0, 0, 0, 0, 0};   // allocated sizes of the six device buffers
-  int chunk = 0;              // entries per chunk the tables were cut for
+  size_t cap[5] = {0, 0, 0, 0, 0};   // allocated sizes of the five device buffers
   int nphase = 0;
-  int64_t nchunk = 0;
 
-  void upload(int chunk_entries, hipStream_t s);   // (re)builds the chunk tables for a chunk size
+  void upload(hipStream_t s);
   void release();
 };
 
@@ -85,8 +82,9 @@ struct BatchPlan {
 int batch_max_blocks_per_cu();
 int batch_cu_count();
 // One step: clears the counters and launches blocks_per_cu x CUs workgroups cooperatively;
-// queue: chunks from the per-phase work queue, else a fixed round-robin deal of the chunks.
-void batch_launch(BatchPlan& plan, int blocks_per_cu, bool queue, hipStream_t s);
+// chunks of `chunk` entries (a multiple of 256) from the per-phase work queue (queue) or dealt
+// round-robin.
+void batch_launch(BatchPlan& plan, int blocks_per_cu, int chunk, bool queue, hipStream_t s);
 // After a step: synchronises and throws if a grid barrier's bounded wait ran out.
 void batch_check(const BatchPlan& plan, hipStream_t s);
 

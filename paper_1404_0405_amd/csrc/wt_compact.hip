@@ -151,6 +151,7 @@ struct CJob {
   int64_t n;
   int32_t* out;
   int64_t chunk0;
+  int64_t* dn;   // the list's device count
 };
 
 __device__ __forceinline__ int job_of(const CJob* __restrict__ jobs, int njob, int64_t chunk) {
@@ -205,7 +206,10 @@ __global__ __launch_bounds__(CB) void k_scan_b(const CJob* __restrict__ jobs, in
     carry += s_sum[CB - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0) totals[k] = carry;
+  if (threadIdx.x == 0) {
+    totals[k] = carry;
+    *jobs[k].dn = carry;
+  }
 }
 
 __global__ __launch_bounds__(CB) void k_scatter_b(const CJob* __restrict__ jobs, int njob,
@@ -270,6 +274,7 @@ void CompactBatch::add(const uint8_t* pred, int64_t n, WorkList& L) {
     L.cap = n > 0 ? n : 1;
     HIPCHK(hipMalloc(&L.idx, L.cap * sizeof(int32_t)));
   }
+  if (!L.dn) HIPCHK(hipMalloc(&L.dn, sizeof(int64_t)));
   jobs.push_back(Job{pred, n, &L});
 }
 
@@ -279,7 +284,7 @@ void CompactBatch::run(hipStream_t s) {
   std::vector<CJob> cj(njob);
   int64_t nchunk = 0;
   for (int k = 0; k < njob; ++k) {
-    cj[k] = CJob{jobs[k].pred, jobs[k].n, jobs[k].list->idx, nchunk};
+    cj[k] = CJob{jobs[k].pred, jobs[k].n, jobs[k].list->idx, nchunk, jobs[k].list->dn};
     nchunk += std::max<int64_t>(1, (jobs[k].n + CHUNK - 1) / CHUNK);   // every job owns a chunk
   }
   if (njob > job_cap || nchunk > chunk_cap) {
@@ -340,6 +345,7 @@ void CompactBatch::release() {
 
 void free_list(WorkList& L) {
   if (L.idx) (void)hipFree(L.idx);
+  if (L.dn) (void)hipFree(L.dn);
   L = WorkList{};
 }
 

@@ -16,6 +16,7 @@ namespace wt {
 struct WorkList {
   int32_t* idx = nullptr;   // device
   int64_t n = 0, cap = 0, bound = 0;
+  int64_t* dn = nullptr;    // device copy of n, written by the compaction (batched compaction only)
 };
 
 struct CompactScratch {
