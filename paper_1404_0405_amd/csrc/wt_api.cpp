@@ -89,6 +89,10 @@ struct wt_grid {
   bool gated = false;         // the last adapt used the learned gate; the next step is judged
   double last_eps = 0, last_eh = 0, last_eu = 0;
   int64_t redo = 0;
+  // Version of the state and masks (bumped by everything that changes them) and the version the
+  // last passing threshold test saw: the adapt that follows such a test on the same state with
+  // the same eps takes its details, thresholds and significant points instead of recomputing them.
+  uint64_t state_ver = 0, judge_ver = ~uint64_t(0);
   bool use_lists = true;      // adaptive stage over work lists (false: whole levels)
   bool lists_ok = false;      // the lists match the current masks
   bool details_partial = false;   // the stored details cover only the work-list support
@@ -197,6 +201,7 @@ static StageSpec rk_stage(int rk, int s, DevWork& w, double dt) {
 }
 
 static void uniform_step(wt_grid* g, LevelState& ls, double dt) {
+  ++g->state_ver;
   const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
   for (int s = 0; s < 4; ++s) {
     StageSpec sp = rk_stage(g->prm.rk, s, ls.work, dt);
@@ -401,6 +406,7 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
 }
 
 static void ml_step(wt_grid* g, double dt) {
+  ++g->state_ver;
   const bool fp32 = g->prm.precision == WT_FP32_TENDENCY;
   const int nl = g->jmax - g->jmin + 1;
   PhysParams p = phys(g);
@@ -515,7 +521,10 @@ static float level_pos(const wt_grid* g, int j) { return float(j - g->jmin) / fl
 static void snapshot(wt_grid* g, bool restore) {
   // the work lists describe the masks being discarded; the adapt that follows a restore builds
   // them again (and bumps the epoch if the launches change)
-  if (restore) g->lists_ok = false;
+  if (restore) {
+    g->lists_ok = false;
+    ++g->state_ver;
+  }
   for (auto& lp : g->lev) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E;
@@ -557,19 +566,28 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
   // every point's detail, but outside the support the points are inactive with prolonged values
   // and their details vanish, so the transform runs over the work lists in both cases.
   std::vector<double*> dh = state_dh(g), u = state_u(g);
-  prolong_all(g, dh, u, true);
-  details_all(g, dh, u, true);
-  double mh, mu;
-  masked_max_all(g, &mh, &mu);
-  const double eh = eps * mh, eu = eps * mu;
-  clear_significant(g);
-  // R1: significant points
-  const bool listed = g->lists_ok;
-  for (int j = g->jmin; j < g->jmax; ++j) {
-    PairState& P = g->P(j);
-    LevelState& F = g->L(j + 1);
-    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
-                   listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
+  double eh, eu;
+  if (g->judge_ver == g->state_ver && eps == g->last_eps && g->lists_ok) {
+    // the passing threshold test after the last step computed exactly this (details, maxima,
+    // R1) on this state
+    eh = g->last_eh;
+    eu = g->last_eu;
+  } else {
+    prolong_all(g, dh, u, true);
+    details_all(g, dh, u, true);
+    double mh, mu;
+    masked_max_all(g, &mh, &mu);
+    eh = eps * mh;
+    eu = eps * mu;
+    clear_significant(g);
+    // R1: significant points
+    const bool listed = g->lists_ok;
+    for (int j = g->jmin; j < g->jmax; ++j) {
+      PairState& P = g->P(j);
+      LevelState& F = g->L(j + 1);
+      ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
+                     listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
+    }
   }
   {
     std::vector<ByteJob> cp;
@@ -637,6 +655,7 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     }
   }
   touch_epoch(g);
+  ++g->state_ver;
   if (eh_out) *eh_out = eh;
   if (eu_out) *eu_out = eu;
 }
@@ -675,6 +694,7 @@ static int64_t judge_gated_step(wt_grid* g) {
   HIPCHK(hipStreamSynchronize(g->stream));
   int64_t total = 0;
   for (int q = 0; q < k; ++q) total += int64_t(g->host_val[q]);
+  g->judge_ver = total == 0 ? g->state_ver : ~uint64_t(0);
   return total;
 }
 
@@ -882,6 +902,7 @@ int wt_set_params(wt_grid* g, const wt_params* p) {
   if (p->precision != WT_FP64 && p->precision != WT_FP32_TENDENCY)
     return fail(WT_EINVAL, "wt_set_params: bad precision");
   g->prm = *p;
+  ++g->state_ver;
   return WT_OK;
 }
 
@@ -925,6 +946,7 @@ int wt_grid_coords(const wt_grid* g, int level, double* nx, double* em, double* 
 
 static int set_state_impl(wt_grid* g, int level, const void* dh, const void* u, hipMemcpyKind k) {
   if (bad_level(g, level)) return fail(WT_EINVAL, "wt_set_state: bad level");
+  ++g->state_ver;
   if (!dh || !u) return fail(WT_EINVAL, "wt_set_state: null array");
   try {
     LevelState& ls = g->L(level);
@@ -1043,6 +1065,7 @@ int wt_load(wt_grid* g, const char* path) {
   get(magic, 8);
   if (!ok || std::memcmp(magic, kCkptEnd, 8) != 0) return bad("missing end marker");
   std::fclose(f);
+  ++g->state_ver;
   try {
     for (size_t q = 0; q < g->lev.size(); ++q) {
       LevelState& l = *g->lev[q];
@@ -1148,6 +1171,7 @@ int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
 
 int wt_set_work_lists(wt_grid* g, int enable) {
   if (!g) return fail(WT_EINVAL, "wt_set_work_lists: null grid");
+  ++g->state_ver;
   try {
     g->use_lists = enable != 0;
     build_work_lists(g);
@@ -1208,6 +1232,7 @@ int wt_patch_labels(wt_grid* g, int level, float* y_device) {
 
 int wt_forward(wt_grid* g) {
   if (!g) return fail(WT_EINVAL, "wt_forward: null grid");
+  ++g->state_ver;
   if (!g->have_state) return fail(WT_ESTATE, "wt_forward: call wt_set_state first");
   if (!g->multi()) return WT_OK;
   try {
@@ -1222,6 +1247,7 @@ int wt_forward(wt_grid* g) {
 
 int wt_inverse(wt_grid* g) {
   if (!g) return fail(WT_EINVAL, "wt_inverse: null grid");
+  ++g->state_ver;
   if (!g->have_state) return fail(WT_ESTATE, "wt_inverse: call wt_set_state first");
   if (!g->multi()) return WT_OK;
   try {
@@ -1253,6 +1279,7 @@ int wt_get_details(wt_grid* g, int level, double* dh, double* dpair, double* din
 
 int wt_set_mask(wt_grid* g, int level, const uint8_t* na, const uint8_t* ea) {
   if (bad_level(g, level) || !na || !ea) return fail(WT_EINVAL, "wt_set_mask: bad argument");
+  ++g->state_ver;
   try {
     LevelState& l = g->L(level);
     HIPCHK(hipMemcpyAsync(l.na, na, l.tab.N, hipMemcpyHostToDevice, g->stream));
@@ -1833,6 +1860,7 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
       HIPCHK(hipStreamSynchronize(e->s0));
       ++e->launches;
     }
+    for (auto* m : e->m) ++m->state_ver;   // the launch stepped every member
   } catch (const std::exception& x) {
     return fail(WT_EDEVICE, std::string("wt_ensemble_step: ") + x.what());
   }
