@@ -15,6 +15,9 @@ Workloads (stand-ins for the paper's test cases, Sec. 6):
 * ``jet``: zonal jet u = 80 exp(-((lat-45)/8)^2) m/s with the height in gradient-wind balance
   (composite Simpson quadrature), mean depth 10 km, plus a Gaussian height bump (stand-in for
   the Galewsky jet of Sec. 6.4).
+* ``turbulence``: seeded random non-divergent flow u = k x grad(psi) with an isotropic energy
+  spectrum peaked at degree 40, rms speed 20 m/s, mean depth 1 km, height from linear balance
+  g h' = f psi (stand-in for the rotating turbulence of Sec. 7).
 """
 from __future__ import annotations
 
@@ -144,6 +147,50 @@ def jet(node_xyz, edge_mid, edge_tan, bump=120.0, bump_lat=45.0, bump_lon=0.0,
     east /= np.maximum(np.linalg.norm(east, axis=1, keepdims=True), 1e-300)
     u = speed * (east * edge_tan).sum(1)
     return h - mean_depth, u, mean_depth
+
+
+def turbulence_coefficients(seed=SEED_BASE + 5, l_peak=40, width=None, u_rms=20.0, radius=EARTH_RADIUS):
+    """Streamfunction coefficients psi_lm (m^2/s) of orthonormal real harmonics, in the layout of
+    ``real_sph_harm_sum``, and the degree cut-off.  Kinetic energy per degree
+    E(l) ~ exp(-((l - l_peak) / width)^2) on l_peak +- 3 width (width l_peak / 5 by default); the
+    coefficients of degree l are N(0, sigma_l^2) with (2l+1) l(l+1) sigma_l^2 ~ E(l), scaled so
+    that the area mean of |u|^2, sum l(l+1) psi_lm^2 / (4 pi a^2), is u_rms^2 exactly."""
+    width = float(l_peak) / 5.0 if width is None else float(width)
+    l_lo = max(1, int(math.floor(l_peak - 3 * width)))
+    lmax = int(math.ceil(l_peak + 3 * width))
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((lmax + 1, 2 * lmax + 1))
+    l = np.arange(lmax + 1, dtype=np.float64)
+    spec = np.where(l >= l_lo, np.exp(-((l - l_peak) / width) ** 2), 0.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sig = np.where(l >= 1, np.sqrt(spec / np.maximum((2 * l + 1) * l * (l + 1), 1.0)), 0.0)
+    c *= sig[:, None]
+    for k in range(lmax + 1):          # only |m| <= l exists
+        c[k, : lmax - k] = 0.0
+        c[k, lmax + k + 1:] = 0.0
+    mean_u2 = (l[:, None] * (l[:, None] + 1) * c * c).sum() / (4.0 * math.pi * radius * radius)
+    return c * (u_rms / math.sqrt(mean_u2)), lmax
+
+
+def turbulence(node_xyz, edge_mid, edge_tan, seed=SEED_BASE + 5, l_peak=40, width=None, u_rms=20.0,
+               mean_depth=1000.0, radius=EARTH_RADIUS, omega=OMEGA, gravity=GRAVITY, device=None,
+               delta=1e-5):
+    """Returns (dh, u, H).  u_e = (k x grad psi) . t_e at the edge midpoint, i.e. the derivative
+    of psi along t_e x k, taken by a central difference over two points an angle 2 atan(delta)
+    apart (error ~ (l delta)^2); dh = f psi / g at the nodes (zero area mean: psi has no degree 1
+    part)."""
+    c, lmax = turbulence_coefficients(seed, l_peak, width, u_rms, radius)
+    x = node_xyz / np.linalg.norm(node_xyz, axis=1, keepdims=True)
+    psi_n = real_sph_harm_sum(x, c, lmax, device)
+    dh = 2.0 * omega * x[:, 2] * psi_n / gravity
+    m = edge_mid / np.linalg.norm(edge_mid, axis=1, keepdims=True)
+    t = edge_tan - (edge_tan * m).sum(1, keepdims=True) * m
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    dirn = np.cross(t, m)                  # t x k: grad psi . (t x k) = (k x grad psi) . t
+    psi_p = real_sph_harm_sum(m + delta * dirn, c, lmax, device)
+    psi_m = real_sph_harm_sum(m - delta * dirn, c, lmax, device)
+    u = (psi_p - psi_m) / (2.0 * math.atan(delta) * radius)
+    return dh, u, mean_depth
 
 
 def mlp_init(seed=SEED_BASE + 3, n_in=64, n_hidden=128, n_out=4):
