@@ -216,6 +216,130 @@ def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, warmup=2, ensemble_members=
     return out
 
 
+def _turb_grid(jmin, jmax, precision):
+    from paper_1404_0405_amd import inputs, wt
+    g = wt.Grid(jmin, jmax, 8)
+    x, m, t = g.coords(jmax)
+    dh, u, H = inputs.turbulence(x, m, t, device="cuda")
+    del x, m, t
+    g.set_params(mean_depth=H, rk=wt.WT_RK4, precision=precision)
+    g.set_state(jmax, dh, u)
+    return g, H
+
+
+def run_turbulence(jmin=6, jmax=10, eps=1e-2, train_steps=200, collect_every=20, test_steps=20,
+                   max_samples=150000, iters=300, lr=2e-3):
+    """Learned-zone workload on rotating turbulence: seeded random non-divergent flow peaked at
+    degree 40, rms 20 m/s, depth 1 km, levels jmin..jmax, eps relative.  A plain FP64 run of
+    train_steps steps provides the predictor's training set (features after an adapt, labels
+    after the next step, every collect_every steps, at most max_samples patches); then plain
+    FP64 and FP32 tendencies + learned zone each run test_steps timed steps from the state at
+    the end of the training window (a checkpoint).  Metric as for the jet."""
+    import os
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_1404_0405_amd import inputs, wt
+    t_build = time.perf_counter()
+    g, H = _turb_grid(jmin, jmax, wt.WT_FP64)
+    build_s = time.perf_counter() - t_build
+    N, E, _ = g.info(jmax)
+    ckpt = os.path.join(tempfile.mkdtemp(prefix="turb"), "train_end.ckpt")
+    Xs, Ys = [], []
+    with g:
+        dt = g.suggest_dt(0.8)
+        d0, _ = g.diagnostics()
+        t0 = time.perf_counter()
+        prev = None
+        timeline = {}
+        for k in range(train_steps):
+            g.adapt(eps)
+            if k in (0, 10, 20, 50, 100, 150) or k == train_steps - 1:
+                d, _ = g.diagnostics()
+                timeline[k] = {"nodes": list(d.active_nodes)[jmin:jmax + 1],
+                               "edges": list(d.active_edges)[jmin:jmax + 1]}
+            if prev is not None:
+                for j, x in prev:
+                    y = torch.empty((x.shape[0], 4), dtype=torch.float32, device="cuda")
+                    g.patch_labels(j, y)
+                    Xs.append(x)
+                    Ys.append(y)
+                prev = None
+            if k % collect_every == 0 and k + 1 < train_steps:
+                prev = []
+                for j in range(jmin + 1, jmax):
+                    if g.patch_count(j) > 0:
+                        x = torch.empty((g.patch_count(j), 64), dtype=torch.float32, device="cuda")
+                        g.patch_features(j, x)
+                        prev.append((j, x))
+            g.step(dt)
+        torch.cuda.synchronize()
+        train_run_s = time.perf_counter() - t0
+        dtr, _ = g.diagnostics()
+        g.save(ckpt)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    if X.shape[0] > max_samples:
+        keep = torch.from_numpy(np.random.default_rng(inputs.SEED_BASE + 6).choice(
+            X.shape[0], max_samples, replace=False)).cuda()
+        X, Y = X[keep].contiguous(), Y[keep].contiguous()
+    mlp = wt.Mlp(inputs.mlp_init())
+    l0 = mlp.gradient(X, Y)[1]
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        mlp.train_step(X, Y, lr, want_loss=False)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    l1 = mlp.gradient(X, Y)[1]
+    out = {"workload": f"rotating turbulence (random non-divergent flow peaked at degree 40, rms 20 m/s, "
+                       f"depth 1 km), levels {jmin}..{jmax}, eps={eps}, RK4, dt = 0.8 x stable step",
+           "dt_s": dt, "grid_build_and_ic_s": build_s,
+           "training_window": {"steps": train_steps, "simulated_h": train_steps * dt / 3600.0,
+                               "wall_s": train_run_s, "active_dof_at_end": int(sum(dtr.active_nodes) + sum(dtr.active_edges)),
+                               "active_per_level_after_adapt": timeline},
+           "training": {"samples": int(X.shape[0]), "loss_before": l0, "loss_after": l1, "train_s": train_s,
+                        "iterations": iters},
+           "uniform_dof_at_jmax": int(N + E)}
+    del X, Y, Xs, Ys
+    final = {}
+    for name, prec, learned in (("plain_fp64", wt.WT_FP64, False), ("fp32_learned", wt.WT_FP32_TENDENCY, True)):
+        h = wt.Grid(jmin, jmax, 8)
+        with h:
+            h.load(ckpt)
+            h.set_params(precision=prec)
+            if learned:
+                h.set_predictor(mlp, 0.5)
+            d0, _ = h.diagnostics()
+            active, wall, wall_adapt = 0, 0.0, 0.0
+            for _ in range(test_steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h.adapt(eps)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                h.step(dt)
+                torch.cuda.synchronize()
+                wall += time.perf_counter() - t0
+                wall_adapt += t1 - t0
+                d, _ = h.diagnostics()
+                active += sum(d.active_nodes) + sum(d.active_edges)
+            d1, code = h.diagnostics()
+            final[name] = h.get_state(jmax)[0]
+            out[name] = {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / test_steps,
+                         "ms_adapt_per_step": wall_adapt * 1e3 / test_steps,
+                         "active_dof_per_step": active / test_steps,
+                         "compression": (N + E) * test_steps / active,
+                         "mass_drift": abs(d1.mass / d0.mass - 1), "redo": h.redo_count(),
+                         "finite": code == wt.WT_OK}
+    os.remove(ckpt)
+    os.rmdir(os.path.dirname(ckpt))
+    mlp.close()
+    a, b = final["fp32_learned"], final["plain_fp64"]
+    out["test_window"] = {"steps": test_steps, "simulated_h": test_steps * dt / 3600.0}
+    out["fp32_learned"]["rel_l2_height_vs_plain_fp64"] = float(np.sqrt(((a - b) ** 2).sum() / ((H + b) ** 2).sum()))
+    out["speedup_fp32_learned_over_plain_fp64"] = out["fp32_learned"]["value"] / out["plain_fp64"]["value"]
+    return out
+
+
 def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=10, mlp=None):
     """Ensemble of jet members (seeded bump amplitude/position, Jmax and eps drawn per member),
     FP32 tendencies / FP64 state, learned zone when a network is given: one graph launch per
@@ -362,9 +486,18 @@ def main():
     ap.add_argument("--adaptive-steps", type=int, default=10)
     ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive jet comparison")
     ap.add_argument("--ensemble-members", type=int, default=64, help="0 skips the ensemble")
+    ap.add_argument("--turbulence", action="store_true", help="add the learned-zone turbulence workload")
+    ap.add_argument("--only-turbulence", action="store_true", help="run only the turbulence workload")
+    ap.add_argument("--turb-train-steps", type=int, default=200)
+    ap.add_argument("--turb-test-steps", type=int, default=20)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    turb_kw = dict(train_steps=args.turb_train_steps, test_steps=args.turb_test_steps,
+                   collect_every=max(1, args.turb_train_steps // 10))
+    if args.only_turbulence:
+        print(json.dumps({"turbulence": run_turbulence(**turb_kw)}), flush=True)
         return
     if args.only_adaptive:
         print(json.dumps({"adaptive": run_adaptive(steps=args.adaptive_steps,
@@ -409,6 +542,8 @@ def main():
     }
     if not args.no_adaptive:
         line["adaptive"] = run_adaptive(steps=args.adaptive_steps, ensemble_members=args.ensemble_members)
+    if args.turbulence:
+        line["turbulence"] = run_turbulence(**turb_kw)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -130,7 +130,7 @@ static void alloc_work(LevelState& ls) {
   A(&p, E); w.qe = p;
   A(&p, E); w.Q = p;
   A(&w.c, N);
-  A(&w.red, 8 * 1024 + 16);
+  A(&w.red, MAX_JOBS * MAX_BLOCKS + MAX_JOBS);   // batched maxima: partials, then results
   auto M = [](uint8_t** q, int64_t n) { HIPCHK(hipMalloc(q, n)); HIPCHK(hipMemset(*q, 0, n)); };
   M(&ls.na, N); M(&ls.ea, E); M(&ls.nn, N); M(&ls.ne, E); M(&ls.sn, N); M(&ls.se, E);
 }

@@ -69,7 +69,7 @@ void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, co
                 hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
 // max |v[i]| over act[i] != 0 for up to MAX_JOBS arrays at once; scratch holds
 // MAX_JOBS * MAX_BLOCKS doubles, out[k] receives job k's maximum (0 when nothing is active)
-constexpr int MAX_JOBS = 32, MAX_BLOCKS = 128;
+constexpr int MAX_JOBS = 32, MAX_BLOCKS = 512;
 struct MaxJob {
   const double* v;
   const uint8_t* act;
