@@ -311,6 +311,14 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
 static void touch_epoch(wt_grid* g) {
   std::vector<int64_t> sig;
   sig.push_back(g->use_lists && g->lists_ok);
+  // the physical constants and scheme are kernel arguments too
+  int64_t bits[2];
+  std::memcpy(&bits[0], &g->prm.gravity, 8);
+  std::memcpy(&bits[1], &g->prm.mean_depth, 8);
+  sig.push_back(bits[0]);
+  sig.push_back(bits[1]);
+  sig.push_back(g->prm.rk);
+  sig.push_back(g->prm.precision);
   auto add = [&](const WorkList& L) {
     sig.push_back(reinterpret_cast<int64_t>(L.idx));
     sig.push_back(L.bound);
@@ -523,6 +531,7 @@ static void snapshot(wt_grid* g, bool restore) {
   // them again (and bumps the epoch if the launches change)
   if (restore) {
     g->lists_ok = false;
+    touch_epoch(g);
     ++g->state_ver;
   }
   for (auto& lp : g->lev) {
@@ -903,6 +912,7 @@ int wt_set_params(wt_grid* g, const wt_params* p) {
     return fail(WT_EINVAL, "wt_set_params: bad precision");
   g->prm = *p;
   ++g->state_ver;
+  touch_epoch(g);
   return WT_OK;
 }
 

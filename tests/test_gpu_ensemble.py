@@ -127,3 +127,43 @@ def test_batched_ensemble_mixed_schemes_and_whole_levels():
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
         g.close()
+
+
+def test_ensemble_graph_follows_parameter_changes():
+    """A captured ensemble step is replayed only while its launches stay the same: changing a
+    member's scheme or precision between steps (no adapt in between, so the work lists stay)
+    recaptures it, and the states equal the members stepped one by one on the same schedule."""
+    params = inputs.ensemble_members(3, seed=inputs.SEED_BASE + 9, jmax_choices=(5, 6))
+    changes = [dict(rk=wt.WT_SSPRK43), dict(precision=wt.WT_FP32_TENDENCY), dict(mean_depth=9000.0)]
+
+    def schedule(step_all, set_all, adapt_all):
+        adapt_all()
+        step_all()
+        step_all()
+        set_all()
+        step_all()
+        step_all()
+
+    ref, dts = [], []
+    for p, ch in zip(params, changes):
+        g = _member(p)
+        with g:
+            dt = g.suggest_dt(0.8)
+            dts.append(dt)
+            schedule(lambda: g.step(dt), lambda: g.set_params(**ch), lambda: g.adapt(p["eps"]))
+            ref.append([g.get_state(j) for j in range(g.jmin, g.jmax + 1)])
+    grids = [_member(p) for p in params]
+    with wt.Ensemble(grids) as ens:
+        def set_all():
+            for g, ch in zip(grids, changes):
+                g.set_params(**ch)
+        schedule(lambda: ens.step(dts), set_all, lambda: ens.adapt([p["eps"] for p in params]))
+        captures, launches = ens.stats()
+    _say(f"captures {captures}, launches {launches}")
+    assert launches == 4 and captures == 2
+    for g, states in zip(grids, ref):
+        got = [g.get_state(j) for j in range(g.jmin, g.jmax + 1)]
+        for a, b in zip(got, states):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        g.close()
