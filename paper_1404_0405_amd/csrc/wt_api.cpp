@@ -353,6 +353,9 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
   }
   hipStream_t s = g->stream;
   CompactBatch& cb = g->cb;
+  // every level's rings, patch lists and predicates in batched launches (levels are independent)
+  std::vector<PatchJob> pj;
+  std::vector<ByteJob> clr;
   for (auto& lp : g->lev) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E, T = l.tab.T;
@@ -368,29 +371,43 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
       HIPCHK(hipMalloc(&l.pred_a, N));
     }
     // rings of same-level neighbours: 1, 2 (scratch), 3 (kept), 4, 5 (kept); patches far from
-    // every active point skip the gathers
+    // every active point skip the gathers (their points are cleared here)
     const int nl = 1 << l.geo.J;
-    const int32_t* pl = nullptr;
     if (nl >= 8) {
       const int64_t np = 10 * int64_t(nl / 8) * (nl / 8);
       if (!l.pf) {
         HIPCHK(hipMalloc(&l.pf, np));
         HIPCHK(hipMalloc(&l.plist, (np + 1) * sizeof(int32_t)));
       }
-      ml_patch_list(nl, l.na, l.ea, l.pf, l.plist, s);
-      pl = l.plist;
-      const ByteJob clr[] = {{l.rn_, nullptr, N, 0}, {l.re_, nullptr, E, 0}, {l.s5n, nullptr, N, 0},
-                             {l.s5e, nullptr, E, 0}, {l.s3n, nullptr, N, 0}, {l.s3e, nullptr, E, 0}};
-      ml_bytes_batch(clr, 6, s);
+      pj.push_back(PatchJob{l.geo.J, l.na, l.ea, l.pf, l.plist, l.plist + np});
+      const ByteJob c[] = {{l.rn_, nullptr, N, 0}, {l.re_, nullptr, E, 0}, {l.s5n, nullptr, N, 0},
+                           {l.s5e, nullptr, E, 0}, {l.s3n, nullptr, N, 0}, {l.s3e, nullptr, E, 0}};
+      clr.insert(clr.end(), c, c + 6);
     }
-    ml_ring(l.tab, nl, l.na, l.ea, l.rn_, l.re_, s, pl);
-    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s, pl);
-    ml_ring(l.tab, nl, l.s5n, l.s5e, l.s3n, l.s3e, s, pl);
-    ml_ring(l.tab, nl, l.s3n, l.s3e, l.rn_, l.re_, s, pl);
-    ml_ring(l.tab, nl, l.rn_, l.re_, l.s5n, l.s5e, s, pl);
-    pred_tri(T, l.tab.t_e, l.s3e, l.pred_t, s);
-    pred_elem(N, l.tab.n_elem, l.s3n, l.s3e, l.pred_e, s);
-    pred_elem(N, l.tab.n_elem, l.na, l.ea, l.pred_a, s);
+  }
+  if (!clr.empty()) ml_bytes_batch(clr.data(), int(clr.size()), s);
+  if (!pj.empty()) ml_patch_list_batch(pj.data(), int(pj.size()), s);
+  for (int r = 0; r < 5; ++r) {
+    std::vector<RingJob> rj;
+    for (auto& lp : g->lev) {
+      LevelState& l = *lp;
+      const int nl = 1 << l.geo.J;
+      const uint8_t* an[5] = {l.na, l.rn_, l.s5n, l.s3n, l.rn_};
+      const uint8_t* ae[5] = {l.ea, l.re_, l.s5e, l.s3e, l.re_};
+      uint8_t* bn[5] = {l.rn_, l.s5n, l.s3n, l.rn_, l.s5n};
+      uint8_t* be[5] = {l.re_, l.s5e, l.s3e, l.re_, l.s5e};
+      if (nl >= 8) rj.push_back(ring_job(l.tab, nl, an[r], ae[r], bn[r], be[r], l.plist));
+      else ml_ring(l.tab, nl, an[r], ae[r], bn[r], be[r], s, nullptr);
+    }
+    if (!rj.empty()) ml_ring_batch(rj.data(), int(rj.size()), s);
+  }
+  std::vector<PredJob> pr;
+  for (auto& lp : g->lev) {
+    LevelState& l = *lp;
+    const int64_t N = l.tab.N, E = l.tab.E, T = l.tab.T;
+    pr.push_back(pred_tri_job(T, l.tab.t_e, l.s3e, l.pred_t));
+    pr.push_back(pred_elem_job(N, l.tab.n_elem, l.s3n, l.s3e, l.pred_e));
+    pr.push_back(pred_elem_job(N, l.tab.n_elem, l.na, l.ea, l.pred_a));
     cb.add(l.pred_t, T, l.l_tri);
     cb.add(l.pred_e, N, l.l_elem);
     cb.add(l.s3e, E, l.l_edge);
@@ -403,11 +420,12 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
     const int64_t Nc = P.dev.Nc, Ec = P.dev.Ec, Tc = P.dev.Tc;
     if (!P.pred) HIPCHK(hipMalloc(&P.pred, Nc + Ec + Tc));
     uint8_t *pn = P.pred, *pe = P.pred + Nc, *pt = P.pred + Nc + Ec;
-    pred_pair(P.dev, F.s5n, F.s5e, pn, pe, pt, s);
+    pr.push_back(pred_pair_job(P.dev, F.s5n, F.s5e, pn, pe, pt));
     cb.add(pn, Nc, P.l_cn);
     cb.add(pe, Ec, P.l_ce);
     cb.add(pt, Tc, P.l_ct);
   }
+  pred_batch(pr.data(), int(pr.size()), s);
   cb.run(s);
   g->lists_ok = true;
   if (touch) touch_epoch(g);

@@ -290,6 +290,7 @@ void CompactBatch::run(hipStream_t s) {
   if (njob > job_cap || nchunk > chunk_cap) {
     HIPCHK(hipStreamSynchronize(s));
     release();
+    uploaded.clear();
     job_cap = std::max(njob, 64);
     chunk_cap = std::max<int64_t>(nchunk, 1024);
     HIPCHK(hipMalloc(&d_jobs, job_cap * sizeof(CJob)));
@@ -299,10 +300,17 @@ void CompactBatch::run(hipStream_t s) {
     HIPCHK(hipMalloc(&d_tot, job_cap * sizeof(int64_t)));
     HIPCHK(hipHostMalloc(&h_tot, job_cap * sizeof(int64_t), hipHostMallocDefault));
   }
-  // the pinned staging buffer may still feed a queued copy of the previous batch
-  HIPCHK(hipStreamSynchronize(s));
-  std::memcpy(h_jobs, cj.data(), njob * sizeof(CJob));
-  HIPCHK(hipMemcpyAsync(d_jobs, h_jobs, njob * sizeof(CJob), hipMemcpyHostToDevice, s));
+  // the device keeps the job table of the last batch: an unchanged table (the usual case, the
+  // same predicates into the same lists) is not uploaded again
+  const unsigned char* cb = reinterpret_cast<const unsigned char*>(cj.data());
+  const size_t nbytes = njob * sizeof(CJob);
+  if (uploaded.size() != nbytes || std::memcmp(uploaded.data(), cb, nbytes) != 0) {
+    // the pinned staging buffer may still feed a queued copy of the previous batch
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(h_jobs, cj.data(), nbytes);
+    HIPCHK(hipMemcpyAsync(d_jobs, h_jobs, nbytes, hipMemcpyHostToDevice, s));
+    uploaded.assign(cb, cb + nbytes);
+  }
   const CJob* J = static_cast<const CJob*>(d_jobs);
   k_count_b<<<unsigned(nchunk), CB, 0, s>>>(J, njob, d_cnt);
   k_scan_b<<<unsigned(njob), CB, 0, s>>>(J, njob, nchunk, d_cnt, d_off, d_tot);
@@ -385,6 +393,69 @@ __global__ __launch_bounds__(CB) void k_pred_pair(DevPair P, const uint8_t* __re
   if (k < P.Nc) pn[k] = snf[P.even[k]] ? 1 : 0;
   if (k < P.Ec) pe[k] = (snf[P.mid[k]] | sef[P.h1[k]] | sef[P.h2[k]]) ? 1 : 0;
   if (k < P.Tc) pt[k] = (sef[P.int_e[3 * k]] | sef[P.int_e[3 * k + 1]] | sef[P.int_e[3 * k + 2]]) ? 1 : 0;
+}
+
+// The predicates of several levels and pairs in one launch: blockIdx.y picks the job, whose
+// entities the row's blocks cover with a grid-stride loop; each job evaluates exactly the
+// predicate of k_pred_tri, k_pred_elem or k_pred_pair.
+__global__ __launch_bounds__(CB) void k_pred_b(PredJobs J) {
+  const PredJob& jb = J.j[blockIdx.y];
+  const int64_t stride = int64_t(gridDim.x) * CB;
+  if (jb.kind == PRED_TRI) {
+    for (int64_t t = TIDX; t < jb.n; t += stride)
+      jb.o1[t] = (jb.se[jb.a[3 * t]] | jb.se[jb.a[3 * t + 1]] | jb.se[jb.a[3 * t + 2]]) ? 1 : 0;
+  } else if (jb.kind == PRED_ELEM) {
+    for (int64_t i = TIDX; i < jb.n; i += stride) {
+      bool p = jb.sn[i] != 0;
+      if (i < jb.n_elem) p = p || jb.se[3 * i] || jb.se[3 * i + 1] || jb.se[3 * i + 2];
+      jb.o1[i] = p ? 1 : 0;
+    }
+  } else {
+    for (int64_t k = TIDX; k < jb.n; k += stride) {
+      if (k < jb.Nc) jb.o1[k] = jb.sn[jb.a[k]] ? 1 : 0;
+      if (k < jb.Ec) jb.o2[k] = (jb.sn[jb.b[k]] | jb.se[jb.c[k]] | jb.se[jb.d[k]]) ? 1 : 0;
+      if (k < jb.Tc) jb.o3[k] = (jb.se[jb.e[3 * k]] | jb.se[jb.e[3 * k + 1]] | jb.se[jb.e[3 * k + 2]]) ? 1 : 0;
+    }
+  }
+}
+
+PredJob pred_tri_job(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt) {
+  PredJob j{};
+  j.kind = PRED_TRI; j.n = T; j.a = t_e; j.se = se; j.o1 = pt;
+  return j;
+}
+
+PredJob pred_elem_job(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe) {
+  PredJob j{};
+  j.kind = PRED_ELEM; j.n = N; j.n_elem = n_elem; j.sn = sn; j.se = se; j.o1 = pe;
+  return j;
+}
+
+PredJob pred_pair_job(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe,
+                      uint8_t* pt) {
+  PredJob j{};
+  j.kind = PRED_PAIR;
+  j.Nc = P.Nc; j.Ec = P.Ec; j.Tc = P.Tc;
+  j.n = P.Nc > P.Ec ? P.Nc : P.Ec;
+  if (P.Tc > j.n) j.n = P.Tc;
+  j.a = P.even; j.b = P.mid; j.c = P.h1; j.d = P.h2; j.e = P.int_e;
+  j.sn = snf; j.se = sef; j.o1 = pn; j.o2 = pe; j.o3 = pt;
+  return j;
+}
+
+void pred_batch(const PredJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_PRED_JOBS) {
+    PredJobs J{};
+    const int nk = njobs - k0 < MAX_PRED_JOBS ? njobs - k0 : MAX_PRED_JOBS;
+    int64_t m = 1;
+    for (int k = 0; k < nk; ++k) {
+      J.j[k] = jobs[k0 + k];
+      if (J.j[k].n > m) m = J.j[k].n;
+    }
+    const unsigned grid = nbk(m) < 4096u ? nbk(m) : 4096u;
+    k_pred_b<<<dim3(grid, nk), CB, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
 }
 
 void pred_tri(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt, hipStream_t s) {

@@ -46,6 +46,7 @@ struct CompactBatch {
   int64_t *d_off = nullptr, *d_tot = nullptr, *h_tot = nullptr;
   int job_cap = 0;
   int64_t chunk_cap = 0;
+  std::vector<unsigned char> uploaded;   // the job table on the device (skip the upload if equal)
 
   void add(const uint8_t* pred, int64_t n, WorkList& L);   // sizes L for n indices
   void run(hipStream_t s);   // compacts every job, sets the counts and bounds, pads with -1
@@ -59,5 +60,23 @@ void pred_tri(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt, hip
 void pred_elem(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe, hipStream_t s);
 void pred_pair(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe, uint8_t* pt,
                hipStream_t s);
+// The same predicates for several levels and pairs in one launch.
+enum PredKind : int32_t { PRED_TRI = 0, PRED_ELEM = 1, PRED_PAIR = 2 };
+struct PredJob {
+  int32_t kind;
+  int64_t n, n_elem, Nc, Ec, Tc;
+  const int32_t *a, *b, *c, *d, *e;
+  const uint8_t *sn, *se;
+  uint8_t *o1, *o2, *o3;
+};
+constexpr int MAX_PRED_JOBS = 24;   // per launch (kernel argument size)
+struct PredJobs {
+  PredJob j[MAX_PRED_JOBS];
+};
+PredJob pred_tri_job(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt);
+PredJob pred_elem_job(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe);
+PredJob pred_pair_job(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe,
+                      uint8_t* pt);
+void pred_batch(const PredJob* jobs, int njobs, hipStream_t s);
 
 }  // namespace wt

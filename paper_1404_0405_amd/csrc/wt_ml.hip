@@ -497,6 +497,119 @@ void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int
   HIPCHK(hipGetLastError());
 }
 
+// The same ring over the patch lists of several levels in one launch: blockIdx.y picks the level,
+// whose blocks (the first nblk of the row) stride over its list exactly as k_ring's grid does.
+__global__ __launch_bounds__(BS) void k_ring_b(RingJobs J) {
+  const RingJob& jb = J.j[blockIdx.y];
+  if (int(blockIdx.x) >= jb.nblk) return;
+  const int sh = jb.sh, ps = sh - 3, m = 1 << ps;
+  const int tid = threadIdx.x;
+  const int32_t cnt = *jb.pcount;
+  for (int32_t b = blockIdx.x; b < cnt; b += jb.nblk) {
+    const int32_t p = jb.plist[b];
+    const int32_t L = p >> (2 * ps);
+    const int pi = (p >> ps) & (m - 1), pj = p & (m - 1);
+    if (tid < 64) {
+      const int32_t id = (((L << sh) + 8 * pi + (tid >> 3)) << sh) + 8 * pj + (tid & 7);
+      jb.bn[id] = ring_node(id, sh, jb.c_e, jb.e_c, jb.an, jb.ae) ? 1 : 0;
+    } else {
+      const int q = (tid - 64) / 3, d = (tid - 64) - 3 * q;
+      const int32_t id = (((L << sh) + 8 * pi + (q >> 3)) << sh) + 8 * pj + (q & 7);
+      const int32_t e = 3 * id + d;
+      jb.be[e] = ring_edge(e, sh, jb.e_c, jb.e_v, jb.t_e, jb.an, jb.ae) ? 1 : 0;
+    }
+  }
+  const int32_t pole = (10 << (2 * sh)) + tid;
+  if (blockIdx.x == 0 && pole < jb.N) jb.bn[pole] = ring_node(pole, sh, jb.c_e, jb.e_c, jb.an, jb.ae) ? 1 : 0;
+}
+
+RingJob ring_job(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
+                 const int32_t* plist) {
+  if (n < 8 || (n & (n - 1)) != 0) throw std::runtime_error("ring_job: lozenge side must be 2^k >= 8");
+  const int64_t lat = int64_t(10) * n * n;
+  if (t.E != 3 * lat || t.N < lat || t.N - lat > BS || t.N + t.E >= (int64_t(1) << 31))
+    throw std::runtime_error("ring_job: tables do not match the lattice size");
+  const int64_t np = lat / 64;
+  RingJob j{};
+  j.N = int32_t(t.N);
+  j.sh = __builtin_ctz(unsigned(n));
+  j.nblk = int32_t(np < 1024 ? np : 1024);
+  j.plist = plist;
+  j.pcount = plist + np;
+  j.c_e = t.c_e; j.e_c = t.e_c; j.e_v = t.e_v; j.t_e = t.t_e;
+  j.an = an; j.ae = ae; j.bn = bn; j.be = be;
+  return j;
+}
+
+void ml_ring_batch(const RingJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_LEVJOBS) {
+    RingJobs J{};
+    const int nk = njobs - k0 < MAX_LEVJOBS ? njobs - k0 : MAX_LEVJOBS;
+    int grid = 1;
+    for (int k = 0; k < nk; ++k) {
+      J.j[k] = jobs[k0 + k];
+      if (J.j[k].nblk > grid) grid = J.j[k].nblk;
+    }
+    k_ring_b<<<dim3(grid, nk), BS, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+// Patch lists of several levels: blockIdx.y picks the level; rows beyond a level's range exit.
+__global__ __launch_bounds__(BS) void k_patch_any_b(PatchJobs J) {
+  const PatchJob& jb = J.j[blockIdx.y];
+  const int sh = jb.sh, ps = sh - 3;
+  const int64_t rows = int64_t(10) << (2 * sh - 3);
+  if (int64_t(blockIdx.x) * BS >= rows) return;   // whole block out of range (uniform)
+  const int64_t t = TID;
+  if (t == 0) *jb.pcount = 0;
+  const bool valid = t < rows;
+  bool any = false;
+  if (valid) {
+    const int64_t p = t >> 3;
+    const int m = 1 << ps, r = int(t & 7);
+    const int64_t L = p >> (2 * ps);
+    const int pi = int((p >> ps) & (m - 1)), pj = int(p & (m - 1));
+    const int64_t id0 = ((L << sh) + 8 * pi + r) * (int64_t(1) << sh) + 8 * pj;
+    const uint64_t a = *reinterpret_cast<const uint64_t*>(jb.an + id0);
+    const uint64_t* ew = reinterpret_cast<const uint64_t*>(jb.ae + 3 * id0);
+    any = (a | ew[0] | ew[1] | ew[2]) != 0;
+  }
+  const uint64_t bal = __ballot(any);
+  const int lane = threadIdx.x & 63;
+  if (valid && (lane & 7) == 0) jb.pf[t >> 3] = ((bal >> lane) & 0xffu) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(BS) void k_patch_list_b(PatchJobs J) {
+  const PatchJob& jb = J.j[blockIdx.y];
+  const int ps = jb.sh - 3, m = 1 << ps;
+  const int64_t p = TID;
+  if (p >= int64_t(10) << (2 * ps)) return;
+  const int64_t L = p >> (2 * ps);
+  const int pi = int((p >> ps) & (m - 1)), pj = int(p & (m - 1));
+  uint8_t v = (pi == 0 || pj == 0 || pi == m - 1 || pj == m - 1) ? 1 : 0;
+  for (int di = -1; di <= 1 && !v; ++di)
+    for (int dj = -1; dj <= 1 && !v; ++dj) v = jb.pf[((L << ps) + pi + di) * m + pj + dj];
+  if (v) jb.plist[atomicAdd(jb.pcount, 1)] = int32_t(p);
+}
+
+void ml_patch_list_batch(const PatchJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_LEVJOBS) {
+    PatchJobs J{};
+    const int nk = njobs - k0 < MAX_LEVJOBS ? njobs - k0 : MAX_LEVJOBS;
+    int64_t rows = 0;
+    for (int k = 0; k < nk; ++k) {
+      J.j[k] = jobs[k0 + k];
+      if (J.j[k].sh < 3) throw std::runtime_error("ml_patch_list_batch: lozenge side must be 2^k >= 8");
+      const int64_t r = int64_t(10) << (2 * J.j[k].sh - 3);
+      if (r > rows) rows = r;
+    }
+    k_patch_any_b<<<dim3(nb(rows), nk), BS, 0, s>>>(J);
+    k_patch_list_b<<<dim3(nb(rows / 8), nk), BS, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
+}
+
 void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s) {
   k_r2_nodes<<<nb(t.N), BS, 0, s>>>(t.N, t.c_e, t.c_div, t.e_c, sn, nn, ne);
   k_r2_edges<<<nb(t.E), BS, 0, s>>>(t.E, t.e_c, t.e_v, t.t_e, se, nn, ne);

@@ -67,6 +67,31 @@ void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, co
                 const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
                 const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
                 hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
+// Several levels' support rings or patch lists in one launch (blockIdx.y = level job).
+constexpr int MAX_LEVJOBS = 16;
+struct RingJob {
+  int32_t N, sh, nblk;
+  const int32_t *plist, *pcount, *c_e, *e_c, *e_v, *t_e;
+  const uint8_t *an, *ae;
+  uint8_t *bn, *be;
+};
+struct RingJobs {
+  RingJob j[MAX_LEVJOBS];
+};
+// one ring of (an, ae) into (bn, be) over the listed patches of a level with lozenge side n >= 8
+RingJob ring_job(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
+                 const int32_t* plist);
+void ml_ring_batch(const RingJob* jobs, int njobs, hipStream_t s);
+struct PatchJob {
+  int32_t sh;   // lozenge side 2^sh >= 8
+  const uint8_t *an, *ae;
+  uint8_t* pf;
+  int32_t *plist, *pcount;
+};
+struct PatchJobs {
+  PatchJob j[MAX_LEVJOBS];
+};
+void ml_patch_list_batch(const PatchJob* jobs, int njobs, hipStream_t s);
 // max |v[i]| over act[i] != 0 for up to MAX_JOBS arrays at once; scratch holds
 // MAX_JOBS * MAX_BLOCKS doubles, out[k] receives job k's maximum (0 when nothing is active)
 constexpr int MAX_JOBS = 32, MAX_BLOCKS = 512;
