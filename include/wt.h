@@ -169,6 +169,14 @@ int wt_get_details(wt_grid* g, int level, double* dh_host, double* dpair_host, d
  * bitwise at every active point).  Default: enabled.  Synchronises. */
 int wt_set_work_lists(wt_grid* g, int enable);
 
+/* The listed step of a multilevel grid (Sec. 3.1 per stage: prolongation, intermediates,
+ * restriction, tendencies; then the partial height transform) merges the launches of work that
+ * does not depend on each other -- the same kernel on every level, the odd and interior
+ * prolongation of a pair, the edge and B restriction of a pair -- into one launch each (84
+ * launches per RK4 step for five levels instead of ~180).  enable = 0 launches one kernel per
+ * level and kind (test hook: the two agree bitwise).  Default: enabled.  Synchronises. */
+int wt_set_step_phases(wt_grid* g, int enable);
+
 /* Replace the active masks of `level` (host arrays of N and E bytes, 1 = active).  Test hook,
  * used to resynchronise masks with a reference at exact threshold ties. */
 int wt_set_mask(wt_grid* g, int level, const uint8_t* node_active_host, const uint8_t* edge_active_host);

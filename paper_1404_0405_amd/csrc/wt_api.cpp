@@ -98,6 +98,13 @@ struct wt_grid {
   bool details_partial = false;   // the stored details cover only the work-list support
   uint64_t epoch = 0;         // bumped whenever the launches of a step change (see touch_epoch)
   std::vector<int64_t> step_sig;   // what the launches of a step depend on, as of the last bump
+  // the listed step as one launch per phase (all levels of a phase together), from a plan built
+  // for the step signature and dt it was made for
+  bool step_phases = true;
+  BatchPlan splan;
+  std::vector<PhaseArgs> sphase;
+  std::vector<int64_t> splan_sig;
+  double splan_dt = 0.0;
   CompactScratch csc;
   CompactBatch cb;
   // batched read-backs of per-level maxima (pinned)
@@ -914,6 +921,7 @@ void wt_grid_destroy(wt_grid* g) {
   }
   free_scratch(g->csc);
   g->cb.release();
+  g->splan.release();
   if (g->host_val) (void)hipHostFree(g->host_val);
   if (g->own) (void)hipStreamDestroy(g->own);
   delete g;
@@ -1143,13 +1151,47 @@ int wt_get_state(wt_grid* g, int level, double* dh, double* u, uint8_t* na, uint
   return WT_OK;
 }
 
+static void build_batch_plan(const std::vector<wt_grid*>& members, const double* dt, BatchPlan& pl);
+
+// The listed multilevel step with the launches of independent work merged: per stage, the even
+// prolongation of a pair, then its odd and interior prolongation together, the three
+// intermediate kernels each over all levels, per pair the fine divergence, then the edge and B
+// restriction together, the tendencies of all levels; then the partial transform pair by pair
+// (84 launches for five levels instead of ~180).  Every entry runs the same per-point body as
+// ml_step, so the results are bitwise equal.
+// Whether the merged form applies, with its plan brought up to date (this synchronises when the
+// plan is rebuilt, so it is called before a capture, not inside one).
+static bool phase_plan_ready(wt_grid* g, double dt) {
+  if (!g->step_phases || !(g->use_lists && g->lists_ok)) return false;
+  touch_epoch(g);
+  if (g->sphase.empty() || g->splan_sig != g->step_sig || g->splan_dt != dt) {
+    build_batch_plan({g}, &dt, g->splan);
+    g->splan.upload(g->stream);
+    phase_prepare(g->splan, g->sphase);
+    g->splan_sig = g->step_sig;
+    g->splan_dt = dt;
+  }
+  return !g->sphase.empty();
+}
+
+// the step with a ready plan: launches only (capturable)
+static void ml_step_phases(wt_grid* g) {
+  ++g->state_ver;
+  for (const PhaseArgs& a : g->sphase) phase_launch(g->splan, a, g->stream);
+}
+
+static void ml_step_run(wt_grid* g, double dt) {
+  if (phase_plan_ready(g, dt)) ml_step_phases(g);
+  else ml_step(g, dt);
+}
+
 int wt_step(wt_grid* g, double dt) {
   if (!g) return fail(WT_EINVAL, "wt_step: null grid");
   if (!g->have_state) return fail(WT_ESTATE, "wt_step: call wt_set_state first");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(WT_EINVAL, "wt_step: dt must be positive");
   try {
     if (g->multi()) {
-      ml_step(g, dt);
+      ml_step_run(g, dt);
       if (g->gated) {
         // the exact threshold test judges the learned zone; a miss redoes the step from the
         // state before the gated adapt with the blanket zone
@@ -1157,7 +1199,7 @@ int wt_step(wt_grid* g, double dt) {
         if (judge_gated_step(g) > 0) {
           snapshot(g, true);
           adapt_impl(g, g->last_eps, nullptr, nullptr, false);
-          ml_step(g, dt);
+          ml_step_run(g, dt);
           ++g->redo;
         }
       }
@@ -1194,6 +1236,17 @@ int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
   g->predictor = m;
   g->pred_thr = threshold;
   g->gated = false;
+  return WT_OK;
+}
+
+int wt_set_step_phases(wt_grid* g, int enable) {
+  if (!g) return fail(WT_EINVAL, "wt_set_step_phases: null grid");
+  try {
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_set_step_phases: ") + e.what());
+  }
+  g->step_phases = enable != 0;
   return WT_OK;
 }
 
@@ -1551,6 +1604,7 @@ struct wt_ensemble {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<uint64_t> epochs;   // member epochs the graph (or the batch plan) was built with
+  std::vector<char> phased;       // members captured in the merged-phase form
   std::vector<double> dts;
   int64_t captures = 0, launches = 0;
   // batched persistent step
@@ -1576,8 +1630,7 @@ struct wt_ensemble {
 // The batched step replays the phases of ml_step for every member at once (same per-point code
 // and the same dependencies: prolongation pair by pair upwards, intermediates, restriction pair
 // by pair downwards, tendencies, per stage; then the partial height transform downwards).
-static void build_batch_plan(wt_ensemble* e, const double* dt) {
-  BatchPlan& pl = e->plan;
+static void build_batch_plan(const std::vector<wt_grid*>& members, const double* dt, BatchPlan& pl) {
   pl.levels.clear();
   pl.pairs.clear();
   pl.jobs.clear();
@@ -1588,8 +1641,8 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
   };
   std::vector<MInfo> mi;
   int J0 = 1 << 30, J1 = -1;
-  for (size_t k = 0; k < e->m.size(); ++k) {
-    wt_grid* g = e->m[k];
+  for (size_t k = 0; k < members.size(); ++k) {
+    wt_grid* g = members[k];
     if (!g->multi()) throw std::runtime_error("the batched step needs multilevel members");
     MInfo x{int(pl.levels.size()), int(pl.pairs.size()), g->jmin, g->jmax, g->use_lists && g->lists_ok,
             g->prm.precision == WT_FP32_TENDENCY};
@@ -1629,7 +1682,7 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
   auto job = [&](int kind, int a, int st, const MInfo& x, const WorkList& L, int64_t dense) {
     if (x.wl) {
       if (!L.idx || !L.dn) throw std::runtime_error("batched step: a member's work lists are not built");
-      pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, L.idx, L.dn, 0});
+      pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, L.idx, L.dn, L.bound});
     } else if (dense > 0) {
       pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, nullptr, nullptr, dense});
     }
@@ -1643,13 +1696,13 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
     for (int j = J0; j < J1; ++j) {
       for (size_t k = 0; k < mi.size(); ++k)
         if (mi[k].jmin <= j && j < mi[k].jmax) {
-          const PairState& P = e->m[k]->P(j);
+          const PairState& P = members[k]->P(j);
           job(BK_PRO_EVEN, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_cn, P.dev.Nc);
         }
       flush();
       for (size_t k = 0; k < mi.size(); ++k)
         if (mi[k].jmin <= j && j < mi[k].jmax) {
-          const PairState& P = e->m[k]->P(j);
+          const PairState& P = members[k]->P(j);
           job(BK_PRO_ODD, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_ce, P.dev.Ec);
           job(BK_PRO_INT, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_ct, P.dev.Tc);
         }
@@ -1658,7 +1711,7 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
     const int kinds[3] = {BK_VERTEX, BK_EDGE_CELL, BK_Q};
     for (int kind : kinds) {
       for (size_t k = 0; k < mi.size(); ++k) {
-        wt_grid* g = e->m[k];
+        wt_grid* g = members[k];
         for (int q = 0; q < int(g->lev.size()); ++q) {
           const LevelState& l = *g->lev[q];
           if (kind == BK_VERTEX) job(kind, mi[k].lev0 + q, st, mi[k], l.l_tri, l.tab.T);
@@ -1671,20 +1724,20 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
     for (int j = J1 - 1; j >= J0; --j) {
       for (size_t k = 0; k < mi.size(); ++k)
         if (mi[k].jmin <= j && j < mi[k].jmax) {
-          const LevelState& F = e->m[k]->L(j + 1);
+          const LevelState& F = members[k]->L(j + 1);
           job(BK_DIV, mi[k].lev0 + (j + 1 - mi[k].jmin), st, mi[k], F.l_node, F.tab.N);
         }
       flush();
       for (size_t k = 0; k < mi.size(); ++k)
         if (mi[k].jmin <= j && j < mi[k].jmax) {
-          const PairState& P = e->m[k]->P(j);
+          const PairState& P = members[k]->P(j);
           job(BK_RES_E, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_ce, P.dev.Ec);
           job(BK_RES_B, mi[k].pair0 + j - mi[k].jmin, st, mi[k], P.l_cn, P.dev.Nc);
         }
       flush();
     }
     for (size_t k = 0; k < mi.size(); ++k) {
-      wt_grid* g = e->m[k];
+      wt_grid* g = members[k];
       for (int q = 0; q < int(g->lev.size()); ++q)
         job(BK_TEND, mi[k].lev0 + q, st, mi[k], g->lev[q]->l_tend, g->lev[q]->tab.N);
     }
@@ -1693,7 +1746,7 @@ static void build_batch_plan(wt_ensemble* e, const double* dt) {
   for (int j = J1 - 1; j >= J0; --j) {
     for (size_t k = 0; k < mi.size(); ++k)
       if (mi[k].jmin <= j && j < mi[k].jmax) {
-        const PairState& P = e->m[k]->P(j);
+        const PairState& P = members[k]->P(j);
         job(BK_PARTIAL_H, mi[k].pair0 + j - mi[k].jmin, 0, mi[k], P.l_cn, P.dev.Nc);
       }
     flush();
@@ -1750,7 +1803,7 @@ static void batched_step(wt_ensemble* e, const double* dt) {
       }
   }
   if (!e->plan_ok || sig != e->plan_sig) {
-    build_batch_plan(e, dt);
+    build_batch_plan(e->m, dt, e->plan);
     e->plan.upload(e->s0);
     e->plan_ok = true;
     e->plan_sig.swap(sig);
@@ -1843,7 +1896,19 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
     for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
     if (e->batched) {
       batched_step(e, dt);
-    } else if (stale) {
+    } else {
+      // members whose merged-phase plan had to be rebuilt change their launches
+      std::vector<char> phased(n);
+      for (size_t k = 0; k < n; ++k) {
+        wt_grid* m = e->m[k];
+        const bool had = !m->sphase.empty() && m->splan_sig == m->step_sig && m->splan_dt == dt[k];
+        phased[k] = m->multi() && phase_plan_ready(m, dt[k]);
+        if (phased[k] && !had) stale = true;
+      }
+      if (phased != e->phased) stale = true;
+      e->phased.swap(phased);
+    }
+    if (!e->batched && stale) {
       // capture every member's step on its own stream, forked from and joined into s0
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed));
@@ -1852,7 +1917,8 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
         for (size_t k = 0; k < n; ++k) {
           wt_grid* m = e->m[k];
           HIPCHK(hipStreamWaitEvent(m->stream, e->fork, 0));
-          if (m->multi()) ml_step(m, dt[k]);
+          if (e->phased[k]) ml_step_phases(m);
+          else if (m->multi()) ml_step(m, dt[k]);
           else uniform_step(m, m->L(m->jmax), dt[k]);
           HIPCHK(hipEventRecord(e->join[k], m->stream));
           HIPCHK(hipStreamWaitEvent(e->s0, e->join[k], 0));
@@ -1902,7 +1968,7 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
       if (judge_gated_step(m) > 0) {
         snapshot(m, true);
         adapt_impl(m, m->last_eps, nullptr, nullptr, false);
-        ml_step(m, dt[k]);
+        ml_step_run(m, dt[k]);
         ++m->redo;
       }
       HIPCHK(hipStreamSynchronize(m->stream));

@@ -232,6 +232,50 @@ __global__ __launch_bounds__(BB) void k_batch(const BatchLevel* __restrict__ LV,
   }
 }
 
+// One phase as an ordinary launch: workgroup c runs entries [256 (c - pre[j]), +256) of the job j
+// with pre[j] <= c < pre[j+1] (jobs without entries have no workgroup).
+__global__ __launch_bounds__(BB) void k_phase(const BatchLevel* __restrict__ LV, const BatchPair* __restrict__ PR,
+                                              const BatchJob* __restrict__ JB, PhaseArgs a) {
+  const int32_t c = int32_t(blockIdx.x);
+  int j = 0;
+  while (j + 1 < a.nj && a.pre[j + 1] <= c) ++j;
+  const BatchJob jb = JB[a.j0 + j];
+  const int64_t r = int64_t(c - a.pre[j]) * BB + threadIdx.x;
+  if (r >= jb.cnt) return;
+  int64_t i = r;
+  if (jb.lst) {
+    i = jb.lst[r];
+    if (i < 0) return;   // padding of a work list
+  }
+  if (jb.fp32) batch_entry<float>(jb, i, LV, PR);
+  else batch_entry<double>(jb, i, LV, PR);
+}
+
+void phase_prepare(const BatchPlan& plan, std::vector<PhaseArgs>& out) {
+  out.clear();
+  for (const BatchPhase& ph : plan.phases) {
+    PhaseArgs a{};
+    a.j0 = ph.j0;
+    a.nj = ph.j1 - ph.j0;
+    if (a.nj > PHASE_MAX_JOBS) throw std::runtime_error("phase step: too many jobs in one phase");
+    int64_t run = 0;
+    for (int j = 0; j < a.nj; ++j) {
+      a.pre[j] = int32_t(run);
+      run += (plan.jobs[ph.j0 + j].cnt + BB - 1) / BB;
+    }
+    if (run >= (int64_t(1) << 31)) throw std::runtime_error("phase step: too many workgroups");
+    a.pre[a.nj] = int32_t(run);
+    a.total = int32_t(run);
+    if (a.total > 0) out.push_back(a);
+  }
+}
+
+void phase_launch(const BatchPlan& plan, const PhaseArgs& a, hipStream_t s) {
+  if (a.total <= 0) return;
+  k_phase<<<unsigned(a.total), BB, 0, s>>>(plan.d_levels, plan.d_pairs, plan.d_jobs, a);
+  HIPCHK(hipGetLastError());
+}
+
 // device words of a plan's counters: one work-queue counter per phase, BAR_SLOTS barrier lines
 // per phase, the error flag
 static size_t ctr_words(size_t nphase) {

@@ -43,7 +43,8 @@ struct BatchPair {
 
 // a job: kind, the level (a) or pair (a) it works on, the stage, the member's tendency precision
 // and its entries: lst[0..*dn) of a work list (its count as the compaction left it on the
-// device), or 0..cnt of a whole level (lst and dn null)
+// device; cnt holds the list's padded bound when the plan was built), or 0..cnt of a whole level
+// (lst and dn null)
 struct BatchJob {
   int32_t kind, a, stage, fp32;
   const int32_t* lst;
@@ -77,6 +78,18 @@ struct BatchPlan {
   void upload(hipStream_t s);
   void release();
 };
+
+// One phase of a plan as an ordinary launch (a single grid's step, phase after phase in stream
+// order): every job's entry count is its host-side cnt (a work list's padded bound: padding
+// entries are skipped), one workgroup per 256 entries.  phase_prepare computes the per-phase
+// chunk prefixes after the plan is built.
+constexpr int PHASE_MAX_JOBS = 32;
+struct PhaseArgs {
+  int32_t j0, nj, total;
+  int32_t pre[PHASE_MAX_JOBS + 1];
+};
+void phase_prepare(const BatchPlan& plan, std::vector<PhaseArgs>& out);
+void phase_launch(const BatchPlan& plan, const PhaseArgs& a, hipStream_t s);
 
 // Largest cooperative grid (workgroups per CU x CUs) the device holds for the batch kernel.
 int batch_max_blocks_per_cu();

@@ -88,6 +88,7 @@ SIGNATURES = [
     ("wt_set_predictor", C.c_int, [_P, _P, C.c_double]),
     ("wt_redo_count", C.c_int, [_P, _I64]),
     ("wt_set_work_lists", C.c_int, [_P, C.c_int]),
+    ("wt_set_step_phases", C.c_int, [_P, C.c_int]),
     ("wt_ensemble_create", _P, [C.POINTER(_P), C.c_int]),
     ("wt_ensemble_destroy", None, [_P]),
     ("wt_ensemble_adapt", C.c_int, [_P, _D]),
@@ -328,6 +329,10 @@ class Grid:
 
     def set_work_lists(self, enable):
         _check(load().wt_set_work_lists(self._h, 1 if enable else 0))
+
+    def set_step_phases(self, enable):
+        """Merge the independent launches of the listed step (default) or launch per kernel."""
+        _check(load().wt_set_step_phases(self._h, 1 if enable else 0))
 
     def redo_count(self):
         r = C.c_int64()

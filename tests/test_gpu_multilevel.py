@@ -264,3 +264,30 @@ def test_checkpoint_restart_is_bitwise(tmp_path):
         open(junk, "wb").write(b"not a checkpoint")
         with pytest.raises(wt.WtError):
             other.load(junk)
+
+
+@pytest.mark.parametrize("rk,prec", [(wt.WT_RK4, wt.WT_FP64), (wt.WT_SSPRK43, wt.WT_FP32_TENDENCY)])
+def test_merged_phase_launches_equal_kernel_by_kernel(rk, prec):
+    """The listed step with the launches of independent work merged (one launch per phase over
+    all levels) gives bitwise the states and masks of one launch per kernel and level, across
+    adapts that change the work lists and a change of dt."""
+    jmin, jmax, eps = 4, 8, 5e-3
+    runs = []
+    for merged in (True, False):
+        _say(f"merged phases={merged} rk={rk} precision={prec}")
+        g = wt.Grid(jmin, jmax, 8)
+        with g:
+            x, m, t = g.coords(jmax)
+            dh, u, Hd = inputs.jet(x, m, t)
+            g.set_params(mean_depth=Hd, rk=rk, precision=prec)
+            g.set_state(jmax, dh, u)
+            g.set_step_phases(merged)
+            dt = g.suggest_dt(0.8)
+            for k in range(6):
+                g.adapt(eps)
+                g.step(dt if k != 3 else 0.5 * dt)
+            g.step(dt)
+            runs.append([g.get_state(j) for j in range(jmin, jmax + 1)])
+    for s1, s2 in zip(*runs):
+        for a, b in zip(s1, s2):
+            assert np.array_equal(a, b)
