@@ -237,11 +237,13 @@ static void prolong_all(wt_grid* g, const std::vector<double*>& dh, const std::v
 static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
                         bool listed = false) {
   const bool L = listed && g->lists_ok;
+  std::vector<MaskJob> jobs;   // pairs are independent: one launch
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
-    ml_details(P.dev, g->L(j).tab, dh[j + 1 - g->jmin], u[j + 1 - g->jmin], u[j - g->jmin], P.d_h, P.d_p,
-               P.d_i, g->stream, L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
+    ml_details_jobs(jobs, P.dev, g->L(j).tab, dh[j + 1 - g->jmin], u[j + 1 - g->jmin], u[j - g->jmin], P.d_h,
+                    P.d_p, P.d_i, L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
+  ml_mask_ops(jobs.data(), int(jobs.size()), g->stream);
   g->details_partial = L;
 }
 
@@ -616,12 +618,14 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     clear_significant(g);
     // R1: significant points
     const bool listed = g->lists_ok;
+    std::vector<MaskJob> jobs;
     for (int j = g->jmin; j < g->jmax; ++j) {
       PairState& P = g->P(j);
       LevelState& F = g->L(j + 1);
-      ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
-                     listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
+      ml_significant_jobs(jobs, P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se,
+                          listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
     }
+    ml_mask_ops(jobs.data(), int(jobs.size()), g->stream);
   }
   {
     std::vector<ByteJob> cp;
@@ -644,15 +648,20 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
       learn_gate(l.npatch, l.Pr, g->pred_thr, l.stats, l.allow, l.dropped, g->stream);
     }
   }
-  // R2: same-level neighbours; R3: children on the next level
-  for (int j = g->jmin; j <= g->jmax; ++j) {
-    LevelState& l = g->L(j);
-    ml_r2(l.tab, l.sn, l.se, l.nn, l.ne, g->stream);
-    if (j < g->jmax) {
-      LevelState& F = g->L(j + 1);
-      const bool gj = gate && learnable(g, j);
-      ml_r3(g->P(j).dev, F.tab, l.sn, l.se, F.nn, F.ne, g->stream, gj ? l.allow : nullptr, gj ? (1 << j) : 0);
+  // R2: same-level neighbours; R3: children on the next level (all levels in one batch: the rules
+  // only set mask bytes)
+  {
+    std::vector<MaskJob> jobs;
+    for (int j = g->jmin; j <= g->jmax; ++j) {
+      LevelState& l = g->L(j);
+      ml_r2_jobs(jobs, l.tab, l.sn, l.se, l.nn, l.ne);
+      if (j < g->jmax) {
+        LevelState& F = g->L(j + 1);
+        const bool gj = gate && learnable(g, j);
+        ml_r3_jobs(jobs, g->P(j).dev, F.tab, l.sn, l.se, F.nn, F.ne, gj ? l.allow : nullptr, gj ? (1 << j) : 0);
+      }
     }
+    ml_mask_ops(jobs.data(), int(jobs.size()), g->stream);
   }
   LevelState& L0 = g->L(g->jmin);
   const ByteJob all0[] = {{L0.nn, nullptr, L0.tab.N, 1}, {L0.ne, nullptr, L0.tab.E, 1}};
@@ -708,12 +717,14 @@ static int64_t judge_gated_step(wt_grid* g) {
   const double eh = g->last_eps * mh, eu = g->last_eps * mu;
   clear_significant(g);
   const bool L = g->lists_ok;
+  std::vector<MaskJob> jobs;
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);
-    ml_significant(P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se, g->stream,
-                   L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
+    ml_significant_jobs(jobs, P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se,
+                        L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
+  ml_mask_ops(jobs.data(), int(jobs.size()), g->stream);
   g->last_eh = eh;
   g->last_eu = eu;
   learn_stats_all(g, eh, eu);

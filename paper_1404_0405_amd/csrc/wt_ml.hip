@@ -224,105 +224,7 @@ void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, con
 }
 
 // ------------------------------------------------------------------ details
-__global__ __launch_bounds__(BS) void k_details_edge(DevPair P, const int32_t* __restrict__ e_v_c,
-                                                     const double* __restrict__ hf,
-                                                     const double* __restrict__ uf,
-                                                     const double* __restrict__ uc,
-                                                     double* __restrict__ dh, double* __restrict__ dp,
-    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(e, cnt, lst)
-  dh[e] = h_detail(P, e, hf);
-  dp[e] = (uf[P.h1[e]] - uf[P.h2[e]]) - pair_pred(P, e, e_v_c, uc);
-}
-
-__global__ __launch_bounds__(BS) void k_details_int(DevPair P, const double* __restrict__ uf,
-                                                    const double* __restrict__ uc, double* __restrict__ di,
-    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(t, cnt, lst)
-#pragma unroll
-  for (int s = 0; s < 3; ++s) di[3 * t + s] = uf[P.int_e[3 * t + s]] - int_pred(P, t, s, uc);
-}
-
-void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
-                const double* uc, double* dh, double* dp, double* di, hipStream_t s, Span le, Span lt) {
-  const int64_t ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
-  if (ne) k_details_edge<<<nb(ne), BS, 0, s>>>(P, tc.e_v, hf, uf, uc, dh, dp, le.idx, ne);
-  if (nt) k_details_int<<<nb(nt), BS, 0, s>>>(P, uf, uc, di, lt.idx, nt);
-  HIPCHK(hipGetLastError());
-}
-
 // ------------------------------------------------------------------ masks
-// R1: significant points of the fine level of a pair (active, |d| >= eps).
-__global__ __launch_bounds__(BS) void k_sig_edge(DevPair P, const uint8_t* __restrict__ naf,
-                                                 const uint8_t* __restrict__ eaf,
-                                                 const double* __restrict__ dh, const double* __restrict__ dp,
-                                                 double eh, double eu, uint8_t* __restrict__ sn,
-                                                 uint8_t* __restrict__ se,
-    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(e, cnt, lst)
-  int32_t m = P.mid[e];
-  if (naf[m] && fabs(dh[e]) >= eh) sn[m] = 1;
-  int32_t h1 = P.h1[e], h2 = P.h2[e];
-  if (eaf[h1] && eaf[h2] && fabs(dp[e]) >= eu) {
-    se[h1] = 1;
-    se[h2] = 1;
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_sig_int(DevPair P, const uint8_t* __restrict__ eaf,
-                                                const double* __restrict__ di, double eu,
-                                                uint8_t* __restrict__ se,
-    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(t, cnt, lst)
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    int32_t f = P.int_e[3 * t + s];
-    if (eaf[f] && fabs(di[3 * t + s]) >= eu) se[f] = 1;
-  }
-}
-
-void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
-                    const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
-                    hipStream_t s, Span le, Span lt) {
-  const int64_t ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
-  if (ne) k_sig_edge<<<nb(ne), BS, 0, s>>>(P, naf, eaf, dh, dp, eh, eu, sn, se, le.idx, ne);
-  if (nt) k_sig_int<<<nb(nt), BS, 0, s>>>(P, eaf, di, eu, se, lt.idx, nt);
-  HIPCHK(hipGetLastError());
-}
-
-// R2: same-level neighbours of significant nodes (neighbour nodes, incident edges) and edges
-// (end nodes, the edges of both triangles).
-__global__ __launch_bounds__(BS) void k_r2_nodes(int64_t N, const int32_t* __restrict__ c_e,
-                                                 const double* __restrict__ c_div,
-                                                 const int32_t* __restrict__ e_c,
-                                                 const uint8_t* __restrict__ sn, uint8_t* __restrict__ nn,
-                                                 uint8_t* __restrict__ ne) {
-  int64_t i = TID;
-  if (i >= N || !sn[i]) return;
-  for (int q = 0; q < 6; ++q) {
-    if (c_div[6 * i + q] == 0.0) continue;  // padded pentagon slot
-    int32_t e = c_e[6 * i + q];
-    ne[e] = 1;
-    nn[e_c[2 * e]] = 1;
-    nn[e_c[2 * e + 1]] = 1;
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_r2_edges(int64_t E, const int32_t* __restrict__ e_c,
-                                                 const int32_t* __restrict__ e_v,
-                                                 const int32_t* __restrict__ t_e,
-                                                 const uint8_t* __restrict__ se, uint8_t* __restrict__ nn,
-                                                 uint8_t* __restrict__ ne) {
-  int64_t e = TID;
-  if (e >= E || !se[e]) return;
-  nn[e_c[2 * e]] = 1;
-  nn[e_c[2 * e + 1]] = 1;
-  for (int side = 0; side < 2; ++side) {
-    int32_t t = e_v[2 * e + side];
-    for (int s = 0; s < 3; ++s) ne[t_e[3 * t + s]] = 1;
-  }
-}
-
 // One ring in gather form: B = A and the same-level neighbours of A in the sense of R2 (a node
 // joins if it, a neighbour node or an incident edge is in A; an edge joins if it, an end node or
 // an edge of one of its triangles is in A).  No copy of A and no scatter.  Points away from the
@@ -610,26 +512,75 @@ void ml_patch_list_batch(const PatchJob* jobs, int njobs, hipStream_t s) {
   }
 }
 
-void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s) {
-  k_r2_nodes<<<nb(t.N), BS, 0, s>>>(t.N, t.c_e, t.c_div, t.e_c, sn, nn, ne);
-  k_r2_edges<<<nb(t.E), BS, 0, s>>>(t.E, t.e_c, t.e_v, t.t_e, se, nn, ne);
-  HIPCHK(hipGetLastError());
+
+// ------------------------------------------------------------------ details and masks R1-R3
+// Per-point bodies of the forward transform's details (eqs. (WTpred), velocity prediction) and
+// of the rules R1 (significant points: active, |d| >= eps), R2 (same-level neighbours of
+// significant nodes -- neighbour nodes, incident edges -- and edges -- end nodes, the edges of
+// both triangles) and R3 (children on the next level of significant coarse nodes -- fine copy,
+// its neighbours and incident fine edges -- and edges -- midpoint and the fine edges at it).
+// The mask rules only set bytes to 1, so jobs of one launch may write the same mask.
+__device__ __forceinline__ void op_det_edge(int64_t e, const MaskJob& j) {
+  const DevPair& P = j.P;
+  j.dh[e] = h_detail(P, e, j.hf);
+  j.dp[e] = (j.uf[P.h1[e]] - j.uf[P.h2[e]]) - pair_pred(P, e, j.e_v, j.uc);
 }
 
-// R3: children on the next level of significant coarse nodes (fine copy, its neighbours and
-// incident fine edges) and edges (midpoint and the fine edges at it).
-__device__ __forceinline__ void mark_cell(int64_t f, const int32_t* __restrict__ c_e,
-                                          const double* __restrict__ c_div,
-                                          const int32_t* __restrict__ e_c, uint8_t* __restrict__ nn,
-                                          uint8_t* __restrict__ ne, bool nbrs) {
-  nn[f] = 1;
+__device__ __forceinline__ void op_det_int(int64_t t, const MaskJob& j) {
+  const DevPair& P = j.P;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) j.di[3 * t + s] = j.uf[P.int_e[3 * t + s]] - int_pred(P, t, s, j.uc);
+}
+
+__device__ __forceinline__ void op_sig_edge(int64_t e, const MaskJob& j) {
+  const DevPair& P = j.P;
+  const int32_t m = P.mid[e];
+  if (j.a_n[m] && fabs(j.dh[e]) >= j.eh) j.o_n[m] = 1;
+  const int32_t h1 = P.h1[e], h2 = P.h2[e];
+  if (j.a_e[h1] && j.a_e[h2] && fabs(j.dp[e]) >= j.eu) {
+    j.o_e[h1] = 1;
+    j.o_e[h2] = 1;
+  }
+}
+
+__device__ __forceinline__ void op_sig_int(int64_t t, const MaskJob& j) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int32_t f = j.P.int_e[3 * t + s];
+    if (j.a_e[f] && fabs(j.di[3 * t + s]) >= j.eu) j.o_e[f] = 1;
+  }
+}
+
+__device__ __forceinline__ void op_r2_node(int64_t i, const MaskJob& j) {
+  if (!j.a_n[i]) return;
   for (int q = 0; q < 6; ++q) {
-    if (c_div[6 * f + q] == 0.0) continue;
-    int32_t e = c_e[6 * f + q];
-    ne[e] = 1;
+    if (j.c_div[6 * i + q] == 0.0) continue;  // padded pentagon slot
+    const int32_t e = j.c_e[6 * i + q];
+    j.o_e[e] = 1;
+    j.o_n[j.e_c[2 * e]] = 1;
+    j.o_n[j.e_c[2 * e + 1]] = 1;
+  }
+}
+
+__device__ __forceinline__ void op_r2_edge(int64_t e, const MaskJob& j) {
+  if (!j.a_e[e]) return;
+  j.o_n[j.e_c[2 * e]] = 1;
+  j.o_n[j.e_c[2 * e + 1]] = 1;
+  for (int side = 0; side < 2; ++side) {
+    const int32_t t = j.e_v[2 * e + side];
+    for (int s = 0; s < 3; ++s) j.o_e[j.t_e[3 * t + s]] = 1;
+  }
+}
+
+__device__ __forceinline__ void mark_cell(int64_t f, const MaskJob& j, bool nbrs) {
+  j.o_n[f] = 1;
+  for (int q = 0; q < 6; ++q) {
+    if (j.c_div[6 * f + q] == 0.0) continue;
+    const int32_t e = j.c_e[6 * f + q];
+    j.o_e[e] = 1;
     if (nbrs) {
-      nn[e_c[2 * e]] = 1;
-      nn[e_c[2 * e + 1]] = 1;
+      j.o_n[j.e_c[2 * e]] = 1;
+      j.o_n[j.e_c[2 * e + 1]] = 1;
     }
   }
 }
@@ -644,33 +595,99 @@ __device__ __forceinline__ bool r3_allowed(const uint8_t* __restrict__ allow, in
   return allow[4 * patch + 2 * ((i % 8) / 4) + (j % 8) / 4] != 0;
 }
 
-__global__ __launch_bounds__(BS) void k_r3_nodes(DevPair P, const uint8_t* __restrict__ snc,
-                                                 const int32_t* __restrict__ c_e_f,
-                                                 const double* __restrict__ c_div_f,
-                                                 const int32_t* __restrict__ e_c_f, uint8_t* __restrict__ nnf,
-                                                 uint8_t* __restrict__ nef, const uint8_t* __restrict__ allow,
-                                                 int nc) {
-  int64_t k = TID;
-  if (k >= P.Nc || !snc[k] || !r3_allowed(allow, nc, k)) return;
-  mark_cell(P.even[k], c_e_f, c_div_f, e_c_f, nnf, nef, true);
+__device__ __forceinline__ void op_r3_node(int64_t k, const MaskJob& j) {
+  if (!j.a_n[k] || !r3_allowed(j.allow, j.nc, k)) return;
+  mark_cell(j.P.even[k], j, true);
 }
 
-__global__ __launch_bounds__(BS) void k_r3_edges(DevPair P, const uint8_t* __restrict__ sec,
-                                                 const int32_t* __restrict__ c_e_f,
-                                                 const double* __restrict__ c_div_f,
-                                                 const int32_t* __restrict__ e_c_f, uint8_t* __restrict__ nnf,
-                                                 uint8_t* __restrict__ nef, const uint8_t* __restrict__ allow,
-                                                 int nc) {
-  int64_t e = TID;
-  if (e >= P.Ec || !sec[e] || !r3_allowed(allow, nc, e / 3)) return;
-  mark_cell(P.mid[e], c_e_f, c_div_f, e_c_f, nnf, nef, false);
+__device__ __forceinline__ void op_r3_edge(int64_t e, const MaskJob& j) {
+  if (!j.a_e[e] || !r3_allowed(j.allow, j.nc, e / 3)) return;
+  mark_cell(j.P.mid[e], j, false);
 }
 
-void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
-           uint8_t* nef, hipStream_t s, const uint8_t* allow, int nc) {
-  k_r3_nodes<<<nb(P.Nc), BS, 0, s>>>(P, snc, tf.c_e, tf.c_div, tf.e_c, nnf, nef, allow, nc);
-  k_r3_edges<<<nb(P.Ec), BS, 0, s>>>(P, sec, tf.c_e, tf.c_div, tf.e_c, nnf, nef, allow, nc);
-  HIPCHK(hipGetLastError());
+// blockIdx.y picks the job; its entries (a list, padding -1 skipped, or 0..cnt) by grid stride
+__global__ __launch_bounds__(BS) void k_mask_b(MaskJobs J) {
+  const MaskJob& jb = J.j[blockIdx.y];
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = TID; r < jb.cnt; r += stride) {
+    int64_t i = r;
+    if (jb.lst) {
+      i = jb.lst[r];
+      if (i < 0) continue;
+    }
+    switch (jb.op) {
+      case MO_DET_EDGE: op_det_edge(i, jb); break;
+      case MO_DET_INT: op_det_int(i, jb); break;
+      case MO_SIG_EDGE: op_sig_edge(i, jb); break;
+      case MO_SIG_INT: op_sig_int(i, jb); break;
+      case MO_R2_NODE: op_r2_node(i, jb); break;
+      case MO_R2_EDGE: op_r2_edge(i, jb); break;
+      case MO_R3_NODE: op_r3_node(i, jb); break;
+      case MO_R3_EDGE: op_r3_edge(i, jb); break;
+      default: break;
+    }
+  }
+}
+
+void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_MASK_JOBS) {
+    MaskJobs J{};
+    int nk = 0;
+    int64_t m = 1;
+    for (int k = k0; k < njobs && k < k0 + MAX_MASK_JOBS; ++k) {
+      if (jobs[k].cnt <= 0) continue;
+      J.j[nk++] = jobs[k];
+      if (jobs[k].cnt > m) m = jobs[k].cnt;
+    }
+    if (nk == 0) continue;
+    const unsigned grid = nb(m) < 2048u ? nb(m) : 2048u;
+    k_mask_b<<<dim3(grid, nk), BS, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+void ml_details_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tc, const double* hf,
+                     const double* uf, const double* uc, double* dh, double* dp, double* di, Span le, Span lt) {
+  MaskJob a{};
+  a.P = P; a.e_v = tc.e_v; a.hf = hf; a.uf = uf; a.uc = uc; a.dh = dh; a.dp = dp; a.di = di;
+  a.op = MO_DET_EDGE; a.cnt = span_n(le, P.Ec); a.lst = le.idx;
+  out.push_back(a);
+  a.op = MO_DET_INT; a.cnt = span_n(lt, P.Tc); a.lst = lt.idx;
+  out.push_back(a);
+}
+
+void ml_significant_jobs(std::vector<MaskJob>& out, const DevPair& P, const uint8_t* naf, const uint8_t* eaf,
+                         const double* dh, const double* dp, const double* di, double eh, double eu, uint8_t* sn,
+                         uint8_t* se, Span le, Span lt) {
+  MaskJob a{};
+  a.P = P; a.a_n = naf; a.a_e = eaf; a.dh = const_cast<double*>(dh); a.dp = const_cast<double*>(dp);
+  a.di = const_cast<double*>(di); a.eh = eh; a.eu = eu; a.o_n = sn; a.o_e = se;
+  a.op = MO_SIG_EDGE; a.cnt = span_n(le, P.Ec); a.lst = le.idx;
+  out.push_back(a);
+  a.op = MO_SIG_INT; a.cnt = span_n(lt, P.Tc); a.lst = lt.idx;
+  out.push_back(a);
+}
+
+void ml_r2_jobs(std::vector<MaskJob>& out, const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn,
+                uint8_t* ne) {
+  MaskJob a{};
+  a.c_e = t.c_e; a.c_div = t.c_div; a.e_c = t.e_c; a.e_v = t.e_v; a.t_e = t.t_e;
+  a.a_n = sn; a.a_e = se; a.o_n = nn; a.o_e = ne;
+  a.op = MO_R2_NODE; a.cnt = t.N;
+  out.push_back(a);
+  a.op = MO_R2_EDGE; a.cnt = t.E;
+  out.push_back(a);
+}
+
+void ml_r3_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tf, const uint8_t* snc,
+                const uint8_t* sec, uint8_t* nnf, uint8_t* nef, const uint8_t* allow, int nc) {
+  MaskJob a{};
+  a.P = P; a.c_e = tf.c_e; a.c_div = tf.c_div; a.e_c = tf.e_c;
+  a.a_n = snc; a.a_e = sec; a.o_n = nnf; a.o_e = nef; a.allow = allow; a.nc = nc;
+  a.op = MO_R3_NODE; a.cnt = P.Nc;
+  out.push_back(a);
+  a.op = MO_R3_EDGE; a.cnt = P.Ec;
+  out.push_back(a);
 }
 
 // R4: edges at active nodes, then end nodes of active edges.

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "wt_internal.hpp"
 #include "wt_pair.hpp"
@@ -41,12 +42,41 @@ void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, dou
                        hipStream_t s);
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
                   const uint8_t* eaf, const double* hf, double* hc, hipStream_t s, Span lcn = {});
-void ml_details(const DevPair& P, const DevTables& tc, const double* hf, const double* uf,
-                const double* uc, double* dh, double* dp, double* di, hipStream_t s, Span le = {}, Span lt = {});
-void ml_significant(const DevPair& P, const uint8_t* naf, const uint8_t* eaf, const double* dh,
-                    const double* dp, const double* di, double eh, double eu, uint8_t* sn, uint8_t* se,
-                    hipStream_t s, Span le = {}, Span lt = {});
-void ml_r2(const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn, uint8_t* ne, hipStream_t s);
+// Details of a pair (edge and interior jobs), R1 significance of a pair, R2 of a level and R3 of
+// a pair as jobs of ml_mask_ops, which runs any number of them, MAX_MASK_JOBS per launch
+// (blockIdx.y = job): jobs of one call must not depend on each other (the mask rules only set
+// bytes, so several may write one mask).
+enum MaskOp : int32_t {
+  MO_DET_EDGE = 0, MO_DET_INT, MO_SIG_EDGE, MO_SIG_INT, MO_R2_NODE, MO_R2_EDGE, MO_R3_NODE, MO_R3_EDGE
+};
+struct MaskJob {
+  int32_t op, nc;      // nc: coarse lozenge side of the R3 gate
+  int64_t cnt;         // entries: lst[0..cnt) (-1 padding skipped) or 0..cnt
+  const int32_t* lst;
+  DevPair P;
+  const int32_t *c_e, *e_c, *e_v, *t_e;
+  const double* c_div;
+  const double *hf, *uf, *uc;
+  double *dh, *dp, *di;
+  const uint8_t *a_n, *a_e, *allow;
+  uint8_t *o_n, *o_e;
+  double eh, eu;
+};
+constexpr int MAX_MASK_JOBS = 10;   // per launch (kernel argument size)
+struct MaskJobs {
+  MaskJob j[MAX_MASK_JOBS];
+};
+void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s);
+void ml_details_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tc, const double* hf,
+                     const double* uf, const double* uc, double* dh, double* dp, double* di, Span le = {},
+                     Span lt = {});
+void ml_significant_jobs(std::vector<MaskJob>& out, const DevPair& P, const uint8_t* naf, const uint8_t* eaf,
+                         const double* dh, const double* dp, const double* di, double eh, double eu, uint8_t* sn,
+                         uint8_t* se, Span le = {}, Span lt = {});
+void ml_r2_jobs(std::vector<MaskJob>& out, const DevTables& t, const uint8_t* sn, const uint8_t* se, uint8_t* nn,
+                uint8_t* ne);
+void ml_r3_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tf, const uint8_t* snc,
+                const uint8_t* sec, uint8_t* nnf, uint8_t* nef, const uint8_t* allow = nullptr, int nc = 0);
 // (bn, be) = (an, ae) grown by one ring of same-level neighbours (the R2 relation, gather form)
 // (n = lattice size 2^level).  With plist (from ml_patch_list of the set the ring chain starts
 // from, at most 7 rings ago) only the listed patches and the poles are written: the caller clears
@@ -58,8 +88,6 @@ void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, ui
 // bytes of scratch; n >= 8)
 void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int32_t* plist, hipStream_t s);
 // allow (optional): learned gate per quadrant of the 8 x 8 patches of the coarse level (lattice size nc)
-void ml_r3(const DevPair& P, const DevTables& tf, const uint8_t* snc, const uint8_t* sec, uint8_t* nnf,
-           uint8_t* nef, hipStream_t s, const uint8_t* allow = nullptr, int nc = 0);
 void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s);
 void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
            uint8_t* nec, hipStream_t s);
