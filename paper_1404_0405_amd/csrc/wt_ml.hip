@@ -5,6 +5,7 @@
 // mask (idempotent), so results do not depend on thread order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <stdexcept>
 #include <string>
 
@@ -605,11 +606,15 @@ __device__ __forceinline__ void op_r3_edge(int64_t e, const MaskJob& j) {
   mark_cell(j.P.mid[e], j, false);
 }
 
-// blockIdx.y picks the job; its entries (a list, padding -1 skipped, or 0..cnt) by grid stride
+// Each job owns a range of workgroups, pre[j] <= blockIdx.x < pre[j+1], about one thread per
+// entry (a list, padding -1 skipped, or 0..cnt), striding if the job has more entries.
 __global__ __launch_bounds__(BS) void k_mask_b(MaskJobs J) {
-  const MaskJob& jb = J.j[blockIdx.y];
-  const int64_t stride = int64_t(gridDim.x) * BS;
-  for (int64_t r = TID; r < jb.cnt; r += stride) {
+  const int32_t c = int32_t(blockIdx.x);
+  int q = 0;
+  while (q + 1 < J.n && J.pre[q + 1] <= c) ++q;
+  const MaskJob& jb = J.j[q];
+  const int64_t stride = int64_t(J.pre[q + 1] - J.pre[q]) * BS;
+  for (int64_t r = int64_t(c - J.pre[q]) * BS + threadIdx.x; r < jb.cnt; r += stride) {
     int64_t i = r;
     if (jb.lst) {
       i = jb.lst[r];
@@ -630,18 +635,21 @@ __global__ __launch_bounds__(BS) void k_mask_b(MaskJobs J) {
 }
 
 void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s) {
+  constexpr int64_t kMaxBlocks = 16384;   // per job; more entries are strided over
   for (int k0 = 0; k0 < njobs; k0 += MAX_MASK_JOBS) {
     MaskJobs J{};
     int nk = 0;
-    int64_t m = 1;
+    int64_t run = 0;
     for (int k = k0; k < njobs && k < k0 + MAX_MASK_JOBS; ++k) {
       if (jobs[k].cnt <= 0) continue;
+      J.pre[nk] = int32_t(run);
       J.j[nk++] = jobs[k];
-      if (jobs[k].cnt > m) m = jobs[k].cnt;
+      run += std::min<int64_t>(kMaxBlocks, (jobs[k].cnt + BS - 1) / BS);
     }
     if (nk == 0) continue;
-    const unsigned grid = nb(m) < 2048u ? nb(m) : 2048u;
-    k_mask_b<<<dim3(grid, nk), BS, 0, s>>>(J);
+    J.pre[nk] = int32_t(run);
+    J.n = nk;
+    k_mask_b<<<unsigned(run), BS, 0, s>>>(J);
     HIPCHK(hipGetLastError());
   }
 }

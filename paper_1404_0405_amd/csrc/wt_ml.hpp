@@ -65,6 +65,8 @@ struct MaskJob {
 constexpr int MAX_MASK_JOBS = 10;   // per launch (kernel argument size)
 struct MaskJobs {
   MaskJob j[MAX_MASK_JOBS];
+  int32_t pre[MAX_MASK_JOBS + 1];   // workgroup ranges of the jobs
+  int32_t n;
 };
 void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s);
 void ml_details_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tc, const double* hf,
