@@ -35,7 +35,7 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __restrict__ list, DevTables tb,
                                                const double* __restrict__ dh, const double* __restrict__ u,
                                                double H, T* __restrict__ qv) {
-  int64_t t = int64_t(blockIdx.x) * BS + threadIdx.x;
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   if (list) {
     t = list[t];
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, const int32_t* __re
                                                   const double* __restrict__ dh, const double* __restrict__ u,
                                                   const T* __restrict__ qv, double g, double H, T* __restrict__ B,
                                                   double* __restrict__ F, T* __restrict__ qe) {
-  int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
+  int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= N) return;
   if (list) {
     id = list[id];
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
                                              const T* __restrict__ B, const double* __restrict__ F,
                                              const T* __restrict__ qe, StagePtrs pdh, StagePtrs pu,
                                              StageOut c) {
-  int64_t id = int64_t(blockIdx.x) * BS + threadIdx.x;
+  int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= N) return;
   if (list) {
     id = list[id];
@@ -179,17 +179,21 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
     return 8.0 * r;
   };
   const double e_dof = epi(c, sdh, true);
+  // the rim lists are short (a few tens of thousands of points): small workgroups spread their
+  // gathers over every CU
+  const int bs = use_lat ? 64 : BS;
+  auto grid = [bs](int64_t n) { return unsigned((n + bs - 1) / bs); };
   {
     TimedLaunch tl_(tm, K_VERTEX, s, double(nt) * (80.0 + 16.0 + sz));
-    k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tl, t, sdh.x, su.x, p.H, qv);
+    k_vertex<T><<<grid(nt), bs, 0, s>>>(nt, tl, t, sdh.x, su.x, p.H, qv);
   }
   {
     TimedLaunch tl_(tm, K_EDGE_CELL, s, double(ne) * (120.0 + 32.0 + 24.0 + 6.0 * sz));
-    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, el, t, sdh.x, su.x, qv, p.g, p.H, B, F, qe);
+    k_edge_cell<T><<<grid(ne), bs, 0, s>>>(ne, el, t, sdh.x, su.x, qv, p.g, p.H, B, F, qe);
   }
   {
     TimedLaunch tl_(tm, K_TEND, s, double(nr) * (480.0 + 24.0 + 4.0 * sz + 4.0 * e_dof));
-    k_tend<T><<<nblk(nr), BS, 0, s>>>(nr, t.n_elem, rl, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl, B, F,
+    k_tend<T><<<grid(nr), bs, 0, s>>>(nr, t.n_elem, rl, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl, B, F,
                                       qe, sdh, su, c);
   }
   HIPCHK(hipGetLastError());
