@@ -614,6 +614,48 @@ __global__ __launch_bounds__(BS) void k_mask_b(MaskJobs J) {
   while (q + 1 < J.n && J.pre[q + 1] <= c) ++q;
   const MaskJob& jb = J.j[q];
   const int64_t stride = int64_t(J.pre[q + 1] - J.pre[q]) * BS;
+  if (jb.sparse) {
+    // large whole-level rules, a wavefront at a time: each lane tests the significance bytes of 16
+    // points with one load, a ballot collects the groups holding one (few: significant points are
+    // sparse), and the wavefront then runs four such groups per pass, one point per lane.  The
+    // last, partial group is always visited (its points are bounds-checked).
+    const uint8_t* a = (jb.op == MO_R2_NODE || jb.op == MO_R3_NODE) ? jb.a_n : jb.a_e;
+    const int64_t ng = (jb.cnt + 15) / 16;
+    const int lane = threadIdx.x & 63;
+    for (int64_t gb = int64_t(c - J.pre[q]) * BS + (threadIdx.x & ~63); gb < ng; gb += stride) {
+      const int64_t g = gb + lane;
+      bool hit = false;
+      if (g < ng) {
+        if (16 * g + 16 <= jb.cnt) {
+          const uint4 w = *reinterpret_cast<const uint4*>(a + 16 * g);
+          hit = (w.x | w.y | w.z | w.w) != 0u;
+        } else {
+          hit = true;
+        }
+      }
+      uint64_t rem = __ballot(hit);
+      while (rem) {
+        int sel[4], k = 0;
+        for (; k < 4 && rem; ++k) {
+          sel[k] = __ffsll(static_cast<unsigned long long>(rem)) - 1;
+          rem &= rem - 1;
+        }
+        const int sub = lane >> 4;
+        if (sub < k) {
+          const int64_t i = 16 * (gb + sel[sub]) + (lane & 15);
+          if (i < jb.cnt) {
+            switch (jb.op) {
+              case MO_R2_NODE: op_r2_node(i, jb); break;
+              case MO_R2_EDGE: op_r2_edge(i, jb); break;
+              case MO_R3_NODE: op_r3_node(i, jb); break;
+              default: op_r3_edge(i, jb); break;
+            }
+          }
+        }
+      }
+    }
+    return;
+  }
   for (int64_t r = int64_t(c - J.pre[q]) * BS + threadIdx.x; r < jb.cnt; r += stride) {
     int64_t i = r;
     if (jb.lst) {
@@ -642,9 +684,20 @@ void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s) {
     int64_t run = 0;
     for (int k = k0; k < njobs && k < k0 + MAX_MASK_JOBS; ++k) {
       if (jobs[k].cnt <= 0) continue;
+      const MaskJob& jk = jobs[k];
+      if (jk.op >= MO_R2_NODE && jk.lst)
+        throw std::runtime_error("ml_mask_ops: the mask rules run over whole levels");
+      if (jk.op >= MO_R2_NODE &&
+          (reinterpret_cast<uintptr_t>(jk.op == MO_R2_NODE || jk.op == MO_R3_NODE ? jk.a_n : jk.a_e) & 15))
+        throw std::runtime_error("ml_mask_ops: significance masks must be 16-byte aligned");
+      // rule jobs over large levels scan 16 points per lane (their significant points are
+      // sparse); the others take one point per thread
+      const bool sparse = jk.op >= MO_R2_NODE && jk.cnt >= (int64_t(1) << 21);
+      const int64_t units = sparse ? (jk.cnt + 15) / 16 : jk.cnt;
       J.pre[nk] = int32_t(run);
-      J.j[nk++] = jobs[k];
-      run += std::min<int64_t>(kMaxBlocks, (jobs[k].cnt + BS - 1) / BS);
+      J.j[nk] = jk;
+      J.j[nk++].sparse = sparse ? 1 : 0;
+      run += std::min<int64_t>(kMaxBlocks, (units + BS - 1) / BS);
     }
     if (nk == 0) continue;
     J.pre[nk] = int32_t(run);

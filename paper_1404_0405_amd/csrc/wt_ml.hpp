@@ -51,6 +51,7 @@ enum MaskOp : int32_t {
 };
 struct MaskJob {
   int32_t op, nc;      // nc: coarse lozenge side of the R3 gate
+  int32_t sparse;      // set by ml_mask_ops: scan a large rule job 16 points per lane
   int64_t cnt;         // entries: lst[0..cnt) (-1 padding skipped) or 0..cnt
   const int32_t* lst;
   DevPair P;
