@@ -414,7 +414,7 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
   for (auto& lp : g->lev) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E, T = l.tab.T;
-    pr.push_back(pred_tri_job(T, l.tab.t_e, l.s3e, l.pred_t));
+    pr.push_back(pred_tri_job(T, l.geo.J, l.tab.t_e, l.s3e, l.pred_t));
     pr.push_back(pred_elem_job(N, l.tab.n_elem, l.s3n, l.s3e, l.pred_e));
     pr.push_back(pred_elem_job(N, l.tab.n_elem, l.na, l.ea, l.pred_a));
     cb.add(l.pred_t, T, l.l_tri);
@@ -429,7 +429,7 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
     const int64_t Nc = P.dev.Nc, Ec = P.dev.Ec, Tc = P.dev.Tc;
     if (!P.pred) HIPCHK(hipMalloc(&P.pred, Nc + Ec + Tc));
     uint8_t *pn = P.pred, *pe = P.pred + Nc, *pt = P.pred + Nc + Ec;
-    pr.push_back(pred_pair_job(P.dev, F.s5n, F.s5e, pn, pe, pt));
+    pr.push_back(pred_pair_job(P.dev, j, F.s5n, F.s5e, pn, pe, pt));
     cb.add(pn, Nc, P.l_cn);
     cb.add(pe, Ec, P.l_ce);
     cb.add(pt, Tc, P.l_ct);

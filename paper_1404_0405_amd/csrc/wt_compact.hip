@@ -397,13 +397,32 @@ __global__ __launch_bounds__(CB) void k_pred_pair(DevPair P, const uint8_t* __re
 
 // The predicates of several levels and pairs in one launch: blockIdx.y picks the job, whose
 // entities the row's blocks cover with a grid-stride loop; each job evaluates exactly the
-// predicate of k_pred_tri, k_pred_elem or k_pred_pair.
+// predicate of k_pred_tri, k_pred_elem or k_pred_pair.  The lattice gives the edges of a
+// triangle away from the lozenge's last row and column, and the fine copies, midpoints and
+// half-edges of every coarse node and edge, by index arithmetic (canonical numbering: element
+// (L,i,j) -> (L n + i) n + j, edges 3 id + d, triangles 2 id + t, poles last), so those tables are
+// not read; the other triangles and the interior edges of coarse triangles use the tables.
 __global__ __launch_bounds__(CB) void k_pred_b(PredJobs J) {
   const PredJob& jb = J.j[blockIdx.y];
   const int64_t stride = int64_t(gridDim.x) * CB;
   if (jb.kind == PRED_TRI) {
-    for (int64_t t = TIDX; t < jb.n; t += stride)
-      jb.o1[t] = (jb.se[jb.a[3 * t]] | jb.se[jb.a[3 * t + 1]] | jb.se[jb.a[3 * t + 2]]) ? 1 : 0;
+    const int sh = jb.sh;
+    const int64_t n = int64_t(1) << sh, mk = n - 1;
+    for (int64_t t = TIDX; t < jb.n; t += stride) {
+      const int64_t id = t >> 1;
+      const int64_t i = (id >> sh) & mk, j = id & mk;
+      int64_t e0, e1, e2;
+      if (i < n - 1 && j < n - 1) {
+        if ((t & 1) == 0) {   // ((i,j), (i+1,j), (i+1,j+1))
+          e0 = 3 * id; e1 = 3 * (id + n) + 2; e2 = 3 * id + 1;
+        } else {              // ((i,j), (i+1,j+1), (i,j+1))
+          e0 = 3 * id + 1; e1 = 3 * (id + 1); e2 = 3 * id + 2;
+        }
+      } else {
+        e0 = jb.a[3 * t]; e1 = jb.a[3 * t + 1]; e2 = jb.a[3 * t + 2];
+      }
+      jb.o1[t] = (jb.se[e0] | jb.se[e1] | jb.se[e2]) ? 1 : 0;
+    }
   } else if (jb.kind == PRED_ELEM) {
     for (int64_t i = TIDX; i < jb.n; i += stride) {
       bool p = jb.sn[i] != 0;
@@ -411,17 +430,31 @@ __global__ __launch_bounds__(CB) void k_pred_b(PredJobs J) {
       jb.o1[i] = p ? 1 : 0;
     }
   } else {
+    const int shc = jb.sh;
+    const int64_t nc = int64_t(1) << shc, mk = nc - 1, nf = 2 * nc, lat = 10 * nc * nc;
     for (int64_t k = TIDX; k < jb.n; k += stride) {
-      if (k < jb.Nc) jb.o1[k] = jb.sn[jb.a[k]] ? 1 : 0;
-      if (k < jb.Ec) jb.o2[k] = (jb.sn[jb.b[k]] | jb.se[jb.c[k]] | jb.se[jb.d[k]]) ? 1 : 0;
+      if (k < jb.Nc) {
+        const int64_t f = k < lat ? (((k >> (2 * shc)) * nf + 2 * ((k >> shc) & mk)) * nf + 2 * (k & mk))
+                                  : 10 * nf * nf + (k - lat);
+        jb.o1[k] = jb.sn[f] ? 1 : 0;
+      }
+      if (k < jb.Ec) {
+        const int64_t id = k / 3;
+        const int d = int(k - 3 * id);
+        const int64_t L = id >> (2 * shc), i = (id >> shc) & mk, j = id & mk;
+        const int64_t f0 = (L * nf + 2 * i) * nf + 2 * j;
+        const int64_t fm = (L * nf + 2 * i + (d < 2 ? 1 : 0)) * nf + 2 * j + (d > 0 ? 1 : 0);
+        jb.o2[k] = (jb.sn[fm] | jb.se[3 * f0 + d] | jb.se[3 * fm + d]) ? 1 : 0;
+      }
       if (k < jb.Tc) jb.o3[k] = (jb.se[jb.e[3 * k]] | jb.se[jb.e[3 * k + 1]] | jb.se[jb.e[3 * k + 2]]) ? 1 : 0;
     }
   }
 }
 
-PredJob pred_tri_job(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt) {
+PredJob pred_tri_job(int64_t T, int sh, const int32_t* t_e, const uint8_t* se, uint8_t* pt) {
+  if (T != 20 * (int64_t(1) << (2 * sh))) throw std::runtime_error("pred_tri_job: triangle count does not match 2^sh");
   PredJob j{};
-  j.kind = PRED_TRI; j.n = T; j.a = t_e; j.se = se; j.o1 = pt;
+  j.kind = PRED_TRI; j.sh = sh; j.n = T; j.a = t_e; j.se = se; j.o1 = pt;
   return j;
 }
 
@@ -431,10 +464,14 @@ PredJob pred_elem_job(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_
   return j;
 }
 
-PredJob pred_pair_job(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe,
-                      uint8_t* pt) {
+PredJob pred_pair_job(const DevPair& P, int shc, const uint8_t* snf, const uint8_t* sef, uint8_t* pn,
+                      uint8_t* pe, uint8_t* pt) {
+  const int64_t nc = int64_t(1) << shc;
+  if (P.Ec != 30 * nc * nc || P.Nc != 10 * nc * nc + 2 || P.Nf != 40 * nc * nc + 2)
+    throw std::runtime_error("pred_pair_job: pair sizes do not match 2^shc");
   PredJob j{};
   j.kind = PRED_PAIR;
+  j.sh = shc;
   j.Nc = P.Nc; j.Ec = P.Ec; j.Tc = P.Tc;
   j.n = P.Nc > P.Ec ? P.Nc : P.Ec;
   if (P.Tc > j.n) j.n = P.Tc;

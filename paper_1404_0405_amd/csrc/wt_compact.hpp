@@ -63,7 +63,7 @@ void pred_pair(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t
 // The same predicates for several levels and pairs in one launch.
 enum PredKind : int32_t { PRED_TRI = 0, PRED_ELEM = 1, PRED_PAIR = 2 };
 struct PredJob {
-  int32_t kind;
+  int32_t kind, sh;   // sh: log2 of the lozenge side (triangles: the level; pairs: the coarse level)
   int64_t n, n_elem, Nc, Ec, Tc;
   const int32_t *a, *b, *c, *d, *e;
   const uint8_t *sn, *se;
@@ -73,10 +73,10 @@ constexpr int MAX_PRED_JOBS = 24;   // per launch (kernel argument size)
 struct PredJobs {
   PredJob j[MAX_PRED_JOBS];
 };
-PredJob pred_tri_job(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt);
+PredJob pred_tri_job(int64_t T, int sh, const int32_t* t_e, const uint8_t* se, uint8_t* pt);
 PredJob pred_elem_job(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe);
-PredJob pred_pair_job(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe,
-                      uint8_t* pt);
+PredJob pred_pair_job(const DevPair& P, int shc, const uint8_t* snf, const uint8_t* sef, uint8_t* pn,
+                      uint8_t* pe, uint8_t* pt);
 void pred_batch(const PredJob* jobs, int njobs, hipStream_t s);
 
 }  // namespace wt
