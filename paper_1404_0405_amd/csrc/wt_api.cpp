@@ -109,6 +109,7 @@ struct wt_grid {
   CompactBatch cb;
   // batched read-backs of per-level maxima (pinned)
   static constexpr int kSlots = 256;
+  static constexpr int kThr = 254;   // slots of the adapt's thresholds (eh, eu)
   double* host_val = nullptr;
   wt_params prm{};
   std::vector<std::unique_ptr<LevelState>> lev;    // index j - jmin
@@ -137,7 +138,7 @@ static void alloc_work(LevelState& ls) {
   A(&p, E); w.qe = p;
   A(&p, E); w.Q = p;
   A(&w.c, N);
-  A(&w.red, MAX_JOBS * MAX_BLOCKS + MAX_JOBS);   // batched maxima: partials, then results
+  A(&w.red, MAX_JOBS * MAX_BLOCKS + MAX_JOBS + 8);   // batched maxima: partials, results, thresholds
   auto M = [](uint8_t** q, int64_t n) { HIPCHK(hipMalloc(q, n)); HIPCHK(hipMemset(*q, 0, n)); };
   M(&ls.na, N); M(&ls.ea, E); M(&ls.nn, N); M(&ls.ne, E); M(&ls.sn, N); M(&ls.se, E);
 }
@@ -508,6 +509,24 @@ static void masked_max_all(wt_grid* g, double* mh, double* mu) {
   *mu = bu;
 }
 
+// The same maxima turned into the thresholds eps * max on the device (no read-back); the host
+// copy (host_val[kThr], [kThr + 1]) is valid once the stream has been synchronised.  Returns the
+// device thresholds.
+static const double* thresholds_async(wt_grid* g, double eps) {
+  if (!g->host_val) HIPCHK(hipHostMalloc(&g->host_val, wt_grid::kSlots * sizeof(double), hipHostMallocDefault));
+  MaxJobs jobs{};
+  int k = 0;
+  for (auto& l : g->lev) jobs.j[k++] = MaxJob{l->work.dh, l->na, l->tab.N};
+  for (auto& l : g->lev) jobs.j[k++] = MaxJob{l->work.u, l->ea, l->tab.E};
+  double* red = g->lev.front()->work.red;
+  double* out = red + MAX_JOBS * MAX_BLOCKS;
+  double* thr = out + MAX_JOBS;
+  ml_masked_max_batch(jobs, k, red, out, g->stream);
+  ml_thresholds(out, k / 2, eps, thr, g->stream);
+  HIPCHK(hipMemcpyAsync(g->host_val + wt_grid::kThr, thr, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  return thr;
+}
+
 // ---------------------------------------------------------------- learned adjacent zone
 // Levels whose children rule can be gated: jmin < j < jmax (level jmin has no significant
 // points of its own) with at least one 8 x 8 patch per lozenge side.
@@ -602,7 +621,10 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
   // every point's detail, but outside the support the points are inactive with prolonged values
   // and their details vanish, so the transform runs over the work lists in both cases.
   std::vector<double*> dh = state_dh(g), u = state_u(g);
-  double eh, eu;
+  // thresholds: reused from the passing test, or computed on the device (their host copy is read
+  // once the stream has been synchronised, by the gate below or by the work-list build)
+  double eh = 0.0, eu = 0.0;
+  bool thr_pending = false;
   if (g->judge_ver == g->state_ver && eps == g->last_eps && g->lists_ok) {
     // the passing threshold test after the last step computed exactly this (details, maxima,
     // R1) on this state
@@ -611,10 +633,8 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
   } else {
     prolong_all(g, dh, u, true);
     details_all(g, dh, u, true);
-    double mh, mu;
-    masked_max_all(g, &mh, &mu);
-    eh = eps * mh;
-    eu = eps * mu;
+    const double* thr = thresholds_async(g, eps);
+    thr_pending = true;
     clear_significant(g);
     // R1: significant points
     const bool listed = g->lists_ok;
@@ -622,11 +642,20 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     for (int j = g->jmin; j < g->jmax; ++j) {
       PairState& P = g->P(j);
       LevelState& F = g->L(j + 1);
-      ml_significant_jobs(jobs, P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, eh, eu, F.sn, F.se,
+      ml_significant_jobs(jobs, P.dev, F.na, F.ea, P.d_h, P.d_p, P.d_i, 0.0, 0.0, F.sn, F.se,
                           listed ? span(P.l_ce) : Span{}, listed ? span(P.l_ct) : Span{});
+      jobs[jobs.size() - 1].thr = thr;
+      jobs[jobs.size() - 2].thr = thr;
     }
     ml_mask_ops(jobs.data(), int(jobs.size()), g->stream);
   }
+  auto read_thresholds = [&]() {
+    if (!thr_pending) return;
+    HIPCHK(hipStreamSynchronize(g->stream));
+    eh = g->host_val[wt_grid::kThr];
+    eu = g->host_val[wt_grid::kThr + 1];
+    thr_pending = false;
+  };
   {
     std::vector<ByteJob> cp;
     for (auto& l : g->lev) {
@@ -635,10 +664,9 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
     }
     ml_bytes_batch(cp.data(), int(cp.size()), g->stream);
   }
-  g->last_eh = eh;
-  g->last_eu = eu;
   // learned zone: the predictor proposes, per patch quadrant, whether the children rule applies
   if (gate) {
+    read_thresholds();
     learn_stats_all(g, eh, eu);
     for (int j = g->jmin + 1; j < g->jmax; ++j) {
       if (!learnable(g, j)) continue;
@@ -682,6 +710,15 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
   // the new masks' work lists first: the inverse then rewrites only the support (the old masks
   // stay in nn/ne for it)
   build_work_lists(g, false);
+  if (thr_pending && g->lists_ok) {
+    // the list build's compaction synchronised the stream after the thresholds' copy
+    eh = g->host_val[wt_grid::kThr];
+    eu = g->host_val[wt_grid::kThr + 1];
+    thr_pending = false;
+  }
+  read_thresholds();
+  g->last_eh = eh;
+  g->last_eu = eu;
   inverse_all(g, dh, u, true, true, true);
   // the new masks go back into the buffers that held the old ones, so the mask addresses a
   // recorded step uses stay the same from one adapt to the next

@@ -535,20 +535,22 @@ __device__ __forceinline__ void op_det_int(int64_t t, const MaskJob& j) {
 
 __device__ __forceinline__ void op_sig_edge(int64_t e, const MaskJob& j) {
   const DevPair& P = j.P;
+  const double eh = j.thr ? j.thr[0] : j.eh, eu = j.thr ? j.thr[1] : j.eu;
   const int32_t m = P.mid[e];
-  if (j.a_n[m] && fabs(j.dh[e]) >= j.eh) j.o_n[m] = 1;
+  if (j.a_n[m] && fabs(j.dh[e]) >= eh) j.o_n[m] = 1;
   const int32_t h1 = P.h1[e], h2 = P.h2[e];
-  if (j.a_e[h1] && j.a_e[h2] && fabs(j.dp[e]) >= j.eu) {
+  if (j.a_e[h1] && j.a_e[h2] && fabs(j.dp[e]) >= eu) {
     j.o_e[h1] = 1;
     j.o_e[h2] = 1;
   }
 }
 
 __device__ __forceinline__ void op_sig_int(int64_t t, const MaskJob& j) {
+  const double eu = j.thr ? j.thr[1] : j.eu;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int32_t f = j.P.int_e[3 * t + s];
-    if (j.a_e[f] && fabs(j.di[3 * t + s]) >= j.eu) j.o_e[f] = 1;
+    if (j.a_e[f] && fabs(j.di[3 * t + s]) >= eu) j.o_e[f] = 1;
   }
 }
 
@@ -970,6 +972,22 @@ __global__ __launch_bounds__(BS) void k_max_final_b(int nblk, const double* __re
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+__global__ void k_thresholds(const double* __restrict__ maxima, int nl, double eps, double* __restrict__ thr) {
+  if (threadIdx.x != 0) return;
+  double bh = 0.0, bu = 0.0;
+  for (int q = 0; q < nl; ++q) {
+    bh = fmax(bh, maxima[q]);
+    bu = fmax(bu, maxima[nl + q]);
+  }
+  thr[0] = eps * bh;
+  thr[1] = eps * bu;
+}
+
+void ml_thresholds(const double* maxima, int nl, double eps, double* thr, hipStream_t s) {
+  k_thresholds<<<1, 64, 0, s>>>(maxima, nl, eps, thr);
+  HIPCHK(hipGetLastError());
 }
 
 void ml_masked_max_batch(const MaxJobs& jobs, int njobs, double* scratch, double* out, hipStream_t s) {

@@ -62,6 +62,7 @@ struct MaskJob {
   const uint8_t *a_n, *a_e, *allow;
   uint8_t *o_n, *o_e;
   double eh, eu;
+  const double* thr;   // R1: thresholds (eh, eu) on the device instead of eh, eu (null: use eh, eu)
 };
 constexpr int MAX_MASK_JOBS = 10;   // per launch (kernel argument size)
 struct MaskJobs {
@@ -135,6 +136,9 @@ struct MaxJobs {
   MaxJob j[MAX_JOBS];
 };
 void ml_masked_max_batch(const MaxJobs& jobs, int njobs, double* scratch, double* out, hipStream_t s);
+// thr[0] = eps * max(maxima[0..nl)), thr[1] = eps * max(maxima[nl..2 nl)) (maxima combined in index
+// order from 0, as the host would), on the device
+void ml_thresholds(const double* maxima, int nl, double eps, double* thr, hipStream_t s);
 // dst[0..n) = src[0..n) (src non-null) or the byte val, for any number of 16-byte aligned
 // buffers, MAX_JOBS per launch
 struct ByteJob {
