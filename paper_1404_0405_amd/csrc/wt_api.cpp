@@ -255,16 +255,30 @@ static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::v
 // every stage prolongs the inactive points of the support before reading them)
 static void inverse_all(wt_grid* g, const std::vector<double*>& dh, const std::vector<double*>& u,
                         bool use_new, bool swapped = false, bool listed = false) {
-  for (int j = g->jmin; j < g->jmax; ++j) {
-    PairState& P = g->P(j);
+  auto masks = [&](int j, const uint8_t*& na_old, const uint8_t*& na_new, const uint8_t*& ea_old,
+                   const uint8_t*& ea_new) {
     LevelState& F = g->L(j + 1);
-    const uint8_t *na_old = F.na, *ea_old = F.ea, *na_new = F.na, *ea_new = F.ea;
+    na_old = na_new = F.na;
+    ea_old = ea_new = F.ea;
     if (use_new && !swapped) { na_new = F.nn; ea_new = F.ne; }
     if (use_new && swapped) { na_old = F.nn; ea_old = F.ne; }
-    const bool L = listed && g->lists_ok;
-    ml_inverse(P.dev, g->L(j).tab, na_old, na_new, ea_old, ea_new, P.d_h, P.d_p, P.d_i, P.d_k, dh[j - g->jmin],
-               u[j - g->jmin], dh[j + 1 - g->jmin], u[j + 1 - g->jmin], g->stream, L ? span(P.l_cn) : Span{},
-               L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
+  };
+  std::vector<KeepJob> keep;
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    const uint8_t *na_old, *na_new, *ea_old, *ea_new;
+    masks(j, na_old, na_new, ea_old, ea_new);
+    keep.push_back(KeepJob{P.dev.mid, P.dev.Ec, na_old, na_new, P.d_h, P.d_k});
+  }
+  ml_inverse_keep_batch(keep.data(), int(keep.size()), g->stream);
+  const bool L = listed && g->lists_ok;
+  for (int j = g->jmin; j < g->jmax; ++j) {
+    PairState& P = g->P(j);
+    const uint8_t *na_old, *na_new, *ea_old, *ea_new;
+    masks(j, na_old, na_new, ea_old, ea_new);
+    ml_inverse_pair(P.dev, g->L(j).tab, ea_old, ea_new, P.d_p, P.d_i, P.d_k, dh[j - g->jmin], u[j - g->jmin],
+                    dh[j + 1 - g->jmin], u[j + 1 - g->jmin], g->stream, L ? span(P.l_cn) : Span{},
+                    L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
 }
 

@@ -823,19 +823,18 @@ void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint
 // Top-down, one pair at a time: kept details (points active before and after) or zero;
 // even fine nodes h^j_k - sum_m s_km d_m, then odd nodes d_m + sum_c s~_cm h_even(c);
 // half-edges u^j -+ ((p1-p2) + d)/2; interior edges d + prediction.
-__global__ __launch_bounds__(BS) void k_inv_keep(DevPair P, const uint8_t* __restrict__ na_old,
-                                                 const uint8_t* __restrict__ na_new,
-                                                 const double* __restrict__ dh, double* __restrict__ dk) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
-  int32_t m = P.mid[e];
-  dk[e] = (na_old[m] && na_new[m]) ? dh[e] : 0.0;
+// the kept details of every coarse edge of several pairs (an even node's update reads up to 12
+// of them): blockIdx.y picks the pair
+__global__ __launch_bounds__(BS) void k_inv_keep_b(KeepJobs J) {
+  const KeepJob& jb = J.j[blockIdx.y];
+  for (int64_t e = TID; e < jb.Ec; e += int64_t(gridDim.x) * BS) {
+    const int32_t m = jb.mid[e];
+    jb.dk[e] = (jb.na_old[m] && jb.na_new[m]) ? jb.dh[e] : 0.0;
+  }
 }
 
-__global__ __launch_bounds__(BS) void k_inv_even(DevPair P, const double* __restrict__ dk,
-                                                 const double* __restrict__ hc, double* __restrict__ hf,
-    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(k, cnt, lst)
+__device__ __forceinline__ void inv_even(int64_t k, const DevPair& P, const double* __restrict__ dk,
+                                         const double* __restrict__ hc, double* __restrict__ hf) {
   double s = hc[k];
 #pragma unroll
   for (int q = 0; q < MK_MAX; ++q) {   // valid entries first, then -1: same order as a break
@@ -843,6 +842,46 @@ __global__ __launch_bounds__(BS) void k_inv_even(DevPair P, const double* __rest
     if (ec >= 0) s -= P.s_upd[ec] * dk[ec >> 2];
   }
   hf[P.even[k]] = s;
+}
+
+__device__ __forceinline__ void inv_int(int64_t t, const DevPair& P, const uint8_t* __restrict__ ea_old,
+                                        const uint8_t* __restrict__ ea_new, const double* __restrict__ di,
+                                        const double* __restrict__ uc, double* __restrict__ uf) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int32_t f = P.int_e[3 * t + s];
+    const bool keep = ea_old[f] && ea_new[f];
+    uf[f] = (keep ? di[3 * t + s] : 0.0) + int_pred(P, t, s, uc);
+  }
+}
+
+// even nodes (heights) and interior fine edges (velocities) of a pair in one launch: they do not
+// read each other's outputs; blocks [0, be) take the even nodes, the rest the coarse triangles
+__global__ __launch_bounds__(BS) void k_inv_even_int(DevPair P, const double* __restrict__ dk,
+                                                     const double* __restrict__ hc, double* __restrict__ hf,
+                                                     const int32_t* __restrict__ ln, int64_t nn, int be,
+                                                     const uint8_t* __restrict__ ea_old,
+                                                     const uint8_t* __restrict__ ea_new,
+                                                     const double* __restrict__ di, const double* __restrict__ uc,
+                                                     double* __restrict__ uf, const int32_t* __restrict__ lt,
+                                                     int64_t nt) {
+  if (int(blockIdx.x) < be) {
+    int64_t k = int64_t(blockIdx.x) * BS + threadIdx.x;
+    if (k >= nn) return;
+    if (ln) {
+      k = ln[k];
+      if (k < 0) return;
+    }
+    inv_even(k, P, dk, hc, hf);
+  } else {
+    int64_t t = int64_t(int(blockIdx.x) - be) * BS + threadIdx.x;
+    if (t >= nt) return;
+    if (lt) {
+      t = lt[t];
+      if (t < 0) return;
+    }
+    inv_int(t, P, ea_old, ea_new, di, uc, uf);
+  }
 }
 
 __global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* __restrict__ e_v_c,
@@ -865,30 +904,30 @@ __global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* _
   uf[h2] = uc[e] - half;
 }
 
-__global__ __launch_bounds__(BS) void k_inv_int(DevPair P, const uint8_t* __restrict__ ea_old,
-                                                const uint8_t* __restrict__ ea_new,
-                                                const double* __restrict__ di, const double* __restrict__ uc,
-                                                double* __restrict__ uf,
-    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(t, cnt, lst)
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    int32_t f = P.int_e[3 * t + s];
-    bool keep = ea_old[f] && ea_new[f];
-    uf[f] = (keep ? di[3 * t + s] : 0.0) + int_pred(P, t, s, uc);
+void ml_inverse_keep_batch(const KeepJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_LEVJOBS) {
+    KeepJobs J{};
+    const int nk = njobs - k0 < MAX_LEVJOBS ? njobs - k0 : MAX_LEVJOBS;
+    int64_t m = 1;
+    for (int k = 0; k < nk; ++k) {
+      J.j[k] = jobs[k0 + k];
+      if (J.j[k].Ec > m) m = J.j[k].Ec;
+    }
+    const unsigned grid = nb(m) < 8192u ? nb(m) : 8192u;
+    k_inv_keep_b<<<dim3(grid, nk), BS, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
   }
 }
 
-void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, const uint8_t* na_new,
-                const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
-                const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
-                hipStream_t s, Span ln, Span le, Span lt) {
-  // the kept details of every coarse edge (an even node's update reads up to 12 of them)
-  k_inv_keep<<<nb(P.Ec), BS, 0, s>>>(P, na_old, na_new, dh, dk);
+void ml_inverse_pair(const DevPair& P, const DevTables& tc, const uint8_t* ea_old, const uint8_t* ea_new,
+                     const double* dp, const double* di, const double* dk, const double* hc, const double* uc,
+                     double* hf, double* uf, hipStream_t s, Span ln, Span le, Span lt) {
   const int64_t nn = span_n(ln, P.Nc), ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
-  if (nn) k_inv_even<<<nb(nn), BS, 0, s>>>(P, dk, hc, hf, ln.idx, nn);
+  const int be = int(nb(nn)), bt = int(nb(nt));
+  if (be + bt > 0)
+    k_inv_even_int<<<unsigned(be + bt), BS, 0, s>>>(P, dk, hc, hf, ln.idx, nn, be, ea_old, ea_new, di, uc, uf,
+                                                    lt.idx, nt);
   if (ne) k_inv_odd_pair<<<nb(ne), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf, le.idx, ne);
-  if (nt) k_inv_int<<<nb(nt), BS, 0, s>>>(P, ea_old, ea_new, di, uc, uf, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 

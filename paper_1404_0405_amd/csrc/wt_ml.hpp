@@ -22,6 +22,8 @@ struct DevPair {
   const double *st, *s_upd, *w_int, *w_pl, *w_pr, *rf_fw, *rf_cw;
 };
 
+constexpr int MAX_LEVJOBS = 16;   // level or pair jobs per batched launch
+
 void upload_pair(const PairTables& P, DevPair& d);
 void free_pair(DevPair& d);
 
@@ -95,12 +97,25 @@ void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int
 void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s);
 void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
            uint8_t* nec, hipStream_t s);
-void ml_inverse(const DevPair& P, const DevTables& tc, const uint8_t* na_old, const uint8_t* na_new,
-                const uint8_t* ea_old, const uint8_t* ea_new, const double* dh, const double* dp,
-                const double* di, double* dk, const double* hc, const double* uc, double* hf, double* uf,
-                hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
+// Inverse transform of the pairs, top-down: first the kept details of every pair (one batched
+// launch; they depend only on the details and the old and new masks), then per pair the even
+// nodes and interior edges (one launch), then the odd nodes and half-edges (they read the even
+// nodes).
+struct KeepJob {
+  const int32_t* mid;
+  int64_t Ec;
+  const uint8_t *na_old, *na_new;
+  const double* dh;
+  double* dk;
+};
+struct KeepJobs {
+  KeepJob j[MAX_LEVJOBS];
+};
+void ml_inverse_keep_batch(const KeepJob* jobs, int njobs, hipStream_t s);
+void ml_inverse_pair(const DevPair& P, const DevTables& tc, const uint8_t* ea_old, const uint8_t* ea_new,
+                     const double* dp, const double* di, const double* dk, const double* hc, const double* uc,
+                     double* hf, double* uf, hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
 // Several levels' support rings or patch lists in one launch (blockIdx.y = level job).
-constexpr int MAX_LEVJOBS = 16;
 struct RingJob {
   int32_t N, sh, nblk;
   const int32_t *plist, *pcount, *c_e, *e_c, *e_v, *t_e;
