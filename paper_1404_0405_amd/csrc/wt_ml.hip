@@ -42,21 +42,33 @@ __global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* _
   body_prolong_even(k, P, naf, hc, hf);
 }
 
-__global__ __launch_bounds__(BS) void k_prolong_odd_pair(DevPair P, const uint8_t* __restrict__ naf,
-                                                         const uint8_t* __restrict__ eaf,
-                                                         const int32_t* __restrict__ e_v_c,
-                                                         const double* __restrict__ uc,
-                                                         double* __restrict__ hf, double* __restrict__ uf,
-                                                         const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(e, cnt, lst)
-  body_prolong_odd_pair(e, P, naf, eaf, e_v_c, uc, hf, uf);
-}
-
-__global__ __launch_bounds__(BS) void k_prolong_int(DevPair P, const uint8_t* __restrict__ eaf,
-                                                    const double* __restrict__ uc, double* __restrict__ uf,
-                                                    const int32_t* __restrict__ lst, int64_t cnt) {
-  LISTED(t, cnt, lst)
-  body_prolong_int(t, P, eaf, uc, uf);
+// odd nodes / half-edges and interior edges of a pair in one launch (they do not read each
+// other's outputs; both read the even nodes written before): blocks [0, bo) take the coarse
+// edges, the rest the coarse triangles
+__global__ __launch_bounds__(BS) void k_prolong_odd_int(DevPair P, const uint8_t* __restrict__ naf,
+                                                        const uint8_t* __restrict__ eaf,
+                                                        const int32_t* __restrict__ e_v_c,
+                                                        const double* __restrict__ uc, double* __restrict__ hf,
+                                                        double* __restrict__ uf, const int32_t* __restrict__ le,
+                                                        int64_t ne, int bo, const int32_t* __restrict__ lt,
+                                                        int64_t nt) {
+  if (int(blockIdx.x) < bo) {
+    int64_t e = int64_t(blockIdx.x) * BS + threadIdx.x;
+    if (e >= ne) return;
+    if (le) {
+      e = le[e];
+      if (e < 0) return;
+    }
+    body_prolong_odd_pair(e, P, naf, eaf, e_v_c, uc, hf, uf);
+  } else {
+    int64_t t = int64_t(int(blockIdx.x) - bo) * BS + threadIdx.x;
+    if (t >= nt) return;
+    if (lt) {
+      t = lt[t];
+      if (t < 0) return;
+    }
+    body_prolong_int(t, P, eaf, uc, uf);
+  }
 }
 
 void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
@@ -64,8 +76,9 @@ void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const
                 Span lt) {
   const int64_t nn = span_n(ln, P.Nc), ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
   if (nn) k_prolong_even<<<nb(nn), BS, 0, s>>>(P, naf, hc, hf, ln.idx, nn);
-  if (ne) k_prolong_odd_pair<<<nb(ne), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf, le.idx, ne);
-  if (nt) k_prolong_int<<<nb(nt), BS, 0, s>>>(P, eaf, uc, uf, lt.idx, nt);
+  const int bo = int(nb(ne)), bt = int(nb(nt));
+  if (bo + bt > 0)
+    k_prolong_odd_int<<<unsigned(bo + bt), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf, le.idx, ne, bo, lt.idx, nt);
   HIPCHK(hipGetLastError());
 }
 
