@@ -790,45 +790,37 @@ void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s) {
   HIPCHK(hipGetLastError());
 }
 
-// R5: prediction stencils on the coarse level of every active fine point.
-__global__ __launch_bounds__(BS) void k_r5_edge(DevPair P, const int32_t* __restrict__ e_v_c,
-                                                const uint8_t* __restrict__ nnf,
-                                                const uint8_t* __restrict__ nef, uint8_t* __restrict__ nnc,
-                                                uint8_t* __restrict__ nec) {
-  int64_t e = TID;
-  if (e >= P.Ec) return;
-  if (nnf[P.mid[e]])
-    for (int c = 0; c < 4; ++c) nnc[P.cells[4 * e + c]] = 1;
-  if (nef[P.h1[e]] || nef[P.h2[e]]) {
-    nec[e] = 1;
-    int32_t tl = e_v_c[2 * e], tr = e_v_c[2 * e + 1];
-    for (int k = 0; k < 9; ++k) {
-      nec[P.v_sten[9 * tl + k]] = 1;
-      nec[P.v_sten[9 * tr + k]] = 1;
+// R5: prediction stencils on the coarse level of every active fine point.  Thread k takes coarse
+// edge k, coarse node k and coarse triangle k (the three rules only set coarse mask bytes from
+// the fine masks, so one launch holds them all).
+__global__ __launch_bounds__(BS) void k_r5(DevPair P, const int32_t* __restrict__ e_v_c,
+                                           const uint8_t* __restrict__ nnf, const uint8_t* __restrict__ nef,
+                                           uint8_t* __restrict__ nnc, uint8_t* __restrict__ nec) {
+  const int64_t k = TID;
+  if (k < P.Ec) {
+    const int64_t e = k;
+    if (nnf[P.mid[e]])
+      for (int c = 0; c < 4; ++c) nnc[P.cells[4 * e + c]] = 1;
+    if (nef[P.h1[e]] || nef[P.h2[e]]) {
+      nec[e] = 1;
+      const int32_t tl = e_v_c[2 * e], tr = e_v_c[2 * e + 1];
+      for (int q = 0; q < 9; ++q) {
+        nec[P.v_sten[9 * tl + q]] = 1;
+        nec[P.v_sten[9 * tr + q]] = 1;
+      }
     }
   }
-}
-
-__global__ __launch_bounds__(BS) void k_r5_node(DevPair P, const uint8_t* __restrict__ nnf,
-                                                uint8_t* __restrict__ nnc) {
-  int64_t k = TID;
-  if (k >= P.Nc) return;
-  if (nnf[P.even[k]]) nnc[k] = 1;
-}
-
-__global__ __launch_bounds__(BS) void k_r5_tri(DevPair P, const uint8_t* __restrict__ nef,
-                                               uint8_t* __restrict__ nec) {
-  int64_t t = TID;
-  if (t >= P.Tc) return;
-  if (nef[P.int_e[3 * t]] || nef[P.int_e[3 * t + 1]] || nef[P.int_e[3 * t + 2]])
-    for (int k = 0; k < 9; ++k) nec[P.v_sten[9 * t + k]] = 1;
+  if (k < P.Nc && nnf[P.even[k]]) nnc[k] = 1;
+  if (k < P.Tc && (nef[P.int_e[3 * k]] || nef[P.int_e[3 * k + 1]] || nef[P.int_e[3 * k + 2]]))
+    for (int q = 0; q < 9; ++q) nec[P.v_sten[9 * k + q]] = 1;
 }
 
 void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
            uint8_t* nec, hipStream_t s) {
-  k_r5_edge<<<nb(P.Ec), BS, 0, s>>>(P, tc.e_v, nnf, nef, nnc, nec);
-  k_r5_node<<<nb(P.Nc), BS, 0, s>>>(P, nnf, nnc);
-  k_r5_tri<<<nb(P.Tc), BS, 0, s>>>(P, nef, nec);
+  int64_t m = P.Ec;
+  if (P.Nc > m) m = P.Nc;
+  if (P.Tc > m) m = P.Tc;
+  k_r5<<<nb(m), BS, 0, s>>>(P, tc.e_v, nnf, nef, nnc, nec);
   HIPCHK(hipGetLastError());
 }
 
