@@ -421,7 +421,7 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
       uint8_t* bn[5] = {l.rn_, l.s5n, l.s3n, l.rn_, l.s5n};
       uint8_t* be[5] = {l.re_, l.s5e, l.s3e, l.re_, l.s5e};
       if (nl >= 8) rj.push_back(ring_job(l.tab, nl, an[r], ae[r], bn[r], be[r], l.plist));
-      else ml_ring(l.tab, nl, an[r], ae[r], bn[r], be[r], s, nullptr);
+      else ml_ring(l.tab, nl, an[r], ae[r], bn[r], be[r], s);
     }
     if (!rj.empty()) ml_ring_batch(rj.data(), int(rj.size()), s);
   }

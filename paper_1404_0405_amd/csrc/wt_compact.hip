@@ -367,37 +367,10 @@ void free_scratch(CompactScratch& sc) {
 #define TIDX (int64_t(blockIdx.x) * CB + threadIdx.x)
 static inline unsigned nbk(int64_t n) { return unsigned((n + CB - 1) / CB); }
 
-// triangles with an edge in the edge support
-__global__ __launch_bounds__(CB) void k_pred_tri(int64_t T, const int32_t* __restrict__ t_e,
-                                                 const uint8_t* __restrict__ se, uint8_t* __restrict__ pt) {
-  const int64_t t = TIDX;
-  if (t >= T) return;
-  pt[t] = (se[t_e[3 * t]] | se[t_e[3 * t + 1]] | se[t_e[3 * t + 2]]) ? 1 : 0;
-}
-
-// elements (node + the 3 edges it owns; poles own none) with a point in the support
-__global__ __launch_bounds__(CB) void k_pred_elem(int64_t N, int64_t n_elem, const uint8_t* __restrict__ sn,
-                                                  const uint8_t* __restrict__ se, uint8_t* __restrict__ pe) {
-  const int64_t i = TIDX;
-  if (i >= N) return;
-  bool p = sn[i] != 0;
-  if (i < n_elem) p = p || se[3 * i] || se[3 * i + 1] || se[3 * i + 2];
-  pe[i] = p ? 1 : 0;
-}
-
-// coarse entities of a pair whose fine points lie in the fine support
-__global__ __launch_bounds__(CB) void k_pred_pair(DevPair P, const uint8_t* __restrict__ snf,
-                                                  const uint8_t* __restrict__ sef, uint8_t* __restrict__ pn,
-                                                  uint8_t* __restrict__ pe, uint8_t* __restrict__ pt) {
-  const int64_t k = TIDX;
-  if (k < P.Nc) pn[k] = snf[P.even[k]] ? 1 : 0;
-  if (k < P.Ec) pe[k] = (snf[P.mid[k]] | sef[P.h1[k]] | sef[P.h2[k]]) ? 1 : 0;
-  if (k < P.Tc) pt[k] = (sef[P.int_e[3 * k]] | sef[P.int_e[3 * k + 1]] | sef[P.int_e[3 * k + 2]]) ? 1 : 0;
-}
-
 // The predicates of several levels and pairs in one launch: blockIdx.y picks the job, whose
-// entities the row's blocks cover with a grid-stride loop; each job evaluates exactly the
-// predicate of k_pred_tri, k_pred_elem or k_pred_pair.  The lattice gives the edges of a
+// entities the row's blocks cover with a grid-stride loop: triangles with an edge in the edge
+// support; elements (node + the 3 edges it owns; poles own none) with a point in the support;
+// coarse nodes, edges and triangles of a pair whose fine points lie in the fine support.  The lattice gives the edges of a
 // triangle away from the lozenge's last row and column, and the fine copies, midpoints and
 // half-edges of every coarse node and edge, by index arithmetic (canonical numbering: element
 // (L,i,j) -> (L n + i) n + j, edges 3 id + d, triangles 2 id + t, poles last), so those tables are
@@ -493,25 +466,6 @@ void pred_batch(const PredJob* jobs, int njobs, hipStream_t s) {
     k_pred_b<<<dim3(grid, nk), CB, 0, s>>>(J);
     HIPCHK(hipGetLastError());
   }
-}
-
-void pred_tri(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt, hipStream_t s) {
-  k_pred_tri<<<nbk(T), CB, 0, s>>>(T, t_e, se, pt);
-  HIPCHK(hipGetLastError());
-}
-
-void pred_elem(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe, hipStream_t s) {
-  k_pred_elem<<<nbk(N), CB, 0, s>>>(N, n_elem, sn, se, pe);
-  HIPCHK(hipGetLastError());
-}
-
-void pred_pair(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe, uint8_t* pt,
-               hipStream_t s) {
-  int64_t m = P.Nc;
-  if (P.Ec > m) m = P.Ec;
-  if (P.Tc > m) m = P.Tc;
-  k_pred_pair<<<nbk(m), CB, 0, s>>>(P, snf, sef, pn, pe, pt);
-  HIPCHK(hipGetLastError());
 }
 
 }  // namespace wt

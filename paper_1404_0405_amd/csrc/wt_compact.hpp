@@ -54,13 +54,9 @@ struct CompactBatch {
 };
 void free_scratch(CompactScratch& sc);
 
-// predicates: triangles with an edge in `se`; elements with a point in (sn, se); coarse nodes,
-// edges, triangles of a pair with a fine point in the fine support (snf, sef)
-void pred_tri(int64_t T, const int32_t* t_e, const uint8_t* se, uint8_t* pt, hipStream_t s);
-void pred_elem(int64_t N, int64_t n_elem, const uint8_t* sn, const uint8_t* se, uint8_t* pe, hipStream_t s);
-void pred_pair(const DevPair& P, const uint8_t* snf, const uint8_t* sef, uint8_t* pn, uint8_t* pe, uint8_t* pt,
-               hipStream_t s);
-// The same predicates for several levels and pairs in one launch.
+// Predicates of the work lists, for several levels and pairs in one launch: triangles with an edge
+// in the edge support `se`; elements with a point in (sn, se); coarse nodes, edges, triangles of a
+// pair with a fine point in the fine support (snf, sef).
 enum PredKind : int32_t { PRED_TRI = 0, PRED_ELEM = 1, PRED_PAIR = 2 };
 struct PredJob {
   int32_t kind, sh;   // sh: log2 of the lozenge side (triangles: the level; pairs: the coarse level)

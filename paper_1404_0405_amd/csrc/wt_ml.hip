@@ -298,37 +298,6 @@ __device__ __forceinline__ uint8_t ring_edge(int32_t e, int sh, const int32_t* _
   return m;
 }
 
-// Ring over the listed 8 x 8 node patches: one block per patch (threads 0..63 the nodes, 64..255
-// their 192 edges), blocks striding over the device-side list; block 0 also does the poles.  The
-// points of unlisted patches are not written (the caller cleared them).
-__global__ __launch_bounds__(BS) void k_ring(int32_t N, int sh, const int32_t* __restrict__ plist,
-                                             const int32_t* __restrict__ pcount, const int32_t* __restrict__ c_e,
-                                             const int32_t* __restrict__ e_c, const int32_t* __restrict__ e_v,
-                                             const int32_t* __restrict__ t_e, const uint8_t* __restrict__ an,
-                                             const uint8_t* __restrict__ ae, uint8_t* __restrict__ bn,
-                                             uint8_t* __restrict__ be) {
-  static_assert(BS == 256, "one block covers the 64 nodes and 192 edges of a patch");
-  const int ps = sh - 3, m = 1 << ps;
-  const int tid = threadIdx.x;
-  const int32_t cnt = *pcount;
-  for (int32_t b = blockIdx.x; b < cnt; b += gridDim.x) {
-    const int32_t p = plist[b];
-    const int32_t L = p >> (2 * ps);
-    const int pi = (p >> ps) & (m - 1), pj = p & (m - 1);
-    if (tid < 64) {
-      const int32_t id = (((L << sh) + 8 * pi + (tid >> 3)) << sh) + 8 * pj + (tid & 7);
-      bn[id] = ring_node(id, sh, c_e, e_c, an, ae) ? 1 : 0;
-    } else {
-      const int q = (tid - 64) / 3, d = (tid - 64) - 3 * q;
-      const int32_t id = (((L << sh) + 8 * pi + (q >> 3)) << sh) + 8 * pj + (q & 7);
-      const int32_t e = 3 * id + d;
-      be[e] = ring_edge(e, sh, e_c, e_v, t_e, an, ae) ? 1 : 0;
-    }
-  }
-  const int32_t pole = (10 << (2 * sh)) + tid;
-  if (blockIdx.x == 0 && pole < N) bn[pole] = ring_node(pole, sh, c_e, e_c, an, ae) ? 1 : 0;
-}
-
 // Levels with lozenge side below 8: one thread per node, then one per edge.
 __global__ __launch_bounds__(BS) void k_ring_small(int32_t N, int32_t E, int sh, const int32_t* __restrict__ c_e,
                                                    const int32_t* __restrict__ e_c, const int32_t* __restrict__ e_v,
@@ -341,81 +310,24 @@ __global__ __launch_bounds__(BS) void k_ring_small(int32_t N, int32_t E, int sh,
 }
 
 void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
-             hipStream_t s, const int32_t* plist) {
+             hipStream_t s) {
   if (n <= 0 || (n & (n - 1)) != 0) throw std::runtime_error("ml_ring: lozenge side must be a power of two");
   if (t.N + t.E >= (int64_t(1) << 31)) throw std::runtime_error("ml_ring: level too large for 32-bit ids");
   const int64_t lat = int64_t(10) * n * n;
   if (t.E != 3 * lat || t.N < lat || t.N - lat > BS)
     throw std::runtime_error("ml_ring: tables do not match the lattice size");
   const int sh = __builtin_ctz(unsigned(n));
-  if (!plist) {
-    k_ring_small<<<nb(t.N + t.E), BS, 0, s>>>(int32_t(t.N), int32_t(t.E), sh, t.c_e, t.e_c, t.e_v, t.t_e, an, ae,
-                                              bn, be);
-  } else {
-    if (n < 8) throw std::runtime_error("ml_ring: a patch list needs a lozenge side of at least 8");
-    const int64_t np = lat / 64;
-    const unsigned grid = unsigned(np < 1024 ? np : 1024);
-    k_ring<<<grid, BS, 0, s>>>(int32_t(t.N), sh, plist, plist + np, t.c_e, t.e_c, t.e_v, t.t_e, an, ae, bn, be);
-  }
+  k_ring_small<<<nb(t.N + t.E), BS, 0, s>>>(int32_t(t.N), int32_t(t.E), sh, t.c_e, t.e_c, t.e_v, t.t_e, an, ae,
+                                            bn, be);
   HIPCHK(hipGetLastError());
 }
 
-// Patch list for the ring dilation: pf[p] = the 8 x 8 node patch p (patch (L, pi, pj) ->
-// (L m + pi) m + pj, m = n / 8) holds an active node or an active edge of its nodes; p is listed
-// when some patch of its 3 x 3 neighbourhood in the lozenge is flagged, or p touches the lozenge
-// border.  A node of an unlisted patch is more than 7 lattice steps from every active point (a
-// path from another lozenge crosses the border, 8 steps away), so up to 7 rings leave it and its
-// edges inactive.  The list order is the order of the appends (the ring does not depend on it).
-// One thread per row of a patch (t = ((L m + pi) m + pj) 8 + r): the 8 mask bytes of its nodes and
-// the 24 of their edges; the 8 lanes of a patch are combined by a wavefront ballot.
-__global__ __launch_bounds__(BS) void k_patch_any(int sh, const uint8_t* __restrict__ an,
-                                                  const uint8_t* __restrict__ ae, uint8_t* __restrict__ pf,
-                                                  int32_t* __restrict__ pcount) {
-  const int ps = sh - 3;
-  const int64_t t = TID;
-  if (t == 0) *pcount = 0;
-  const bool valid = t < (int64_t(10) << (2 * sh - 3));
-  bool any = false;
-  if (valid) {
-    const int64_t p = t >> 3;
-    const int m = 1 << ps, r = int(t & 7);
-    const int64_t L = p >> (2 * ps);
-    const int pi = int((p >> ps) & (m - 1)), pj = int(p & (m - 1));
-    const int64_t id0 = ((L << sh) + 8 * pi + r) * (int64_t(1) << sh) + 8 * pj;
-    const uint64_t a = *reinterpret_cast<const uint64_t*>(an + id0);
-    const uint64_t* ew = reinterpret_cast<const uint64_t*>(ae + 3 * id0);
-    any = (a | ew[0] | ew[1] | ew[2]) != 0;
-  }
-  const uint64_t bal = __ballot(any);
-  const int lane = threadIdx.x & 63;
-  if (valid && (lane & 7) == 0) pf[t >> 3] = ((bal >> lane) & 0xffu) ? 1 : 0;
-}
-
-__global__ __launch_bounds__(BS) void k_patch_list(int ps, const uint8_t* __restrict__ pf,
-                                                   int32_t* __restrict__ plist, int32_t* __restrict__ pcount) {
-  const int m = 1 << ps;
-  const int64_t p = TID;
-  if (p >= int64_t(10) << (2 * ps)) return;
-  const int64_t L = p >> (2 * ps);
-  const int pi = int((p >> ps) & (m - 1)), pj = int(p & (m - 1));
-  uint8_t v = (pi == 0 || pj == 0 || pi == m - 1 || pj == m - 1) ? 1 : 0;
-  for (int di = -1; di <= 1 && !v; ++di)
-    for (int dj = -1; dj <= 1 && !v; ++dj) v = pf[((L << ps) + pi + di) * m + pj + dj];
-  if (v) plist[atomicAdd(pcount, 1)] = int32_t(p);
-}
-
-void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int32_t* plist, hipStream_t s) {
-  if (n < 8 || (n & (n - 1)) != 0) throw std::runtime_error("ml_patch_list: lozenge side must be 2^k >= 8");
-  const int sh = __builtin_ctz(unsigned(n)), ps = sh - 3;
-  const int64_t np = int64_t(10) << (2 * ps);
-  k_patch_any<<<nb(np * 8), BS, 0, s>>>(sh, an, ae, pf, plist + np);
-  k_patch_list<<<nb(np), BS, 0, s>>>(ps, pf, plist, plist + np);
-  HIPCHK(hipGetLastError());
-}
-
-// The same ring over the patch lists of several levels in one launch: blockIdx.y picks the level,
-// whose blocks (the first nblk of the row) stride over its list exactly as k_ring's grid does.
+// One ring over the listed 8 x 8 node patches of several levels in one launch: blockIdx.y picks
+// the level, whose first nblk blocks stride over its list, one block per patch (threads 0..63 the
+// nodes, 64..255 their 192 edges); block 0 also does the poles.  The points of unlisted patches
+// are not written (the caller cleared them).
 __global__ __launch_bounds__(BS) void k_ring_b(RingJobs J) {
+  static_assert(BS == 256, "one block covers the 64 nodes and 192 edges of a patch");
   const RingJob& jb = J.j[blockIdx.y];
   if (int(blockIdx.x) >= jb.nblk) return;
   const int sh = jb.sh, ps = sh - 3, m = 1 << ps;
@@ -471,7 +383,15 @@ void ml_ring_batch(const RingJob* jobs, int njobs, hipStream_t s) {
   }
 }
 
-// Patch lists of several levels: blockIdx.y picks the level; rows beyond a level's range exit.
+// Patch list for the ring dilation: pf[p] = the 8 x 8 node patch p (patch (L, pi, pj) ->
+// (L m + pi) m + pj, m = n / 8) holds an active node or an active edge of its nodes; p is listed
+// when some patch of its 3 x 3 neighbourhood in the lozenge is flagged, or p touches the lozenge
+// border.  A node of an unlisted patch is more than 7 lattice steps from every active point (a
+// path from another lozenge crosses the border, 8 steps away), so up to 7 rings leave it and its
+// edges inactive.  The list order is the order of the appends (the ring does not depend on it).
+// Several levels per launch (blockIdx.y picks the level; rows beyond a level's range exit).
+// One thread per row of a patch (t = ((L m + pi) m + pj) 8 + r): the 8 mask bytes of its nodes and
+// the 24 of their edges; the 8 lanes of a patch are combined by a wavefront ballot.
 __global__ __launch_bounds__(BS) void k_patch_any_b(PatchJobs J) {
   const PatchJob& jb = J.j[blockIdx.y];
   const int sh = jb.sh, ps = sh - 3;
@@ -937,42 +857,6 @@ void ml_inverse_pair(const DevPair& P, const DevTables& tc, const uint8_t* ea_ol
 }
 
 // ------------------------------------------------------------------ masked maxima
-__global__ __launch_bounds__(BS) void k_masked_max(int64_t n, const double* __restrict__ v,
-                                                   const uint8_t* __restrict__ act, double* __restrict__ part) {
-  __shared__ double sh[BS];
-  double m = 0.0;
-  for (int64_t i = TID; i < n; i += int64_t(gridDim.x) * BS)
-    if (act[i]) m = fmax(m, fabs(v[i]));
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int st = BS / 2; st > 0; st >>= 1) {
-    if (int(threadIdx.x) < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
-}
-
-__global__ __launch_bounds__(BS) void k_max_final(int n, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double sh[BS];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += BS) m = fmax(m, part[i]);
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int st = BS / 2; st > 0; st >>= 1) {
-    if (int(threadIdx.x) < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = sh[0];
-}
-
-void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
-                   hipStream_t s) {
-  const int nblk = 512;
-  k_masked_max<<<nblk, BS, 0, s>>>(n, v, act, scratch);
-  k_max_final<<<1, BS, 0, s>>>(nblk, scratch, out);
-  HIPCHK(hipGetLastError());
-}
-
 // Several masked maxima in one launch: blockIdx.y picks the job, gridDim.x blocks share its range.
 // Each thread takes 8 consecutive points per pass (one 8-byte mask load, four 16-byte value loads,
 // all independent of the mask so they are in flight together); the maximum is exact, so the

@@ -84,15 +84,9 @@ void ml_r2_jobs(std::vector<MaskJob>& out, const DevTables& t, const uint8_t* sn
 void ml_r3_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tf, const uint8_t* snc,
                 const uint8_t* sec, uint8_t* nnf, uint8_t* nef, const uint8_t* allow = nullptr, int nc = 0);
 // (bn, be) = (an, ae) grown by one ring of same-level neighbours (the R2 relation, gather form)
-// (n = lattice size 2^level).  With plist (from ml_patch_list of the set the ring chain starts
-// from, at most 7 rings ago) only the listed patches and the poles are written: the caller clears
-// (bn, be) once before the chain.
+// over a whole level of lozenge side n < 8 (larger levels: ml_ring_batch over patch lists).
 void ml_ring(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
-             hipStream_t s, const int32_t* plist = nullptr);
-// 8 x 8 node patches within one patch of an active point of (an, ae) or on a lozenge border:
-// plist[0..count) with count = plist[np], np = 10 (n/8)^2 (plist holds np + 1 ints, pf np
-// bytes of scratch; n >= 8)
-void ml_patch_list(int n, const uint8_t* an, const uint8_t* ae, uint8_t* pf, int32_t* plist, hipStream_t s);
+             hipStream_t s);
 // allow (optional): learned gate per quadrant of the 8 x 8 patches of the coarse level (lattice size nc)
 void ml_r4(const DevTables& t, uint8_t* nn, uint8_t* ne, hipStream_t s);
 void ml_r5(const DevPair& P, const DevTables& tc, const uint8_t* nnf, const uint8_t* nef, uint8_t* nnc,
@@ -126,6 +120,8 @@ struct RingJobs {
   RingJob j[MAX_LEVJOBS];
 };
 // one ring of (an, ae) into (bn, be) over the listed patches of a level with lozenge side n >= 8
+// (plist from ml_patch_list_batch of the set the ring chain starts from, at most 7 rings ago; the
+// caller clears (bn, be) once before the chain)
 RingJob ring_job(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae, uint8_t* bn, uint8_t* be,
                  const int32_t* plist);
 void ml_ring_batch(const RingJob* jobs, int njobs, hipStream_t s);
@@ -138,6 +134,9 @@ struct PatchJob {
 struct PatchJobs {
   PatchJob j[MAX_LEVJOBS];
 };
+// 8 x 8 node patches within one patch of an active point of (an, ae) or on a lozenge border, per
+// level: plist[0..count) with count = *pcount = plist[np], np = 10 (n/8)^2 (plist holds np + 1
+// ints, pf np bytes of scratch)
 void ml_patch_list_batch(const PatchJob* jobs, int njobs, hipStream_t s);
 // max |v[i]| over act[i] != 0 for up to MAX_JOBS arrays at once; scratch holds
 // MAX_JOBS * MAX_BLOCKS doubles, out[k] receives job k's maximum (0 when nothing is active)
@@ -166,8 +165,6 @@ struct ByteJobs {
   ByteJob j[MAX_JOBS];
 };
 void ml_bytes_batch(const ByteJob* jobs, int njobs, hipStream_t s);
-void ml_masked_max(int64_t n, const double* v, const uint8_t* act, double* scratch, double* out,
-                   hipStream_t s);
 void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipStream_t s);
 
 }  // namespace wt
