@@ -571,12 +571,14 @@ static void ensure_learn_buffers(wt_grid* g) {
 static void learn_stats_all(wt_grid* g, double eh, double eu) {
   ensure_learn_buffers(g);
   const bool L = g->details_partial;   // then only the work lists' details are current
+  std::vector<PointRJob> pr;
   for (int j = g->jmin + 1; j <= g->jmax; ++j) {
     PairState& P = g->P(j - 1);
     LevelState& l = g->L(j);
-    learn_point_r(P.dev, P.d_h, P.d_p, P.d_i, eh, eu, l.rn, l.re, g->stream, L ? span(P.l_ce) : Span{},
-                  L ? span(P.l_ct) : Span{});
+    pr.push_back(point_r_job(P.dev, P.d_h, P.d_p, P.d_i, eh, eu, l.rn, l.re, L ? span(P.l_ce) : Span{},
+                             L ? span(P.l_ct) : Span{}));
   }
+  learn_point_r_batch(pr.data(), int(pr.size()), g->stream);
   for (int j = g->jmin + 1; j < g->jmax; ++j) {
     if (!learnable(g, j)) continue;
     LevelState &l = g->L(j), &F = g->L(j + 1);

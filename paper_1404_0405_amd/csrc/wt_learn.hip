@@ -7,6 +7,7 @@
 // (L, 2 pi + a, 2 pj + b) of level j+1.  The poles belong to no patch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 #include <string>
@@ -34,49 +35,68 @@ __device__ __forceinline__ float rlog(double d, double eps) {
   return 0.125f * v;
 }
 
-__global__ __launch_bounds__(LB) void k_fill_f(float* __restrict__ a, int64_t n, float v) {
-  const int64_t i = TID;
-  if (i < n) a[i] = v;
+// Detail size of every fine point of several pairs (each fine point carries at most one detail),
+// in two launches: every pair's arrays filled with the floor, then every pair's edge and triangle
+// entries (blockIdx.y = 2 pair for the edges, 2 pair + 1 for the triangles).
+__global__ __launch_bounds__(LB) void k_fill_pr_b(PointRJobs J) {
+  const PointRJob& jb = J.j[blockIdx.y >> 1];
+  float* a = (blockIdx.y & 1) ? jb.re : jb.rn;
+  const int64_t n = (blockIdx.y & 1) ? jb.P.Ef : jb.P.Nf;
+  for (int64_t i = TID; i < n; i += int64_t(gridDim.x) * LB) a[i] = -2.f;
 }
 
-// Detail size of every fine point of a pair (each fine point carries at most one detail).
-__global__ __launch_bounds__(LB) void k_point_r_edge(DevPair P, const double* __restrict__ dh,
-                                                     const double* __restrict__ dp, double eh, double eu,
-                                                     float* __restrict__ rn, float* __restrict__ re,
-                                                     const int32_t* __restrict__ lst, int64_t cnt) {
-  int64_t e = TID;
-  if (e >= cnt) return;
-  if (lst) {
-    e = lst[e];
-    if (e < 0) return;   // padding of a work list
-  }
-  rn[P.mid[e]] = rlog(dh[e], eh);
-  const float ru = rlog(dp[e], eu);
-  re[P.h1[e]] = ru;
-  re[P.h2[e]] = ru;
-}
-
-__global__ __launch_bounds__(LB) void k_point_r_int(DevPair P, const double* __restrict__ di, double eu,
-                                                    float* __restrict__ re, const int32_t* __restrict__ lst,
-                                                    int64_t cnt) {
-  int64_t t = TID;
-  if (t >= cnt) return;
-  if (lst) {
-    t = lst[t];
-    if (t < 0) return;   // padding of a work list
-  }
+__global__ __launch_bounds__(LB) void k_point_r_b(PointRJobs J) {
+  const PointRJob& jb = J.j[blockIdx.y >> 1];
+  const DevPair& P = jb.P;
+  const int64_t stride = int64_t(gridDim.x) * LB;
+  if ((blockIdx.y & 1) == 0) {
+    for (int64_t r = TID; r < jb.ne; r += stride) {
+      int64_t e = r;
+      if (jb.le) {
+        e = jb.le[r];
+        if (e < 0) continue;   // padding of a work list
+      }
+      jb.rn[P.mid[e]] = rlog(jb.dh[e], jb.eh);
+      const float ru = rlog(jb.dp[e], jb.eu);
+      jb.re[P.h1[e]] = ru;
+      jb.re[P.h2[e]] = ru;
+    }
+  } else {
+    for (int64_t r = TID; r < jb.nt; r += stride) {
+      int64_t t = r;
+      if (jb.lt) {
+        t = jb.lt[r];
+        if (t < 0) continue;
+      }
 #pragma unroll
-  for (int s = 0; s < 3; ++s) re[P.int_e[3 * t + s]] = rlog(di[3 * t + s], eu);
+      for (int s = 0; s < 3; ++s) jb.re[P.int_e[3 * t + s]] = rlog(jb.di[3 * t + s], jb.eu);
+    }
+  }
 }
 
-void learn_point_r(const DevPair& P, const double* dh, const double* dp, const double* di, double eh, double eu,
-                   float* rn, float* re, hipStream_t s, Span le, Span lt) {
-  k_fill_f<<<nb(P.Nf), LB, 0, s>>>(rn, P.Nf, -2.f);
-  k_fill_f<<<nb(P.Ef), LB, 0, s>>>(re, P.Ef, -2.f);
-  const int64_t ne = le.idx ? le.n : P.Ec, nt = lt.idx ? lt.n : P.Tc;
-  if (ne) k_point_r_edge<<<nb(ne), LB, 0, s>>>(P, dh, dp, eh, eu, rn, re, le.idx, ne);
-  if (nt) k_point_r_int<<<nb(nt), LB, 0, s>>>(P, di, eu, re, lt.idx, nt);
-  HIPCHK(hipGetLastError());
+void learn_point_r_batch(const PointRJob* jobs, int njobs, hipStream_t s) {
+  for (int k0 = 0; k0 < njobs; k0 += MAX_PR_JOBS) {
+    PointRJobs J{};
+    const int nk = njobs - k0 < MAX_PR_JOBS ? njobs - k0 : MAX_PR_JOBS;
+    int64_t mf = 1, mp = 1;
+    for (int k = 0; k < nk; ++k) {
+      J.j[k] = jobs[k0 + k];
+      mf = std::max<int64_t>(mf, J.j[k].P.Ef);
+      mp = std::max<int64_t>(mp, std::max(J.j[k].ne, J.j[k].nt));
+    }
+    k_fill_pr_b<<<dim3(std::min(nb(mf), 8192u), 2 * nk), LB, 0, s>>>(J);
+    k_point_r_b<<<dim3(std::min(nb(mp), 8192u), 2 * nk), LB, 0, s>>>(J);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+PointRJob point_r_job(const DevPair& P, const double* dh, const double* dp, const double* di, double eh, double eu,
+                      float* rn, float* re, Span le, Span lt) {
+  PointRJob j{};
+  j.P = P; j.dh = dh; j.dp = dp; j.di = di; j.eh = eh; j.eu = eu; j.rn = rn; j.re = re;
+  j.le = le.idx; j.ne = le.idx ? le.n : P.Ec;
+  j.lt = lt.idx; j.nt = lt.idx ? lt.n : P.Tc;
+  return j;
 }
 
 // Per-patch statistics, one wavefront per patch (lane = element of the patch):

@@ -10,12 +10,26 @@ namespace wt {
 
 constexpr int LEARN_STATS = 32;   // statistics per patch (layout in wt_learn.hip)
 
-// rn[Nf], re[Ef]: detail size of every fine point of the pair (floor where there is none).
-// With work lists (le: coarse edges, lt: coarse triangles) only the listed points are read and
-// every other point gets the floor: the points outside the lists are inactive with prolonged
-// values, whose details vanish (up to rounding, far below the floor).
-void learn_point_r(const DevPair& P, const double* dh, const double* dp, const double* di, double eh, double eu,
-                   float* rn, float* re, hipStream_t s, Span le = {}, Span lt = {});
+// rn[Nf], re[Ef]: detail size of every fine point of a pair (floor where there is none), for
+// several pairs in two launches (the pairs' arrays are disjoint).  With work lists (le: coarse
+// edges, lt: coarse triangles) only the listed points are read and every other point gets the
+// floor: the points outside the lists are inactive with prolonged values, whose details vanish
+// (up to rounding, far below the floor).
+struct PointRJob {
+  DevPair P;
+  const double *dh, *dp, *di;
+  double eh, eu;
+  float *rn, *re;
+  const int32_t *le, *lt;
+  int64_t ne, nt;
+};
+constexpr int MAX_PR_JOBS = 12;   // per launch (kernel argument size)
+struct PointRJobs {
+  PointRJob j[MAX_PR_JOBS];
+};
+PointRJob point_r_job(const DevPair& P, const double* dh, const double* dp, const double* di, double eh, double eu,
+                      float* rn, float* re, Span le = {}, Span lt = {});
+void learn_point_r_batch(const PointRJob* jobs, int njobs, hipStream_t s);
 // statistics of the npatch = 10 (n/8)^2 patches of a level with lattice size n: rn, re of the
 // level (details of the pair below), rnf, ref of the level above, masks na (level), naf
 // (level above), significant points sn, se of the level
