@@ -1672,6 +1672,10 @@ struct wt_ensemble {
   hipGraphExec_t exec = nullptr;
   std::vector<uint64_t> epochs;   // member epochs the graph (or the batch plan) was built with
   std::vector<char> phased;       // members captured in the merged-phase form
+  // merged phases across members: one launch per phase over every member's jobs (graph form)
+  bool merged = false;            // the current graph holds this form
+  wt::BatchPlan mplan;
+  std::vector<wt::PhaseDev> mphase;
   std::vector<double> dts;
   int64_t captures = 0, launches = 0;
   // batched persistent step
@@ -1935,6 +1939,7 @@ void wt_ensemble_destroy(wt_ensemble* e) {
   if (!e) return;
   if (e->s0) (void)hipStreamSynchronize(e->s0);
   e->plan.release();
+  e->mplan.release();
   if (e->t0) (void)hipEventDestroy(e->t0);
   if (e->t1) (void)hipEventDestroy(e->t1);
   if (e->exec) (void)hipGraphExecDestroy(e->exec);
@@ -1959,36 +1964,56 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
     if (!(dt[k] > 0) || !std::isfinite(dt[k])) return fail(WT_EINVAL, "wt_ensemble_step: dt must be positive");
   }
   try {
+    for (auto* m : e->m)
+      if (m->multi()) touch_epoch(m);   // the signatures below see every change of the launches
     bool stale = !e->exec || e->dts.size() != n;
     for (size_t k = 0; k < n && !stale; ++k) stale = e->epochs[k] != e->m[k]->epoch || e->dts[k] != dt[k];
+    bool merged = false;
     if (e->batched) {
       batched_step(e, dt);
     } else {
-      // members whose merged-phase plan had to be rebuilt change their launches
-      std::vector<char> phased(n);
-      for (size_t k = 0; k < n; ++k) {
-        wt_grid* m = e->m[k];
-        const bool had = !m->sphase.empty() && m->splan_sig == m->step_sig && m->splan_dt == dt[k];
-        phased[k] = m->multi() && phase_plan_ready(m, dt[k]);
-        if (phased[k] && !had) stale = true;
+      // every member listed and multilevel: one launch per phase over all members' jobs
+      merged = true;
+      for (auto* m : e->m) merged = merged && m->multi() && m->step_phases && m->use_lists && m->lists_ok;
+      if (merged) {
+        if (stale || !e->merged) {
+          build_batch_plan(e->m, dt, e->mplan);
+          e->mplan.upload(e->s0);
+          phase_prepare_dev(e->mplan, e->mphase, e->s0);
+          stale = true;
+        }
+      } else {
+        // members whose merged-phase plan had to be rebuilt change their launches
+        std::vector<char> phased(n);
+        for (size_t k = 0; k < n; ++k) {
+          wt_grid* m = e->m[k];
+          const bool had = !m->sphase.empty() && m->splan_sig == m->step_sig && m->splan_dt == dt[k];
+          phased[k] = m->multi() && phase_plan_ready(m, dt[k]);
+          if (phased[k] && !had) stale = true;
+        }
+        if (phased != e->phased || e->merged) stale = true;
+        e->phased.swap(phased);
       }
-      if (phased != e->phased) stale = true;
-      e->phased.swap(phased);
     }
     if (!e->batched && stale) {
-      // capture every member's step on its own stream, forked from and joined into s0
+      // capture the merged phases on s0, or every member's step on its own stream, forked from
+      // and joined into s0
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed));
       try {
-        HIPCHK(hipEventRecord(e->fork, e->s0));
-        for (size_t k = 0; k < n; ++k) {
-          wt_grid* m = e->m[k];
-          HIPCHK(hipStreamWaitEvent(m->stream, e->fork, 0));
-          if (e->phased[k]) ml_step_phases(m);
-          else if (m->multi()) ml_step(m, dt[k]);
-          else uniform_step(m, m->L(m->jmax), dt[k]);
-          HIPCHK(hipEventRecord(e->join[k], m->stream));
-          HIPCHK(hipStreamWaitEvent(e->s0, e->join[k], 0));
+        if (merged) {
+          for (const auto& ph : e->mphase) phase_launch_dev(e->mplan, ph, e->s0);
+        } else {
+          HIPCHK(hipEventRecord(e->fork, e->s0));
+          for (size_t k = 0; k < n; ++k) {
+            wt_grid* m = e->m[k];
+            HIPCHK(hipStreamWaitEvent(m->stream, e->fork, 0));
+            if (e->phased[k]) ml_step_phases(m);
+            else if (m->multi()) ml_step(m, dt[k]);
+            else uniform_step(m, m->L(m->jmax), dt[k]);
+            HIPCHK(hipEventRecord(e->join[k], m->stream));
+            HIPCHK(hipStreamWaitEvent(e->s0, e->join[k], 0));
+          }
         }
       } catch (...) {
         hipGraph_t dropped = nullptr;
@@ -2014,6 +2039,7 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
       e->epochs.resize(n);
       for (size_t k = 0; k < n; ++k) e->epochs[k] = e->m[k]->epoch;
       e->dts.assign(dt, dt + n);
+      e->merged = merged;
       ++e->captures;
     }
     if (!e->batched) {

@@ -276,6 +276,62 @@ void phase_launch(const BatchPlan& plan, const PhaseArgs& a, hipStream_t s) {
   HIPCHK(hipGetLastError());
 }
 
+// One phase as an ordinary launch with the chunk prefix on the device: workgroup c runs entries
+// [256 (c - pre[j]), +256) of the job j with pre[j] <= c < pre[j+1].
+__global__ __launch_bounds__(BB) void k_phase_dev(const BatchLevel* __restrict__ LV, const BatchPair* __restrict__ PR,
+                                                  const BatchJob* __restrict__ JB, int32_t j0, int32_t nj,
+                                                  const int32_t* __restrict__ pre) {
+  const int32_t c = int32_t(blockIdx.x);
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {   // the last j with pre[j] <= c (jobs without entries are passed over)
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchJob jb = JB[j0 + lo];
+  const int64_t r = int64_t(c - pre[lo]) * BB + threadIdx.x;
+  if (r >= jb.cnt) return;
+  int64_t i = r;
+  if (jb.lst) {
+    i = jb.lst[r];
+    if (i < 0) return;   // padding of a work list
+  }
+  if (jb.fp32) batch_entry<float>(jb, i, LV, PR);
+  else batch_entry<double>(jb, i, LV, PR);
+}
+
+void phase_prepare_dev(BatchPlan& plan, std::vector<PhaseDev>& out, hipStream_t s) {
+  out.clear();
+  std::vector<int32_t> pre;
+  for (const BatchPhase& ph : plan.phases) {
+    PhaseDev a{ph.j0, ph.j1 - ph.j0, 0, int32_t(pre.size())};
+    int64_t run = 0;
+    for (int j = 0; j < a.nj; ++j) {
+      pre.push_back(int32_t(run));
+      run += (plan.jobs[ph.j0 + j].cnt + BB - 1) / BB;
+    }
+    if (run >= (int64_t(1) << 31)) throw std::runtime_error("phase step: too many workgroups");
+    pre.push_back(int32_t(run));
+    a.total = int32_t(run);
+    if (a.total > 0) out.push_back(a);
+  }
+  HIPCHK(hipStreamSynchronize(s));   // the previous table may still be read by a queued launch
+  if (!plan.d_pre || plan.cap_pre < pre.size()) {
+    if (plan.d_pre) HIPCHK(hipFree(plan.d_pre));
+    plan.cap_pre = std::max<size_t>(1, pre.size() + pre.size() / 2);
+    HIPCHK(hipMalloc(&plan.d_pre, plan.cap_pre * sizeof(int32_t)));
+  }
+  HIPCHK(hipMemcpyAsync(plan.d_pre, pre.data(), pre.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));   // pre is a local vector
+}
+
+void phase_launch_dev(const BatchPlan& plan, const PhaseDev& a, hipStream_t s) {
+  if (a.total <= 0) return;
+  k_phase_dev<<<unsigned(a.total), BB, 0, s>>>(plan.d_levels, plan.d_pairs, plan.d_jobs, a.j0, a.nj,
+                                               plan.d_pre + a.off);
+  HIPCHK(hipGetLastError());
+}
+
 // device words of a plan's counters: one work-queue counter per phase, BAR_SLOTS barrier lines
 // per phase, the error flag
 static size_t ctr_words(size_t nphase) {
@@ -314,7 +370,7 @@ void BatchPlan::upload(hipStream_t s) {
 }
 
 void BatchPlan::release() {
-  void* ps[] = {d_levels, d_pairs, d_jobs, d_phases, d_ctr};
+  void* ps[] = {d_levels, d_pairs, d_jobs, d_phases, d_ctr, d_pre};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& c : cap) c = 0;
@@ -323,6 +379,8 @@ void BatchPlan::release() {
   d_jobs = nullptr;
   d_phases = nullptr;
   d_ctr = nullptr;
+  d_pre = nullptr;
+  cap_pre = 0;
   nphase = 0;
 }
 

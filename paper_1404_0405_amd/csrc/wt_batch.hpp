@@ -74,6 +74,8 @@ struct BatchPlan {
   int32_t* d_ctr = nullptr;   // work-queue counters, barrier slots and error flag of the phases
   size_t cap[5] = {0, 0, 0, 0, 0};   // allocated sizes of the five device buffers
   int nphase = 0;
+  int32_t* d_pre = nullptr;   // chunk prefixes of the phases for ordinary launches (phase_prepare_dev)
+  size_t cap_pre = 0;
 
   void upload(hipStream_t s);
   void release();
@@ -90,6 +92,13 @@ struct PhaseArgs {
 };
 void phase_prepare(const BatchPlan& plan, std::vector<PhaseArgs>& out);
 void phase_launch(const BatchPlan& plan, const PhaseArgs& a, hipStream_t s);
+// The same for phases with any number of jobs (an ensemble's): the prefixes live on the device
+// (uploaded here, synchronising s), the workgroup finds its job by binary search.
+struct PhaseDev {
+  int32_t j0, nj, total, off;   // off: start of the phase's prefix in plan.d_pre
+};
+void phase_prepare_dev(BatchPlan& plan, std::vector<PhaseDev>& out, hipStream_t s);
+void phase_launch_dev(const BatchPlan& plan, const PhaseDev& a, hipStream_t s);
 
 // Largest cooperative grid (workgroups per CU x CUs) the device holds for the batch kernel.
 int batch_max_blocks_per_cu();
