@@ -322,11 +322,13 @@ int wt_redo_count(const wt_grid* g, int64_t* redo);
 /* ---------------------------------------------------------------------------------------
  * Ensembles (an addition to the method, not from the paper): independent members -- grids of
  * any levels, thresholds and precision -- advanced together.  One step of the ensemble is ONE
- * launch of a HIP graph that holds every member's Runge-Kutta step, each member on its own
- * stream so the members' kernels run concurrently; the graph is captured again (or updated in
- * place) only when a member's work lists or time step changed since the last capture.  Adapt
- * runs member by member (it reads thresholds back to the host).  With the learned zone, each
- * member's step is judged after the graph and redone on its own if needed. */
+ * launch of a HIP graph that holds every member's Runge-Kutta step: when every member is a
+ * multilevel grid stepping over work lists, as one launch per phase of the step over all
+ * members' work (prolongation, intermediates, restriction, tendencies, partial transform), else
+ * each member's step on its own stream; the graph is captured again (or updated in place) only
+ * when a member's work lists, parameters or time step changed since the last capture.  Adapt
+ * runs member by member on a few host threads (it reads list counts back to the host).  With the
+ * learned zone, each member's step is judged after the graph and redone on its own if needed. */
 typedef struct wt_ensemble wt_ensemble;
 /* members: n distinct grids with distinct streams (the caller keeps them alive). */
 wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n);
