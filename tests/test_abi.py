@@ -71,3 +71,15 @@ def test_lattice_reference_geometry(J):
     assert tiles == (n // 16) * (n // 32) - 4
     assert rim == 4 * 16 * 32 * 10 + 2
     assert err < 1e-12, err
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus N > 1 exits with status 2 and says so, before any GPU
+    work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
