@@ -1,6 +1,7 @@
 """GPU parity of the uniform-level TRiSK stage: HIP library (through the C ABI) against the
 FP64 oracle on the same seeded inputs."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -176,3 +177,30 @@ def test_full_size_j10_properties():
     assert abs(d1.mass / d0.mass - 1) < 1e-13
     assert abs(d1.energy / d0.energy - 1) < 1e-9
     assert np.abs(gdh - dh).max() < 5.0 and np.abs(gu - u).max() < 2.0
+
+
+def test_full_size_j10_sampled_parity():
+    """Full size (level 10, 10,485,762 cells), the grid and kernels the bench times: tendencies
+    of eqs. (height),(velo) and one classical RK4 step of a seeded random state against oracle
+    values stored at sampled nodes and edges (every pentagon, lozenge borders, seeded random
+    entities; tests/golden/make_j10_samples.py), within 1e-11 of the full field's maximum; the
+    maxima of the full fields, which cover every entity, agree to the same bound."""
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "j10_samples.npz"))
+    J = int(ref["level"])
+    _say(f"full size J={J} sampled parity")
+    g = wt.Grid(J, J, 8)
+    with g:
+        N, E, _ = g.info(J)
+        dh, u = inputs.random_state(N, E, int(ref["seed"]))
+        g.set_params(mean_depth=float(ref["mean_depth"]), rk=wt.WT_RK4, precision=wt.WT_FP64)
+        g.set_state(J, dh, u)
+        a, b = g.tendency(J)
+        g.step(float(ref["dt"]))
+        gdh, gu, _, _ = g.get_state(J)
+    nodes, edges = ref["nodes"], ref["edges"]
+    for got, full, want, wmax in ((a[nodes], a, ref["ddh"], ref["ddh_max"]), (b[edges], b, ref["du"], ref["du_max"]),
+                                  (gdh[nodes], gdh, ref["dh1"], ref["dh1_max"]),
+                                  (gu[edges], gu, ref["u1"], ref["u1_max"])):
+        err = np.abs(got - want).max() / float(wmax)
+        assert err < 1e-11, err
+        assert np.abs(full).max() == pytest.approx(float(wmax), rel=1e-11)
