@@ -540,8 +540,9 @@ class Hierarchy:
         details that are kept (those of points active before and after); coarse values are
         never changed, so the mass on jmin is unchanged."""
         det = self.details()
-        mh = max(np.abs(self.dh[j][self.node_act[j]]).max() for j in self.levels)
-        mu = max(np.abs(self.u[j][self.edge_act[j]]).max() for j in self.levels)
+        # a level with no active point adds nothing to the maxima (every jmin point is active)
+        mh = max(np.abs(self.dh[j][self.node_act[j]]).max(initial=0.0) for j in self.levels)
+        mu = max(np.abs(self.u[j][self.edge_act[j]]).max(initial=0.0) for j in self.levels)
         eh, eu = eps * mh, eps * mu
         sig_n = {j: np.zeros(self.g[j].N, bool) for j in self.levels}
         sig_e = {j: np.zeros(self.g[j].E, bool) for j in self.levels}

@@ -136,6 +136,30 @@ def test_adaptive_run_parity_and_mass():
     assert d.active_nodes[5] == H.node_act[5].sum()
 
 
+def test_adaptive_run_through_an_empty_level():
+    """TC2 on levels 2..5 at eps = 1e-2: the first adapt empties level 5, later adaptations fill
+    it again (an empty level adds nothing to the threshold maxima); after each of 5 steps and
+    adaptations the masks are identical and the fields within 1e-11 of the oracle."""
+    _say("adaptive run through an empty level 2..5")
+    H, g, dh, u, p = _pair(2, 5, "tc2")
+    with g:
+        g.set_state(5, dh, u)
+        H.set_state(5, dh, u)
+        g.adapt(1e-2)
+        H.adapt(1e-2)
+        _compare_all(H, g, 1e-12)
+        assert not H.node_act[5].any()
+        for _ in range(5):
+            g.step(400.0)
+            H.step(400.0, p)
+            g.adapt(1e-2)
+            H.adapt(1e-2)
+            _compare_all(H, g, 1e-11)
+        d, code = g.diagnostics()
+    assert code == wt.WT_OK and H.node_act[5].any()
+    assert abs(d.mass / H.mass(p) - 1) < 1e-13
+
+
 def test_eps_zero_equals_uniform_on_gpu():
     """eps = 0 keeps every point: the jmax field equals a uniform GPU run to round-off."""
     _say("eps=0 vs uniform")

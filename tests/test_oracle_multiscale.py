@@ -226,3 +226,28 @@ def test_tc2_adaptive_config0_closed_form():
     err = np.abs(x - dh).max() / np.abs(dh).max()
     assert err < 2e-2, err
     assert abs(H.mass(p) / m0 - 1) < 1e-13
+
+
+def test_adapt_with_an_empty_level():
+    """A smooth zonal flow (TC2) on levels 2..5 at eps = 1e-2 leaves level 5 without an active
+    point; the next adapt takes the threshold maxima over the levels that have active points (an
+    empty level adds nothing, every jmin point is active) and finds the same masks; through steps
+    and adaptations the level fills again and the jmin mass stays conserved."""
+    H = Hierarchy(2, 5)
+    g = H.g[5]
+    dh, u, Hd = inputs.tc2(g.xyz, g.e_mid, g.e_tan)
+    p = trisk.Params(mean_depth=Hd)
+    H.set_state(5, dh, u)
+    H.adapt(1e-2)
+    assert not H.node_act[5].any() and not H.edge_act[5].any()
+    first = {j: (H.node_act[j].copy(), H.edge_act[j].copy()) for j in H.levels}
+    H.adapt(1e-2)
+    for j in H.levels:
+        assert np.array_equal(first[j][0], H.node_act[j]) and np.array_equal(first[j][1], H.edge_act[j])
+    m0 = H.mass(p)
+    for _ in range(5):
+        H.step(400.0, p)
+        H.adapt(1e-2)
+    assert H.node_act[5].any()
+    assert abs(H.mass(p) / m0 - 1) < 1e-14
+    assert abs(H.reconstructed_mass(p) / m0 - 1) < 1e-14
