@@ -1,5 +1,6 @@
 """GPU parity of the multilevel (adaptive wavelet) path: HIP library through the C ABI against
 the FP64 oracle, on the same seeded inputs."""
+import os
 import sys
 
 import numpy as np
@@ -361,3 +362,41 @@ def test_turbulence_adaptive_parity():
     assert code == wt.WT_OK
     assert 0.0 < err < 1e-5
     assert abs(d.mass / m0 - 1) < 1e-13
+
+
+def test_full_size_jet_levels_5_to_9():
+    """The adaptive workload at full size (zonal jet + 120 m bump, levels 5..9, eps = 5e-3, RK4 at
+    0.8 of the stable step), in the configuration the bench times, against the oracle's run
+    stored by tests/golden/make_jet_l5_9_samples.py: after four rounds of adapt and step every
+    level's node and edge masks are identical, the state at seeded samples of every level's
+    active points is within 1e-11 of the level's maximum, and the jmin mass agrees to 1e-13."""
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "jet_l5_9_samples.npz"))
+    jmin, jmax = int(ref["jmin"]), int(ref["jmax"])
+    eps, dt = float(ref["eps"]), float(ref["dt"])
+    _say(f"full size jet levels {jmin}..{jmax} eps={eps}")
+    g = wt.Grid(jmin, jmax, 8)
+    with g:
+        x, m, t = g.coords(jmax)
+        dh, u, depth = inputs.jet(x, m, t)
+        g.set_params(mean_depth=depth, rk=wt.WT_RK4, precision=wt.WT_FP64)
+        g.set_state(jmax, dh, u)
+        assert abs(g.suggest_dt(0.8) / dt - 1) < 1e-12
+        for _ in range(int(ref["rounds"])):
+            g.adapt(eps)
+            g.step(dt)
+        d, code = g.diagnostics()
+        states = {j: g.get_state(j) for j in range(jmin, jmax + 1)}
+    assert code == wt.WT_OK
+    for j, (a, b, na, ea) in states.items():
+        assert np.array_equal(np.packbits(na.astype(bool)), ref[f"na{j}"]), f"node mask differs on level {j}"
+        assert np.array_equal(np.packbits(ea.astype(bool)), ref[f"ea{j}"]), f"edge mask differs on level {j}"
+        ni, ei = ref[f"ni{j}"], ref[f"ei{j}"]
+        if ni.size:
+            err = np.abs(a[ni] - ref[f"dh{j}"]).max() / float(ref[f"dhmax{j}"])
+            assert err < 1e-11, (j, err)
+            assert np.abs(a[na.astype(bool)]).max() == pytest.approx(float(ref[f"dhmax{j}"]), rel=1e-11)
+        if ei.size:
+            err = np.abs(b[ei] - ref[f"u{j}"]).max() / float(ref[f"umax{j}"])
+            assert err < 1e-11, (j, err)
+            assert np.abs(b[ea.astype(bool)]).max() == pytest.approx(float(ref[f"umax{j}"]), rel=1e-11)
+    assert abs(d.mass / float(ref["mass"]) - 1) < 1e-13
