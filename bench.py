@@ -206,7 +206,9 @@ def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, warmup=2, ensemble_members=
             out[name] = {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / steps,
                          "ms_adapt_per_step": wall_adapt * 1e3 / steps,
                          "active_dof_per_step": active / steps, "mass_drift": abs(d1.mass / d0.mass - 1),
-                         "redo": g.redo_count(), "finite": code == wt.WT_OK}
+                         "redo": g.redo_count(), "finite": code == wt.WT_OK,
+                         "active_dof_last_step_by_level": {str(j): d.active_nodes[j] + d.active_edges[j]
+                                                           for j in range(jmin, jmax + 1)}}
     a, b = final["fp32_learned"], final["plain_fp64"]
     out["fp32_learned"]["rel_l2_height_vs_plain_fp64"] = float(np.sqrt(((a - b) ** 2).sum() / ((H + b) ** 2).sum()))
     out["speedup_fp32_learned_over_plain_fp64"] = out["fp32_learned"]["value"] / out["plain_fp64"]["value"]
