@@ -105,6 +105,20 @@ def run_gpu(args):
                          finite=code == wt.WT_OK)
         if mode == "fp64":
             state64 = g.get_state(J)[:2]
+            # the same steps with the state handed over in host memory (pageable numpy arrays)
+            # and read back, transfers inside the clock: the PCIe-inclusive rate (context only)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.set_state(J, dh0, u0)
+            for _ in range(args.steps):
+                g.step(dt)
+            g.get_state(J)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out[mode]["pcie_inclusive"] = {"value": (N + E) * 4 * args.steps / (t1 - t0),
+                                           "ms_total": (t1 - t0) * 1e3,
+                                           "ms_transfers": (t1 - t0 - wall) * 1e3,
+                                           "host_bytes": (N + E) * (8 + 8 + 1)}
         else:
             state32 = g.get_state(J)[:2]
     # error of the FP32-tendency run against the FP64 run (same steps)
@@ -541,6 +555,7 @@ def main():
                           if "fp32" in res else None),
         "mass_drift_fp64": f64["mass_drift"],
         "energy_drift_fp64": f64["energy_drift"],
+        "pcie_inclusive_fp64": f64.get("pcie_inclusive"),
     }
     if not args.no_adaptive:
         line["adaptive"] = run_adaptive(steps=args.adaptive_steps, ensemble_members=args.ensemble_members)
