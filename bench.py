@@ -28,22 +28,23 @@ HBM_PEAK_GBS = 8000.0
 # then WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0 --modes fp64`, averaged
 # over the four stage launches of an RK4 step and scaled by what the same counters read for a
 # 2 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).
-# Valid only for the kernel source it was taken on: a changed source reports null.
+# Valid only for the kernel source and the grid level it was taken on: otherwise null.
 MEASURED_TRAFFIC = {
     "trisk_lattice": {
         "sources": ("paper_1404_0405_amd/csrc/wt_lattice.hip", "paper_1404_0405_amd/csrc/wt_lattice_dev.hpp"),
         "sha256": ("e40cb0f7a89d2560bfeccc6eb813884e92b3e2a75b98192730198251dd98fb2b",
                    "67492eda7ad1558bc8dfcf39ef6757221c2ebd22ca59db129d4cf93d8c38dd94"),
-        "fetch_kib": 673244.5, "write_kib": 572320.7, "fetch_scale": 2.000, "write_scale": 1.000,
+        "level": 10, "fetch_kib": 673244.5, "write_kib": 572320.7, "fetch_scale": 2.000, "write_scale": 1.000,
     },
 }
 
 
-def measured_traffic(kernel):
-    """Scaled HBM bytes per launch of `kernel`, or None if not measured on the current source."""
+def measured_traffic(kernel, level):
+    """Scaled HBM bytes per launch of `kernel` on the uniform grid of `level`, or None if not
+    measured on that grid or on the current source."""
     import hashlib
     rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None:
+    if rec is None or rec["level"] != level:
         return None
     for path, digest in zip(rec["sources"], rec["sha256"]):
         try:
@@ -545,7 +546,7 @@ def main():
                                f"dt={dt:.3f} s (CFL 0.8)",
                    "level": args.level, "cells": N, "edges": E, "rk": "rk4", "stages_per_step": 4},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.level),
                      "algorithmic_bytes": kd["algorithmic_bytes"]},
         "kernels_fp64": f64["kernels"],
         "stage_ms_fp64": f64["ms_per_step"] / 4,

@@ -83,3 +83,25 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_traffic_only_for_the_measured_grid_and_source():
+    """The HBM traffic figure of the bench line comes from counters taken on one grid level and
+    one kernel source: the level-10 lattice kernel reports it while its source is the one measured,
+    any other level or an unknown kernel reports null."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    import hashlib
+    rec = bench.MEASURED_TRAFFIC["trisk_lattice"]
+    current = all(hashlib.sha256(open(os.path.join(root, f), "rb").read()).hexdigest() == h
+                  for f, h in zip(rec["sources"], rec["sha256"]))
+    t = bench.measured_traffic("trisk_lattice", 10)
+    if current:
+        assert t is not None and 1.8e9 < t < 2.2e9
+    else:
+        assert t is None
+    assert bench.measured_traffic("trisk_lattice", 8) is None
+    assert bench.measured_traffic("trisk_tend", 10) is None
