@@ -1,7 +1,7 @@
 /* Oracle helper (test infrastructure only): area of the intersection of two convex spherical
  * polygons on the unit sphere.
  *
- * Sec. 4.2 of the paper computes the areas A_km shared by a coarse hexagon k and a fine
+ * Sec. 4.1 of the paper computes the areas A_km shared by a coarse hexagon k and a fine
  * hexagon m.  Here the intersection is found with the Sutherland-Hodgman algorithm, clipping
  * the subject polygon against the great-circle half-spaces of the clip polygon's edges, and its
  * area is the sum of a fan of spherical triangles (Van Oosterom-Strackee formula).

@@ -8,12 +8,12 @@ Only active points are updated.  Passages followed:
 
 * Sec. 2.2, eqs. (WTpred), (WTupd): lifting -- predict the odd fine values from the even ones,
   then update the coarse values with the details.
-* Sec. 4.2, eq. (Rh) and the two area conditions after it: height restriction with
+* Sec. 4.1, eq. (Rh) and the two area conditions after it: height restriction with
   s~_km = A_km/A_m and s_km = A_km/A_k, where A_km is the area shared by coarse hexagon k and
   fine hexagon m; mass is conserved between levels.
 * Sec. 4.1: vector (velocity) transform, second-order prediction from coarse edges with a
   symmetric stencil and two 6x6 least-squares systems per edge.
-* Sec. 4.2-4.4, eqs. (divRcommute), (R_f), (restr_flux), (ho_flux), (kml): flux restriction
+* Sec. 4.1-4.3, eqs. (divRcommute), (R_f), (restr_flux), (ho_flux), (kml): flux restriction
   R_F = R_F0 + R'_F, which makes R_h(div_{j+1} F) = div_j(R_F F).
 * Sec. 3.1 (time step): q and K everywhere; B, F and qF^perp on the locally finest level and
   restricted to coarser levels; tendencies; partial (height only) transforms; adaptation.
@@ -107,7 +107,7 @@ class Pair:
         self._height_weights()
         self._velocity_weights()
 
-    # --------------------------------------------------------------- height (Sec. 4.2)
+    # --------------------------------------------------------------- height (Sec. 4.1)
     def _height_weights(self):
         """A_cm = area(coarse hexagon c  intersect  fine hexagon m) for the four coarse cells
         c = (a, b, p, q) around the odd node m of coarse edge a-b; the paper splits hexagons
@@ -261,7 +261,7 @@ class Hierarchy:
     def levels(self):
         return range(self.jmin, self.jmax + 1)
 
-    # --------------------------------------------------------------- areas (Sec. 4.2)
+    # --------------------------------------------------------------- areas (Sec. 4.1)
     def _effective_areas(self):
         """Reading of the two area conditions after eq. (Rh) (the second prints A_k^{j+1}
         inside the sum where A_m^{j+1} is meant): starting from the geometric areas of jmax,
@@ -278,7 +278,7 @@ class Hierarchy:
             self.g[j].A_geo = self.g[j].A_i
             self.g[j].A_i = self.A[j]
 
-    # --------------------------------------------------------------- R_F (Sec. 4.3-4.4)
+    # --------------------------------------------------------------- R_F (Sec. 4.2-4.3)
     def _flux_restriction(self, j):
         """Coarse integrated fluxes Phi = l^j F^j on every coarse edge as a linear map of the
         fine integrated fluxes (l F)^{j+1} and fine divergences c^{j+1} = div_{j+1} F^{j+1}.
@@ -388,9 +388,24 @@ class Hierarchy:
         F, B, Q = {}, {}, {}
         for j in self.levels:
             g = self.g[j]
-            _, F[j] = trisk.edge_quantities(g, dh[j], u[j], p)
+            # F: the total mass flux whose divergence is taken and restricted; Q uses the
+            # thickness flux h u itself
+            _, Fa = trisk.edge_quantities(g, dh[j], u[j], p)
+            F[j] = Fa
+            if p.adv:
+                # advection form (Sec. 6.1): only the mass flux enters
+                B[j], Q[j] = np.zeros(g.N), np.zeros(g.E)
+                continue
             B[j] = p.g * dh[j] + trisk.kinetic_energy(g, u[j])
-            Q[j] = trisk.perp_pv_flux(g, F[j], trisk.vertex_pv(g, dh[j], u[j], p))
+            Q[j] = trisk.perp_pv_flux(g, Fa, trisk.vertex_pv(g, dh[j], u[j], p))
+            if p.nu:
+                # viscous form (Sec. 3.1): nu div grad dh as the divergence of the flux
+                # -nu grad dh, nu grad div u as the gradient of -nu div u added to B, and
+                # -nu grad^perp curl u added to the perpendicular term, so that all three are
+                # restricted to coarser levels like the inviscid quantities
+                F[j] = Fa - p.nu * trisk.gradient(g, dh[j])
+                B[j] = B[j] - p.nu * trisk.divergence(g, u[j])
+                Q[j] = Q[j] + p.nu * trisk.curl_adjoint(g, trisk.curl(g, u[j]))
         for j in range(self.jmax - 1, self.jmin - 1, -1):
             P = self.pairs[j]
             ne, nn = self.nonleaf(j)
@@ -402,7 +417,10 @@ class Hierarchy:
         for j in self.levels:
             g = self.g[j]
             ddh[j] = np.where(self.node_act[j], -trisk.divergence(g, F[j]), 0.0)
-            du[j] = np.where(self.edge_act[j], -Q[j] - trisk.gradient(g, B[j]), 0.0)
+            if p.adv:
+                du[j] = np.zeros(g.E)   # advection form: the velocity is prescribed (Sec. 6.1)
+            else:
+                du[j] = np.where(self.edge_act[j], -Q[j] - trisk.gradient(g, B[j]), 0.0)
         return ddh, du
 
     # --------------------------------------------------------------- completeness and R_h
@@ -525,8 +543,11 @@ class Hierarchy:
             out[j] = (P.h_details(dh[j + 1]), dp, di)
         return out
 
-    def adapt(self, eps):
+    def adapt(self, eps, thresholds=None):
         """Threshold and adjacent zone (Sec. 2.3) and the h/u consistency step (Sec. 3.1).
+
+        thresholds: absolute (eps_h, eps_u) -- e.g. from `regime_thresholds` -- instead of the
+        relative reading below.
 
         Readings: eps is relative, eps_h = eps max|dh|, eps_u = eps max|u| over active points;
         significant iff |d| >= eps_var (the paper's >=).  Rules, in order: R1 significant
@@ -543,7 +564,7 @@ class Hierarchy:
         # a level with no active point adds nothing to the maxima (every jmin point is active)
         mh = max(np.abs(self.dh[j][self.node_act[j]]).max(initial=0.0) for j in self.levels)
         mu = max(np.abs(self.u[j][self.edge_act[j]]).max(initial=0.0) for j in self.levels)
-        eh, eu = eps * mh, eps * mu
+        eh, eu = (eps * mh, eps * mu) if thresholds is None else thresholds
         sig_n = {j: np.zeros(self.g[j].N, bool) for j in self.levels}
         sig_e = {j: np.zeros(self.g[j].E, bool) for j in self.levels}
         for j in range(self.jmin, self.jmax):
@@ -616,9 +637,33 @@ class Hierarchy:
         return eh, eu
 
     # --------------------------------------------------------------- diagnostics
+    def finest_level(self):
+        """Highest level holding an active point: the maximum level the thresholds select when
+        jmax only caps the refinement (Sec. 3.1, Jmax set implicitly by eps)."""
+        return max(j for j in self.levels if self.node_act[j].any() or self.edge_act[j].any())
+
     def mass(self, p):
         return float((self.A[self.jmin] * (p.H + self.dh[self.jmin])).sum())
 
     def reconstructed_mass(self, p):
         dh, _, _, _ = self.get_state(self.jmax)
         return float((self.A[self.jmax] * (p.H + dh)).sum())
+
+
+def regime_thresholds(eps, regime, U, g, L=None, f=None, H=None):
+    """Absolute thresholds (eps_h [m], eps_u [m/s]) of the two flow regimes of Sec. 3.1.
+
+    Reading: the printed pair gives a velocity threshold in m/s and a height threshold in
+    geopotential units (m^2/s^2) under exchanged names; with the names swapped back and the
+    geopotential divided by g,
+      quasi-geostrophic, Ro = U/(f L):  eps_u = U Ro eps^1.5,  eps_h = f U L Ro eps^1.5 / g;
+      inertia-gravity, c = sqrt(g H):   eps_u = U eps^1.5,     eps_h = c U eps^1.5 / g.
+    """
+    e32 = eps ** 1.5
+    if regime == "qg":
+        Ro = U / (f * L)
+        return f * U * L * Ro * e32 / g, U * Ro * e32
+    if regime == "ig":
+        c = np.sqrt(g * H)
+        return c * U * e32 / g, U * e32
+    raise ValueError(regime)

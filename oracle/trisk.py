@@ -8,7 +8,11 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/grid.py``).
 * Sec. 3.1 (time discretisation): four-stage third-order SSP Runge-Kutta; classical RK4 is
   provided as well.
 * Sec. 7.2: total energy E = 1/2 int g h (g h + |u|^2) dS - 1/2 c^4 A_S, c^2 = (g/A_S) int h dS.
-* Sec. 3.2: mass  sum_k A_k h_k.
+* Sec. 4.1 (mass conservation of the height restriction): mass  sum_k A_k h_k.
+* Sec. 3.1, dissipative form: nu div grad (dh) added to the height tendency and
+  nu (grad div u - grad^perp curl u) to the velocity tendency.
+* Sec. 6.1: advection of the height by a prescribed, time-independent velocity (the velocity
+  equation is dropped; the thickness flux is h u).
 """
 from __future__ import annotations
 
@@ -18,9 +22,13 @@ from .grid import GRAVITY
 
 
 class Params:
-    def __init__(self, gravity=GRAVITY, mean_depth=2.94e4 / GRAVITY):
+    """g, mean depth H, viscosity nu (0: inviscid) and adv (True: advection of the height alone)."""
+
+    def __init__(self, gravity=GRAVITY, mean_depth=2.94e4 / GRAVITY, nu=0.0, adv=False):
         self.g = gravity
         self.H = mean_depth
+        self.nu = nu
+        self.adv = adv
 
 
 def edge_quantities(g, dh, u, p):
@@ -53,6 +61,26 @@ def curl(g, u):
     return (g.t_signs * g.d_e[g.t_edges] * u[g.t_edges]).sum(1) / g.A_v
 
 
+def curl_adjoint(g, zeta):
+    """grad^perp of a dual-vertex field: the adjoint of `curl` for the inner products
+    sum_v A_v zeta_v eta_v and sum_e l_e d_e u_e w_e.  From sum_v A_v curl(u)_v eta_v
+    = sum_v sum_{e in v} t_{e,v} d_e u_e eta_v, the edge value is (1/l_e) sum_{v at e} t_{e,v} eta_v:
+    every triangle scatters its t_{e,v} eta_v to its three edges."""
+    acc = np.zeros(g.E)
+    np.add.at(acc, g.t_edges.ravel(), (g.t_signs * zeta[:, None]).ravel())
+    return acc / g.l_e
+
+
+def laplacian(g, a):
+    """div grad of a node field."""
+    return divergence(g, gradient(g, a))
+
+
+def vector_laplacian(g, u):
+    """grad div u - grad^perp curl u (the dissipation operator of the velocity, Sec. 3.1)."""
+    return gradient(g, divergence(g, u)) - curl_adjoint(g, curl(g, u))
+
+
 def vertex_pv(g, dh, u, p):
     """q_v = (zeta_v + f_v) / h_v, with h_v the kite-weighted mean of the three cells."""
     h = p.H + dh
@@ -68,11 +96,19 @@ def perp_pv_flux(g, F, qv):
 
 
 def tendencies(g, dh, u, p):
-    """Right-hand side of eqs. (height) and (velo) on one uniform level."""
+    """Right-hand side of eqs. (height) and (velo) on one uniform level (with the dissipative
+    terms when p.nu > 0; the height equation alone, u fixed, when p.adv)."""
     _, F = edge_quantities(g, dh, u, p)
+    ddh = -divergence(g, F)
+    if p.adv:
+        return ddh, np.zeros_like(u)
     B = p.g * dh + kinetic_energy(g, u)
     Q = perp_pv_flux(g, F, vertex_pv(g, dh, u, p))
-    return -divergence(g, F), -Q - gradient(g, B)
+    du = -Q - gradient(g, B)
+    if p.nu:
+        ddh = ddh + p.nu * laplacian(g, dh)
+        du = du + p.nu * vector_laplacian(g, u)
+    return ddh, du
 
 
 # ---------------------------------------------------------------- time schemes
@@ -141,8 +177,12 @@ def suggest_dt(g, dh, u, p, cfl):
     """dt = cfl * min(1/omega_max, min_e d_e/|u_e|), omega = sqrt(f^2 + g h (pi/dx)^2).
 
     The frequency bound printed in Sec. 3.1 is dimensionally inconsistent; the wavenumber
-    pi/dx is squared here (the gravity-wave dispersion relation on the grid).
+    pi/dx is squared here (the gravity-wave dispersion relation on the grid).  The advection
+    form has no gravity waves: dt = cfl * min_e d_e/|u_e|.
     """
+    if p.adv:
+        ua = np.abs(u)
+        return float(cfl * np.min(np.where(ua > 0, g.d_e / np.maximum(ua, 1e-300), np.inf)))
     h = p.H + dh
     he = 0.5 * (h[g.e_nodes[:, 0]] + h[g.e_nodes[:, 1]])
     fe = 0.5 * (g.f_v[g.e_tris[:, 0]] + g.f_v[g.e_tris[:, 1]])

@@ -15,6 +15,13 @@ Workloads (stand-ins for the paper's test cases, Sec. 6):
 * ``jet``: zonal jet u = 80 exp(-((lat-45)/8)^2) m/s with the height in gradient-wind balance
   (composite Simpson quadrature), mean depth 10 km, plus a Gaussian height bump (stand-in for
   the Galewsky jet of Sec. 6.4).
+* ``tc1``: advection of a bell by solid-body rotation (Williamson test 1, Sec. 6.1): velocity
+  u = U (cos(lat) cos(alpha) + sin(lat) cos(lon) sin(alpha)), v = -U sin(lon) sin(alpha),
+  U = 2 pi a / 12 d, i.e. rotation about the axis (-sin alpha, 0, cos alpha) once per 12 days;
+  cosine bell h = (H0/2)(1 + cos(pi r/L)) for r < L (0 outside) or smooth bell
+  h = H0 exp(r^2 / (r^2 - 2 L^2)) for r < sqrt(2) L (0 outside), r = a arccos(cos(lat) cos(lon))
+  the distance from (0, 0), H0 = 1000 m, L = a/3, zero mean depth; at time t the same bell
+  turned about the axis by the angle U t / a (the exact solution).
 * ``turbulence``: seeded random non-divergent flow u = k x grad(psi) with an isotropic energy
   spectrum peaked at degree 40, rms speed 20 m/s, mean depth 1 km, height from linear balance
   g h' = f psi (stand-in for the rotating turbulence of Sec. 7).
@@ -47,6 +54,43 @@ def tc2(node_xyz, edge_mid, edge_tan, radius=EARTH_RADIUS, omega=OMEGA, gravity=
     vel = u0 * np.stack([-m[:, 1], m[:, 0], np.zeros_like(m[:, 0])], 1)   # u0 * z_hat x x
     u = (vel * edge_tan).sum(1)
     return dh, u, H
+
+
+def tc1_axis(alpha, radius=EARTH_RADIUS):
+    """Angular velocity vector [1/s] of the test-1 rotation: |w| = U / a, U = 2 pi a / 12 d."""
+    w = 2.0 * math.pi / (12.0 * DAY)
+    return w * np.array([-math.sin(alpha), 0.0, math.cos(alpha)])
+
+
+def tc1_bell(xyz, bell="cosine", h0=1000.0, t=0.0, alpha=0.0, radius=EARTH_RADIUS):
+    """Bell height at unit positions xyz after time t of rotation (t = 0: the initial bell)."""
+    x = xyz / np.linalg.norm(xyz, axis=1, keepdims=True)
+    if t != 0.0:
+        # position at time 0 of the fluid now at x: turn x back about the axis (Rodrigues)
+        w = tc1_axis(alpha, radius)
+        k = w / np.linalg.norm(w)
+        ang = -np.linalg.norm(w) * t
+        c, s = math.cos(ang), math.sin(ang)
+        x = x * c + np.cross(k, x) * s + np.outer(x @ k, k) * (1.0 - c)
+    # distance from the bell centre (lat 0, lon 0): cos(lat) cos(lon) = x
+    r = radius * np.arccos(np.clip(x[:, 0], -1.0, 1.0))
+    L = radius / 3.0
+    if bell == "cosine":
+        return np.where(r < L, 0.5 * h0 * (1.0 + np.cos(np.pi * r / L)), 0.0)
+    if bell == "smooth":
+        q = r * r - 2.0 * L * L
+        inside = q < 0
+        return np.where(inside, h0 * np.exp(np.where(inside, r * r / np.where(inside, q, -1.0), 0.0)), 0.0)
+    raise ValueError(bell)
+
+
+def tc1(node_xyz, edge_mid, edge_tan, bell="cosine", alpha=0.0, t=0.0, radius=EARTH_RADIUS):
+    """Returns (dh, u, H): bell height at nodes (time t), prescribed normal velocity at edges,
+    mean depth 0."""
+    m = edge_mid / np.linalg.norm(edge_mid, axis=1, keepdims=True)
+    vel = np.cross(tc1_axis(alpha, radius), m) * radius
+    u = (vel * edge_tan).sum(1)
+    return tc1_bell(node_xyz, bell, t=t, alpha=alpha, radius=radius), u, 0.0
 
 
 def real_sph_harm_sum(xyz, coeffs, lmax, device=None):

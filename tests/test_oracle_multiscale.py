@@ -41,7 +41,7 @@ def test_clipping_closed_forms():
 
 @pytest.mark.parametrize("j", [2, 3, 4])
 def test_overlap_areas_partition(j):
-    """Sec. 4.2: the partial areas A_km cover the fine and coarse hexagons: the four coarse
+    """Sec. 4.1: the partial areas A_km cover the fine and coarse hexagons: the four coarse
     cells of every odd node tile its fine hexagon, and the pieces inside every coarse cell tile
     it, so the effective coarse areas equal the geometric ones up to round-off."""
     H = hier(2, 5)

@@ -178,7 +178,7 @@ def test_mass_conserved_over_steps(oracle_grid):
 def test_tc2_balance_converges(oracle_grid):
     """Williamson test 2 (Sec. 6.2): the steady geostrophic flow keeps its closed form; the
     1-day height error falls at least at first order per bisection level on the plain
-    bisection grid (first order on far-from-equilateral grids, Sec. 3.3)."""
+    bisection grid (first order on far-from-equilateral grids, Sec. 3.2)."""
     p = trisk.Params()
     errs = []
     for J in (2, 3, 4, 5):
