@@ -50,25 +50,55 @@ enum {
  * four-stage RK4.  Both evaluate the tendencies four times per step. */
 enum { WT_RK4 = 0, WT_SSPRK43 = 1 };
 
-/* Arithmetic of the tendencies.  WT_FP64: everything in double.  WT_FP32_TENDENCY: the
- * tendencies and the velocity/vorticity parts of the transforms are computed in single
- * precision while the prognostic state, the Runge-Kutta accumulation, the mass flux F and its
- * restriction, the divergence sums, the height transform and the mass/energy diagnostics stay
- * in double (the paper keeps the quantities that carry the mimetic properties in double and
- * truncation-limited ones in single, Sec. 5.1), so mass is conserved to round-off in both. */
+/* Arithmetic of the tendencies and transforms.  WT_FP64: everything in double.
+ * WT_FP32_TENDENCY: single precision for the TRiSK quantities q, K, B, qF^perp and the velocity
+ * products of the tendencies, and for the stencil sums of the velocity transform's predictions
+ * (Sec. 4.1: 18 coarse edges per half-edge pair, 9 per interior edge) in the forward transform
+ * (details), the inverse transform and the prolongation of inactive points.  Double precision is
+ * kept for the prognostic state and the Runge-Kutta accumulation, the mass flux F, its
+ * divergence and its restriction R_F, the combination of each prediction with the stored values
+ * (detail = value - prediction, value = detail + prediction), the whole height transform (its
+ * prediction, eq. (WTpred), is part of the area-weighted restriction R_h, eq. (Rh), whose exact
+ * inversion by the adapt's reconstruction keeps the partial transform mass-conservative), and the
+ * mass/energy diagnostics (the paper keeps the quantities that carry the mimetic properties in
+ * double and truncation-limited ones in single, Sec. 5.1), so mass is conserved to round-off in
+ * both modes. */
 enum { WT_FP64 = 0, WT_FP32_TENDENCY = 1 };
+
+/* Equations.  WT_SWE: the rotating shallow-water equations (height) and (velo) of Sec. 3.1.
+ * WT_ADVECTION: the height equation alone, its thickness flux h u carried by the velocity field
+ * of the state, which stays fixed (du/dt = 0; the advection test of Sec. 6.1). */
+enum { WT_SWE = 0, WT_ADVECTION = 1 };
+
+/* Thresholds of the adapt (Sec. 3.1).  WT_THR_RELATIVE: eps_h = eps max|dh|, eps_u = eps max|u|
+ * over the active points.  WT_THR_QG / WT_THR_IG: the regime thresholds of Sec. 3.1 from the
+ * typical velocity U, length L and Coriolis parameter f of the flow (scale_u, scale_l, scale_f)
+ * and the gravity-wave speed c = sqrt(g H).  The printed formulas give the velocity threshold in
+ * m/s and the height threshold in geopotential units (m^2/s^2) with their two names exchanged;
+ * read with the names swapped back and the height threshold divided by g:
+ *   quasi-geostrophic (Ro = U / (f L)):  eps_u = U Ro eps^(3/2),  eps_h = f U L Ro eps^(3/2) / g,
+ *   inertia-gravity:                     eps_u = U eps^(3/2),     eps_h = c U eps^(3/2) / g. */
+enum { WT_THR_RELATIVE = 0, WT_THR_QG = 1, WT_THR_IG = 2 };
 
 typedef struct {
   double radius;      /* sphere radius a [m], default 6.371e6 */
   double omega;       /* rotation rate [1/s], default 7.292e-5 (Sec. 6) */
   double gravity;     /* g [m/s^2], default 9.80616 (Sec. 6) */
-  double mean_depth;  /* H [m], h = H + dh; default 2.94e4 / g */
+  double mean_depth;  /* H [m], h = H + dh; default 2.94e4 / g; > 0 (>= 0 for WT_ADVECTION) */
   int rk;             /* WT_RK4 (default) or WT_SSPRK43 */
   int precision;      /* WT_FP64 (default) or WT_FP32_TENDENCY */
+  double viscosity;   /* nu [m^2/s] >= 0, default 0: the dissipative form of Sec. 3.1 adds
+                         nu div grad dh to the height and nu (grad div u - grad^perp curl u) to
+                         the velocity tendency */
+  int equations;      /* WT_SWE (default) or WT_ADVECTION */
+  int threshold;      /* WT_THR_RELATIVE (default), WT_THR_QG or WT_THR_IG */
+  double scale_u;     /* U [m/s] of the regime thresholds (> 0 when they are used) */
+  double scale_l;     /* L [m] of the quasi-geostrophic thresholds */
+  double scale_f;     /* f [1/s] of the quasi-geostrophic thresholds */
 } wt_params;
 
 typedef struct {
-  double mass;        /* sum_k A_k (H + dh_k) on level jmin [m^3] (Sec. 3.2); below jmax A_k
+  double mass;        /* sum_k A_k (H + dh_k) on level jmin [m^3] (Sec. 4.1); below jmax A_k
                          are the effective areas of the height transform */
   double mass_reconstructed; /* the same sum of the jmax reconstruction (equal up to rounding) */
   double energy;      /* E of Sec. 7.2 of the jmax reconstruction [m^5/s^2] */
@@ -76,6 +106,10 @@ typedef struct {
   double max_abs_u;   /* max |u| over active edges of all levels */
   int64_t active_nodes[16]; /* per level j (index j), active node count */
   int64_t active_edges[16]; /* per level j (index j), active edge count */
+  int32_t finest_level; /* highest level holding an active point: the maximum level the
+                           thresholds select (Sec. 3.1: Jmax set implicitly by eps, the grid's
+                           jmax acting as a cap) */
+  int32_t pad_;
 } wt_diag;
 
 /* Create a grid with levels jmin..jmax (0 <= jmin <= jmax <= 12) and adaptivity patch size
@@ -83,7 +117,7 @@ typedef struct {
  * results do not depend on it).  Builds the geometry of every level on the host (Sec. 4.1)
  * and uploads it; selects HIP device 0 unless one is current.  Returns NULL on error.
  * The geometry-only host tables of each level and level pair (those not depending on the
- * effective areas, Sec. 4.2) are kept in a process-wide cache and shared by later grids. */
+ * effective areas, Sec. 4.1) are kept in a process-wide cache and shared by later grids. */
 wt_grid* wt_grid_create(int jmin, int jmax, int patch);
 /* Frees the host table cache of wt_grid_create (existing grids are not affected). */
 void wt_table_cache_clear(void);
@@ -185,7 +219,7 @@ int wt_set_mask(wt_grid* g, int level, const uint8_t* node_active_host, const ui
  * arrays ddh_host[N], du_host[E] (canonical order).  Test and diagnostic hook; synchronises. */
 int wt_tendency(wt_grid* g, int level, double* ddh_host, double* du_host);
 
-/* Diagnostics of the current state (mass Sec. 3.2, energy Sec. 7.2, maxima); synchronises.
+/* Diagnostics of the current state (mass Sec. 4.1, energy Sec. 7.2, maxima); synchronises.
  * Returns WT_ENUMERIC (and fills the struct) if the state holds a non-finite value. */
 int wt_diagnostics(wt_grid* g, wt_diag* d);
 
@@ -197,6 +231,23 @@ double wt_suggest_dt(wt_grid* g, double cfl);
 /* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) for all
  * later device work of the grid; NULL selects the library's own stream. */
 int wt_set_stream(wt_grid* g, void* hip_stream);
+
+/* Device allocator of the grid's buffers, e.g. PyTorch's caching allocator.  With g non-NULL,
+ * later allocations of g (buffers created lazily: work lists, scratch, checkpoint staging ...)
+ * use it; with g NULL it becomes the allocator of every grid created afterwards, so that all of
+ * their device buffers come from it.  alloc(bytes, ctx) returns device memory of the current
+ * HIP device (NULL on failure: the calling function then fails with WT_EDEVICE); free_(ptr,
+ * ctx) returns it.  The library waits for all queued device work before each free_, so the
+ * allocator may hand the memory out again at once.  Buffers keep the allocator that produced
+ * them.  Both functions NULL: hipMalloc / hipFree (the default).  WT_EINVAL if only one is
+ * given.  The pair (and ctx) must stay valid while a buffer they produced is alive. */
+int wt_set_allocator(wt_grid* g, void* (*alloc)(size_t bytes, void* ctx), void (*free_)(void* ptr, void* ctx),
+                     void* ctx);
+
+/* Live device buffers owned by grid g: count and bytes from an allocator hook (n_hook,
+ * bytes_hook) and from hipMalloc (n_direct, bytes_direct).  Any pointer may be NULL. */
+int wt_alloc_stats(const wt_grid* g, int64_t* n_hook, int64_t* bytes_hook, int64_t* n_direct,
+                   int64_t* bytes_direct);
 
 /* Kernel timing for measurement: when enabled, every launch of the uniform-level TRiSK stage
  * kernels is bracketed by HIP events on the grid's stream.  wt_kernel_time returns the summed
@@ -227,7 +278,7 @@ int wt_host_level_tables(int level, double radius, double omega, double* A_i_hos
  * jc..jmax (no device needed; jc < jmax <= 8).  Coarse sizes Nc, Ec, Tc are those of level jc.
  * cells_host[4Ec]: for every coarse edge a->b its cells (a, b, p, q), p opposite in the left
  * and q in the right triangle; st_host[4Ec] prediction weights s~_cm = A_cm / A_m of the
- * height transform (eq. (WTpred), Sec. 4.2); s_upd_host[4Ec] update weights s_km = A_km / A_k
+ * height transform (eq. (WTpred), Sec. 4.1); s_upd_host[4Ec] update weights s_km = A_km / A_k
  * (eq. (WTupd)); A_c_host[Nc] effective coarse cell areas; v_sten_host[9Tc] the coarse edges of
  * each coarse triangle's velocity stencil; w_int_host[27Tc] prediction weights of its three
  * interior fine edges (Sec. 4.1); w_pl_host[9Ec], w_pr_host[9Ec] weights of (p1 - p2) on the

@@ -543,28 +543,16 @@ class Hierarchy:
             out[j] = (P.h_details(dh[j + 1]), dp, di)
         return out
 
-    def adapt(self, eps, thresholds=None):
-        """Threshold and adjacent zone (Sec. 2.3) and the h/u consistency step (Sec. 3.1).
-
-        thresholds: absolute (eps_h, eps_u) -- e.g. from `regime_thresholds` -- instead of the
-        relative reading below.
-
-        Readings: eps is relative, eps_h = eps max|dh|, eps_u = eps max|u| over active points;
-        significant iff |d| >= eps_var (the paper's >=).  Rules, in order: R1 significant
-        points; R2 their same-level neighbours (a node: its neighbour nodes and incident edges;
-        an edge: its end nodes and the other edges of its two triangles); R3 their children
-        on the next level (a node: its fine copy, the odd nodes and half-edges around it; an
-        edge: its midpoint and the six fine edges at it); all of jmin; then top-down, per
-        level, R4 h/u consistency (edges at active nodes, then end nodes of active edges) and
-        R5 the prediction stencils of every active point on the level below.  Finally the
-        inverse transform rewrites every active fine point from its coarse level and the
-        details that are kept (those of points active before and after); coarse values are
-        never changed, so the mass on jmin is unchanged."""
-        det = self.details()
-        # a level with no active point adds nothing to the maxima (every jmin point is active)
+    def thresholds(self, eps):
+        """Relative thresholds eps max|dh|, eps max|u| over the active points (an empty level adds
+        nothing to the maxima; every jmin point is active)."""
         mh = max(np.abs(self.dh[j][self.node_act[j]]).max(initial=0.0) for j in self.levels)
         mu = max(np.abs(self.u[j][self.edge_act[j]]).max(initial=0.0) for j in self.levels)
-        eh, eu = (eps * mh, eps * mu) if thresholds is None else thresholds
+        return eps * mh, eps * mu
+
+    def significant(self, det, eh, eu):
+        """R1: active fine points whose detail reaches the threshold (|d| >= eps_var): odd nodes,
+        both half-edges of a coarse edge (one detail per pair), interior edges."""
         sig_n = {j: np.zeros(self.g[j].N, bool) for j in self.levels}
         sig_e = {j: np.zeros(self.g[j].E, bool) for j in self.levels}
         for j in range(self.jmin, self.jmax):
@@ -579,6 +567,32 @@ class Hierarchy:
             sig_e[f][P.h2] |= sp_
             si = ea[P.int_e] & (np.abs(di) >= eu)
             sig_e[f][P.int_e[si]] = True
+        return sig_n, sig_e
+
+    def adapt(self, eps, thresholds=None, allow=None):
+        """Threshold and adjacent zone (Sec. 2.3) and the h/u consistency step (Sec. 3.1).
+
+        thresholds: absolute (eps_h, eps_u) -- e.g. from `regime_thresholds` -- instead of the
+        relative reading below.  allow: optional {level j: function(elements) -> bool array}
+        that restricts the children rule R3 of level j's significant points to the elements it
+        passes (the learned zone, not from the paper); the significant points, details and
+        thresholds of the call are kept in ``self.last``.
+
+        Readings: eps is relative, eps_h = eps max|dh|, eps_u = eps max|u| over active points;
+        significant iff |d| >= eps_var (the paper's >=).  Rules, in order: R1 significant
+        points; R2 their same-level neighbours (a node: its neighbour nodes and incident edges;
+        an edge: its end nodes and the other edges of its two triangles); R3 their children
+        on the next level (a node: its fine copy, the odd nodes and half-edges around it; an
+        edge: its midpoint and the six fine edges at it); all of jmin; then top-down, per
+        level, R4 h/u consistency (edges at active nodes, then end nodes of active edges) and
+        R5 the prediction stencils of every active point on the level below.  Finally the
+        inverse transform rewrites every active fine point from its coarse level and the
+        details that are kept (those of points active before and after); coarse values are
+        never changed, so the mass on jmin is unchanged."""
+        det = self.details()
+        eh, eu = self.thresholds(eps) if thresholds is None else thresholds
+        sig_n, sig_e = self.significant(det, eh, eu)
+        self.last = dict(det=det, eh=eh, eu=eu, sig_n=sig_n, sig_e=sig_e)
         new_n = {j: sig_n[j].copy() for j in self.levels}
         new_e = {j: sig_e[j].copy() for j in self.levels}
         for j in self.levels:
@@ -597,6 +611,9 @@ class Hierarchy:
                 P = self.pairs[j]
                 f = j + 1
                 gf = self.g[f]
+                if allow is not None and j in allow:
+                    sn = sn & allow[j](np.arange(g.N))
+                    se = se & allow[j](np.arange(g.E) // 3)
                 kids = P.even[sn]
                 new_n[f][kids] = True
                 nbk = gf.c_nbrs[kids]

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwt.so")
 
-SOURCES = ["wt_grid.cpp", "wt_pair.cpp", "wt_lattice.cpp", "wt_api.cpp", "wt_mlp_api.cpp", "wt_kernels.hip",
+SOURCES = ["wt_grid.cpp", "wt_pair.cpp", "wt_lattice.cpp", "wt_api.cpp", "wt_mlp_api.cpp", "wt_alloc.cpp", "wt_kernels.hip",
            "wt_ml.hip", "wt_lattice.hip", "wt_mlp.hip", "wt_learn.hip", "wt_compact.hip", "wt_batch.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{ROOT}/include"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

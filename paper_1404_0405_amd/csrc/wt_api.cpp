@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -17,6 +19,7 @@
 #include "../../include/wt.h"
 #include "wt_grid.hpp"
 #include "wt_internal.hpp"
+#include "wt_alloc.hpp"
 #include "wt_batch.hpp"
 #include "wt_compact.hpp"
 #include "wt_lattice_dev.hpp"
@@ -115,6 +118,7 @@ struct wt_grid {
   std::vector<std::unique_ptr<LevelState>> lev;    // index j - jmin
   std::vector<std::unique_ptr<PairState>> pairs;   // pair (j, j+1) at index j - jmin
   hipStream_t own = nullptr, stream = nullptr;
+  AllocHook hook;             // device allocator of the grid's buffers (none: hipMalloc)
   bool have_state = false;
   Timer timer;
   LevelState& L(int j) { return *lev[j - jmin]; }
@@ -122,10 +126,15 @@ struct wt_grid {
   bool multi() const { return jmax > jmin; }
 };
 
+// The grid's device buffers come from its allocator while one of its calls runs.
+struct GridScope : AllocScope {
+  explicit GridScope(wt_grid* g) : AllocScope(g ? &g->hook : nullptr, g, g ? g->stream : nullptr) {}
+};
+
 static void alloc_work(LevelState& ls) {
   const int64_t N = ls.tab.N, E = ls.tab.E, T = ls.tab.T;
   DevWork& w = ls.work;
-  auto A = [](double** p, int64_t n) { HIPCHK(hipMalloc(p, n * sizeof(double))); HIPCHK(hipMemset(*p, 0, n * sizeof(double))); };
+  auto A = [](double** p, int64_t n) { HIPCHK(wt::dmalloc(p, n * sizeof(double))); HIPCHK(hipMemset(*p, 0, n * sizeof(double))); };
   A(&w.dh, N); A(&w.u, E);
   A(&w.dh_acc, N); A(&w.u_acc, E);
   A(&w.dh_s[0], N); A(&w.u_s[0], E);
@@ -139,20 +148,20 @@ static void alloc_work(LevelState& ls) {
   A(&p, E); w.Q = p;
   A(&w.c, N);
   A(&w.red, MAX_JOBS * MAX_BLOCKS + MAX_JOBS + 8);   // batched maxima: partials, results, thresholds
-  auto M = [](uint8_t** q, int64_t n) { HIPCHK(hipMalloc(q, n)); HIPCHK(hipMemset(*q, 0, n)); };
+  auto M = [](uint8_t** q, int64_t n) { HIPCHK(wt::dmalloc(q, n)); HIPCHK(hipMemset(*q, 0, n)); };
   M(&ls.na, N); M(&ls.ea, E); M(&ls.nn, N); M(&ls.ne, E); M(&ls.sn, N); M(&ls.se, E);
 }
 
 static void free_work(LevelState& ls) {
   DevWork& w = ls.work;
   void* ps[] = {w.dh, w.u, w.dh_acc, w.u_acc, w.dh_s[0], w.u_s[0], w.dh_s[1], w.u_s[1],
-                w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red,
+                w.ddh, w.du, w.qv, w.B, w.F, w.qe, w.Q, w.c, w.red, w.G,
                 ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
                 ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
                 ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.rn_, ls.re_, ls.pred_t,
                 ls.pred_e, ls.pred_a, ls.pf, ls.plist};
   for (void* p : ps)
-    if (p) (void)hipFree(p);
+    if (p) (void)wt::dfree(p);
   w = DevWork{};
   free_list(ls.l_tri);
   free_list(ls.l_elem);
@@ -161,7 +170,10 @@ static void free_work(LevelState& ls) {
   free_list(ls.l_tend);
 }
 
-static PhysParams phys(const wt_grid* g) { return PhysParams{g->prm.gravity, g->prm.mean_depth}; }
+static PhysParams phys(const wt_grid* g) {
+  return PhysParams{g->prm.gravity, g->prm.mean_depth, g->prm.viscosity, g->prm.equations == WT_ADVECTION ? 1 : 0};
+}
+static bool fp32_of(const wt_grid* g) { return g->prm.precision == WT_FP32_TENDENCY; }
 
 // ---------------------------------------------------------------- Runge-Kutta stages
 // Stage s of a step: input x, and the epilogue o1/o2 = a*y + b*acc + c*x + d*k (see
@@ -230,7 +242,7 @@ static void prolong_all(wt_grid* g, const std::vector<double*>& dh, const std::v
     LevelState& F = g->L(j + 1);
     PairState& P = g->P(j);
     ml_prolong(P.dev, g->L(j).tab, F.na, F.ea, dh[j - g->jmin], u[j - g->jmin], dh[j + 1 - g->jmin],
-               u[j + 1 - g->jmin], g->stream, L ? span(P.l_cn) : Span{}, L ? span(P.l_ce) : Span{},
+               u[j + 1 - g->jmin], fp32_of(g), g->stream, L ? span(P.l_cn) : Span{}, L ? span(P.l_ce) : Span{},
                L ? span(P.l_ct) : Span{});
   }
 }
@@ -242,7 +254,7 @@ static void details_all(wt_grid* g, const std::vector<double*>& dh, const std::v
   for (int j = g->jmin; j < g->jmax; ++j) {
     PairState& P = g->P(j);
     ml_details_jobs(jobs, P.dev, g->L(j).tab, dh[j + 1 - g->jmin], u[j + 1 - g->jmin], u[j - g->jmin], P.d_h,
-                    P.d_p, P.d_i, L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
+                    P.d_p, P.d_i, fp32_of(g), L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
   ml_mask_ops(jobs.data(), int(jobs.size()), g->stream);
   g->details_partial = L;
@@ -277,7 +289,7 @@ static void inverse_all(wt_grid* g, const std::vector<double*>& dh, const std::v
     const uint8_t *na_old, *na_new, *ea_old, *ea_new;
     masks(j, na_old, na_new, ea_old, ea_new);
     ml_inverse_pair(P.dev, g->L(j).tab, ea_old, ea_new, P.d_p, P.d_i, P.d_k, dh[j - g->jmin], u[j - g->jmin],
-                    dh[j + 1 - g->jmin], u[j + 1 - g->jmin], g->stream, L ? span(P.l_cn) : Span{},
+                    dh[j + 1 - g->jmin], u[j + 1 - g->jmin], fp32_of(g), g->stream, L ? span(P.l_cn) : Span{},
                     L ? span(P.l_ce) : Span{}, L ? span(P.l_ct) : Span{});
   }
 }
@@ -343,6 +355,10 @@ static void touch_epoch(wt_grid* g) {
   sig.push_back(bits[1]);
   sig.push_back(g->prm.rk);
   sig.push_back(g->prm.precision);
+  int64_t nub = 0;
+  std::memcpy(&nub, &g->prm.viscosity, 8);
+  sig.push_back(nub);
+  sig.push_back(g->prm.equations);
   auto add = [&](const WorkList& L) {
     sig.push_back(reinterpret_cast<int64_t>(L.idx));
     sig.push_back(L.bound);
@@ -384,15 +400,15 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E, T = l.tab.T;
     if (!l.s3n) {
-      HIPCHK(hipMalloc(&l.s3n, N));
-      HIPCHK(hipMalloc(&l.s3e, E));
-      HIPCHK(hipMalloc(&l.s5n, N));
-      HIPCHK(hipMalloc(&l.s5e, E));
-      HIPCHK(hipMalloc(&l.rn_, N));
-      HIPCHK(hipMalloc(&l.re_, E));
-      HIPCHK(hipMalloc(&l.pred_t, T));
-      HIPCHK(hipMalloc(&l.pred_e, N));
-      HIPCHK(hipMalloc(&l.pred_a, N));
+      HIPCHK(wt::dmalloc(&l.s3n, N));
+      HIPCHK(wt::dmalloc(&l.s3e, E));
+      HIPCHK(wt::dmalloc(&l.s5n, N));
+      HIPCHK(wt::dmalloc(&l.s5e, E));
+      HIPCHK(wt::dmalloc(&l.rn_, N));
+      HIPCHK(wt::dmalloc(&l.re_, E));
+      HIPCHK(wt::dmalloc(&l.pred_t, T));
+      HIPCHK(wt::dmalloc(&l.pred_e, N));
+      HIPCHK(wt::dmalloc(&l.pred_a, N));
     }
     // rings of same-level neighbours: 1, 2 (scratch), 3 (kept), 4, 5 (kept); patches far from
     // every active point skip the gathers (their points are cleared here)
@@ -400,8 +416,8 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
     if (nl >= 8) {
       const int64_t np = 10 * int64_t(nl / 8) * (nl / 8);
       if (!l.pf) {
-        HIPCHK(hipMalloc(&l.pf, np));
-        HIPCHK(hipMalloc(&l.plist, (np + 1) * sizeof(int32_t)));
+        HIPCHK(wt::dmalloc(&l.pf, np));
+        HIPCHK(wt::dmalloc(&l.plist, (np + 1) * sizeof(int32_t)));
       }
       pj.push_back(PatchJob{l.geo.J, l.na, l.ea, l.pf, l.plist, l.plist + np});
       const ByteJob c[] = {{l.rn_, nullptr, N, 0}, {l.re_, nullptr, E, 0}, {l.s5n, nullptr, N, 0},
@@ -442,7 +458,7 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
     PairState& P = g->P(j);
     LevelState& F = g->L(j + 1);
     const int64_t Nc = P.dev.Nc, Ec = P.dev.Ec, Tc = P.dev.Tc;
-    if (!P.pred) HIPCHK(hipMalloc(&P.pred, Nc + Ec + Tc));
+    if (!P.pred) HIPCHK(wt::dmalloc(&P.pred, Nc + Ec + Tc));
     uint8_t *pn = P.pred, *pe = P.pred + Nc, *pt = P.pred + Nc + Ec;
     pr.push_back(pred_pair_job(P.dev, j, F.s5n, F.s5e, pn, pe, pt));
     cb.add(pn, Nc, P.l_cn);
@@ -475,7 +491,7 @@ static void ml_step(wt_grid* g, double dt) {
       LevelState& F = g->L(j + 1);
       PairState& P = g->P(j);
       ml_prolong(P.dev, g->L(j).tab, F.na, F.ea, xdh[j - g->jmin], xu[j - g->jmin], xdh[j + 1 - g->jmin],
-                 xu[j + 1 - g->jmin], g->stream, LS(P.l_cn), LS(P.l_ce), LS(P.l_ct));
+                 xu[j + 1 - g->jmin], fp32, g->stream, LS(P.l_cn), LS(P.l_ce), LS(P.l_ct));
     }
     for (int q = 0; q < nl; ++q) {
       LevelState& l = *g->lev[q];
@@ -485,12 +501,12 @@ static void ml_step(wt_grid* g, double dt) {
     for (int j = g->jmax - 1; j >= g->jmin; --j) {
       LevelState &C = g->L(j), &F = g->L(j + 1);
       PairState& P = g->P(j);
-      ml_restrict(P.dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, fp32, g->stream, LS(F.l_node), LS(P.l_ce),
+      ml_restrict(P.dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, p, fp32, g->stream, LS(F.l_node), LS(P.l_ce),
                   LS(P.l_cn));
     }
     for (int q = 0; q < nl; ++q) {
       LevelState& l = *g->lev[q];
-      ml_tend(l.tab, l.work, l.na, l.ea, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, LS(l.l_tend));
+      ml_tend(l.tab, l.work, l.na, l.ea, p, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, LS(l.l_tend));
     }
   }
   // partial height transform at complete nodes, bottom-up
@@ -523,9 +539,24 @@ static void masked_max_all(wt_grid* g, double* mh, double* mu) {
   *mu = bu;
 }
 
+// Regime thresholds of Sec. 3.1 (the reading stated with WT_THR_QG / WT_THR_IG in wt.h): the
+// velocity threshold in m/s and the height threshold in metres.
+static void regime_thresholds(const wt_params& p, double eps, double* eh, double* eu) {
+  const double e32 = eps * std::sqrt(eps);
+  if (p.threshold == WT_THR_QG) {
+    const double Ro = p.scale_u / (p.scale_f * p.scale_l);
+    *eu = p.scale_u * Ro * e32;
+    *eh = p.scale_f * p.scale_u * p.scale_l * Ro * e32 / p.gravity;
+  } else {
+    const double c = std::sqrt(p.gravity * p.mean_depth);
+    *eu = p.scale_u * e32;
+    *eh = c * p.scale_u * e32 / p.gravity;
+  }
+}
+
 // The same maxima turned into the thresholds eps * max on the device (no read-back); the host
 // copy (host_val[kThr], [kThr + 1]) is valid once the stream has been synchronised.  Returns the
-// device thresholds.
+// device thresholds.  With the regime thresholds the device values are the host's formulas.
 static const double* thresholds_async(wt_grid* g, double eps) {
   if (!g->host_val) HIPCHK(hipHostMalloc(&g->host_val, wt_grid::kSlots * sizeof(double), hipHostMallocDefault));
   MaxJobs jobs{};
@@ -537,6 +568,11 @@ static const double* thresholds_async(wt_grid* g, double eps) {
   double* thr = out + MAX_JOBS;
   ml_masked_max_batch(jobs, k, red, out, g->stream);
   ml_thresholds(out, k / 2, eps, thr, g->stream);
+  if (g->prm.threshold != WT_THR_RELATIVE) {
+    double* up = g->host_val + wt_grid::kThr - 2;   // pinned staging of the upload
+    regime_thresholds(g->prm, eps, &up[0], &up[1]);
+    HIPCHK(hipMemcpyAsync(thr, up, 2 * sizeof(double), hipMemcpyHostToDevice, g->stream));
+  }
   HIPCHK(hipMemcpyAsync(g->host_val + wt_grid::kThr, thr, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
   return thr;
 }
@@ -550,18 +586,18 @@ static void ensure_learn_buffers(wt_grid* g) {
   for (int j = g->jmin + 1; j <= g->jmax; ++j) {
     LevelState& l = g->L(j);
     if (!l.rn) {
-      HIPCHK(hipMalloc(&l.rn, l.tab.N * sizeof(float)));
-      HIPCHK(hipMalloc(&l.re, l.tab.E * sizeof(float)));
+      HIPCHK(wt::dmalloc(&l.rn, l.tab.N * sizeof(float)));
+      HIPCHK(wt::dmalloc(&l.re, l.tab.E * sizeof(float)));
     }
     if (learnable(g, j) && !l.stats) {
       const int64_t n = int64_t(1) << j, m = n / 8;
       l.npatch = 10 * m * m;
-      HIPCHK(hipMalloc(&l.stats, l.npatch * LEARN_STATS * sizeof(float)));
-      HIPCHK(hipMalloc(&l.X, l.npatch * 64 * sizeof(float)));
-      HIPCHK(hipMalloc(&l.Pr, l.npatch * 4 * sizeof(float)));
-      HIPCHK(hipMalloc(&l.allow, l.npatch * 4));
-      HIPCHK(hipMalloc(&l.dropped, l.npatch * 4));
-      HIPCHK(hipMalloc(&l.viol, l.npatch * 4));
+      HIPCHK(wt::dmalloc(&l.stats, l.npatch * LEARN_STATS * sizeof(float)));
+      HIPCHK(wt::dmalloc(&l.X, l.npatch * 64 * sizeof(float)));
+      HIPCHK(wt::dmalloc(&l.Pr, l.npatch * 4 * sizeof(float)));
+      HIPCHK(wt::dmalloc(&l.allow, l.npatch * 4));
+      HIPCHK(wt::dmalloc(&l.dropped, l.npatch * 4));
+      HIPCHK(wt::dmalloc(&l.viol, l.npatch * 4));
     }
   }
 }
@@ -600,10 +636,10 @@ static void snapshot(wt_grid* g, bool restore) {
     LevelState& l = *lp;
     const int64_t N = l.tab.N, E = l.tab.E;
     if (!l.snap_dh) {
-      HIPCHK(hipMalloc(&l.snap_dh, N * sizeof(double)));
-      HIPCHK(hipMalloc(&l.snap_u, E * sizeof(double)));
-      HIPCHK(hipMalloc(&l.snap_na, N));
-      HIPCHK(hipMalloc(&l.snap_ea, E));
+      HIPCHK(wt::dmalloc(&l.snap_dh, N * sizeof(double)));
+      HIPCHK(wt::dmalloc(&l.snap_u, E * sizeof(double)));
+      HIPCHK(wt::dmalloc(&l.snap_na, N));
+      HIPCHK(wt::dmalloc(&l.snap_ea, E));
     }
     auto cp = [&](void* dst, const void* src, size_t b) {
       HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, g->stream));
@@ -767,7 +803,8 @@ static int64_t judge_gated_step(wt_grid* g) {
   details_all(g, dh, u, true);
   double mh, mu;
   masked_max_all(g, &mh, &mu);
-  const double eh = g->last_eps * mh, eu = g->last_eps * mu;
+  double eh = g->last_eps * mh, eu = g->last_eps * mu;
+  if (g->prm.threshold != WT_THR_RELATIVE) regime_thresholds(g->prm, g->last_eps, &eh, &eu);
   clear_significant(g);
   const bool L = g->lists_ok;
   std::vector<MaskJob> jobs;
@@ -796,38 +833,98 @@ static int64_t judge_gated_step(wt_grid* g) {
   return total;
 }
 
-// fn(k) for every member k, members spread over host threads (each member has its own stream,
-// so their kernels overlap on the device); the first failure (in member order) is returned with
-// its message.  fn returns WT_OK or an error code and leaves its message in g_err.
-template <typename Fn>
-static int for_members(size_t n, Fn fn) {
-  std::vector<int> rc(n, WT_OK);
-  std::vector<std::string> msg(n);
-  const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
-  // four threads: a process gets four hardware queues by default, and more threads only contend
-  // for them (32-member ensemble: batched step 16.1 ms with 4 or 8 threads, 17.2 with 16, 17.7
-  // with 32)
-  const size_t nt = std::min<size_t>({n, hw, size_t(4)});
-  auto work = [&](size_t t0) {
-    for (size_t k = t0; k < n; k += nt) {
-      rc[k] = fn(k);
-      if (rc[k] != WT_OK) msg[k] = g_err;
+// Host threads of an ensemble: created once with the ensemble and kept until it is destroyed
+// (a thread per call would create and tear down threads, and their HIP thread state, every
+// step).  run(n, fn) calls fn(k) for every member k: thread t takes k = t, t + nt, ... and the
+// calling thread is thread 0, so a member is always served by the same thread.  Four threads: a
+// process gets four hardware queues by default, and more threads only contend for them (32-member
+// ensemble: batched step 16.1 ms with 4 or 8 threads, 17.2 with 16, 17.7 with 32).
+class MemberPool {
+ public:
+  MemberPool() {
+    const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
+    nt_ = std::min<size_t>(hw, 4);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    for (size_t t = 1; t < nt_; ++t) {
+      try {
+        th_.emplace_back([this, t, dev]() { loop(t, dev); });
+      } catch (const std::exception&) {
+        break;   // fewer threads: the caller covers the shares of the missing ones
+      }
     }
-  };
-  std::vector<std::thread> th;
-  size_t started = 0;
-  try {
-    for (size_t t = 1; t < nt; ++t, ++started) th.emplace_back(work, t);
-  } catch (const std::exception&) {
-    // no more threads: the calling thread takes the shares that were not started
   }
-  work(0);
-  for (size_t t = started + 1; t < nt; ++t) work(t);
-  for (auto& x : th) x.join();
-  for (size_t k = 0; k < n; ++k)
-    if (rc[k] != WT_OK) return fail(rc[k], msg[k]);
-  return WT_OK;
-}
+  ~MemberPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& x : th_) x.join();
+  }
+  // fn(k) for k in [0, n); the first failure (in member order) is returned with its message.  fn
+  // returns WT_OK or an error code and leaves its message in the calling thread's g_err.
+  int run(size_t n, const std::function<int(size_t)>& fn) {
+    std::vector<int> rc(n, WT_OK);
+    std::vector<std::string> msg(n);
+    const std::function<void(size_t)> share = [&](size_t t) {
+      for (size_t k = t; k < n; k += nt_) {
+        try {
+          rc[k] = fn(k);
+        } catch (const std::exception& x) {
+          rc[k] = fail(WT_EDEVICE, x.what());
+        }
+        if (rc[k] != WT_OK) msg[k] = g_err;
+      }
+    };
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      job_ = &share;
+      pending_ = th_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    share(0);
+    for (size_t t = th_.size() + 1; t < nt_; ++t) share(t);   // shares of threads that failed to start
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      done_cv_.wait(lk, [&] { return pending_ == 0; });
+      job_ = nullptr;
+    }
+    for (size_t k = 0; k < n; ++k)
+      if (rc[k] != WT_OK) return fail(rc[k], msg[k]);
+    return WT_OK;
+  }
+
+ private:
+  void loop(size_t t, int dev) {
+    (void)hipSetDevice(dev);
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(size_t)>* job = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        job = job_;
+      }
+      (*job)(t);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (--pending_ == 0) done_cv_.notify_all();
+      }
+    }
+  }
+  size_t nt_ = 1;
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(size_t)>* job_ = nullptr;
+  size_t pending_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
 
 // Host tables are expensive to build (seconds at level 9) and depend only on the level (pairs:
 // on the coarse level) and the sphere's radius and rotation rate: grids built in one process share
@@ -911,8 +1008,13 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
     g->prm.mean_depth = 2.94e4 / 9.80616;
     g->prm.rk = WT_RK4;
     g->prm.precision = WT_FP64;
+    g->prm.viscosity = 0.0;
+    g->prm.equations = WT_SWE;
+    g->prm.threshold = WT_THR_RELATIVE;
     HIPCHK(hipStreamCreate(&g->own));
     g->stream = g->own;
+    g->hook = default_hook();
+    GridScope scope(g.get());
     std::vector<std::shared_ptr<const Level>> raw;
     for (int j = jmin; j <= jmax; ++j) raw.push_back(cached_level(j, g->prm.radius, g->prm.omega));
     for (int j = jmin; j < jmax; ++j) {
@@ -920,7 +1022,7 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
       ps->host = *cached_pair(*raw[j - jmin], *raw[j + 1 - jmin]);
       g->pairs.push_back(std::move(ps));
     }
-    // effective areas, bottom-up from the geometric areas of jmax (area conditions, Sec. 4.2)
+    // effective areas, bottom-up from the geometric areas of jmax (area conditions, Sec. 4.1)
     const int nl = jmax - jmin + 1;
     std::vector<std::vector<double>> Aeff(nl);
     Aeff[nl - 1] = raw[nl - 1]->A_i;
@@ -948,7 +1050,7 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
     raw.clear();
     for (auto& ps : g->pairs) {
       upload_pair(ps->host, ps->dev);
-      auto A2 = [](double** q, int64_t n) { HIPCHK(hipMalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };
+      auto A2 = [](double** q, int64_t n) { HIPCHK(wt::dmalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };
       A2(&ps->d_h, ps->host.Ec); A2(&ps->d_p, ps->host.Ec); A2(&ps->d_k, ps->host.Ec); A2(&ps->d_i, 3 * ps->host.Tc);
       A2(&ps->r_h, ps->host.Ec); A2(&ps->r_p, ps->host.Ec); A2(&ps->r_i, 3 * ps->host.Tc);
       // keep only what the device path needs on the host
@@ -981,10 +1083,10 @@ void wt_grid_destroy(wt_grid* g) {
     free_list(ps->l_cn);
     free_list(ps->l_ce);
     free_list(ps->l_ct);
-    if (ps->pred) (void)hipFree(ps->pred);
+    if (ps->pred) (void)wt::dfree(ps->pred);
     void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k, ps->r_h, ps->r_p, ps->r_i};
     for (void* x : q)
-      if (x) (void)hipFree(x);
+      if (x) (void)wt::dfree(x);
   }
   free_scratch(g->csc);
   g->cb.release();
@@ -995,14 +1097,39 @@ void wt_grid_destroy(wt_grid* g) {
 }
 
 int wt_set_params(wt_grid* g, const wt_params* p) {
+  GridScope scope_(g);
   if (!g || !p) return fail(WT_EINVAL, "wt_set_params: null argument");
   if (p->radius != g->prm.radius || p->omega != g->prm.omega)
     return fail(WT_EINVAL, "wt_set_params: radius and omega are fixed at grid creation");
-  if (!(p->gravity > 0) || !(p->mean_depth > 0))
-    return fail(WT_EINVAL, "wt_set_params: gravity and mean_depth must be positive");
+  if (p->equations != WT_SWE && p->equations != WT_ADVECTION) return fail(WT_EINVAL, "wt_set_params: bad equations");
+  const bool adv = p->equations == WT_ADVECTION;
+  if (!(p->gravity > 0) || !(adv ? p->mean_depth >= 0 : p->mean_depth > 0) || !std::isfinite(p->mean_depth))
+    return fail(WT_EINVAL, "wt_set_params: gravity and mean_depth must be positive (mean_depth >= 0 for advection)");
   if (p->rk != WT_RK4 && p->rk != WT_SSPRK43) return fail(WT_EINVAL, "wt_set_params: bad rk");
   if (p->precision != WT_FP64 && p->precision != WT_FP32_TENDENCY)
     return fail(WT_EINVAL, "wt_set_params: bad precision");
+  if (!(p->viscosity >= 0) || !std::isfinite(p->viscosity))
+    return fail(WT_EINVAL, "wt_set_params: viscosity must be >= 0");
+  if (adv && p->viscosity != 0) return fail(WT_EINVAL, "wt_set_params: the advection form has no viscosity");
+  if (p->threshold != WT_THR_RELATIVE && p->threshold != WT_THR_QG && p->threshold != WT_THR_IG)
+    return fail(WT_EINVAL, "wt_set_params: bad threshold");
+  if (p->threshold != WT_THR_RELATIVE && !(p->scale_u > 0))
+    return fail(WT_EINVAL, "wt_set_params: the regime thresholds need scale_u > 0");
+  if (p->threshold == WT_THR_QG && !(p->scale_l > 0 && p->scale_f > 0))
+    return fail(WT_EINVAL, "wt_set_params: the quasi-geostrophic thresholds need scale_l, scale_f > 0");
+  if (p->threshold == WT_THR_IG && !(p->mean_depth > 0))
+    return fail(WT_EINVAL, "wt_set_params: the inertia-gravity thresholds need mean_depth > 0");
+  try {
+    // the viscous form's total mass flux G: one more edge array per level
+    if (p->viscosity != 0)
+      for (auto& l : g->lev)
+        if (!l->work.G) {
+          HIPCHK(wt::dmalloc(&l->work.G, l->tab.E * sizeof(double)));
+          HIPCHK(hipMemsetAsync(l->work.G, 0, l->tab.E * sizeof(double), g->stream));
+        }
+  } catch (const std::exception& e) {
+    return fail(WT_ENOMEM, std::string("wt_set_params: ") + e.what());
+  }
   g->prm = *p;
   ++g->state_ver;
   touch_epoch(g);
@@ -1073,10 +1200,12 @@ static int set_state_impl(wt_grid* g, int level, const void* dh, const void* u, 
 }
 
 int wt_set_state(wt_grid* g, int level, const double* dh, const double* u) {
+  GridScope scope_(g);
   return set_state_impl(g, level, dh, u, hipMemcpyHostToDevice);
 }
 
 int wt_set_state_device(wt_grid* g, int level, const void* dh, const void* u) {
+  GridScope scope_(g);
   return set_state_impl(g, level, dh, u, hipMemcpyDeviceToDevice);
 }
 
@@ -1086,6 +1215,7 @@ static const char kCkptMagic[8] = {'W', 'T', 'C', 'K', 'P', 'T', '0', '1'};
 static const char kCkptEnd[8] = {'W', 'T', 'C', 'K', 'P', 'E', 'N', 'D'};
 
 int wt_save(wt_grid* g, const char* path) {
+  GridScope scope_(g);
   if (!g || !path) return fail(WT_EINVAL, "wt_save: null argument");
   if (!g->have_state) return fail(WT_ESTATE, "wt_save: no state loaded");
   std::FILE* f = std::fopen(path, "wb");
@@ -1128,6 +1258,7 @@ int wt_save(wt_grid* g, const char* path) {
 }
 
 int wt_load(wt_grid* g, const char* path) {
+  GridScope scope_(g);
   if (!g || !path) return fail(WT_EINVAL, "wt_load: null argument");
   std::FILE* f = std::fopen(path, "rb");
   if (!f) return fail(WT_EINVAL, std::string("wt_load: cannot open ") + path);
@@ -1196,6 +1327,7 @@ int wt_load(wt_grid* g, const char* path) {
 }
 
 int wt_get_state(wt_grid* g, int level, double* dh, double* u, uint8_t* na, uint8_t* ea) {
+  GridScope scope_(g);
   if (bad_level(g, level)) return fail(WT_EINVAL, "wt_get_state: bad level");
   if (!g->have_state) return fail(WT_ESTATE, "wt_get_state: no state loaded");
   try {
@@ -1241,8 +1373,35 @@ static bool phase_plan_ready(wt_grid* g, double dt) {
   return !g->sphase.empty();
 }
 
+// A plan fixes each member's precision, physical constants and state buffers when it is built;
+// one launched after a parameter change that did not rebuild it would step with the old values, so
+// every launch checks the plan against the members' current parameters and fails loudly instead.
+static void check_plan(const BatchPlan& pl, const std::vector<wt_grid*>& members) {
+  size_t q = 0;
+  for (wt_grid* g : members) {
+    const int32_t fp = g->prm.precision == WT_FP32_TENDENCY ? 1 : 0;
+    for (auto& lp : g->lev) {
+      if (q >= pl.levels.size()) throw std::runtime_error("step plan does not cover every level");
+      const BatchLevel& b = pl.levels[q++];
+      const PhysParams p = phys(g);
+      if (b.fp32 != fp || b.ph.g != p.g || b.ph.H != p.H || b.ph.nu != p.nu || b.ph.adv != p.adv ||
+          b.dh != lp->work.dh || b.G != total_flux(lp->work, p))
+        throw std::runtime_error("step plan built for other parameters than the grid's current ones");
+    }
+  }
+  if (q != pl.levels.size()) throw std::runtime_error("step plan holds other levels than the members'");
+  for (const BatchJob& jb : pl.jobs) {
+    const bool on_level = jb.kind == BK_VERTEX || jb.kind == BK_EDGE_CELL || jb.kind == BK_Q || jb.kind == BK_DIV ||
+                          jb.kind == BK_TEND;
+    const int lev = on_level ? jb.a : pl.pairs.at(size_t(jb.a)).c;
+    if (jb.fp32 != pl.levels.at(size_t(lev)).fp32)
+      throw std::runtime_error("step plan job precision differs from its level's");
+  }
+}
+
 // the step with a ready plan: launches only (capturable)
 static void ml_step_phases(wt_grid* g) {
+  check_plan(g->splan, {g});
   ++g->state_ver;
   for (const PhaseArgs& a : g->sphase) phase_launch(g->splan, a, g->stream);
 }
@@ -1253,6 +1412,7 @@ static void ml_step_run(wt_grid* g, double dt) {
 }
 
 int wt_step(wt_grid* g, double dt) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_step: null grid");
   if (!g->have_state) return fail(WT_ESTATE, "wt_step: call wt_set_state first");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(WT_EINVAL, "wt_step: dt must be positive");
@@ -1280,6 +1440,7 @@ int wt_step(wt_grid* g, double dt) {
 }
 
 int wt_adapt(wt_grid* g, double eps) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_adapt: null grid");
   if (!g->have_state) return fail(WT_ESTATE, "wt_adapt: call wt_set_state first");
   if (!(eps >= 0) || !std::isfinite(eps)) return fail(WT_EINVAL, "wt_adapt: eps must be >= 0");
@@ -1298,6 +1459,7 @@ int wt_adapt(wt_grid* g, double eps) {
 }
 
 int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_set_predictor: null grid");
   if (m && !(threshold >= 0.0 && threshold <= 1.5)) return fail(WT_EINVAL, "wt_set_predictor: threshold out of range");
   g->predictor = m;
@@ -1307,6 +1469,7 @@ int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
 }
 
 int wt_set_step_phases(wt_grid* g, int enable) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_set_step_phases: null grid");
   try {
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -1318,6 +1481,7 @@ int wt_set_step_phases(wt_grid* g, int enable) {
 }
 
 int wt_set_work_lists(wt_grid* g, int enable) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_set_work_lists: null grid");
   ++g->state_ver;
   try {
@@ -1371,14 +1535,17 @@ static int patch_data(wt_grid* g, int level, float* out, bool labels, const char
 }
 
 int wt_patch_features(wt_grid* g, int level, float* x_device) {
+  GridScope scope_(g);
   return patch_data(g, level, x_device, false, "wt_patch_features");
 }
 
 int wt_patch_labels(wt_grid* g, int level, float* y_device) {
+  GridScope scope_(g);
   return patch_data(g, level, y_device, true, "wt_patch_labels");
 }
 
 int wt_forward(wt_grid* g) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_forward: null grid");
   ++g->state_ver;
   if (!g->have_state) return fail(WT_ESTATE, "wt_forward: call wt_set_state first");
@@ -1394,6 +1561,7 @@ int wt_forward(wt_grid* g) {
 }
 
 int wt_inverse(wt_grid* g) {
+  GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_inverse: null grid");
   ++g->state_ver;
   if (!g->have_state) return fail(WT_ESTATE, "wt_inverse: call wt_set_state first");
@@ -1410,6 +1578,7 @@ int wt_inverse(wt_grid* g) {
 }
 
 int wt_get_details(wt_grid* g, int level, double* dh, double* dpair, double* dint) {
+  GridScope scope_(g);
   if (!g || level <= g->jmin || level > g->jmax) return fail(WT_EINVAL, "wt_get_details: bad level");
   try {
     if (g->have_state) dense_details(g);
@@ -1426,6 +1595,7 @@ int wt_get_details(wt_grid* g, int level, double* dh, double* dpair, double* din
 }
 
 int wt_set_mask(wt_grid* g, int level, const uint8_t* na, const uint8_t* ea) {
+  GridScope scope_(g);
   if (bad_level(g, level) || !na || !ea) return fail(WT_EINVAL, "wt_set_mask: bad argument");
   ++g->state_ver;
   try {
@@ -1441,6 +1611,7 @@ int wt_set_mask(wt_grid* g, int level, const uint8_t* na, const uint8_t* ea) {
 }
 
 int wt_tendency(wt_grid* g, int level, double* ddh, double* du) {
+  GridScope scope_(g);
   if (bad_level(g, level)) return fail(WT_EINVAL, "wt_tendency: bad level");
   if (!g->have_state) return fail(WT_ESTATE, "wt_tendency: no state loaded");
   try {
@@ -1473,6 +1644,7 @@ static void diag_fine(wt_grid* g, double* r) {
 }
 
 int wt_diagnostics(wt_grid* g, wt_diag* d) {
+  GridScope scope_(g);
   if (!g || !d) return fail(WT_EINVAL, "wt_diagnostics: null argument");
   if (!g->have_state) return fail(WT_ESTATE, "wt_diagnostics: no state loaded");
   try {
@@ -1508,6 +1680,7 @@ int wt_diagnostics(wt_grid* g, wt_diag* d) {
       HIPCHK(hipStreamSynchronize(g->stream));
       d->active_nodes[j] = int64_t(cn);
       d->active_edges[j] = int64_t(ce);
+      if (cn > 0 || ce > 0) d->finest_level = j;
     }
     if (nonfinite > 0) return fail(WT_ENUMERIC, "wt_diagnostics: non-finite values in the state");
   } catch (const std::exception& e) {
@@ -1517,16 +1690,65 @@ int wt_diagnostics(wt_grid* g, wt_diag* d) {
 }
 
 double wt_suggest_dt(wt_grid* g, double cfl) {
+  GridScope scope_(g);
   if (!g || !(cfl > 0)) { fail(WT_EINVAL, "wt_suggest_dt: bad argument"); return -1.0; }
   if (!g->have_state) { fail(WT_ESTATE, "wt_suggest_dt: no state loaded"); return -1.0; }
   try {
     double r[8];
     diag_fine(g, r);
+    // the advection form has no gravity waves: the advective limit alone
+    if (g->prm.equations == WT_ADVECTION) return cfl * r[6];
     return cfl * std::fmin(1.0 / r[5], r[6]);
   } catch (const std::exception& e) {
     fail(WT_EDEVICE, std::string("wt_suggest_dt: ") + e.what());
     return -1.0;
   }
+}
+
+int wt_set_allocator(wt_grid* g, void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return fail(WT_EINVAL, "wt_set_allocator: give both functions or neither");
+  // the hook's own signature has no stream; the trampolines keep the caller's pair in ctx
+  struct Pair {
+    void* (*a)(size_t, void*);
+    void (*f)(void*, void*);
+    void* ctx;
+  };
+  AllocHook h;
+  if (alloc) {
+    // one record per distinct (alloc, free, ctx); records live as long as the process
+    static std::mutex mu;
+    static std::vector<std::unique_ptr<Pair>>* keep = new std::vector<std::unique_ptr<Pair>>();
+    Pair* pr = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto& x : *keep)
+        if (x->a == alloc && x->f == free_ && x->ctx == ctx) pr = x.get();
+      if (!pr) {
+        keep->push_back(std::make_unique<Pair>(Pair{alloc, free_, ctx}));
+        pr = keep->back().get();
+      }
+    }
+    h.alloc = [](size_t bytes, void*, void* c) { auto* q = static_cast<Pair*>(c); return q->a(bytes, q->ctx); };
+    h.free_ = [](void* p, void* c) {
+      auto* q = static_cast<Pair*>(c);
+      // the memory may be handed to other work as soon as it is returned: wait for all queued
+      // device work first (hipFree does the same)
+      (void)hipDeviceSynchronize();
+      q->f(p, q->ctx);
+    };
+    h.ctx = pr;
+  }
+  if (g) g->hook = h;
+  else set_default_hook(h);
+  return WT_OK;
+}
+
+int wt_alloc_stats(const wt_grid* g, int64_t* n_hook, int64_t* bytes_hook, int64_t* n_direct,
+                   int64_t* bytes_direct) {
+  if (!g) return fail(WT_EINVAL, "wt_alloc_stats: null grid");
+  alloc_stats(g, n_hook, bytes_hook, n_direct, bytes_direct);
+  return WT_OK;
 }
 
 int wt_set_stream(wt_grid* g, void* s) {
@@ -1665,6 +1887,7 @@ int wt_host_lattice_check(int level, int64_t* n_tiles, int64_t* n_rim, double* m
 // ---------------------------------------------------------------- ensemble
 struct wt_ensemble {
   std::vector<wt_grid*> m;
+  std::unique_ptr<MemberPool> pool;   // host threads of the members' adapts and threshold tests
   hipStream_t s0 = nullptr;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -1731,8 +1954,8 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
       bl.Q = l.work.Q;
       bl.c = l.work.c;
       bl.dh = l.work.dh;
-      bl.g = p.g;
-      bl.H = p.H;
+      bl.ph = p;
+      bl.G = total_flux(l.work, p);
       bl.fp32 = x.fp32;
       for (int st = 0; st < 4; ++st) {
         const StageSpec sp = rk_stage(g->prm.rk, st, l.work, dt[k]);
@@ -1859,6 +2082,13 @@ static void batched_step(wt_ensemble* e, const double* dt) {
     int64_t bits = 0;
     std::memcpy(&bits, &dt[k], sizeof(bits));
     sig.push_back(bits);
+    std::memcpy(&bits, &g->prm.gravity, sizeof(bits));
+    sig.push_back(bits);
+    std::memcpy(&bits, &g->prm.mean_depth, sizeof(bits));
+    sig.push_back(bits);
+    std::memcpy(&bits, &g->prm.viscosity, sizeof(bits));
+    sig.push_back(bits);
+    sig.push_back(g->prm.equations);
     for (auto& l : g->lev) {
       for (const WorkList* L : {&l->l_tri, &l->l_elem, &l->l_edge, &l->l_node, &l->l_tend}) {
         sig.push_back(reinterpret_cast<int64_t>(L->idx));
@@ -1886,6 +2116,7 @@ static void batched_step(wt_ensemble* e, const double* dt) {
     HIPCHK(hipEventCreate(&e->t1));
   }
   HIPCHK(hipEventRecord(e->t0, e->s0));
+  check_plan(e->plan, e->m);
   batch_launch(e->plan, bpc, chunk, queue, e->s0);
   HIPCHK(hipEventRecord(e->t1, e->s0));
   batch_check(e->plan, e->s0);
@@ -1923,6 +2154,7 @@ wt_ensemble* wt_ensemble_create(wt_grid* const* members, int n) {
   auto* e = new wt_ensemble;
   try {
     e->m.assign(members, members + n);
+    e->pool = std::make_unique<MemberPool>();
     HIPCHK(hipStreamCreateWithFlags(&e->s0, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
     e->join.resize(n);
@@ -1953,7 +2185,7 @@ void wt_ensemble_destroy(wt_ensemble* e) {
 
 int wt_ensemble_adapt(wt_ensemble* e, const double* eps) {
   if (!e || !eps) return fail(WT_EINVAL, "wt_ensemble_adapt: null argument");
-  return for_members(e->m.size(), [&](size_t k) { return wt_adapt(e->m[k], eps[k]); });
+  return e->pool->run(e->m.size(), [&](size_t k) { return wt_adapt(e->m[k], eps[k]); });
 }
 
 int wt_ensemble_step(wt_ensemble* e, const double* dt) {
@@ -1988,6 +2220,7 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
         for (size_t k = 0; k < n; ++k) {
           wt_grid* m = e->m[k];
           const bool had = !m->sphase.empty() && m->splan_sig == m->step_sig && m->splan_dt == dt[k];
+          GridScope scope(m);
           phased[k] = m->multi() && phase_plan_ready(m, dt[k]);
           if (phased[k] && !had) stale = true;
         }
@@ -2002,6 +2235,7 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
       HIPCHK(hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed));
       try {
         if (merged) {
+          check_plan(e->mplan, e->m);
           for (const auto& ph : e->mphase) phase_launch_dev(e->mplan, ph, e->s0);
         } else {
           HIPCHK(hipEventRecord(e->fork, e->s0));
@@ -2053,9 +2287,10 @@ int wt_ensemble_step(wt_ensemble* e, const double* dt) {
   }
   // the threshold test of the learned zone needs the host: each member judged (and redone if
   // needed) on its own stream, members spread over host threads
-  return for_members(n, [&](size_t k) {
+  return e->pool->run(n, [&](size_t k) {
     wt_grid* m = e->m[k];
     if (!m->multi() || !m->gated) return int(WT_OK);
+    GridScope scope(m);
     try {
       m->gated = false;
       if (judge_gated_step(m) > 0) {

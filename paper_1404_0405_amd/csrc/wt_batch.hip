@@ -6,6 +6,7 @@
 #include <stdexcept>
 #include <string>
 
+#include "wt_alloc.hpp"
 #include "wt_batch.hpp"
 #include "wt_body.hpp"
 
@@ -34,42 +35,43 @@ __device__ __forceinline__ void batch_entry(const BatchJob& jb, int64_t i, const
     case BK_PRO_ODD: {
       const BatchPair& bp = PR[jb.a];
       const BatchLevel &C = LV[bp.c], &F = LV[bp.f];
-      body_prolong_odd_pair(i, bp.P, F.na, F.ea, C.t.e_v, C.pu[s].x, const_cast<double*>(F.pdh[s].x),
+      body_prolong_odd_pair<T>(i, bp.P, F.na, F.ea, C.t.e_v, C.pu[s].x, const_cast<double*>(F.pdh[s].x),
                             const_cast<double*>(F.pu[s].x));
       break;
     }
     case BK_PRO_INT: {
       const BatchPair& bp = PR[jb.a];
       const BatchLevel &C = LV[bp.c], &F = LV[bp.f];
-      body_prolong_int(i, bp.P, F.ea, C.pu[s].x, const_cast<double*>(F.pu[s].x));
+      body_prolong_int<T>(i, bp.P, F.ea, C.pu[s].x, const_cast<double*>(F.pu[s].x));
       break;
     }
     case BK_VERTEX: {
       const BatchLevel& L = LV[jb.a];
-      body_vertex<T>(i, L.t, L.pdh[s].x, L.pu[s].x, L.H, static_cast<T*>(L.qv));
+      body_vertex<T>(i, L.t, L.pdh[s].x, L.pu[s].x, L.ph.H, static_cast<T*>(L.qv));
       break;
     }
     case BK_EDGE_CELL: {
       const BatchLevel& L = LV[jb.a];
-      body_edge_cell<T>(i, L.t, L.pdh[s].x, L.pu[s].x, static_cast<const T*>(L.qv), L.g, L.H,
-                        static_cast<T*>(L.B), static_cast<double*>(L.F), static_cast<T*>(L.qe));
+      body_edge_cell<T>(i, L.t, L.pdh[s].x, L.pu[s].x, static_cast<const T*>(L.qv), L.ph, static_cast<T*>(L.B),
+                        static_cast<double*>(L.F), L.G, static_cast<T*>(L.qe));
       break;
     }
     case BK_Q: {
       const BatchLevel& L = LV[jb.a];
-      body_Q<T>(i, L.t, static_cast<const double*>(L.F), static_cast<const T*>(L.qe), static_cast<T*>(L.Q));
+      body_Q<T>(i, L.t, static_cast<const double*>(L.F), static_cast<const T*>(L.qe), static_cast<T*>(L.Q), L.ph.nu,
+                L.pu[s].x);
       break;
     }
     case BK_DIV: {
       const BatchLevel& F = LV[jb.a];
-      body_div(i, F.t, static_cast<const double*>(F.F), F.c);
+      body_div(i, F.t, F.G, F.c);
       break;
     }
     case BK_RES_E: {
       const BatchPair& bp = PR[jb.a];
       const BatchLevel &C = LV[bp.c], &F = LV[bp.f];
-      body_restrict_edges<T>(i, bp.P, F.ea, F.t.l_e, C.t.l_e, static_cast<const double*>(F.F), F.c,
-                             static_cast<const T*>(F.Q), static_cast<double*>(C.F), static_cast<T*>(C.Q));
+      body_restrict_edges<T>(i, bp.P, F.ea, F.t.l_e, C.t.l_e, F.G, F.c, static_cast<const T*>(F.Q), C.G,
+                             static_cast<T*>(C.Q));
       break;
     }
     case BK_RES_B: {
@@ -80,8 +82,8 @@ __device__ __forceinline__ void batch_entry(const BatchJob& jb, int64_t i, const
     }
     case BK_TEND: {
       const BatchLevel& L = LV[jb.a];
-      body_tend_ml<T>(i, L.t, L.na, L.ea, static_cast<const T*>(L.B), static_cast<const double*>(L.F),
-                      static_cast<const T*>(L.Q), L.pdh[s], L.pu[s], L.so[s]);
+      body_tend_ml<T>(i, L.t, L.na, L.ea, static_cast<const T*>(L.B), L.G, static_cast<const T*>(L.Q), L.pdh[s],
+                      L.pu[s], L.so[s], L.ph.adv);
       break;
     }
     case BK_PARTIAL_H: {
@@ -317,9 +319,9 @@ void phase_prepare_dev(BatchPlan& plan, std::vector<PhaseDev>& out, hipStream_t 
   }
   HIPCHK(hipStreamSynchronize(s));   // the previous table may still be read by a queued launch
   if (!plan.d_pre || plan.cap_pre < pre.size()) {
-    if (plan.d_pre) HIPCHK(hipFree(plan.d_pre));
+    if (plan.d_pre) HIPCHK(wt::dfree(plan.d_pre));
     plan.cap_pre = std::max<size_t>(1, pre.size() + pre.size() / 2);
-    HIPCHK(hipMalloc(&plan.d_pre, plan.cap_pre * sizeof(int32_t)));
+    HIPCHK(wt::dmalloc(&plan.d_pre, plan.cap_pre * sizeof(int32_t)));
   }
   HIPCHK(hipMemcpyAsync(plan.d_pre, pre.data(), pre.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));   // pre is a local vector
@@ -343,9 +345,9 @@ static size_t ctr_bytes(size_t nphase) { return std::max<size_t>(1, ctr_words(np
 template <typename X>
 static void upload_vec(const std::vector<X>& v, X*& d, size_t& cap, hipStream_t s) {
   if (!d || cap < v.size()) {
-    if (d) HIPCHK(hipFree(d));
+    if (d) HIPCHK(wt::dfree(d));
     cap = std::max<size_t>(1, v.size() + v.size() / 2);
-    HIPCHK(hipMalloc(&d, cap * sizeof(X)));
+    HIPCHK(wt::dmalloc(&d, cap * sizeof(X)));
   }
   if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s));
 }
@@ -361,9 +363,9 @@ void BatchPlan::upload(hipStream_t s) {
   upload_vec(phases, d_phases, cap[3], s);
   // work-queue counters, then the barrier slots of every phase, then the error flag
   if (!d_ctr || cap[4] < ctr_bytes(phases.size())) {
-    if (d_ctr) HIPCHK(hipFree(d_ctr));
+    if (d_ctr) HIPCHK(wt::dfree(d_ctr));
     cap[4] = ctr_bytes(phases.size() + phases.size() / 2);
-    HIPCHK(hipMalloc(&d_ctr, cap[4]));
+    HIPCHK(wt::dmalloc(&d_ctr, cap[4]));
   }
   HIPCHK(hipStreamSynchronize(s));   // the host vectors of the copies may change afterwards
   nphase = int(phases.size());
@@ -372,7 +374,7 @@ void BatchPlan::upload(hipStream_t s) {
 void BatchPlan::release() {
   void* ps[] = {d_levels, d_pairs, d_jobs, d_phases, d_ctr, d_pre};
   for (void* p : ps)
-    if (p) (void)hipFree(p);
+    if (p) (void)wt::dfree(p);
   for (auto& c : cap) c = 0;
   d_levels = nullptr;
   d_pairs = nullptr;

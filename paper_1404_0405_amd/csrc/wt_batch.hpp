@@ -29,7 +29,8 @@ struct BatchLevel {
   const uint8_t *na, *ea;
   void *qv, *B, *F, *qe, *Q;
   double *c, *dh;   // fine divergence, prognostic height
-  double g, H;
+  double* G;        // total mass flux read by the divergence and the restriction (F if inviscid)
+  PhysParams ph;
   int32_t fp32;
   StagePtrs pdh[4], pu[4];   // per Runge-Kutta stage
   StageOut so[4];

@@ -12,29 +12,50 @@
 namespace wt {
 
 // ------------------------------------------------------------------ inter-scale predictions
+// The velocity prediction sums are evaluated in the compute type T (float in the single-precision
+// mode, with the coarse values and weights rounded to it); a prediction is then combined with the
+// stored values (detail = value - prediction, value = detail + prediction) in double, so the
+// state keeps double precision and the forward and inverse transforms stay exact inverses of
+// each other.  The height transform stays in double in both modes: its prediction is part of the
+// area-weighted restriction R_h (eq. (Rh)), and the partial transform of a step replaces coarse
+// heights by R_h of the fine ones, which conserves mass to round-off only when R_h inverts the
+// adapt's reconstruction exactly (a single-precision height prediction left 1e-10 relative mass
+// drift after 20 steps).
+
 // velocity difference of the two half-edges of coarse edge e predicted from the coarse
 // velocities of its two triangles' stencils
-__device__ __forceinline__ double pair_pred(const DevPair& P, int64_t e, const int32_t* __restrict__ e_v,
-                                            const double* __restrict__ uc) {
+template <typename T>
+__device__ __forceinline__ T pair_pred(const DevPair& P, int64_t e, const int32_t* __restrict__ e_v,
+                                       const double* __restrict__ uc) {
   int32_t tl = e_v[2 * e], tr = e_v[2 * e + 1];
-  double s = 0.0;
+  T s = T(0);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s += P.w_pl[9 * e + k] * uc[P.v_sten[9 * tl + k]];
+  for (int k = 0; k < 9; ++k) s += T(P.w_pl[9 * e + k]) * T(uc[P.v_sten[9 * tl + k]]);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s += P.w_pr[9 * e + k] * uc[P.v_sten[9 * tr + k]];
+  for (int k = 0; k < 9; ++k) s += T(P.w_pr[9 * e + k]) * T(uc[P.v_sten[9 * tr + k]]);
   return s;
 }
 
 // interior fine edge s of coarse triangle t predicted from the triangle's coarse stencil
-__device__ __forceinline__ double int_pred(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
-  double v = 0.0;
+template <typename T>
+__device__ __forceinline__ T int_pred(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
+  T v = T(0);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) v += P.w_int[27 * t + 9 * s + k] * uc[P.v_sten[9 * t + k]];
+  for (int k = 0; k < 9; ++k) v += T(P.w_int[27 * t + 9 * s + k]) * T(uc[P.v_sten[9 * t + k]]);
   return v;
 }
 
-// height detail at the midpoint of coarse edge e: fine value minus the s~-weighted mean of the
-// four even fine neighbours
+// height at the midpoint of coarse edge e predicted from its four even fine neighbours
+// (s~-weighted mean, eq. (WTpred))
+__device__ __forceinline__ double h_pred(const DevPair& P, int64_t e, const double* __restrict__ hf) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
+  return s;
+}
+
+// height detail at the midpoint of coarse edge e: fine value minus the prediction (subtracted
+// term by term)
 __device__ __forceinline__ double h_detail(const DevPair& P, int64_t e, const double* __restrict__ hf) {
   double s = hf[P.mid[e]];
 #pragma unroll
@@ -51,33 +72,30 @@ __device__ __forceinline__ void body_prolong_even(int64_t k, const DevPair& P, c
   if (!naf[f]) hf[f] = hc[k];
 }
 
+template <typename T>
 __device__ __forceinline__ void body_prolong_odd_pair(int64_t e, const DevPair& P, const uint8_t* __restrict__ naf,
                                                       const uint8_t* __restrict__ eaf,
                                                       const int32_t* __restrict__ e_v_c,
                                                       const double* __restrict__ uc, double* __restrict__ hf,
                                                       double* __restrict__ uf) {
   int32_t m = P.mid[e];
-  if (!naf[m]) {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) s += P.st[4 * e + c] * hf[P.even[P.cells[4 * e + c]]];
-    hf[m] = s;
-  }
+  if (!naf[m]) hf[m] = h_pred(P, e, hf);
   int32_t h1 = P.h1[e], h2 = P.h2[e];
   bool a1 = eaf[h1], a2 = eaf[h2];
   if (!a1 || !a2) {
-    double half = 0.5 * pair_pred(P, e, e_v_c, uc);
+    const double half = 0.5 * double(pair_pred<T>(P, e, e_v_c, uc));
     if (!a1) uf[h1] = uc[e] + half;
     if (!a2) uf[h2] = uc[e] - half;
   }
 }
 
+template <typename T>
 __device__ __forceinline__ void body_prolong_int(int64_t t, const DevPair& P, const uint8_t* __restrict__ eaf,
                                                  const double* __restrict__ uc, double* __restrict__ uf) {
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     int32_t f = P.int_e[3 * t + s];
-    if (!eaf[f]) uf[f] = int_pred(P, t, s, uc);
+    if (!eaf[f]) uf[f] = double(int_pred<T>(P, t, s, uc));
   }
 }
 
@@ -95,39 +113,62 @@ __device__ __forceinline__ void body_vertex(int64_t t, const DevTables& tb, cons
   qv[t] = (z + T(tb.f_v[t])) / hv;
 }
 
-// B_i = g dh_i + K_i at node id; F_e = h_e u_e and q_e at its three edges
+// B_i = g dh_i + K_i at node id; F_e = h_e u_e and q_e at its three edges.  Viscous form
+// (Sec. 3.1): B_i - nu (div u)_i and, into G, the total mass flux F_e - nu (grad dh)_e, so that
+// -div G = -div F + nu div grad dh and -grad B = -grad B + nu grad div u.
 template <typename T>
 __device__ __forceinline__ void body_edge_cell(int64_t id, const DevTables& tb, const double* __restrict__ dh,
-                                               const double* __restrict__ u, const T* __restrict__ qv, double g,
-                                               double H, T* __restrict__ B, double* __restrict__ F,
-                                               T* __restrict__ qe) {
-  T K = T(0);
+                                               const double* __restrict__ u, const T* __restrict__ qv,
+                                               const PhysParams& ph, T* __restrict__ B, double* __restrict__ F,
+                                               double* __restrict__ G, T* __restrict__ qe) {
+  T K = T(0), D = T(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     T ue = T(u[tb.c_e[6 * id + k]]);
     K += T(tb.c_ke[6 * id + k]) * ue * ue;
+    if (ph.nu != 0.0) D += T(tb.c_div[6 * id + k]) * ue;
   }
-  B[id] = T(g) * T(dh[id]) + K;
+  T b = T(ph.g) * T(dh[id]) + K;
+  if (ph.nu != 0.0) b -= T(ph.nu) * D;
+  B[id] = b;
   if (id >= tb.n_elem) return;
+  const double H = ph.H;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     int64_t e = 3 * id + d;
-    T he = T(0.5) * ((T(H) + T(dh[tb.e_c[2 * e]])) + (T(H) + T(dh[tb.e_c[2 * e + 1]])));
-    F[e] = double(he * T(u[e]));  // the mass flux is stored in double in both precisions
+    const double ha = dh[tb.e_c[2 * e]], hb = dh[tb.e_c[2 * e + 1]];
+    T he = T(0.5) * ((T(H) + T(ha)) + (T(H) + T(hb)));
+    const double f = double(he * T(u[e]));  // the mass flux is stored in double in both precisions
+    F[e] = f;
+    if (ph.nu != 0.0) G[e] = f - ph.nu * ((hb - ha) * tb.inv_d[e]);
     qe[e] = T(0.5) * (qv[tb.e_v[2 * e]] + qv[tb.e_v[2 * e + 1]]);
   }
 }
 
-// Q_e = sum over the perpendicular-flux stencil of w l'/d F' (q_e + q_e')/2
+// relative vorticity of triangle v (circulation / area)
+template <typename T>
+__device__ __forceinline__ T tri_curl(int64_t v, const DevTables& tb, const double* __restrict__ u) {
+  T z = T(0);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) z += T(tb.t_curl[3 * v + s]) * T(u[tb.t_e[3 * v + s]]);
+  return z;
+}
+
+// Q_e = sum over the perpendicular-flux stencil of w l'/d F' (q_e + q_e')/2.  Viscous form: plus
+// nu (grad^perp curl u)_e = nu (zeta_left - zeta_right) / l_e, the adjoint of the discrete curl
+// (so that -grad^perp curl dissipates enstrophy), with u the stage input.
 template <typename T>
 __device__ __forceinline__ void body_Q(int64_t e, const DevTables& tb, const double* __restrict__ F,
-                                       const T* __restrict__ qe, T* __restrict__ Q) {
+                                       const T* __restrict__ qe, T* __restrict__ Q, double nu,
+                                       const double* __restrict__ u) {
   T q0 = qe[e], s = T(0);
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
     int32_t ep = tb.ecp[10 * e + k];
     s += T(tb.wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
   }
+  if (nu != 0.0)
+    s += T(nu) * (tri_curl<T>(tb.e_v[2 * e], tb, u) - tri_curl<T>(tb.e_v[2 * e + 1], tb, u)) / T(tb.l_e[e]);
   Q[e] = s;
 }
 
@@ -190,12 +231,14 @@ __device__ __forceinline__ void rk_out(int64_t i, double k, const StagePtrs& p, 
 }
 
 // Tendencies at node id and its edges with the level's (possibly restricted) F, Q, B, zero at
-// inactive points, then the stage combination.
+// inactive points, then the stage combination.  F is the total mass flux (G of a viscous run);
+// adv != 0: the advection form, whose velocity does not change.
 template <typename T>
 __device__ __forceinline__ void body_tend_ml(int64_t id, const DevTables& tb, const uint8_t* __restrict__ na,
                                              const uint8_t* __restrict__ ea, const T* __restrict__ B,
                                              const double* __restrict__ F, const T* __restrict__ Q,
-                                             const StagePtrs& pdh, const StagePtrs& pu, const StageOut& c) {
+                                             const StagePtrs& pdh, const StagePtrs& pu, const StageOut& c,
+                                             int32_t adv) {
   double k = 0.0;
   if (na[id]) {
     double div = 0.0;
@@ -209,7 +252,7 @@ __device__ __forceinline__ void body_tend_ml(int64_t id, const DevTables& tb, co
   for (int d = 0; d < 3; ++d) {
     int64_t e = 3 * id + d;
     double ku = 0.0;
-    if (ea[e]) ku = double(-Q[e] - (B[tb.e_c[2 * e + 1]] - B[tb.e_c[2 * e]]) * T(tb.inv_d[e]));
+    if (ea[e] && !adv) ku = double(-Q[e] - (B[tb.e_c[2 * e + 1]] - B[tb.e_c[2 * e]]) * T(tb.inv_d[e]));
     rk_out(e, ku, pu, c);
   }
 }

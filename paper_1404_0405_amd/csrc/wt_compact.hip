@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "wt_alloc.hpp"
 #include "wt_compact.hpp"
 
 namespace wt {
@@ -108,16 +109,16 @@ void compact(const uint8_t* pred, int64_t n, WorkList& L, CompactScratch& sc, hi
   if (nchunk + 1 > sc.cap) {
     // the previous scratch may still be read by queued work of this stream
     HIPCHK(hipStreamSynchronize(s));
-    if (sc.cnt) HIPCHK(hipFree(sc.cnt));
-    if (sc.off) HIPCHK(hipFree(sc.off));
+    if (sc.cnt) HIPCHK(wt::dfree(sc.cnt));
+    if (sc.off) HIPCHK(wt::dfree(sc.off));
     sc.cap = nchunk + 1;
-    HIPCHK(hipMalloc(&sc.cnt, sc.cap * sizeof(int32_t)));
-    HIPCHK(hipMalloc(&sc.off, sc.cap * sizeof(int64_t)));
+    HIPCHK(wt::dmalloc(&sc.cnt, sc.cap * sizeof(int32_t)));
+    HIPCHK(wt::dmalloc(&sc.off, sc.cap * sizeof(int64_t)));
   }
   if (!L.idx || L.cap < n) {
-    if (L.idx) HIPCHK(hipFree(L.idx));
+    if (L.idx) HIPCHK(wt::dfree(L.idx));
     L.cap = n > 0 ? n : 1;
-    HIPCHK(hipMalloc(&L.idx, L.cap * sizeof(int32_t)));
+    HIPCHK(wt::dmalloc(&L.idx, L.cap * sizeof(int32_t)));
   }
   if (n == 0) {
     L.n = 0;
@@ -269,12 +270,12 @@ void CompactBatch::add(const uint8_t* pred, int64_t n, WorkList& L) {
     // the list may still be read by queued work: let it drain before freeing
     if (L.idx) {
       HIPCHK(hipDeviceSynchronize());
-      HIPCHK(hipFree(L.idx));
+      HIPCHK(wt::dfree(L.idx));
     }
     L.cap = n > 0 ? n : 1;
-    HIPCHK(hipMalloc(&L.idx, L.cap * sizeof(int32_t)));
+    HIPCHK(wt::dmalloc(&L.idx, L.cap * sizeof(int32_t)));
   }
-  if (!L.dn) HIPCHK(hipMalloc(&L.dn, sizeof(int64_t)));
+  if (!L.dn) HIPCHK(wt::dmalloc(&L.dn, sizeof(int64_t)));
   jobs.push_back(Job{pred, n, &L});
 }
 
@@ -293,11 +294,11 @@ void CompactBatch::run(hipStream_t s) {
     uploaded.clear();
     job_cap = std::max(njob, 64);
     chunk_cap = std::max<int64_t>(nchunk, 1024);
-    HIPCHK(hipMalloc(&d_jobs, job_cap * sizeof(CJob)));
+    HIPCHK(wt::dmalloc(&d_jobs, job_cap * sizeof(CJob)));
     HIPCHK(hipHostMalloc(&h_jobs, job_cap * sizeof(CJob), hipHostMallocDefault));
-    HIPCHK(hipMalloc(&d_cnt, chunk_cap * sizeof(int32_t)));
-    HIPCHK(hipMalloc(&d_off, chunk_cap * sizeof(int64_t)));
-    HIPCHK(hipMalloc(&d_tot, job_cap * sizeof(int64_t)));
+    HIPCHK(wt::dmalloc(&d_cnt, chunk_cap * sizeof(int32_t)));
+    HIPCHK(wt::dmalloc(&d_off, chunk_cap * sizeof(int64_t)));
+    HIPCHK(wt::dmalloc(&d_tot, job_cap * sizeof(int64_t)));
     HIPCHK(hipHostMalloc(&h_tot, job_cap * sizeof(int64_t), hipHostMallocDefault));
   }
   // the device keeps the job table of the last batch: an unchanged table (the usual case, the
@@ -338,7 +339,7 @@ void CompactBatch::run(hipStream_t s) {
 void CompactBatch::release() {
   void* dv[] = {d_jobs, d_cnt, d_off, d_tot};
   for (void* p : dv)
-    if (p) (void)hipFree(p);
+    if (p) (void)wt::dfree(p);
   if (h_jobs) (void)hipHostFree(h_jobs);
   if (h_tot) (void)hipHostFree(h_tot);
   d_jobs = nullptr;
@@ -352,14 +353,14 @@ void CompactBatch::release() {
 }
 
 void free_list(WorkList& L) {
-  if (L.idx) (void)hipFree(L.idx);
-  if (L.dn) (void)hipFree(L.dn);
+  if (L.idx) (void)wt::dfree(L.idx);
+  if (L.dn) (void)wt::dfree(L.dn);
   L = WorkList{};
 }
 
 void free_scratch(CompactScratch& sc) {
-  if (sc.cnt) (void)hipFree(sc.cnt);
-  if (sc.off) (void)hipFree(sc.off);
+  if (sc.cnt) (void)wt::dfree(sc.cnt);
+  if (sc.off) (void)wt::dfree(sc.off);
   sc = CompactScratch{};
 }
 

@@ -40,14 +40,25 @@ struct DevWork {
   void *qv = nullptr, *B = nullptr, *F = nullptr, *qe = nullptr;     // T-typed intermediates
   void* Q = nullptr;                           // T-typed qF^perp (multilevel path)
   double* c = nullptr;                         // fine divergence (multilevel path)
+  double* G = nullptr;                         // F - nu grad dh (viscous runs; the divergence and
+                                               // the flux restriction read it instead of F)
   double* ddh = nullptr;                       // tendency output buffers (test hook)
   double* du = nullptr;
   double* red = nullptr;                       // reduction scratch
 };
 
+// Physical constants and form of the equations a stage evaluates: gravity g, mean depth H,
+// viscosity nu of the dissipative form (Sec. 3.1; 0: inviscid) and adv != 0 for the advection
+// form (Sec. 6.1: the height carried by the fixed velocity, du/dt = 0).
 struct PhysParams {
-  double g, H;
+  double g, H, nu;
+  int32_t adv;
 };
+
+// The mass flux whose divergence a stage takes: F, or G = F - nu grad dh in the viscous form.
+inline double* total_flux(const DevWork& w, const PhysParams& p) {
+  return p.nu != 0.0 ? w.G : static_cast<double*>(w.F);
+}
 
 // Generic Runge-Kutta epilogue evaluated at every point after the tendency k:
 //   o1 = a1*y + b1*acc + c1*x + d1*k     (if o1 != null)

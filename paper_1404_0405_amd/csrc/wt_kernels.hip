@@ -5,6 +5,8 @@
 //   k_edge_cell  B_i = g dh_i + K_i at the node;  F_e = h_e u_e, q_e at its three edges
 //   k_tend       d(dh)/dt = -div F at the node, du/dt = -Q_e - grad B at the edges, fused
 //                with the Runge-Kutta stage combination (always in double)
+// The viscous form (Sec. 3.1) adds -nu div u to B, -nu grad dh to the flux whose divergence is
+// taken (G) and nu grad^perp curl u to Q; the advection form (Sec. 6.1) keeps u fixed.
 // The compute type T is double, or float for the single-precision tendency mode; the
 // divergence sum, the state and the stage combination are double in both.
 #include <hip/hip_runtime.h>
@@ -13,6 +15,7 @@
 #include <cstdio>
 #include <stdexcept>
 
+#include "wt_alloc.hpp"
 #include "wt_body.hpp"
 #include "wt_internal.hpp"
 #include "wt_lattice_dev.hpp"
@@ -47,15 +50,16 @@ __global__ __launch_bounds__(BS) void k_vertex(int64_t n_tri, const int32_t* __r
 template <typename T>
 __global__ __launch_bounds__(BS) void k_edge_cell(int64_t N, const int32_t* __restrict__ list, DevTables tb,
                                                   const double* __restrict__ dh, const double* __restrict__ u,
-                                                  const T* __restrict__ qv, double g, double H, T* __restrict__ B,
-                                                  double* __restrict__ F, T* __restrict__ qe) {
+                                                  const T* __restrict__ qv, PhysParams ph, T* __restrict__ B,
+                                                  double* __restrict__ F, double* __restrict__ G,
+                                                  T* __restrict__ qe) {
   int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= N) return;
   if (list) {
     id = list[id];
     if (id < 0) return;   // padding of a work list
   }
-  body_edge_cell<T>(id, tb, dh, u, qv, g, H, B, F, qe);
+  body_edge_cell<T>(id, tb, dh, u, qv, ph, B, F, G, qe);
 }
 
 __device__ __forceinline__ void rk_epilogue(int64_t i, double k, const StagePtrs& p,
@@ -86,8 +90,9 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
                                              const int32_t* __restrict__ ecp,
                                              const double* __restrict__ wl,
                                              const T* __restrict__ B, const double* __restrict__ F,
+                                             const double* __restrict__ G,
                                              const T* __restrict__ qe, StagePtrs pdh, StagePtrs pu,
-                                             StageOut c) {
+                                             StageOut c, DevTables tb, double nu, int32_t adv) {
   int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= N) return;
   if (list) {
@@ -96,12 +101,16 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
   }
   double div = 0.0;  // divergence sums stay in double in both precisions
 #pragma unroll
-  for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * F[c_e[6 * id + k]];
+  for (int k = 0; k < 6; ++k) div += c_div[6 * id + k] * G[c_e[6 * id + k]];
   rk_epilogue(id, -div, pdh, c);
   if (id >= n_elem) return;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     int64_t e = 3 * id + d;
+    if (adv) {
+      rk_epilogue(e, 0.0, pu, c);
+      continue;
+    }
     T q0 = qe[e];
     T Q = T(0);
 #pragma unroll
@@ -109,6 +118,8 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
       int32_t ep = ecp[10 * e + k];
       Q += T(wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
     }
+    if (nu != 0.0)
+      Q += T(nu) * (tri_curl<T>(tb.e_v[2 * e], tb, pu.x) - tri_curl<T>(tb.e_v[2 * e + 1], tb, pu.x)) / T(tb.l_e[e]);
     T gradB = (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * T(inv_d[e]);
     rk_epilogue(e, double(-Q - gradB), pu, c);
   }
@@ -155,8 +166,10 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
   T* qv = static_cast<T*>(w.qv);
   T* B = static_cast<T*>(w.B);
   double* F = static_cast<double*>(w.F);
+  double* G = total_flux(w, p);
   T* qe = static_cast<T*>(w.qe);
-  const bool use_lat = lat && lat->ok;
+  // the lattice kernel evaluates the inviscid rotating shallow-water form only
+  const bool use_lat = lat && lat->ok && p.nu == 0.0 && !p.adv;
   // table-driven kernels: the whole level, or only the rim left by the lattice tiles
   const int32_t* tl = use_lat ? lat->sup_tris : nullptr;
   const int32_t* el = use_lat ? lat->sup_elems : nullptr;
@@ -189,12 +202,12 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
   }
   {
     TimedLaunch tl_(tm, K_EDGE_CELL, s, double(ne) * (120.0 + 32.0 + 24.0 + 6.0 * sz));
-    k_edge_cell<T><<<grid(ne), bs, 0, s>>>(ne, el, t, sdh.x, su.x, qv, p.g, p.H, B, F, qe);
+    k_edge_cell<T><<<grid(ne), bs, 0, s>>>(ne, el, t, sdh.x, su.x, qv, p, B, F, G, qe);
   }
   {
     TimedLaunch tl_(tm, K_TEND, s, double(nr) * (480.0 + 24.0 + 4.0 * sz + 4.0 * e_dof));
-    k_tend<T><<<grid(nr), bs, 0, s>>>(nr, t.n_elem, rl, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl, B, F,
-                                      qe, sdh, su, c);
+    k_tend<T><<<grid(nr), bs, 0, s>>>(nr, t.n_elem, rl, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl, B, F, G,
+                                      qe, sdh, su, c, t, p.nu, p.adv);
   }
   HIPCHK(hipGetLastError());
   if (use_lat) {
@@ -217,8 +230,8 @@ static void intermediates_impl(const DevTables& t, DevWork& w, const PhysParams&
   if (nt)
     k_vertex<T><<<nblk(nt), BS, 0, s>>>(nt, tri_list, t, sdh.x, su.x, p.H, qv);
   if (ne)
-    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, elem_list, t, sdh.x, su.x, qv, p.g, p.H, static_cast<T*>(w.B),
-                                           static_cast<double*>(w.F), static_cast<T*>(w.qe));
+    k_edge_cell<T><<<nblk(ne), BS, 0, s>>>(ne, elem_list, t, sdh.x, su.x, qv, p, static_cast<T*>(w.B),
+                                           static_cast<double*>(w.F), total_flux(w, p), static_cast<T*>(w.qe));
   HIPCHK(hipGetLastError());
 }
 
@@ -341,7 +354,7 @@ void launch_diagnostics(const DevTables& t, DevWork& w, const PhysParams& p, hip
 template <typename X>
 static X* dev_upload(const std::vector<X>& v) {
   X* p = nullptr;
-  HIPCHK(hipMalloc(&p, v.size() * sizeof(X)));
+  HIPCHK(wt::dmalloc(&p, v.size() * sizeof(X)));
   HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
   return p;
 }
@@ -393,7 +406,7 @@ void free_tables(DevTables& t) {
   void* ps[] = {t.c_e, t.c_div, t.c_ke, t.e_c, t.e_v, t.inv_d, t.ecp, t.wl,
                 t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, t.A_i, t.l_e, t.d_e};
   for (void* p : ps)
-    if (p) (void)hipFree(p);
+    if (p) (void)wt::dfree(p);
   t = DevTables{};
 }
 

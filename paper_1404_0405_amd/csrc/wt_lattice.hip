@@ -18,6 +18,7 @@
 #include <string>
 #include <type_traits>
 
+#include "wt_alloc.hpp"
 #include "wt_lattice_dev.hpp"
 
 namespace wt {
@@ -426,7 +427,7 @@ void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const Sta
 void upload_lattice(const LatticeHost& h, DevLattice& d) {
   auto up = [](const auto& v, auto** p) {
     using X = typename std::remove_reference<decltype(v)>::type::value_type;
-    HIPCHK(hipMalloc(reinterpret_cast<void**>(p), v.size() * sizeof(X)));
+    HIPCHK(wt::dmalloc(reinterpret_cast<void**>(p), v.size() * sizeof(X)));
     HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
   };
   double* tab;
@@ -457,7 +458,7 @@ void upload_lattice(const LatticeHost& h, DevLattice& d) {
 void free_lattice(DevLattice& d) {
   const void* ps[] = {d.args.tab, d.args.tiles, d.rim, d.sup_elems, d.sup_tris};
   for (const void* p : ps)
-    if (p) (void)hipFree(const_cast<void*>(p));
+    if (p) (void)wt::dfree(const_cast<void*>(p));
   d = DevLattice{};
 }
 

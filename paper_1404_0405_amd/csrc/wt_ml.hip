@@ -9,6 +9,7 @@
 #include <stdexcept>
 #include <string>
 
+#include "wt_alloc.hpp"
 #include "wt_body.hpp"
 #include "wt_ml.hpp"
 
@@ -45,6 +46,7 @@ __global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* _
 // odd nodes / half-edges and interior edges of a pair in one launch (they do not read each
 // other's outputs; both read the even nodes written before): blocks [0, bo) take the coarse
 // edges, the rest the coarse triangles
+template <typename T>
 __global__ __launch_bounds__(BS) void k_prolong_odd_int(DevPair P, const uint8_t* __restrict__ naf,
                                                         const uint8_t* __restrict__ eaf,
                                                         const int32_t* __restrict__ e_v_c,
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(BS) void k_prolong_odd_int(DevPair P, const uint8_t
       e = le[e];
       if (e < 0) return;
     }
-    body_prolong_odd_pair(e, P, naf, eaf, e_v_c, uc, hf, uf);
+    body_prolong_odd_pair<T>(e, P, naf, eaf, e_v_c, uc, hf, uf);
   } else {
     int64_t t = int64_t(int(blockIdx.x) - bo) * BS + threadIdx.x;
     if (t >= nt) return;
@@ -67,28 +69,34 @@ __global__ __launch_bounds__(BS) void k_prolong_odd_int(DevPair P, const uint8_t
       t = lt[t];
       if (t < 0) return;
     }
-    body_prolong_int(t, P, eaf, uc, uf);
+    body_prolong_int<T>(t, P, eaf, uc, uf);
   }
 }
 
 void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
-                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s, Span ln, Span le,
-                Span lt) {
+                const double* hc, const double* uc, double* hf, double* uf, bool fp32, hipStream_t s, Span ln,
+                Span le, Span lt) {
   const int64_t nn = span_n(ln, P.Nc), ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
   if (nn) k_prolong_even<<<nb(nn), BS, 0, s>>>(P, naf, hc, hf, ln.idx, nn);
   const int bo = int(nb(ne)), bt = int(nb(nt));
-  if (bo + bt > 0)
-    k_prolong_odd_int<<<unsigned(bo + bt), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf, le.idx, ne, bo, lt.idx, nt);
+  if (bo + bt > 0) {
+    if (fp32)
+      k_prolong_odd_int<float><<<unsigned(bo + bt), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf, le.idx, ne, bo,
+                                                                lt.idx, nt);
+    else
+      k_prolong_odd_int<double><<<unsigned(bo + bt), BS, 0, s>>>(P, naf, eaf, tc.e_v, uc, hf, uf, le.idx, ne, bo,
+                                                                 lt.idx, nt);
+  }
   HIPCHK(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ Q, divergence, restriction
 template <typename T>
 __global__ __launch_bounds__(BS) void k_Q(int64_t E, DevTables tb, const double* __restrict__ F,
-                                          const T* __restrict__ qe, T* __restrict__ Q,
-                                          const int32_t* __restrict__ lst) {
+                                          const T* __restrict__ qe, T* __restrict__ Q, double nu,
+                                          const double* __restrict__ u, const int32_t* __restrict__ lst) {
   LISTED(e, E, lst)
-  body_Q<T>(e, tb, F, qe, Q);
+  body_Q<T>(e, tb, F, qe, Q, nu, u);
 }
 
 __global__ __launch_bounds__(BS) void k_div(int64_t N, DevTables tf, const double* __restrict__ F,
@@ -123,10 +131,10 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_tend_ml(int64_t N, DevTables tb, const uint8_t* __restrict__ na,
                                                 const uint8_t* __restrict__ ea, const T* __restrict__ B,
                                                 const double* __restrict__ F, const T* __restrict__ Q,
-                                                StagePtrs pdh, StagePtrs pu, StageOut c,
+                                                StagePtrs pdh, StagePtrs pu, StageOut c, int32_t adv,
                                                 const int32_t* __restrict__ lst) {
   LISTED(id, N, lst)
-  body_tend_ml<T>(id, tb, na, ea, B, F, Q, pdh, pu, c);
+  body_tend_ml<T>(id, tb, na, ea, B, F, Q, pdh, pu, c, adv);
 }
 
 template <typename T>
@@ -143,30 +151,31 @@ void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p,
   if (ne == 0) return;
   if (fp32)
     k_Q<float><<<nb(ne), BS, 0, s>>>(ne, t, static_cast<double*>(w.F), static_cast<float*>(w.qe),
-                                     static_cast<float*>(w.Q), led.idx);
+                                     static_cast<float*>(w.Q), p.nu, xu, led.idx);
   else
     k_Q<double><<<nb(ne), BS, 0, s>>>(ne, t, static_cast<double*>(w.F), static_cast<double*>(w.qe),
-                                      static_cast<double*>(w.Q), led.idx);
+                                      static_cast<double*>(w.Q), p.nu, xu, led.idx);
   HIPCHK(hipGetLastError());
 }
 
 void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, DevWork& wc, DevWork& wf,
-                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s, Span lfn, Span lce, Span lcn) {
+                 const uint8_t* naf, const uint8_t* eaf, const PhysParams& p, bool fp32, hipStream_t s, Span lfn,
+                 Span lce, Span lcn) {
   const int64_t nf = span_n(lfn, tf.N), ne = span_n(lce, P.Ec), nn = span_n(lcn, P.Nc);
+  double* Gf = total_flux(wf, p);
+  double* Gc = total_flux(wc, p);
   if (fp32) {
-    if (nf) k_div<<<nb(nf), BS, 0, s>>>(nf, tf, static_cast<double*>(wf.F), wf.c, lfn.idx);
+    if (nf) k_div<<<nb(nf), BS, 0, s>>>(nf, tf, Gf, wf.c, lfn.idx);
     if (ne)
-      k_restrict_edges<float><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
-                                                    static_cast<float*>(wf.Q), static_cast<double*>(wc.F),
+      k_restrict_edges<float><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, Gf, wf.c, static_cast<float*>(wf.Q), Gc,
                                                     static_cast<float*>(wc.Q), lce.idx, ne);
     if (nn)
       k_restrict_B<float><<<nb(nn), BS, 0, s>>>(P, naf, static_cast<float*>(wf.B), static_cast<float*>(wc.B),
                                                 lcn.idx, nn);
   } else {
-    if (nf) k_div<<<nb(nf), BS, 0, s>>>(nf, tf, static_cast<double*>(wf.F), wf.c, lfn.idx);
+    if (nf) k_div<<<nb(nf), BS, 0, s>>>(nf, tf, Gf, wf.c, lfn.idx);
     if (ne)
-      k_restrict_edges<double><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, static_cast<double*>(wf.F), wf.c,
-                                                     static_cast<double*>(wf.Q), static_cast<double*>(wc.F),
+      k_restrict_edges<double><<<nb(ne), BS, 0, s>>>(P, eaf, tf.l_e, tc.l_e, Gf, wf.c, static_cast<double*>(wf.Q), Gc,
                                                      static_cast<double*>(wc.Q), lce.idx, ne);
     if (nn)
       k_restrict_B<double><<<nb(nn), BS, 0, s>>>(P, naf, static_cast<double*>(wf.B), static_cast<double*>(wc.B),
@@ -175,18 +184,17 @@ void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, Dev
   HIPCHK(hipGetLastError());
 }
 
-void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, bool fp32,
+void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, const PhysParams& p, bool fp32,
              const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Span lel) {
   const int64_t n = span_n(lel, t.N);
   if (n == 0) return;
+  double* G = total_flux(w, p);
   if (fp32)
-    k_tend_ml<float><<<nb(n), BS, 0, s>>>(n, t, na, ea,
-                                          static_cast<float*>(w.B), static_cast<double*>(w.F),
-                                          static_cast<float*>(w.Q), sdh, su, c, lel.idx);
+    k_tend_ml<float><<<nb(n), BS, 0, s>>>(n, t, na, ea, static_cast<float*>(w.B), G, static_cast<float*>(w.Q), sdh,
+                                          su, c, p.adv, lel.idx);
   else
-    k_tend_ml<double><<<nb(n), BS, 0, s>>>(n, t, na, ea,
-                                           static_cast<double*>(w.B), static_cast<double*>(w.F),
-                                           static_cast<double*>(w.Q), sdh, su, c, lel.idx);
+    k_tend_ml<double><<<nb(n), BS, 0, s>>>(n, t, na, ea, static_cast<double*>(w.B), G, static_cast<double*>(w.Q),
+                                           sdh, su, c, p.adv, lel.idx);
   HIPCHK(hipGetLastError());
 }
 
@@ -454,16 +462,28 @@ void ml_patch_list_batch(const PatchJob* jobs, int njobs, hipStream_t s) {
 // both triangles) and R3 (children on the next level of significant coarse nodes -- fine copy,
 // its neighbours and incident fine edges -- and edges -- midpoint and the fine edges at it).
 // The mask rules only set bytes to 1, so jobs of one launch may write the same mask.
-__device__ __forceinline__ void op_det_edge(int64_t e, const MaskJob& j) {
+template <typename T>
+__device__ __forceinline__ void op_det_edge_t(int64_t e, const MaskJob& j) {
   const DevPair& P = j.P;
   j.dh[e] = h_detail(P, e, j.hf);
-  j.dp[e] = (j.uf[P.h1[e]] - j.uf[P.h2[e]]) - pair_pred(P, e, j.e_v, j.uc);
+  j.dp[e] = (j.uf[P.h1[e]] - j.uf[P.h2[e]]) - double(pair_pred<T>(P, e, j.e_v, j.uc));
+}
+
+template <typename T>
+__device__ __forceinline__ void op_det_int_t(int64_t t, const MaskJob& j) {
+  const DevPair& P = j.P;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) j.di[3 * t + s] = j.uf[P.int_e[3 * t + s]] - double(int_pred<T>(P, t, s, j.uc));
+}
+
+__device__ __forceinline__ void op_det_edge(int64_t e, const MaskJob& j) {
+  if (j.fp32) op_det_edge_t<float>(e, j);
+  else op_det_edge_t<double>(e, j);
 }
 
 __device__ __forceinline__ void op_det_int(int64_t t, const MaskJob& j) {
-  const DevPair& P = j.P;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) j.di[3 * t + s] = j.uf[P.int_e[3 * t + s]] - int_pred(P, t, s, j.uc);
+  if (j.fp32) op_det_int_t<float>(t, j);
+  else op_det_int_t<double>(t, j);
 }
 
 __device__ __forceinline__ void op_sig_edge(int64_t e, const MaskJob& j) {
@@ -643,9 +663,11 @@ void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s) {
 }
 
 void ml_details_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tc, const double* hf,
-                     const double* uf, const double* uc, double* dh, double* dp, double* di, Span le, Span lt) {
+                     const double* uf, const double* uc, double* dh, double* dp, double* di, bool fp32, Span le,
+                     Span lt) {
   MaskJob a{};
   a.P = P; a.e_v = tc.e_v; a.hf = hf; a.uf = uf; a.uc = uc; a.dh = dh; a.dp = dp; a.di = di;
+  a.fp32 = fp32 ? 1 : 0;
   a.op = MO_DET_EDGE; a.cnt = span_n(le, P.Ec); a.lst = le.idx;
   out.push_back(a);
   a.op = MO_DET_INT; a.cnt = span_n(lt, P.Tc); a.lst = lt.idx;
@@ -769,6 +791,7 @@ __device__ __forceinline__ void inv_even(int64_t k, const DevPair& P, const doub
   hf[P.even[k]] = s;
 }
 
+template <typename T>
 __device__ __forceinline__ void inv_int(int64_t t, const DevPair& P, const uint8_t* __restrict__ ea_old,
                                         const uint8_t* __restrict__ ea_new, const double* __restrict__ di,
                                         const double* __restrict__ uc, double* __restrict__ uf) {
@@ -776,12 +799,13 @@ __device__ __forceinline__ void inv_int(int64_t t, const DevPair& P, const uint8
   for (int s = 0; s < 3; ++s) {
     const int32_t f = P.int_e[3 * t + s];
     const bool keep = ea_old[f] && ea_new[f];
-    uf[f] = (keep ? di[3 * t + s] : 0.0) + int_pred(P, t, s, uc);
+    uf[f] = (keep ? di[3 * t + s] : 0.0) + double(int_pred<T>(P, t, s, uc));
   }
 }
 
 // even nodes (heights) and interior fine edges (velocities) of a pair in one launch: they do not
 // read each other's outputs; blocks [0, be) take the even nodes, the rest the coarse triangles
+template <typename T>
 __global__ __launch_bounds__(BS) void k_inv_even_int(DevPair P, const double* __restrict__ dk,
                                                      const double* __restrict__ hc, double* __restrict__ hf,
                                                      const int32_t* __restrict__ ln, int64_t nn, int be,
@@ -805,10 +829,11 @@ __global__ __launch_bounds__(BS) void k_inv_even_int(DevPair P, const double* __
       t = lt[t];
       if (t < 0) return;
     }
-    inv_int(t, P, ea_old, ea_new, di, uc, uf);
+    inv_int<T>(t, P, ea_old, ea_new, di, uc, uf);
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* __restrict__ e_v_c,
                                                      const uint8_t* __restrict__ ea_old,
                                                      const uint8_t* __restrict__ ea_new,
@@ -824,7 +849,7 @@ __global__ __launch_bounds__(BS) void k_inv_odd_pair(DevPair P, const int32_t* _
   hf[P.mid[e]] = s;
   int32_t h1 = P.h1[e], h2 = P.h2[e];
   bool keep = ea_old[h1] && ea_old[h2] && ea_new[h1] && ea_new[h2];
-  double half = 0.5 * (pair_pred(P, e, e_v_c, uc) + (keep ? dp[e] : 0.0));
+  const double half = 0.5 * (double(pair_pred<T>(P, e, e_v_c, uc)) + (keep ? dp[e] : 0.0));
   uf[h1] = uc[e] + half;
   uf[h2] = uc[e] - half;
 }
@@ -846,13 +871,21 @@ void ml_inverse_keep_batch(const KeepJob* jobs, int njobs, hipStream_t s) {
 
 void ml_inverse_pair(const DevPair& P, const DevTables& tc, const uint8_t* ea_old, const uint8_t* ea_new,
                      const double* dp, const double* di, const double* dk, const double* hc, const double* uc,
-                     double* hf, double* uf, hipStream_t s, Span ln, Span le, Span lt) {
+                     double* hf, double* uf, bool fp32, hipStream_t s, Span ln, Span le, Span lt) {
   const int64_t nn = span_n(ln, P.Nc), ne = span_n(le, P.Ec), nt = span_n(lt, P.Tc);
   const int be = int(nb(nn)), bt = int(nb(nt));
-  if (be + bt > 0)
-    k_inv_even_int<<<unsigned(be + bt), BS, 0, s>>>(P, dk, hc, hf, ln.idx, nn, be, ea_old, ea_new, di, uc, uf,
-                                                    lt.idx, nt);
-  if (ne) k_inv_odd_pair<<<nb(ne), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf, le.idx, ne);
+  if (fp32) {
+    if (be + bt > 0)
+      k_inv_even_int<float><<<unsigned(be + bt), BS, 0, s>>>(P, dk, hc, hf, ln.idx, nn, be, ea_old, ea_new, di, uc,
+                                                             uf, lt.idx, nt);
+    if (ne) k_inv_odd_pair<float><<<nb(ne), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf, le.idx, ne);
+  } else {
+    if (be + bt > 0)
+      k_inv_even_int<double><<<unsigned(be + bt), BS, 0, s>>>(P, dk, hc, hf, ln.idx, nn, be, ea_old, ea_new, di, uc,
+                                                              uf, lt.idx, nt);
+    if (ne)
+      k_inv_odd_pair<double><<<nb(ne), BS, 0, s>>>(P, tc.e_v, ea_old, ea_new, dk, dp, uc, hf, uf, le.idx, ne);
+  }
   HIPCHK(hipGetLastError());
 }
 
@@ -996,7 +1029,7 @@ void ml_count(int64_t n, const uint8_t* act, double* scratch, double* out, hipSt
 template <typename X>
 static const X* up(const std::vector<X>& v) {
   X* p = nullptr;
-  HIPCHK(hipMalloc(&p, v.size() * sizeof(X)));
+  HIPCHK(wt::dmalloc(&p, v.size() * sizeof(X)));
   HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
   return p;
 }
@@ -1013,7 +1046,7 @@ void free_pair(DevPair& d) {
   const void* ps[] = {d.even, d.mid, d.h1, d.h2, d.cells, d.mk, d.int_e, d.v_sten, d.rf_f, d.rf_c,
                       d.st, d.s_upd, d.w_int, d.w_pl, d.w_pr, d.rf_fw, d.rf_cw};
   for (const void* p : ps)
-    if (p) (void)hipFree(const_cast<void*>(p));
+    if (p) (void)wt::dfree(const_cast<void*>(p));
   d = DevPair{};
 }
 

@@ -29,16 +29,17 @@ void free_pair(DevPair& d);
 
 // Stage kernels take optional work lists (coarse nodes / edges / triangles of the pair; the
 // level's triangles, elements, edges; fine nodes): only listed entities are processed.
+// fp32: the predictions in single precision (stored in double)
 void ml_prolong(const DevPair& P, const DevTables& tc, const uint8_t* naf, const uint8_t* eaf,
-                const double* hc, const double* uc, double* hf, double* uf, hipStream_t s, Span ln = {},
-                Span le = {}, Span lt = {});
+                const double* hc, const double* uc, double* hf, double* uf, bool fp32, hipStream_t s,
+                Span ln = {}, Span le = {}, Span lt = {});
 void ml_level_intermediates(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
                             const double* xdh, const double* xu, hipStream_t s, Span ltri = {}, Span lel = {},
                             Span led = {});
 void ml_restrict(const DevPair& P, const DevTables& tc, const DevTables& tf, DevWork& wc, DevWork& wf,
-                 const uint8_t* naf, const uint8_t* eaf, bool fp32, hipStream_t s, Span lfn = {}, Span lce = {},
-                 Span lcn = {});
-void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, bool fp32,
+                 const uint8_t* naf, const uint8_t* eaf, const PhysParams& p, bool fp32, hipStream_t s,
+                 Span lfn = {}, Span lce = {}, Span lcn = {});
+void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* ea, const PhysParams& p, bool fp32,
              const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Span lel = {});
 void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, double* hc, double* uc,
                        hipStream_t s);
@@ -54,6 +55,7 @@ enum MaskOp : int32_t {
 struct MaskJob {
   int32_t op, nc;      // nc: coarse lozenge side of the R3 gate
   int32_t sparse;      // set by ml_mask_ops: scan a large rule job 16 points per lane
+  int32_t fp32;        // details: predictions in single precision
   int64_t cnt;         // entries: lst[0..cnt) (-1 padding skipped) or 0..cnt
   const int32_t* lst;
   DevPair P;
@@ -74,8 +76,8 @@ struct MaskJobs {
 };
 void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s);
 void ml_details_jobs(std::vector<MaskJob>& out, const DevPair& P, const DevTables& tc, const double* hf,
-                     const double* uf, const double* uc, double* dh, double* dp, double* di, Span le = {},
-                     Span lt = {});
+                     const double* uf, const double* uc, double* dh, double* dp, double* di, bool fp32,
+                     Span le = {}, Span lt = {});
 void ml_significant_jobs(std::vector<MaskJob>& out, const DevPair& P, const uint8_t* naf, const uint8_t* eaf,
                          const double* dh, const double* dp, const double* di, double eh, double eu, uint8_t* sn,
                          uint8_t* se, Span le = {}, Span lt = {});
@@ -108,7 +110,7 @@ struct KeepJobs {
 void ml_inverse_keep_batch(const KeepJob* jobs, int njobs, hipStream_t s);
 void ml_inverse_pair(const DevPair& P, const DevTables& tc, const uint8_t* ea_old, const uint8_t* ea_new,
                      const double* dp, const double* di, const double* dk, const double* hc, const double* uc,
-                     double* hf, double* uf, hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
+                     double* hf, double* uf, bool fp32, hipStream_t s, Span ln = {}, Span le = {}, Span lt = {});
 // Several levels' support rings or patch lists in one launch (blockIdx.y = level job).
 struct RingJob {
   int32_t N, sh, nblk;

@@ -6,8 +6,10 @@ loaded, ``load()`` raises: there is no fallback implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -17,6 +19,8 @@ LIB_PATH = os.path.join(PKG, "libwt.so")
 WT_OK, WT_EINVAL, WT_ENOMEM, WT_EDEVICE, WT_ESTATE, WT_ENUMERIC = 0, -1, -2, -3, -4, -5
 WT_RK4, WT_SSPRK43 = 0, 1
 WT_FP64, WT_FP32_TENDENCY = 0, 1
+WT_SWE, WT_ADVECTION = 0, 1
+WT_THR_RELATIVE, WT_THR_QG, WT_THR_IG = 0, 1, 2
 
 
 class WtError(RuntimeError):
@@ -27,13 +31,19 @@ class WtError(RuntimeError):
 
 class wt_params(C.Structure):
     _fields_ = [("radius", C.c_double), ("omega", C.c_double), ("gravity", C.c_double),
-                ("mean_depth", C.c_double), ("rk", C.c_int), ("precision", C.c_int)]
+                ("mean_depth", C.c_double), ("rk", C.c_int), ("precision", C.c_int),
+                ("viscosity", C.c_double), ("equations", C.c_int), ("threshold", C.c_int),
+                ("scale_u", C.c_double), ("scale_l", C.c_double), ("scale_f", C.c_double)]
 
 
 class wt_diag(C.Structure):
     _fields_ = [("mass", C.c_double), ("mass_reconstructed", C.c_double), ("energy", C.c_double), ("max_abs_dh", C.c_double),
                 ("max_abs_u", C.c_double), ("active_nodes", C.c_int64 * 16),
-                ("active_edges", C.c_int64 * 16)]
+                ("active_edges", C.c_int64 * 16), ("finest_level", C.c_int32), ("pad_", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 _P = C.c_void_p
@@ -64,6 +74,8 @@ SIGNATURES = [
     ("wt_diagnostics", C.c_int, [_P, C.POINTER(wt_diag)]),
     ("wt_suggest_dt", C.c_double, [_P, C.c_double]),
     ("wt_set_stream", C.c_int, [_P, _P]),
+    ("wt_set_allocator", C.c_int, [_P, ALLOC_FN, FREE_FN, _P]),
+    ("wt_alloc_stats", C.c_int, [_P, _I64, _I64, _I64, _I64]),
     ("wt_timing_enable", C.c_int, [_P, C.c_int]),
     ("wt_timing_reset", C.c_int, [_P]),
     ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64, _D]),
@@ -122,6 +134,66 @@ def load():
             f.argtypes = args
         _lib = lib
     return _lib
+
+
+# Objects that own library handles, closed in reverse creation order when the interpreter exits:
+# grids, ensembles and networks release their device memory and streams while the HIP runtime is
+# still fully alive, instead of in whatever order garbage collection reaches them at shutdown.
+_LIVE = weakref.WeakValueDictionary()
+_LIVE_SEQ = [0]
+
+
+def _register(obj):
+    _LIVE_SEQ[0] += 1
+    _LIVE[_LIVE_SEQ[0]] = obj
+
+
+@atexit.register
+def _close_all():
+    for k in sorted(list(_LIVE.keys()), reverse=True):
+        obj = _LIVE.get(k)
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
+    if _lib is not None:
+        try:
+            _lib.wt_table_cache_clear()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- device allocator hook
+_ALLOC_HOOK = None   # (alloc, free) ctypes callbacks kept alive while the library may call them
+
+
+def use_torch_allocator(grid=None):
+    """Route the device buffers of `grid` (None: of every grid created afterwards) through
+    PyTorch's caching allocator (wt_set_allocator)."""
+    global _ALLOC_HOOK
+    import torch
+
+    if _ALLOC_HOOK is None:
+        dev = torch.cuda.current_device()
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        _ALLOC_HOOK = (ALLOC_FN(_alloc), FREE_FN(_free))
+    a, f = _ALLOC_HOOK
+    _check(load().wt_set_allocator(grid._h if grid is not None else None, a, f, None))
+
+
+def use_hip_allocator(grid=None):
+    """Back to hipMalloc for later allocations of `grid` (None: of grids created afterwards)."""
+    _check(load().wt_set_allocator(grid._h if grid is not None else None, ALLOC_FN(), FREE_FN(), None))
 
 
 def _ptr(a, ct):
@@ -190,6 +262,7 @@ class Grid:
             raise WtError(WT_EDEVICE, lib.wt_last_error().decode())
         self._h = h
         self.jmin, self.jmax, self.patch = jmin, jmax, patch
+        _register(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -297,6 +370,12 @@ class Grid:
     def set_stream(self, stream_handle):
         _check(load().wt_set_stream(self._h, C.c_void_p(stream_handle) if stream_handle else None))
 
+    def alloc_stats(self):
+        """Live device buffers of the grid: (count, bytes) from the allocator hook and from hipMalloc."""
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().wt_alloc_stats(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"hook": (a.value, b.value), "direct": (c.value, d.value)}
+
     def timing(self, enable=True):
         _check(load().wt_timing_enable(self._h, 1 if enable else 0))
 
@@ -374,6 +453,7 @@ class Mlp:
         if not h:
             raise WtError(WT_EDEVICE, lib.wt_last_error().decode())
         self._h = h
+        _register(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -431,6 +511,7 @@ class Ensemble:
         if not h:
             raise WtError(WT_EINVAL, lib.wt_last_error().decode())
         self._h = h
+        _register(self)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -167,3 +167,44 @@ def test_ensemble_graph_follows_parameter_changes():
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
         g.close()
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_ensemble_members_against_the_oracle(batched):
+    """Every FP64 member of a 3-member ensemble (uneven levels 2..4 / 2..5, different bumps and
+    thresholds; graph or batched step) against the oracle hierarchy stepped alone: masks
+    identical and states within 1e-11 after 6 rounds of adapt + step."""
+    from oracle import trisk
+    from oracle.multiscale import Hierarchy
+    params = inputs.ensemble_members(3, jmax_choices=(4, 5))
+    _say(f"oracle members {[(p['jmax'], p['eps']) for p in params]} batched={batched}")
+    grids, hier, dts = [], [], []
+    for p in params:
+        g = _member(p, jmin=2)
+        H = Hierarchy(2, p["jmax"])
+        og = H.g[p["jmax"]]
+        dh, u, Hd = inputs.jet(og.xyz, og.e_mid, og.e_tan, bump=p["bump"], bump_lat=p["bump_lat"],
+                               bump_lon=p["bump_lon"])
+        H.set_state(p["jmax"], dh, u)
+        grids.append(g)
+        hier.append((H, trisk.Params(mean_depth=Hd)))
+        dts.append(g.suggest_dt(0.8))
+    with wt.Ensemble(grids) as ens:
+        if batched:
+            ens.set_batched(True)
+        for _ in range(6):
+            ens.adapt([p["eps"] for p in params])
+            ens.step(dts)
+            for (H, op), p, dt in zip(hier, params, dts):
+                H.adapt(p["eps"])
+                H.step(dt, op)
+    worst = 0.0
+    for g, (H, _) in zip(grids, hier):
+        for j in H.levels:
+            a, b, na, ea = H.get_state(j)
+            x, y, gna, gea = g.get_state(j)
+            assert np.array_equal(gna.astype(bool), na) and np.array_equal(gea.astype(bool), ea), j
+            worst = max(worst, np.abs(x - a).max() / np.abs(a).max(), np.abs(y - b).max() / np.abs(b).max())
+        g.close()
+    _say(f"worst rel Linf against the oracle {worst:.2e}")
+    assert worst < 1e-11

@@ -271,7 +271,9 @@ def test_trained_predictor_against_plain_zone():
     err = np.sqrt(((hl - hp) ** 2).sum() / ((hp + 1e4) ** 2).sum())
     _say(f"active dof plain {p['act']:.0f}, learned {lrn['act']:.0f} ({lrn['act'] / p['act']:.3f}); "
          f"redo {lrn['redo']}/{nsteps}; rel L2 height vs plain {err:.2e}")
-    assert lrn["act"] <= p["act"]
+    # no gate judged by the threshold test can drop more than the few quadrants that lose their
+    # significance within one step (oracle bound on this jet: 1e-4 of the active dof)
+    assert (1.0 - 0.01) * p["act"] <= lrn["act"] <= p["act"]
     assert lrn["redo"] <= nsteps // 2
     assert err < 1e-4
     m0, m1 = lrn["mass"]
@@ -300,3 +302,69 @@ def test_learned_zone_over_work_lists_equals_whole_levels():
     for a, b in zip(sa, sb):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("min_count", [2, 5])
+def test_learned_zone_against_the_oracle(min_count):
+    """The learned zone on the jet (levels 4..7, eps 5e-3) with a network that proposes a
+    quadrant's children only where it holds at least `min_count` significant points (weights and
+    activations exact in bfloat16, so both sides take the same decisions), against the oracle's
+    learned zone (oracle/learned.py): after every passing threshold test the patch features the
+    next gated adapt reads agree, and after every round of adapt + step + threshold test the masks
+    are identical, the states within 1e-11 and the redo counts equal."""
+    import torch
+    from oracle import learned, trisk
+    from oracle.multiscale import Hierarchy
+    from test_oracle_learned import gate_params
+    jmin, jmax, eps, nsteps = 4, 7, 5e-3, 6
+    _say(f"learned zone vs oracle, min_count={min_count}")
+    theta = gate_params(min_count)
+    H = Hierarchy(jmin, jmax)
+    og = H.g[jmax]
+    dh, u, Hd = inputs.jet(og.xyz, og.e_mid, og.e_tan)
+    p = trisk.Params(mean_depth=Hd)
+    H.set_state(jmax, dh, u)
+    dt = 0.8 * trisk.suggest_dt(og, dh, u, p, 1.0)
+    g = wt.Grid(jmin, jmax, 8)
+    m = wt.Mlp(theta.astype(np.float32))
+    redo_o = 0
+    with g:
+        g.set_params(mean_depth=Hd)
+        g.set_state(jmax, dh, u)
+        # round 0 with the blanket zone, so the gate sees a developed significant set
+        g.adapt(eps)
+        g.step(dt)
+        H.adapt(eps)
+        H.step(dt, p)
+        g.set_predictor(m, 0.5)
+        redone, compared = True, 0
+        for k in range(nsteps):
+            if not redone:
+                # after a passing threshold test both sides hold the details, thresholds and
+                # significant points the next gated adapt uses: its features must agree
+                det = H.details()
+                eh, eu = H.thresholds(eps)
+                sn, se = H.significant(det, eh, eu)
+                for j, st in learned.all_stats(H, det, eh, eu, sn, se).items():
+                    x = torch.empty((g.patch_count(j), 64), dtype=torch.float32, device="cuda")
+                    g.patch_features(j, x)
+                    err = np.abs(x.cpu().numpy() - learned.features(H, j, st)).max()
+                    _say(f"  round {k} level {j}: max |feature diff| {err:.1e}")
+                    assert err < 1e-6
+                    compared += 1
+            g.adapt(eps)
+            g.step(dt)
+            redone, dropped, _ = learned.learned_step(H, eps, dt, p, theta, 0.5)
+            redo_o += int(redone)
+            nd = sum(int(d.sum()) for d in dropped.values())
+            w = 0.0
+            for j in H.levels:
+                a, b, na, ea = H.get_state(j)
+                x, y, gna, gea = g.get_state(j)
+                assert np.array_equal(gna.astype(bool), na) and np.array_equal(gea.astype(bool), ea), (k, j)
+                w = max(w, np.abs(x - a).max() / np.abs(a).max(), np.abs(y - b).max() / np.abs(b).max())
+            _say(f"  round {k}: dropped quadrants {nd}, redone {redone}, GPU redo {g.redo_count()}, rel Linf {w:.1e}")
+            assert w < 1e-11
+            assert g.redo_count() == redo_o
+    m.close()
+    _say(f"  feature comparisons {compared}, redo {redo_o}/{nsteps}")

@@ -27,8 +27,47 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+def _emulated_forward(th, X, flips=()):
+    """The network with bfloat16 operands (oracle.mlp), returning the probabilities and the
+    hidden activations before their bfloat16 rounding; `flips` = ((layer, sample, unit), ...)
+    rounds those activations to the other neighbouring bfloat16 value instead."""
+    W1, b1, W2, b2, W3, b3 = omlp.unpack(th)
+    bf = omlp.bf16
+
+    def other(v):
+        """the neighbouring bfloat16 value on the other side of v from its rounding"""
+        r = bf(v)
+        step = np.abs(bf(np.float32(r) * np.float32(1 + 2 ** -7)) - r)
+        return r - step if r > v else r + step
+
+    def rnd(h, layer):
+        r = bf(h)
+        for (ly, i, k) in flips:
+            if ly == layer:
+                r[i, k] = other(h[i, k])
+        return r
+
+    a1 = np.maximum(bf(X) @ bf(W1) + b1, 0.0)
+    a2 = np.maximum(rnd(a1, 1) @ bf(W2) + b2, 0.0)
+    z = rnd(a2, 2) @ bf(W3) + b3
+    return omlp.sigmoid(z), a1, a2
+
+
+def _tie_margin(h):
+    """How far a non-negative activation lies from a bfloat16 rounding midpoint, relative to
+    its bfloat16 spacing (0: on the midpoint, 0.5: exactly representable)."""
+    f = np.asarray(h, np.float32).view(np.uint32).astype(np.int64)
+    low = f & 0xFFFF
+    return np.where(h > 0, np.abs(low - 0x8000) / 65536.0, 0.5)
+
+
 @pytest.mark.parametrize("n", [1, 16, 17, 100, 1000])
 def test_forward_matches_oracle(n):
+    """Probabilities within 1e-6 of the bfloat16-emulating oracle, except samples where a hidden
+    activation lies so close to a bfloat16 rounding midpoint that the GPU's FP32 sum (other
+    summation order) rounds it to the other neighbour: for every such sample, rounding one (or
+    two) of its nearest-to-midpoint activations the other way in the oracle reproduces the GPU's
+    output within 1e-6."""
     import torch
     _say(f"forward n={n}")
     theta = inputs.mlp_init()
@@ -40,11 +79,24 @@ def test_forward_matches_oracle(n):
         torch.cuda.synchronize()
         got = p.cpu().numpy().astype(np.float64)
     th = theta.astype(np.float64)
-    z_e, _ = omlp.forward(th, X.astype(np.float64), emulate_bf16=True)
-    z_x, _ = omlp.forward(th, X.astype(np.float64))
-    pe, px = omlp.sigmoid(z_e), omlp.sigmoid(z_x)
-    _say(f"max |p - p_bf16emul| {np.abs(got - pe).max():.2e}, max |p - p_fp64| {np.abs(got - px).max():.2e}")
-    assert np.abs(got - pe).max() < 2e-3
+    pe, a1, a2 = _emulated_forward(th, X.astype(np.float64))
+    px = omlp.sigmoid(omlp.forward(th, X.astype(np.float64))[0])
+    diff = np.abs(got - pe).max(1)
+    bad = np.nonzero(diff > 1e-6)[0]
+    _say(f"max |p - p_bf16emul| {diff.max():.2e} ({bad.size} of {n} samples above 1e-6), "
+         f"max |p - p_fp64| {np.abs(got - px).max():.2e}")
+    for i in bad:
+        # candidates: the 6 activations of the sample nearest to a rounding midpoint
+        cand = sorted([(float(_tie_margin(a1[i, k])), 1, k) for k in range(a1.shape[1])] +
+                      [(float(_tie_margin(a2[i, k])), 2, k) for k in range(a2.shape[1])])[:6]
+        trials = [((ly, i, k),) for _, ly, k in cand]
+        trials += [((c[1], i, c[2]), (d[1], i, d[2])) for a, c in enumerate(cand) for d in cand[a + 1:]]
+        best = min(np.abs(_emulated_forward(th, X[i:i + 1].astype(np.float64),
+                                            [(ly, 0, k) for ly, _, k in t])[0] - got[i]).max() for t in trials)
+        _say(f"  sample {i}: diff {diff[i]:.2e}, nearest midpoint margin {cand[0][0]:.1e}, "
+             f"explained by a flipped rounding to {best:.1e}")
+        assert best < 1e-6, (i, diff[i], best)
+    assert bad.size <= max(1, n // 50)
     assert np.abs(got - px).max() < 3e-2
 
 
@@ -66,14 +118,16 @@ def test_gradient_matches_oracle(n):
     cos = float(g @ gx / (np.linalg.norm(g) * np.linalg.norm(gx)))
     _say(f"grad rel err vs bf16-emulating oracle {rel_e:.2e}, vs FP64 oracle {rel_x:.2e}, cos {cos:.6f}; "
          f"loss {loss:.6f} vs {le:.6f}")
-    assert rel_e < 1e-2
     assert rel_x < 5e-2 and cos > 0.998
-    assert loss == pytest.approx(le, rel=1e-4)
-    # every block of the parameter vector is covered
+    assert loss == pytest.approx(le, rel=1e-5)
+    # element by element, within 1e-5 of each parameter block's largest gradient entry
     offs = np.cumsum([0] + [int(np.prod(s)) for s in omlp.SHAPES])
     for k in range(6):
         a, b = g[offs[k]:offs[k + 1]], ge[offs[k]:offs[k + 1]]
-        assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-12, k
+        worst = np.abs(a - b).max() / np.abs(b).max()
+        _say(f"  block {k}: max |g - g_oracle| / max |g_oracle| = {worst:.1e}")
+        assert worst < 1e-5, k
+    assert rel_e < 1e-5
 
 
 def test_adam_step_matches_oracle():
