@@ -334,6 +334,17 @@ int wt_mlp_forward(wt_mlp* m, const float* x_device, int64_t n, float* p_device)
  * (may be NULL) and the loss into *loss (may be NULL); no update.  Synchronises. */
 int wt_mlp_gradient(wt_mlp* m, const float* x_device, const float* y_device, int64_t n,
                     float* grad_host, double* loss);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the gradient of wt_mlp_gradient, bitwise, without any
+ * allocation and without synchronising.  grad_device[WT_MLP_PARAMS + 1] (device memory) receives
+ * the gradient and, in its last entry, the loss summed over samples and outputs (the mean loss
+ * is that / (4 n)).  At most 1024 samples per call (WT_EINVAL beyond).  The per-tile partial
+ * sums live in a 6.6 MB scratch array that the library holds on every GPU it has run on until
+ * the process ends; every call on a GPU uses that GPU's one array, so calls that overlap on one
+ * GPU (on different streams or host threads) race and must be serialised by the caller.
+ * Asynchronous on the network's stream. */
+int wt_mlp_gradient_noalloc(wt_mlp* m, const float* x_device, const float* y_device, int64_t n,
+                            float* grad_device);
 /* One Adam step with learning rate lr on the batch (x, y); *loss (may be NULL) receives the
  * loss before the step, which synchronises; with loss NULL the call is asynchronous. */
 int wt_mlp_train_step(wt_mlp* m, const float* x_device, const float* y_device, int64_t n, double lr,

@@ -11,6 +11,8 @@
 // (deterministic, no atomics), then one Adam step updates the master weights.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <cstdint>
 #include <stdexcept>
@@ -358,6 +360,38 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, float* __r
   th[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + 1e-8f);
 }
 
+// ------------------------------------------------------------------ allocation-free gradient
+// Scratch of wt_mlp_gradient_noalloc: the per-tile contributions and group sums of up to
+// MLP_NOALLOC_MAX samples in a file-scope device array (6.6 MB per GPU, held until the process
+// ends).  Host code never passes the array's name to a kernel (in host code it is only a stand-in
+// for the symbol): its device address is looked up once per device with hipGetSymbolAddress and
+// that address is used instead.
+static __device__ __align__(256) float scratch[(MLP_NOALLOC_MAX / 16 + (MLP_NOALLOC_MAX / 16 + SUM_GROUP - 1) / SUM_GROUP) *
+                                             (MLP_NP + 1)];
+static_assert(MLP_NOALLOC_MAX % 16 == 0, "whole tiles");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+float* noalloc_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw std::runtime_error("noalloc scratch: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    float* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch)));
+    if (!ptr) throw std::runtime_error("noalloc scratch: no device address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+int64_t noalloc_scratch_floats() { return int64_t(sizeof(scratch) / sizeof(float)); }
+
 // ------------------------------------------------------------------ host side
 void MlpDev::alloc() {
   HIPCHK(hipMalloc(&theta, MLP_NP * sizeof(float)));
@@ -391,22 +425,33 @@ void MlpDev::forward(const float* X, int64_t n, float* P, hipStream_t s) const {
   HIPCHK(hipGetLastError());
 }
 
+int64_t grad_scratch_floats(int64_t n) {
+  // tile contributions, then one row per group of tiles
+  const int64_t tiles = (n + 15) / 16;
+  return (tiles + (tiles + SUM_GROUP - 1) / SUM_GROUP) * (MLP_NP + 1);
+}
+
+void MlpDev::gradient_into(const float* X, const float* Y, int64_t n, float* scratch, float* out,
+                           hipStream_t s) const {
+  const int64_t tiles = (n + 15) / 16;
+  // every entry of the scratch rows is written before it is read: no clearing
+  k_grad_tiles<<<unsigned((tiles + WAVES - 1) / WAVES), TPB, 0, s>>>(X, Y, n, theta, frag, scratch);
+  // group sums go to their own rows after the tile rows
+  const int64_t groups = (tiles + SUM_GROUP - 1) / SUM_GROUP;
+  float* gsum = scratch + tiles * (MLP_NP + 1);
+  k_sum_tiles<<<dim3((MLP_NP + 1 + 255) / 256, unsigned(groups)), 256, 0, s>>>(scratch, tiles, gsum);
+  k_sum_tiles<<<dim3((MLP_NP + 1 + 255) / 256, 1), 256, 0, s>>>(gsum, groups, out);
+  HIPCHK(hipGetLastError());
+}
+
 void MlpDev::gradient(const float* X, const float* Y, int64_t n, hipStream_t s) {
   const int64_t tiles = (n + 15) / 16;
   if (tiles > part_tiles) {
     if (part) HIPCHK(hipFree(part));
-    // tile contributions, then one row per group of tiles
-    const int64_t rows = tiles + (tiles + SUM_GROUP - 1) / SUM_GROUP;
-    HIPCHK(hipMalloc(&part, rows * (MLP_NP + 1) * sizeof(float)));
+    HIPCHK(hipMalloc(&part, grad_scratch_floats(n) * sizeof(float)));
     part_tiles = tiles;
   }
-  k_grad_tiles<<<unsigned((tiles + WAVES - 1) / WAVES), TPB, 0, s>>>(X, Y, n, theta, frag, part);
-  // group sums go to their own rows after the tile rows
-  const int64_t groups = (tiles + SUM_GROUP - 1) / SUM_GROUP;
-  float* gsum = part + tiles * (MLP_NP + 1);
-  k_sum_tiles<<<dim3((MLP_NP + 1 + 255) / 256, unsigned(groups)), 256, 0, s>>>(part, tiles, gsum);
-  k_sum_tiles<<<dim3((MLP_NP + 1 + 255) / 256, 1), 256, 0, s>>>(gsum, groups, grad);
-  HIPCHK(hipGetLastError());
+  gradient_into(X, Y, n, part, grad, s);
 }
 
 void MlpDev::adam(double lr, hipStream_t s) {

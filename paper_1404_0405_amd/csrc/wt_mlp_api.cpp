@@ -47,6 +47,7 @@ wt_mlp* wt_mlp_create(const float* params_host) {
     HIPCHK(hipMemcpy(m->dev.theta, params_host, wt::MLP_NP * sizeof(float), hipMemcpyHostToDevice));
     m->dev.pack(m->stream);
     HIPCHK(hipStreamSynchronize(m->stream));
+    (void)wt::noalloc_scratch();   // set-up of the allocation-free gradient on this device
   } catch (const std::exception& e) {
     wt::api_fail(WT_EDEVICE, std::string("wt_mlp_create: ") + e.what());
     m->dev.release();
@@ -103,6 +104,22 @@ int wt_mlp_gradient(wt_mlp* m, const float* x, const float* y, int64_t n, float*
     if (loss) *loss = double(g[wt::MLP_NP]) / (double(n) * wt::MLP_NO);
   } catch (const std::exception& e) {
     return wt::api_fail(WT_EDEVICE, std::string("wt_mlp_gradient: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_mlp_gradient_noalloc(wt_mlp* m, const float* x, const float* y, int64_t n, float* grad_device) {
+  if (!m || n <= 0 || !x || !y || !grad_device) return wt::api_fail(WT_EINVAL, "wt_mlp_gradient_noalloc: bad argument");
+  if (n > wt::MLP_NOALLOC_MAX)
+    return wt::api_fail(WT_EINVAL, "wt_mlp_gradient_noalloc: at most " + std::to_string(wt::MLP_NOALLOC_MAX) +
+                                       " samples per call");
+  try {
+    float* scr = wt::noalloc_scratch();
+    if (wt::grad_scratch_floats(n) > wt::noalloc_scratch_floats())
+      throw std::runtime_error("scratch array smaller than the sample bound");
+    m->dev.gradient_into(x, y, n, scr, grad_device, m->stream);
+  } catch (const std::exception& e) {
+    return wt::api_fail(WT_EDEVICE, std::string("wt_mlp_gradient_noalloc: ") + e.what());
   }
   return WT_OK;
 }

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("wt_mlp_forward", C.c_int, [_P, _P, C.c_int64, _P]),
     ("wt_mlp_gradient", C.c_int, [_P, _P, _P, C.c_int64, _F, _D]),
     ("wt_mlp_train_step", C.c_int, [_P, _P, _P, C.c_int64, C.c_double, _D]),
+    ("wt_mlp_gradient_noalloc", C.c_int, [_P, _P, _P, C.c_int64, _P]),
     ("wt_patch_count", C.c_int64, [_P, C.c_int]),
     ("wt_patch_features", C.c_int, [_P, C.c_int, _P]),
     ("wt_patch_labels", C.c_int, [_P, C.c_int, _P]),
@@ -490,6 +491,17 @@ class Mlp:
                                       _dev_ptr(y, "float32", (MLP_OUTPUTS,)), x.shape[0], _ptr(g, C.c_float),
                                       C.byref(loss)))
         return g, loss.value
+
+    def gradient_noalloc(self, x, y, out):
+        """Gradient and loss sum into the float32 CUDA tensor out[MLP_PARAMS + 1] without any
+        device allocation (at most 1024 samples); asynchronous on the network's stream."""
+        import torch
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.is_contiguous()
+                and out.dtype == torch.float32 and out.numel() == MLP_PARAMS + 1):
+            raise ValueError("out must be a contiguous float32 CUDA tensor of MLP_PARAMS + 1 entries")
+        _check(load().wt_mlp_gradient_noalloc(self._h, _dev_ptr(x, "float32", (MLP_INPUTS,)),
+                                              _dev_ptr(y, "float32", (MLP_OUTPUTS,)), x.shape[0],
+                                              C.c_void_p(out.data_ptr())))
 
     def train_step(self, x, y, lr, want_loss=True):
         loss = C.c_double()
