@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "trisk_lattice": {
         "sources": ("paper_1404_0405_amd/csrc/wt_lattice.hip", "paper_1404_0405_amd/csrc/wt_lattice_dev.hpp"),
-        "sha256": ("e40cb0f7a89d2560bfeccc6eb813884e92b3e2a75b98192730198251dd98fb2b",
+        "sha256": ("ec08c740b852bed348b84f672177da9d9175b7af9d65d3b0021e82b171777206",
                    "67492eda7ad1558bc8dfcf39ef6757221c2ebd22ca59db129d4cf93d8c38dd94"),
-        "level": 10, "fetch_kib": 673244.5, "write_kib": 572320.7, "fetch_scale": 2.000, "write_scale": 1.000,
+        "level": 10, "fetch_kib": 673320.1, "write_kib": 572320.5, "fetch_scale": 2.000, "write_scale": 1.000,
     },
 }
 
@@ -100,7 +100,7 @@ def run_gpu(args):
             avg_ms = ms / cnt
             avg_b = by / cnt
             kernels[k] = {"avg_ms": avg_ms, "launches": cnt, "algorithmic_bytes": avg_b,
-                          "gbs": avg_b / (avg_ms * 1e-3) / 1e9}
+                          "gbs": avg_b / (avg_ms * 1e-3) / 1e9, "units": wt.kernel_units(g, k)}
         out[mode] = dict(value=upd, ms_per_step=wall * 1e3 / args.steps, kernels=kernels,
                          mass_drift=abs(d1.mass / d0.mass - 1), energy_drift=abs(d1.energy / d0.energy - 1),
                          finite=code == wt.WT_OK)
@@ -124,12 +124,50 @@ def run_gpu(args):
             state32 = g.get_state(J)[:2]
     # error of the FP32-tendency run against the FP64 run (same steps)
     if "fp64" in out and "fp32" in out:
-        dh64, _ = state64
-        dh32, _ = state32
-        out["fp32"]["rel_l2_height_vs_fp64"] = float(
-            np.sqrt(((dh32 - dh64) ** 2).sum() / ((H + dh64) ** 2).sum()))
+        out["fp32"].update(_errors(state32, state64, H))
     g.close()
     return out, (N, E, T), dt
+
+
+def _progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _errors(st, ref, H):
+    """Relative L2 differences of a state (dh, u) from a reference: the height perturbation,
+    the height against the total depth H + dh, and the velocity."""
+    import numpy as np
+    (a, u), (b, v) = st, ref
+    return {"rel_l2_dh_vs_fp64": float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum())),
+            "rel_l2_height_vs_fp64": float(np.sqrt(((a - b) ** 2).sum() / ((H + b) ** 2).sum())),
+            "rel_l2_u_vs_fp64": float(np.sqrt(((u - v) ** 2).sum() / (v ** 2).sum()))}
+
+
+def _timed_adaptive(g, eps, dt, steps, jmin, jmax):
+    """adapt + step timed together (threshold test and redo included), active dof of each step."""
+    import torch
+    from paper_1404_0405_amd import wt
+    d0, _ = g.diagnostics()
+    active, wall, wall_adapt = 0, 0.0, 0.0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.adapt(eps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.step(dt)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        wall_adapt += t1 - t0
+        d, _ = g.diagnostics()    # untimed: active counts of the mask the step used
+        active += sum(d.active_nodes) + sum(d.active_edges)
+    d1, code = g.diagnostics()
+    return {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / steps, "ms_adapt_per_step": wall_adapt * 1e3 / steps,
+            "active_dof_per_step": active / steps, "mass_drift": abs(d1.mass / d0.mass - 1), "redo": g.redo_count(),
+            "finite": code == wt.WT_OK, "finest_level": d1.finest_level,
+            "active_dof_last_step_by_level": {str(j): d.active_nodes[j] + d.active_edges[j]
+                                              for j in range(jmin, jmax + 1)}}
 
 
 def _jet_grid(jmin, jmax, precision, bump_lon=0.0):
@@ -181,53 +219,57 @@ def train_predictor(jmin, jmax, eps, steps=12, iters=300, lr=2e-3, bump_lon=-40.
                "iterations": iters}
 
 
-def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, warmup=2, ensemble_members=64):
-    """Adaptive jet workload: plain FP64 (blanket zone) against FP32 tendencies with the learned
-    zone.  Metric: active-point RK-stage updates/s = sum over steps of (active nodes + active
-    edges of all levels) x 4 stages / wall time of adapt + step (the threshold test and any
-    redo included)."""
-    import numpy as np
+def run_adaptive(jmin=5, jmax=9, eps=5e-3, steps=10, spinup_days=2.0, ensemble_members=64):
+    """Adaptive jet workload from a spun-up state: the jet (levels jmin..jmax) is run for
+    `spinup_days` simulated days with adapt + RK4 step every step (untimed; the bump has then
+    grown finer scales, level jmax populated), saved, and from that checkpoint plain FP64 (blanket
+    zone), FP32 with the blanket zone and FP32 with the learned zone each run `steps` timed steps.
+    Metric: active-point RK-stage updates/s = sum over steps of (active nodes + active edges of all
+    levels) x 4 stages / wall time of adapt + step (the threshold test and any redo included)."""
+    import tempfile
     import torch
     from paper_1404_0405_amd import wt
     mlp, train = train_predictor(jmin, jmax, eps)
-    out = {"workload": f"zonal jet + 120 m bump, levels {jmin}..{jmax}, eps={eps}, RK4, dt = 0.8 x stable step",
+    out = {"workload": f"zonal jet + 120 m bump, levels {jmin}..{jmax}, eps={eps}, RK4, dt = 0.8 x stable step, "
+                       f"timed from day {spinup_days:g}",
            "training": train}
+    ckpt = os.path.join(tempfile.mkdtemp(prefix="jet"), "spun_up.ckpt")
+    _progress(f"jet spin-up, {spinup_days:g} days")
+    g, H = _jet_grid(jmin, jmax, wt.WT_FP64)
+    with g:
+        dt = g.suggest_dt(0.8)
+        nspin = int(round(spinup_days * 86400.0 / dt))
+        timeline = {}
+        t0 = time.perf_counter()
+        for k in range(nspin):
+            g.adapt(eps)
+            g.step(dt)
+            if k % max(1, nspin // 4) == 0 or k == nspin - 1:
+                d, _ = g.diagnostics()
+                timeline[f"{(k + 1) * dt / 86400.0:.2f}"] = [d.active_nodes[j] + d.active_edges[j]
+                                                             for j in range(jmin, jmax + 1)]
+        torch.cuda.synchronize()
+        out["spinup"] = {"steps": nspin, "days": nspin * dt / 86400.0, "wall_s": time.perf_counter() - t0,
+                         "active_dof_by_level_at_day": timeline}
+        g.save(ckpt)
     final = {}
-    for name, prec, learned in (("plain_fp64", wt.WT_FP64, False), ("fp32_learned", wt.WT_FP32_TENDENCY, True)):
-        g, H = _jet_grid(jmin, jmax, prec)
+    for name, prec, learned in (("plain_fp64", wt.WT_FP64, False), ("fp32_blanket", wt.WT_FP32_TENDENCY, False),
+                                ("fp32_learned", wt.WT_FP32_TENDENCY, True)):
+        g = wt.Grid(jmin, jmax, 8)
         with g:
-            dt = g.suggest_dt(0.8)
+            g.load(ckpt)
+            g.set_params(precision=prec)
             if learned:
                 g.set_predictor(mlp, 0.5)
-            d0, _ = g.diagnostics()
-            for _ in range(warmup):
-                g.adapt(eps)
-                g.step(dt)
-            active, wall, wall_adapt = 0, 0.0, 0.0
-            for _ in range(steps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                g.adapt(eps)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                g.step(dt)
-                torch.cuda.synchronize()
-                wall += time.perf_counter() - t0
-                wall_adapt += t1 - t0
-                d, _ = g.diagnostics()    # untimed: active counts of the mask the step used
-                active += sum(d.active_nodes) + sum(d.active_edges)
-            d1, code = g.diagnostics()
-            final[name] = g.get_state(jmax)[0]
-            out[name] = {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / steps,
-                         "ms_adapt_per_step": wall_adapt * 1e3 / steps,
-                         "active_dof_per_step": active / steps, "mass_drift": abs(d1.mass / d0.mass - 1),
-                         "redo": g.redo_count(), "finite": code == wt.WT_OK,
-                         "active_dof_last_step_by_level": {str(j): d.active_nodes[j] + d.active_edges[j]
-                                                           for j in range(jmin, jmax + 1)}}
-    a, b = final["fp32_learned"], final["plain_fp64"]
-    out["fp32_learned"]["rel_l2_height_vs_plain_fp64"] = float(np.sqrt(((a - b) ** 2).sum() / ((H + b) ** 2).sum()))
-    out["speedup_fp32_learned_over_plain_fp64"] = out["fp32_learned"]["value"] / out["plain_fp64"]["value"]
+            out[name] = _timed_adaptive(g, eps, dt, steps, jmin, jmax)
+            final[name] = g.get_state(jmax)[:2]
+    os.remove(ckpt)
+    os.rmdir(os.path.dirname(ckpt))
+    for name in ("fp32_blanket", "fp32_learned"):
+        out[name].update(_errors(final[name], final["plain_fp64"], H))
+        out[f"speedup_{name}_over_plain_fp64"] = out[name]["value"] / out["plain_fp64"]["value"]
     if ensemble_members:
+        _progress(f"ensemble of {ensemble_members} members")
         out["ensemble"] = run_ensemble(members=ensemble_members, mlp=mlp)
     mlp.close()
     return out
@@ -318,43 +360,77 @@ def run_turbulence(jmin=6, jmax=10, eps=1e-2, train_steps=200, collect_every=20,
            "uniform_dof_at_jmax": int(N + E)}
     del X, Y, Xs, Ys
     final = {}
-    for name, prec, learned in (("plain_fp64", wt.WT_FP64, False), ("fp32_learned", wt.WT_FP32_TENDENCY, True)):
+    # from the checkpoint: plain FP64, FP32 with the blanket zone, FP32 with the learned zone, and
+    # the viscous form of Sec. 3.1 (nu = 1e4 m^2/s, the paper's viscous turbulence) in FP64
+    for name, prec, learned, nu in (("plain_fp64", wt.WT_FP64, False, 0.0),
+                                    ("fp32_blanket", wt.WT_FP32_TENDENCY, False, 0.0),
+                                    ("fp32_learned", wt.WT_FP32_TENDENCY, True, 0.0),
+                                    ("viscous_fp64", wt.WT_FP64, False, 1e4)):
         h = wt.Grid(jmin, jmax, 8)
         with h:
             h.load(ckpt)
-            h.set_params(precision=prec)
+            h.set_params(precision=prec, viscosity=nu)
             if learned:
                 h.set_predictor(mlp, 0.5)
-            d0, _ = h.diagnostics()
-            active, wall, wall_adapt = 0, 0.0, 0.0
-            for _ in range(test_steps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                h.adapt(eps)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                h.step(dt)
-                torch.cuda.synchronize()
-                wall += time.perf_counter() - t0
-                wall_adapt += t1 - t0
-                d, _ = h.diagnostics()
-                active += sum(d.active_nodes) + sum(d.active_edges)
-            d1, code = h.diagnostics()
-            final[name] = h.get_state(jmax)[0]
-            out[name] = {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / test_steps,
-                         "ms_adapt_per_step": wall_adapt * 1e3 / test_steps,
-                         "active_dof_per_step": active / test_steps,
-                         "compression": (N + E) * test_steps / active,
-                         "mass_drift": abs(d1.mass / d0.mass - 1), "redo": h.redo_count(),
-                         "finite": code == wt.WT_OK}
+            out[name] = _timed_adaptive(h, eps, dt, test_steps, jmin, jmax)
+            out[name]["compression"] = (N + E) / out[name]["active_dof_per_step"]
+            if nu:
+                out[name]["viscosity"] = nu
+            final[name] = h.get_state(jmax)[:2]
     os.remove(ckpt)
     os.rmdir(os.path.dirname(ckpt))
     mlp.close()
-    a, b = final["fp32_learned"], final["plain_fp64"]
     out["test_window"] = {"steps": test_steps, "simulated_h": test_steps * dt / 3600.0}
-    out["fp32_learned"]["rel_l2_height_vs_plain_fp64"] = float(np.sqrt(((a - b) ** 2).sum() / ((H + b) ** 2).sum()))
-    out["speedup_fp32_learned_over_plain_fp64"] = out["fp32_learned"]["value"] / out["plain_fp64"]["value"]
+    for name in ("fp32_blanket", "fp32_learned"):
+        out[name].update(_errors(final[name], final["plain_fp64"], H))
+        out[f"speedup_{name}_over_plain_fp64"] = out[name]["value"] / out["plain_fp64"]["value"]
     return out
+
+
+def run_tc1(jmin=4, jmax=10, eps=2e-2, days=12.0, bell="cosine"):
+    """Advection test 1 (Sec. 6.1): a cosine bell carried once round the sphere by solid-body
+    rotation, levels jmin..jmax with jmax a cap (the thresholds choose the finest level used),
+    eps relative, RK4 at CFL 0.8 of the finest level's advective step.  Reports the finest level
+    used, the error against the closed form (the initial bell after one rotation), mass
+    conservation and the active-point rate of adapt + step."""
+    import numpy as np
+    import torch
+    from paper_1404_0405_amd import inputs, wt
+    g = wt.Grid(jmin, jmax, 8)
+    with g:
+        x, m, t = g.coords(jmax)
+        dh, u, H0 = inputs.tc1(x, m, t, bell=bell)
+        g.set_params(mean_depth=H0, equations=wt.WT_ADVECTION)
+        g.set_state(jmax, dh, u)
+        dt0 = g.suggest_dt(0.8)
+        n = int(math.ceil(days * 86400.0 / dt0))
+        dt = days * 86400.0 / n
+        d0, _ = g.diagnostics()
+        finest, sampled, wall = 0, [], 0.0
+        for k in range(n):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.adapt(eps)
+            g.step(dt)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            if k % 25 == 0:   # untimed: active counts of every 25th step
+                d, _ = g.diagnostics()
+                finest = max(finest, d.finest_level)
+                sampled.append(sum(d.active_nodes) + sum(d.active_edges))
+        d1, code = g.diagnostics()
+        finest = max(finest, d1.finest_level)
+        a, _, _, _ = g.get_state(jmax)
+        err = float(np.sqrt(((a - dh) ** 2).sum() / (dh ** 2).sum()))
+        mean_act = float(np.mean(sampled))
+        return {"workload": f"advection test 1 ({bell} bell, solid-body rotation once in 12 days), levels {jmin}..{jmax} "
+                            f"(jmax a cap), eps={eps}, RK4, CFL 0.8", "steps": n, "dt_s": dt,
+                "finest_level_used": finest, "rel_l2_error_vs_closed_form": err,
+                "mass_drift": abs(d1.mass / d0.mass - 1), "finite": code == wt.WT_OK,
+                "wall_s": wall, "ms_per_step": wall * 1e3 / n, "active_dof_mean_of_sampled_steps": mean_act,
+                "active_dof_last_step_by_level": {str(j): d1.active_nodes[j] + d1.active_edges[j]
+                                                  for j in range(jmin, jmax + 1)},
+                "value": mean_act * 4 / (wall / n)}
 
 
 def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=10, mlp=None):
@@ -451,25 +527,73 @@ def run_ensemble(members=64, jmin=5, jmax_choices=(7, 8, 9), steps=10, mlp=None)
     return out
 
 
-def cpu_baseline(level=8, steps=12):
-    """The oracle as it stands (numpy FP64, one host thread), on a bounded sample of the same
-    workload: `steps` RK4 steps of the same flow on a level-`level` grid."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_stages(g, dh, u, p, stages):
+    from oracle import trisk
+    t0 = time.perf_counter()
+    for _ in range(stages):
+        trisk.tendencies(g, dh, u, p)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(level=9, stages=2, procs=None):
+    """The oracle as it stands (numpy FP64), timed on the host's cores on bounded samples of the
+    workloads: (i) `stages` tendency evaluations (RK stages) of the uniform TC2 + SH flow on the
+    level-`level` grid in one process, then the same in `procs` forked processes at once (all
+    cores; the aggregate rate is `value`) -- level 10, the headline's, would take about five
+    minutes and 30 GB to build the oracle grid, so level 9; (ii) one adaptive step (adapt + RK4
+    step) of the TC2 configuration on levels 4..6, eps 1e-3, one process."""
+    import multiprocessing as mp
     from oracle import trisk
     from oracle.grid import Grid
+    from oracle.multiscale import Hierarchy
     from paper_1404_0405_amd import inputs
+    procs = procs or max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
     og = Grid(level)
+    build_s = time.perf_counter() - t0
     dh, u, H = inputs.tc2_perturbed(og.xyz, og.e_mid, og.e_tan)
     p = trisk.Params(mean_depth=H)
-    dt = trisk.suggest_dt(og, dh, u, p, 0.8)
+    dof = og.N + og.E
+    single = _oracle_stages(og, dh, u, p, stages)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        t0 = time.perf_counter()
+        pool.starmap(_oracle_stages, [(og, dh, u, p, stages)] * procs)
+        wall_all = time.perf_counter() - t0
+    del og
+    Hy = Hierarchy(4, 6)
+    fg = Hy.g[6]
+    dh6, u6, H6 = inputs.tc2(fg.xyz, fg.e_mid, fg.e_tan)
+    p6 = trisk.Params(mean_depth=H6)
+    Hy.set_state(6, dh6, u6)
+    Hy.adapt(1e-3)
+    dt6 = trisk.suggest_dt(fg, dh6, u6, p6, 0.8)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        dh, u = trisk.step(og, dh, u, dt, p)
-    wall = time.perf_counter() - t0
-    return {"value": (og.N + og.E) * 4 * steps / wall, "unit": "active-point RK-stage updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the same TC2+SH flow on the uniform level-{level} grid "
-                      f"({og.N} cells, {og.E} edges), numpy FP64 oracle, one host thread; "
-                      f"{wall:.1f} s"}
+    Hy.adapt(1e-3)
+    Hy.step(dt6, p6)
+    wall_ad = time.perf_counter() - t0
+    act = sum(int(Hy.node_act[j].sum() + Hy.edge_act[j].sum()) for j in Hy.levels)
+    return {"value": procs * dof * stages / wall_all, "unit": "active-point RK-stage updates/s", "cores": procs,
+            "kind": "oracle",
+            "sample": f"{stages} RK stages (tendency evaluations) of the uniform TC2+SH flow on level {level} "
+                      f"({dof} dof), numpy FP64 oracle, in {procs} processes at once "
+                      f"({wall_all:.1f} s); level 10 not built (about 5 minutes and 30 GB for the oracle grid)",
+            "host_cpu": _cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": dof * stages / single, "wall_s": single, "cores": 1},
+            "oracle_grid_build_s": build_s,
+            "adaptive_step_tc2_levels_4_6": {"value": act * 4 / wall_ad, "wall_s": wall_ad, "active_dof": act,
+                                             "cores": 1, "eps": 1e-3}}
 
 
 def copy_probe(nbytes=1 << 31, reps=5):
@@ -503,10 +627,12 @@ def main():
     ap.add_argument("--adaptive-steps", type=int, default=10)
     ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive jet comparison")
     ap.add_argument("--ensemble-members", type=int, default=64, help="0 skips the ensemble")
-    ap.add_argument("--turbulence", action="store_true", help="add the learned-zone turbulence workload")
+    ap.add_argument("--no-turbulence", action="store_true", help="skip the learned-zone turbulence workload")
+    ap.add_argument("--no-tc1", action="store_true", help="skip the advection test 1 workload")
+    ap.add_argument("--jet-days", type=float, default=2.0, help="simulated days of jet spin-up before timing")
     ap.add_argument("--only-turbulence", action="store_true", help="run only the turbulence workload")
-    ap.add_argument("--turb-train-steps", type=int, default=200)
-    ap.add_argument("--turb-test-steps", type=int, default=20)
+    ap.add_argument("--turb-train-steps", type=int, default=100)
+    ap.add_argument("--turb-test-steps", type=int, default=10)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -517,17 +643,25 @@ def main():
         print(json.dumps({"turbulence": run_turbulence(**turb_kw)}), flush=True)
         return
     if args.only_adaptive:
-        print(json.dumps({"adaptive": run_adaptive(steps=args.adaptive_steps,
+        print(json.dumps({"adaptive": run_adaptive(steps=args.adaptive_steps, spinup_days=args.jet_days,
                                                    ensemble_members=args.ensemble_members)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
               "the multi-GPU path is not part of it", file=sys.stderr)
         sys.exit(2)
+    _progress("uniform stage")
     res, (N, E, T), dt = run_gpu(args)
     f64 = res["fp64"]
     dom = max(f64["kernels"], key=lambda k: f64["kernels"][k]["avg_ms"])
     kd = f64["kernels"][dom]
+    # algorithmic bytes per launch of the dominant kernel, per element of the units it processes:
+    # the state passes of an RK4 stage (8 B per dof, 4 dofs per element, r = 4 passes on average
+    # over the stages) and the shared-geometry model of the per-element tables (376 B per element
+    # on a general grid, one lozenge's tables shared by all ten: 37.6 B)
+    units = kd["units"]
+    alg = units * (8.0 * 4 * 4 + 376.0 / 10.0)
+    achieved = alg / (kd["avg_ms"] * 1e-3) / 1e9
     line = {
         "metric": "active-point RK-stage updates/s",
         "value": f64["value"],
@@ -545,9 +679,14 @@ def main():
                                "TC2 zonal flow + seeded SH height perturbation (l<=32, 10 m), RK4, "
                                f"dt={dt:.3f} s (CFL 0.8)",
                    "level": args.level, "cells": N, "edges": E, "rk": "rk4", "stages_per_step": 4},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.level),
-                     "algorithmic_bytes": kd["algorithmic_bytes"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.level),
+                     "algorithmic_bytes": alg, "units_per_launch": units, "avg_launch_ms": kd["avg_ms"],
+                     "byte_model": "RK4 stage: 8 B x 4 dof x 4 passes per element + 376 B / 10 shared tables",
+                     "kernel_byte_model": {"algorithmic_bytes": kd["algorithmic_bytes"], "achieved": kd["gbs"],
+                                           "frac": kd["gbs"] / HBM_PEAK_GBS,
+                                           "model": "stage input + Runge-Kutta arrays read and written + "
+                                                    "58 FP64 geometry values per tile position / 10"}},
         "kernels_fp64": f64["kernels"],
         "stage_ms_fp64": f64["ms_per_step"] / 4,
         "fp32_tendency": ({"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"],
@@ -559,11 +698,19 @@ def main():
         "pcie_inclusive_fp64": f64.get("pcie_inclusive"),
     }
     if not args.no_adaptive:
-        line["adaptive"] = run_adaptive(steps=args.adaptive_steps, ensemble_members=args.ensemble_members)
-    if args.turbulence:
+        _progress("adaptive jet")
+        line["adaptive"] = run_adaptive(steps=args.adaptive_steps, spinup_days=args.jet_days,
+                                        ensemble_members=args.ensemble_members)
+    if not args.no_turbulence:
+        _progress("turbulence")
         line["turbulence"] = run_turbulence(**turb_kw)
+    if not args.no_tc1:
+        _progress("advection test 1")
+        line["advection_tc1"] = run_tc1()
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()
+    _progress("done")
     print(json.dumps(line), flush=True)
 
 

@@ -261,6 +261,10 @@ int wt_alloc_stats(const wt_grid* g, int64_t* n_hook, int64_t* bytes_hook, int64
 int wt_timing_enable(wt_grid* g, int enable);
 int wt_timing_reset(wt_grid* g);
 int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches, double* total_bytes);
+/* Units the last timed launch of kernel `name` processed: elements (a node and its three edges)
+ * for trisk_edge_cell, trisk_tend and trisk_lattice (the lattice kernel: its regular tiles of
+ * all ten lozenges), triangles for trisk_vertex; 0 if none was timed. */
+int wt_kernel_units(wt_grid* g, const char* name, int64_t* units);
 const char* wt_kernel_names(void);
 
 /* Host-only inspection of the grid builder (no device needed): builds level `level` with
@@ -378,6 +382,13 @@ int wt_patch_labels(wt_grid* g, int level, float* y_device);
  * and the adapt and step are redone with the blanket zone.  The grid keeps the pointer; the
  * caller keeps m alive while it is set. */
 int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold);
+/* Test hook of the threshold test: at the next gated wt_adapt, withhold the children rule from
+ * all four quadrants of patch `patch` (index as above) of `level` whatever the network
+ * proposes, so that the following step is judged with those quadrants dropped where they are
+ * significant.  Needs a predictor (WT_ESTATE otherwise); WT_EINVAL for a level without patches
+ * or a patch out of range.  Several calls add up; the list is cleared by the gated adapt. */
+int wt_debug_force_drop(wt_grid* g, int level, int64_t patch);
+
 /* Number of steps redone by the threshold test since the grid was created. */
 int wt_redo_count(const wt_grid* g, int64_t* redo);
 

@@ -89,6 +89,7 @@ struct wt_grid {
   // learned adjacent zone
   wt_mlp* predictor = nullptr;
   double pred_thr = 0.5;
+  std::vector<std::pair<int, int64_t>> force_drop;   // (level, patch) withheld at the next gated adapt
   bool gated = false;         // the last adapt used the learned gate; the next step is judged
   double last_eps = 0, last_eh = 0, last_eu = 0;
   int64_t redo = 0;
@@ -726,7 +727,10 @@ static void adapt_impl(wt_grid* g, double eps, double* eh_out, double* eu_out, b
       learn_features(l.npatch, 1 << j, level_pos(g, j), l.stats, l.X, g->stream);
       mlp_predict(g->predictor, l.X, l.npatch, l.Pr, g->stream);
       learn_gate(l.npatch, l.Pr, g->pred_thr, l.stats, l.allow, l.dropped, g->stream);
+      for (const auto& fd : g->force_drop)
+        if (fd.first == j) learn_force_drop(l.npatch, fd.second, l.stats, l.allow, l.dropped, g->stream);
     }
+    g->force_drop.clear();
   }
   // R2: same-level neighbours; R3: children on the next level (all levels in one batch: the rules
   // only set mask bytes)
@@ -1468,6 +1472,17 @@ int wt_set_predictor(wt_grid* g, wt_mlp* m, double threshold) {
   return WT_OK;
 }
 
+int wt_debug_force_drop(wt_grid* g, int level, int64_t patch) {
+  if (!g) return fail(WT_EINVAL, "wt_debug_force_drop: null grid");
+  if (!g->predictor) return fail(WT_ESTATE, "wt_debug_force_drop: no predictor set");
+  if (level < g->jmin || level > g->jmax || !learnable(g, level))
+    return fail(WT_EINVAL, "wt_debug_force_drop: level has no patches");
+  const int64_t m = (int64_t(1) << level) / 8;
+  if (patch < 0 || patch >= 10 * m * m) return fail(WT_EINVAL, "wt_debug_force_drop: patch out of range");
+  g->force_drop.emplace_back(level, patch);
+  return WT_OK;
+}
+
 int wt_set_step_phases(wt_grid* g, int enable) {
   GridScope scope_(g);
   if (!g) return fail(WT_EINVAL, "wt_set_step_phases: null grid");
@@ -1771,6 +1786,18 @@ int wt_timing_reset(wt_grid* g) {
     (void)hipEventDestroy(r.b);
   }
   g->timer.recs.clear();
+  return WT_OK;
+}
+
+int wt_kernel_units(wt_grid* g, const char* name, int64_t* units) {
+  if (!g || !name || !units) return fail(WT_EINVAL, "wt_kernel_units: null argument");
+  int k = -1;
+  for (int q = 0; q < K_COUNT; ++q)
+    if (std::strcmp(name, kKernelNames[q]) == 0) k = q;
+  if (k < 0) return fail(WT_EINVAL, std::string("wt_kernel_units: unknown kernel ") + name);
+  *units = 0;
+  for (auto& r : g->timer.recs)
+    if (r.k == k) *units = r.units;
   return WT_OK;
 }
 

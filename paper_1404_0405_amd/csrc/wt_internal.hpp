@@ -79,7 +79,8 @@ struct Timer {
   struct Rec {
     int k;
     hipEvent_t a, b;
-    double bytes;  // algorithmic bytes of the launch
+    double bytes;   // algorithmic bytes of the launch
+    int64_t units;  // elements (node + its three edges) or triangles the launch processes
   };
   std::vector<Rec> recs;
 };

@@ -134,7 +134,9 @@ struct TimedLaunch {
   hipStream_t s;
   double bytes;
   hipEvent_t a = nullptr, b = nullptr;
-  TimedLaunch(Timer* tm_, int k_, hipStream_t s_, double bytes_) : tm(tm_), k(k_), s(s_), bytes(bytes_) {
+  int64_t units;
+  TimedLaunch(Timer* tm_, int k_, hipStream_t s_, double bytes_, int64_t units_)
+      : tm(tm_), k(k_), s(s_), bytes(bytes_), units(units_) {
     if (tm && tm->enabled) {
       HIPCHK(hipEventCreate(&a));
       HIPCHK(hipEventCreate(&b));
@@ -144,7 +146,7 @@ struct TimedLaunch {
   ~TimedLaunch() {
     if (a) {
       hipEventRecord(b, s);
-      tm->recs.push_back({k, a, b, bytes});
+      tm->recs.push_back({k, a, b, bytes, units});
     }
   }
 };
@@ -197,15 +199,15 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
   const int bs = use_lat ? 64 : BS;
   auto grid = [bs](int64_t n) { return unsigned((n + bs - 1) / bs); };
   {
-    TimedLaunch tl_(tm, K_VERTEX, s, double(nt) * (80.0 + 16.0 + sz));
+    TimedLaunch tl_(tm, K_VERTEX, s, double(nt) * (80.0 + 16.0 + sz), nt);
     k_vertex<T><<<grid(nt), bs, 0, s>>>(nt, tl, t, sdh.x, su.x, p.H, qv);
   }
   {
-    TimedLaunch tl_(tm, K_EDGE_CELL, s, double(ne) * (120.0 + 32.0 + 24.0 + 6.0 * sz));
+    TimedLaunch tl_(tm, K_EDGE_CELL, s, double(ne) * (120.0 + 32.0 + 24.0 + 6.0 * sz), ne);
     k_edge_cell<T><<<grid(ne), bs, 0, s>>>(ne, el, t, sdh.x, su.x, qv, p, B, F, G, qe);
   }
   {
-    TimedLaunch tl_(tm, K_TEND, s, double(nr) * (480.0 + 24.0 + 4.0 * sz + 4.0 * e_dof));
+    TimedLaunch tl_(tm, K_TEND, s, double(nr) * (480.0 + 24.0 + 4.0 * sz + 4.0 * e_dof), nr);
     k_tend<T><<<grid(nr), bs, 0, s>>>(nr, t.n_elem, rl, t.c_e, t.c_div, t.e_c, t.inv_d, t.ecp, t.wl, B, F, G,
                                       qe, sdh, su, c, t, p.nu, p.adv);
   }
@@ -214,7 +216,8 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
     // stage input read once (dh + 3 u), the stage arrays, and the shared geometry of the
     // regular tile positions once for all 10 lozenges (58 values per position)
     const double nreg = double(lat->n_reg_elems);
-    TimedLaunch tl_(tm, K_LATTICE, s, nreg * (32.0 + 4.0 * epi(c, sdh, false)) + nreg / 10.0 * 58.0 * 8.0);
+    TimedLaunch tl_(tm, K_LATTICE, s, nreg * (32.0 + 4.0 * epi(c, sdh, false)) + nreg / 10.0 * 58.0 * 8.0,
+                    lat->n_reg_elems);
     LatArgs a = lat->args;
     a.g = p.g;
     a.H = p.H;

@@ -218,6 +218,21 @@ __global__ __launch_bounds__(LB) void k_gate(int64_t npatch, const float* __rest
   dropped[q] = (!a && stats[p * LEARN_STATS + 24 + c] > 0.f) ? 1 : 0;
 }
 
+__global__ void k_force_drop(int64_t patch, const float* __restrict__ stats, uint8_t* __restrict__ allow,
+                             uint8_t* __restrict__ dropped) {
+  const int c = threadIdx.x;
+  if (c >= 4) return;
+  allow[4 * patch + c] = 0;
+  dropped[4 * patch + c] = stats[patch * LEARN_STATS + 24 + c] > 0.f ? 1 : 0;
+}
+
+void learn_force_drop(int64_t npatch, int64_t patch, const float* stats, uint8_t* allow, uint8_t* dropped,
+                      hipStream_t s) {
+  if (patch < 0 || patch >= npatch) throw std::runtime_error("learn_force_drop: patch out of range");
+  k_force_drop<<<1, 64, 0, s>>>(patch, stats, allow, dropped);
+  HIPCHK(hipGetLastError());
+}
+
 // Threshold test after a step: a dropped quadrant that holds a significant point again.
 __global__ __launch_bounds__(LB) void k_violations(int64_t npatch, const float* __restrict__ stats,
                                                    const uint8_t* __restrict__ dropped, uint8_t* __restrict__ viol) {

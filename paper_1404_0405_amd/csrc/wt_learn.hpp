@@ -40,6 +40,10 @@ void learn_features(int64_t npatch, int n, float level_pos, const float* stats, 
 void learn_labels(int64_t npatch, const float* stats, float* Y, hipStream_t s);
 void learn_gate(int64_t npatch, const float* P, double thr, const float* stats, uint8_t* allow, uint8_t* dropped,
                 hipStream_t s);
+// Test hook: the children rule of patch `patch` is withheld from all four quadrants (allow = 0;
+// dropped where the quadrant is significant), whatever the network proposed.
+void learn_force_drop(int64_t npatch, int64_t patch, const float* stats, uint8_t* allow, uint8_t* dropped,
+                      hipStream_t s);
 void learn_violations(int64_t npatch, const float* stats, const uint8_t* dropped, uint8_t* viol, hipStream_t s);
 
 }  // namespace wt

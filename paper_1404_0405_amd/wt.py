@@ -80,6 +80,7 @@ SIGNATURES = [
     ("wt_timing_reset", C.c_int, [_P]),
     ("wt_kernel_time", C.c_int, [_P, C.c_char_p, _D, _I64, _D]),
     ("wt_kernel_names", C.c_char_p, []),
+    ("wt_kernel_units", C.c_int, [_P, C.c_char_p, _I64]),
     ("wt_table_cache_clear", None, []),
     ("wt_save", C.c_int, [_P, C.c_char_p]),
     ("wt_load", C.c_int, [_P, C.c_char_p]),
@@ -100,6 +101,7 @@ SIGNATURES = [
     ("wt_patch_labels", C.c_int, [_P, C.c_int, _P]),
     ("wt_set_predictor", C.c_int, [_P, _P, C.c_double]),
     ("wt_redo_count", C.c_int, [_P, _I64]),
+    ("wt_debug_force_drop", C.c_int, [_P, C.c_int, C.c_int64]),
     ("wt_set_work_lists", C.c_int, [_P, C.c_int]),
     ("wt_set_step_phases", C.c_int, [_P, C.c_int]),
     ("wt_ensemble_create", _P, [C.POINTER(_P), C.c_int]),
@@ -414,6 +416,10 @@ class Grid:
         """Merge the independent launches of the listed step (default) or launch per kernel."""
         _check(load().wt_set_step_phases(self._h, 1 if enable else 0))
 
+    def debug_force_drop(self, level, patch):
+        """Withhold the children rule of a patch at the next gated adapt (test hook)."""
+        _check(load().wt_debug_force_drop(self._h, level, int(patch)))
+
     def redo_count(self):
         r = C.c_int64()
         _check(load().wt_redo_count(self._h, C.byref(r)))
@@ -424,6 +430,13 @@ class Grid:
         ms, cnt, by = C.c_double(), C.c_int64(), C.c_double()
         _check(load().wt_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(cnt), C.byref(by)))
         return ms.value, cnt.value, by.value
+
+
+def kernel_units(grid, name):
+    """Units (elements or triangles) the last timed launch of kernel `name` processed."""
+    u = C.c_int64()
+    _check(load().wt_kernel_units(grid._h, name.encode(), C.byref(u)))
+    return u.value
 
 
 def kernel_names():

@@ -368,3 +368,37 @@ def test_learned_zone_against_the_oracle(min_count):
             assert g.redo_count() == redo_o
     m.close()
     _say(f"  feature comparisons {compared}, redo {redo_o}/{nsteps}")
+
+
+def test_forced_drop_is_judged_and_redone():
+    """wt_debug_force_drop: with a gate that proposes everything (threshold 0), withholding the
+    children rule of a patch that holds significant points makes the threshold test find the
+    miss and redo the step (redo count 1, state bitwise the plain run's); withholding it from a
+    patch without significant points drops nothing and redoes nothing."""
+    import torch
+    jmin, jmax, eps, lev = 4, 7, 5e-3, 5
+    out = []
+    for case in ("plain", "significant", "empty"):
+        g = _grid(jmin, jmax)
+        with g:
+            dt = g.suggest_dt(0.8)
+            g.adapt(eps)
+            g.step(dt)
+            m = wt.Mlp(inputs.mlp_init())
+            if case != "plain":
+                g.set_predictor(m, 0.0)
+                y = torch.empty((g.patch_count(lev), 4), dtype=torch.float32, device="cuda")
+                g.patch_labels(lev, y)
+                sig = y.cpu().numpy().max(1) > 0.5
+                patch = int(np.nonzero(sig)[0][0]) if case == "significant" else int(np.nonzero(~sig)[0][0])
+                g.debug_force_drop(lev, patch)
+            g.adapt(eps)
+            g.step(dt)
+            out.append(([g.get_state(j) for j in range(jmin, jmax + 1)], g.redo_count()))
+            m.close()
+    _say(f"forced drop: redo {[r for _, r in out]}")
+    assert [r for _, r in out] == [0, 1, 0]
+    for states, _ in out[1:]:
+        for a, b in zip(states, out[0][0]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
