@@ -144,10 +144,34 @@ def _errors(st, ref, H):
             "rel_l2_u_vs_fp64": float(np.sqrt(((u - v) ** 2).sum() / (v ** 2).sum()))}
 
 
-def _timed_adaptive(g, eps, dt, steps, jmin, jmax):
-    """adapt + step timed together (threshold test and redo included), active dof of each step."""
+# The finest level of an adaptive grid runs whole through the masked lattice kernel once its
+# 3-ring support holds this fraction of its elements (measured break-even: a level-9 jet level
+# with ~21 % of its dof active is as fast listed; the turbulence's level 10 at ~75 % is 1.35x
+# faster as a whole step dense).
+DENSE_MIN = 0.4
+
+
+def _dense_kernel(g):
+    """Launches, average duration and algorithmic rate of the masked lattice kernel (timing on)."""
+    from paper_1404_0405_amd import wt
+    ms, n, by = g.kernel_time("trisk_lattice_masked")
+    if n == 0:
+        return {"launches": 0}
+    gbs = by / (ms * 1e-3) / 1e9
+    return {"launches": n, "avg_ms": ms / n, "algorithmic_bytes_per_launch": by / n,
+            "units_per_launch": wt.kernel_units(g, "trisk_lattice_masked"), "achieved_gbs": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+
+
+def _timed_adaptive(g, eps, dt, steps, jmin, jmax, dense_min=None):
+    """adapt + step timed together (threshold test and redo included), active dof of each step.
+    The finest level runs dense once its support holds DENSE_MIN of its elements (dense_min
+    overrides; above 1: always listed)."""
     import torch
     from paper_1404_0405_amd import wt
+    g.set_dense_levels(DENSE_MIN if dense_min is None else dense_min)
+    g.timing(True)
+    g.timing_reset()
     d0, _ = g.diagnostics()
     active, wall, wall_adapt = 0, 0.0, 0.0
     for _ in range(steps):
@@ -163,9 +187,11 @@ def _timed_adaptive(g, eps, dt, steps, jmin, jmax):
         d, _ = g.diagnostics()    # untimed: active counts of the mask the step used
         active += sum(d.active_nodes) + sum(d.active_edges)
     d1, code = g.diagnostics()
+    dk = _dense_kernel(g)
+    g.timing(False)
     return {"value": active * 4 / wall, "ms_per_step": wall * 1e3 / steps, "ms_adapt_per_step": wall_adapt * 1e3 / steps,
             "active_dof_per_step": active / steps, "mass_drift": abs(d1.mass / d0.mass - 1), "redo": g.redo_count(),
-            "finite": code == wt.WT_OK, "finest_level": d1.finest_level,
+            "finite": code == wt.WT_OK, "finest_level": d1.finest_level, "dense_finest_level": dk,
             "active_dof_last_step_by_level": {str(j): d.active_nodes[j] + d.active_edges[j]
                                               for j in range(jmin, jmax + 1)}}
 
@@ -362,7 +388,10 @@ def run_turbulence(jmin=6, jmax=10, eps=1e-2, train_steps=200, collect_every=20,
     final = {}
     # from the checkpoint: plain FP64, FP32 with the blanket zone, FP32 with the learned zone, and
     # the viscous form of Sec. 3.1 (nu = 1e4 m^2/s, the paper's viscous turbulence) in FP64
+    # (the finest level dense once its support holds DENSE_MIN of it; plain_fp64_listed keeps it
+    # on the listed kernels for comparison; the viscous form always does)
     for name, prec, learned, nu in (("plain_fp64", wt.WT_FP64, False, 0.0),
+                                    ("plain_fp64_listed", wt.WT_FP64, False, 0.0),
                                     ("fp32_blanket", wt.WT_FP32_TENDENCY, False, 0.0),
                                     ("fp32_learned", wt.WT_FP32_TENDENCY, True, 0.0),
                                     ("viscous_fp64", wt.WT_FP64, False, 1e4)):
@@ -372,7 +401,8 @@ def run_turbulence(jmin=6, jmax=10, eps=1e-2, train_steps=200, collect_every=20,
             h.set_params(precision=prec, viscosity=nu)
             if learned:
                 h.set_predictor(mlp, 0.5)
-            out[name] = _timed_adaptive(h, eps, dt, test_steps, jmin, jmax)
+            out[name] = _timed_adaptive(h, eps, dt, test_steps, jmin, jmax,
+                                        dense_min=2.0 if name == "plain_fp64_listed" else None)
             out[name]["compression"] = (N + E) / out[name]["active_dof_per_step"]
             if nu:
                 out[name]["viscosity"] = nu
@@ -381,7 +411,7 @@ def run_turbulence(jmin=6, jmax=10, eps=1e-2, train_steps=200, collect_every=20,
     os.rmdir(os.path.dirname(ckpt))
     mlp.close()
     out["test_window"] = {"steps": test_steps, "simulated_h": test_steps * dt / 3600.0}
-    for name in ("fp32_blanket", "fp32_learned"):
+    for name in ("fp32_blanket", "fp32_learned", "plain_fp64_listed"):
         out[name].update(_errors(final[name], final["plain_fp64"], H))
         out[f"speedup_{name}_over_plain_fp64"] = out[name]["value"] / out["plain_fp64"]["value"]
     return out
@@ -403,7 +433,7 @@ def run_tc1(jmin=4, jmax=10, eps=2e-2, days=12.0, bell="cosine"):
     with g:
         x, m, t = g.coords(jmax)
         dh, u, H0 = inputs.tc1(x, m, t, bell=bell)
-        g.set_params(mean_depth=H0, equations=wt.WT_ADVECTION)
+        g.set_params(mean_depth=H0, equations=wt.WT_ADVECTION)   # (the listed kernels: no dense form)
         g.set_state(jmax, dh, u)
         dt0 = g.suggest_dt(0.8)
         n = int(math.ceil(days * 86400.0 / dt0))
@@ -648,7 +678,10 @@ def main():
     ap.add_argument("--only-turbulence", action="store_true", help="run only the turbulence workload")
     ap.add_argument("--turb-train-steps", type=int, default=100)
     ap.add_argument("--turb-test-steps", type=int, default=10)
+    ap.add_argument("--dense-min", type=float, default=DENSE_MIN,
+                    help="support fraction from which the finest level runs dense (above 1: never)")
     args = ap.parse_args()
+    globals()["DENSE_MIN"] = args.dense_min
     if args.copy_probe:
         copy_probe()
         return

@@ -211,6 +211,19 @@ int wt_set_work_lists(wt_grid* g, int enable);
  * level and kind (test hook: the two agree bitwise).  Default: enabled.  Synchronises. */
 int wt_set_step_phases(wt_grid* g, int enable);
 
+/* Dense finest level (Sec. 3.1 stage on the finest level, Sec. 4.1-4.3 restriction from it):
+ * when the 3-ring support of the finest level's active points holds at least min_fraction of
+ * its elements (always, when the stage runs over whole levels), the level's tile elements run
+ * whole through the lattice kernel of the uniform stage in a masked form -- tendencies zero at
+ * inactive points, and the mass flux F, qF^perp Q and the Bernoulli function B of every element
+ * stored for the restriction chain -- and only the rim round the twelve lozenge corners through
+ * the listed table-driven kernels.  Results agree with the listed stage to round-off (the lattice
+ * kernel sums in another order), not bitwise.  min_fraction > 1 turns it off (the default);
+ * enabling builds the level's lattice geometry (finest level 6 or more, inviscid shallow-water
+ * form only: other forms and ensemble steps keep the listed kernels).  WT_EINVAL for a negative
+ * or non-finite fraction or a finest level below 6.  Synchronises. */
+int wt_set_dense_levels(wt_grid* g, double min_fraction);
+
 /* Replace the active masks of `level` (host arrays of N and E bytes, 1 = active).  Test hook,
  * used to resynchronise masks with a reference at exact threshold ties. */
 int wt_set_mask(wt_grid* g, int level, const uint8_t* node_active_host, const uint8_t* edge_active_host);
@@ -250,20 +263,21 @@ int wt_alloc_stats(const wt_grid* g, int64_t* n_hook, int64_t* bytes_hook, int64
                    int64_t* bytes_direct);
 
 /* Kernel timing for measurement: when enabled, every launch of the uniform-level TRiSK stage
- * kernels is bracketed by HIP events on the grid's stream.  wt_kernel_time returns the summed
+ * kernels and of the masked lattice kernel is bracketed by HIP events on the grid's stream.  wt_kernel_time returns the summed
  * device time (ms), the launch count and the summed algorithmic bytes of the kernel named
  * `name` since the last reset (total_bytes may be NULL).  Algorithmic bytes count every table
  * entry, input and output element of a launch once: table-driven kernels per triangle 96 B +
  * q_v, per element 176 B + 6 intermediates (edge_cell) and 504 B + 4 intermediates + the
  * stage's Runge-Kutta arrays (tend); the lattice kernel per element the stage input (32 B)
  * and the Runge-Kutta arrays, plus its shared geometry (464 B per tile position) once for the
- * 10 lozenges.  Names are listed by wt_kernel_names (comma separated). */
+ * 10 lozenges; its masked form on a dense finest level (trisk_lattice_masked) also the four mask
+ * bytes and the stored F, Q and B.  Names are listed by wt_kernel_names (comma separated). */
 int wt_timing_enable(wt_grid* g, int enable);
 int wt_timing_reset(wt_grid* g);
 int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches, double* total_bytes);
 /* Units the last timed launch of kernel `name` processed: elements (a node and its three edges)
- * for trisk_edge_cell, trisk_tend and trisk_lattice (the lattice kernel: its regular tiles of
- * all ten lozenges), triangles for trisk_vertex; 0 if none was timed. */
+ * for trisk_edge_cell, trisk_tend, trisk_lattice and trisk_lattice_masked (the lattice kernel:
+ * its regular tiles of all ten lozenges), triangles for trisk_vertex; 0 if none was timed. */
 int wt_kernel_units(wt_grid* g, const char* name, int64_t* units);
 const char* wt_kernel_names(void);
 

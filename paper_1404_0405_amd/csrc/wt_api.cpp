@@ -98,6 +98,10 @@ struct wt_grid {
   // the same eps takes its details, thresholds and significant points instead of recomputing them.
   uint64_t state_ver = 0, judge_ver = ~uint64_t(0);
   bool use_lists = true;      // adaptive stage over work lists (false: whole levels)
+  // The finest level runs whole through the masked lattice kernel when its listed support holds
+  // at least this fraction of its elements (above 1: never; built by wt_set_dense_levels).
+  double dense_min = 2.0;
+  bool splan_dense = false;   // the merged-phase plan was built with the finest level dense
   bool lists_ok = false;      // the lists match the current masks
   bool details_partial = false;   // the stored details cover only the work-list support
   uint64_t epoch = 0;         // bumped whenever the launches of a step change (see touch_epoch)
@@ -342,6 +346,18 @@ static void reconstruct(wt_grid* g, std::vector<double*>& rdh, std::vector<doubl
 
 // ---------------------------------------------------------------- work lists
 
+// Whether the finest level of a multilevel grid runs through the masked lattice kernel this step:
+// the level has a lattice form, the stage is the inviscid shallow-water one, and the level is
+// dense (its 3-ring support holds at least dense_min of its elements; always when the stage runs
+// over whole levels).  Deterministic in the masks, so every path of a step takes the same choice.
+static bool dense_finest(const wt_grid* g) {
+  if (!g->multi() || !(g->dense_min <= 1.0)) return false;
+  const LevelState& l = *g->lev.back();
+  if (!l.lat.ok || g->prm.viscosity != 0.0 || g->prm.equations == WT_ADVECTION) return false;
+  if (!(g->use_lists && g->lists_ok)) return true;
+  return double(l.l_elem.n) >= g->dense_min * double(l.tab.N);
+}
+
 // The launches of a multilevel step depend on whether the work lists are used, on the lists'
 // addresses and padded bounds, and on the mask addresses; a captured step stays valid while
 // none of these change.
@@ -360,6 +376,7 @@ static void touch_epoch(wt_grid* g) {
   std::memcpy(&nub, &g->prm.viscosity, 8);
   sig.push_back(nub);
   sig.push_back(g->prm.equations);
+  sig.push_back(dense_finest(g));
   auto add = [&](const WorkList& L) {
     sig.push_back(reinterpret_cast<int64_t>(L.idx));
     sig.push_back(L.bound);
@@ -479,6 +496,8 @@ static void ml_step(wt_grid* g, double dt) {
   PhysParams p = phys(g);
   const bool wl = g->use_lists && g->lists_ok;
   auto LS = [&](const WorkList& L) { return wl ? span(L) : Span{}; };
+  const bool dense = dense_finest(g);
+  const DevLattice& lat = g->lev.back()->lat;
   for (int s = 0; s < 4; ++s) {
     std::vector<StageSpec> sp(nl);
     std::vector<double*> xdh(nl), xu(nl);
@@ -496,6 +515,13 @@ static void ml_step(wt_grid* g, double dt) {
     }
     for (int q = 0; q < nl; ++q) {
       LevelState& l = *g->lev[q];
+      if (dense && q == nl - 1) {
+        // the tile elements whole through the lattice kernel, then the rim from the tables
+        launch_lattice_masked(lat, l.work, l.na, l.ea, p, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, &g->timer);
+        ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, Span{lat.sup_tris, lat.n_sup_tris},
+                               Span{lat.sup_elems, lat.n_sup_elems}, Span{lat.rim_edges, lat.n_rim_edges});
+        continue;
+      }
       ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, LS(l.l_tri), LS(l.l_elem),
                              LS(l.l_edge));
     }
@@ -507,7 +533,8 @@ static void ml_step(wt_grid* g, double dt) {
     }
     for (int q = 0; q < nl; ++q) {
       LevelState& l = *g->lev[q];
-      ml_tend(l.tab, l.work, l.na, l.ea, p, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, LS(l.l_tend));
+      const Span lt = dense && q == nl - 1 ? Span{lat.rim, lat.n_rim} : LS(l.l_tend);
+      ml_tend(l.tab, l.work, l.na, l.ea, p, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, lt);
     }
   }
   // partial height transform at complete nodes, bottom-up
@@ -975,7 +1002,7 @@ void wt_table_cache_clear(void) {
   g_pair_cache.clear();
 }
 
-const char* wt_kernel_names(void) { return "trisk_vertex,trisk_edge_cell,trisk_tend,trisk_lattice"; }
+const char* wt_kernel_names(void) { return "trisk_vertex,trisk_edge_cell,trisk_tend,trisk_lattice,trisk_lattice_masked"; }
 
 wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
   if (jmin < 0 || jmax < jmin || jmax > 12) {
@@ -1354,7 +1381,8 @@ int wt_get_state(wt_grid* g, int level, double* dh, double* u, uint8_t* na, uint
   return WT_OK;
 }
 
-static void build_batch_plan(const std::vector<wt_grid*>& members, const double* dt, BatchPlan& pl);
+static void build_batch_plan(const std::vector<wt_grid*>& members, const double* dt, BatchPlan& pl,
+                             bool allow_dense = false);
 
 // The listed multilevel step with the launches of independent work merged: per stage, the even
 // prolongation of a pair, then its odd and interior prolongation together, the three
@@ -1368,7 +1396,8 @@ static bool phase_plan_ready(wt_grid* g, double dt) {
   if (!g->step_phases || !(g->use_lists && g->lists_ok)) return false;
   touch_epoch(g);
   if (g->sphase.empty() || g->splan_sig != g->step_sig || g->splan_dt != dt) {
-    build_batch_plan({g}, &dt, g->splan);
+    build_batch_plan({g}, &dt, g->splan, true);
+    g->splan_dense = dense_finest(g);
     g->splan.upload(g->stream);
     phase_prepare(g->splan, g->sphase);
     g->splan_sig = g->step_sig;
@@ -1406,8 +1435,21 @@ static void check_plan(const BatchPlan& pl, const std::vector<wt_grid*>& members
 // the step with a ready plan: launches only (capturable)
 static void ml_step_phases(wt_grid* g) {
   check_plan(g->splan, {g});
+  if (g->splan_dense != dense_finest(g))
+    throw std::runtime_error("step plan built for another choice of the finest level's kernel");
   ++g->state_ver;
-  for (const PhaseArgs& a : g->sphase) phase_launch(g->splan, a, g->stream);
+  LevelState& fl = *g->lev.back();
+  const PhysParams p = phys(g);
+  for (const PhaseArgs& a : g->sphase) {
+    if (a.j0 < 0) {
+      // marker of the finest level's masked lattice launch of stage -1 - j0
+      const StageSpec sp = rk_stage(g->prm.rk, -1 - a.j0, fl.work, g->splan_dt);
+      launch_lattice_masked(fl.lat, fl.work, fl.na, fl.ea, p, fp32_of(g), sp.pdh, sp.pu, sp.c, g->stream,
+                            &g->timer);
+    } else {
+      phase_launch(g->splan, a, g->stream);
+    }
+  }
 }
 
 static void ml_step_run(wt_grid* g, double dt) {
@@ -1505,6 +1547,33 @@ int wt_set_work_lists(wt_grid* g, int enable) {
     HIPCHK(hipStreamSynchronize(g->stream));
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_set_work_lists: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_set_dense_levels(wt_grid* g, double min_fraction) {
+  GridScope scope_(g);
+  if (!g) return fail(WT_EINVAL, "wt_set_dense_levels: null grid");
+  if (!(min_fraction >= 0.0) || !std::isfinite(min_fraction))
+    return fail(WT_EINVAL, "wt_set_dense_levels: min_fraction must be finite and >= 0 (above 1: off)");
+  try {
+    if (min_fraction <= 1.0 && g->multi()) {
+      LevelState& l = g->L(g->jmax);
+      if (!l.lat.ok) {
+        if (g->jmax < 6)
+          return fail(WT_EINVAL, "wt_set_dense_levels: the finest level has no lattice form below level 6");
+        auto lv = cached_level(g->jmax, g->prm.radius, g->prm.omega);
+        LatticeHost lh;
+        if (!build_lattice(*lv, lh)) return fail(WT_EINVAL, "wt_set_dense_levels: no regular tiles");
+        upload_lattice(lh, l.lat);
+      }
+    }
+    g->dense_min = min_fraction;
+    touch_epoch(g);
+  } catch (const std::bad_alloc&) {
+    return fail(WT_ENOMEM, "wt_set_dense_levels: out of memory");
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_set_dense_levels: ") + e.what());
   }
   return WT_OK;
 }
@@ -1951,14 +2020,18 @@ struct wt_ensemble {
 // The batched step replays the phases of ml_step for every member at once (same per-point code
 // and the same dependencies: prolongation pair by pair upwards, intermediates, restriction pair
 // by pair downwards, tendencies, per stage; then the partial height transform downwards).
-static void build_batch_plan(const std::vector<wt_grid*>& members, const double* dt, BatchPlan& pl) {
+// allow_dense (a single grid's merged-phase step): a member whose finest level is dense runs
+// that level's tile elements through the masked lattice kernel, marked in the phase list by a
+// phase with j0 = j1 = -1 - stage after the stage's prolongation, and only its rim through jobs.
+static void build_batch_plan(const std::vector<wt_grid*>& members, const double* dt, BatchPlan& pl,
+                             bool allow_dense) {
   pl.levels.clear();
   pl.pairs.clear();
   pl.jobs.clear();
   pl.phases.clear();
   struct MInfo {
     int lev0, pair0, jmin, jmax;
-    bool wl, fp32;
+    bool wl, fp32, dense;
   };
   std::vector<MInfo> mi;
   int J0 = 1 << 30, J1 = -1;
@@ -1966,7 +2039,8 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
     wt_grid* g = members[k];
     if (!g->multi()) throw std::runtime_error("the batched step needs multilevel members");
     MInfo x{int(pl.levels.size()), int(pl.pairs.size()), g->jmin, g->jmax, g->use_lists && g->lists_ok,
-            g->prm.precision == WT_FP32_TENDENCY};
+            g->prm.precision == WT_FP32_TENDENCY, allow_dense && dense_finest(g)};
+    if (x.dense && members.size() != 1) throw std::runtime_error("batched step: dense finest level of a member");
     const PhysParams p = phys(g);
     for (auto& lp : g->lev) {
       LevelState& l = *lp;
@@ -2008,6 +2082,10 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
       pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, nullptr, nullptr, dense});
     }
   };
+  // a fixed index list (the lattice rim of a dense finest level)
+  auto fixed = [&](int kind, int a, int st, const MInfo& x, const int32_t* lst, int64_t n) {
+    if (n > 0) pl.jobs.push_back(BatchJob{kind, a, st, x.fp32 ? 1 : 0, lst, nullptr, n});
+  };
   auto flush = [&]() {
     const int32_t j1 = int32_t(pl.jobs.size());
     if (j1 > j0) pl.phases.push_back(BatchPhase{j0, j1});
@@ -2029,12 +2107,21 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
         }
       flush();
     }
+    for (size_t k = 0; k < mi.size(); ++k)
+      if (mi[k].dense) pl.phases.push_back(BatchPhase{-1 - st, -1 - st});
     const int kinds[3] = {BK_VERTEX, BK_EDGE_CELL, BK_Q};
     for (int kind : kinds) {
       for (size_t k = 0; k < mi.size(); ++k) {
         wt_grid* g = members[k];
         for (int q = 0; q < int(g->lev.size()); ++q) {
           const LevelState& l = *g->lev[q];
+          if (mi[k].dense && q + 1 == int(g->lev.size())) {
+            const DevLattice& lt = l.lat;
+            if (kind == BK_VERTEX) fixed(kind, mi[k].lev0 + q, st, mi[k], lt.sup_tris, lt.n_sup_tris);
+            else if (kind == BK_EDGE_CELL) fixed(kind, mi[k].lev0 + q, st, mi[k], lt.sup_elems, lt.n_sup_elems);
+            else fixed(kind, mi[k].lev0 + q, st, mi[k], lt.rim_edges, lt.n_rim_edges);
+            continue;
+          }
           if (kind == BK_VERTEX) job(kind, mi[k].lev0 + q, st, mi[k], l.l_tri, l.tab.T);
           else if (kind == BK_EDGE_CELL) job(kind, mi[k].lev0 + q, st, mi[k], l.l_elem, l.tab.N);
           else job(kind, mi[k].lev0 + q, st, mi[k], l.l_edge, l.tab.E);
@@ -2059,8 +2146,12 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
     }
     for (size_t k = 0; k < mi.size(); ++k) {
       wt_grid* g = members[k];
-      for (int q = 0; q < int(g->lev.size()); ++q)
-        job(BK_TEND, mi[k].lev0 + q, st, mi[k], g->lev[q]->l_tend, g->lev[q]->tab.N);
+      for (int q = 0; q < int(g->lev.size()); ++q) {
+        if (mi[k].dense && q + 1 == int(g->lev.size()))
+          fixed(BK_TEND, mi[k].lev0 + q, st, mi[k], g->lev[q]->lat.rim, g->lev[q]->lat.n_rim);
+        else
+          job(BK_TEND, mi[k].lev0 + q, st, mi[k], g->lev[q]->l_tend, g->lev[q]->tab.N);
+      }
     }
     flush();
   }

@@ -257,6 +257,12 @@ void phase_prepare(const BatchPlan& plan, std::vector<PhaseArgs>& out) {
   out.clear();
   for (const BatchPhase& ph : plan.phases) {
     PhaseArgs a{};
+    if (ph.j0 < 0) {
+      // a marker for a launch the caller makes itself (no jobs)
+      a.j0 = ph.j0;
+      out.push_back(a);
+      continue;
+    }
     a.j0 = ph.j0;
     a.nj = ph.j1 - ph.j0;
     if (a.nj > PHASE_MAX_JOBS) throw std::runtime_error("phase step: too many jobs in one phase");
@@ -306,6 +312,7 @@ void phase_prepare_dev(BatchPlan& plan, std::vector<PhaseDev>& out, hipStream_t 
   out.clear();
   std::vector<int32_t> pre;
   for (const BatchPhase& ph : plan.phases) {
+    if (ph.j0 < 0) throw std::runtime_error("ensemble step: a plan with marker phases");
     PhaseDev a{ph.j0, ph.j1 - ph.j0, 0, int32_t(pre.size())};
     int64_t run = 0;
     for (int j = 0; j < a.nj; ++j) {
@@ -407,6 +414,8 @@ void batch_launch(BatchPlan& plan, int blocks_per_cu, int chunk, bool queue, hip
     throw std::runtime_error("batch step: " + std::to_string(blocks_per_cu) + " workgroups per CU, at most " +
                              std::to_string(maxb) + " fit");
   if (chunk < BB || chunk % BB) throw std::runtime_error("batch step: chunk must be a multiple of 256");
+  for (const BatchPhase& ph : plan.phases)
+    if (ph.j0 < 0) throw std::runtime_error("batch step: a plan with marker phases");
   HIPCHK(hipMemsetAsync(plan.d_ctr, 0, ctr_bytes(size_t(plan.nphase)), s));
   const BatchLevel* lv = plan.d_levels;
   const BatchPair* pr = plan.d_pairs;

@@ -53,7 +53,8 @@ struct BatchJob {
   int64_t cnt;
 };
 
-// the jobs of a phase: JB[j0..j1)
+// the jobs of a phase: JB[j0..j1); j0 = j1 < 0 marks a launch the single-grid caller makes itself
+// between phases (the masked lattice stage of a dense finest level, stage -1 - j0)
 struct BatchPhase {
   int32_t j0, j1;
 };

@@ -71,7 +71,7 @@ struct StagePtrs {
   double *o1, *o2;
 };
 
-enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_LATTICE, K_COUNT };
+enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_LATTICE, K_LATTICE_ML, K_COUNT };
 extern const char* const kKernelNames[K_COUNT];
 
 struct Timer {
@@ -97,6 +97,13 @@ struct DevLattice;
 void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32,
                   const StagePtrs& sdh, const StagePtrs& su, const StageOut& c,
                   hipStream_t s, Timer* tm, const DevLattice* lat = nullptr);
+
+// The tile elements of the finest level of an adaptive grid through the masked lattice kernel:
+// tendencies zero at inactive points (na, ea), F, Q, B of every tile element stored for the
+// restriction.  The rim round the lozenge corners is left to the listed kernels.
+void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na, const uint8_t* ea,
+                           const PhysParams& p, bool fp32, const StagePtrs& sdh, const StagePtrs& su,
+                           const StageOut& c, hipStream_t s, Timer* tm);
 
 // q_v, B, F, q_e of one level (no tendency, no stage output): every triangle / element, or the
 // listed ones (nt, ne < 0: the whole level).

@@ -11,7 +11,9 @@
 // phase C h_e, F, q_e and B = g dh + K on the tile + 1 halo, phase D the tendencies
 // d(dh)/dt = -div F and du/dt = -qF^perp - grad B of the tile (eqs. (height), (velo)) fused
 // with the Runge-Kutta stage combination.  The Coriolis parameter comes from the rotated
-// reference circumcentre.
+// reference circumcentre.  On the finest level of an adaptive grid the same kernel runs the level
+// whole (the masked form): tendencies are zero at inactive points, and F, Q and B of the tile
+// elements are stored for the restriction to the coarser level (Sec. 4.1-4.3).
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
@@ -158,8 +160,8 @@ __device__ __forceinline__ AAddr a_address(const ASlot& sl, int L, int n) {
 // for this lozenge's operands never waits for the next lozenge's prefetch.
 enum { EPI_Y = 1, EPI_ACC = 2, EPI_O2 = 4 };
 
-template <typename T, int EPI>
-__global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, StagePtrs pu, StageOut c) {
+template <typename T, int EPI, bool ML>
+__global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, StagePtrs pu, StageOut c, LatML m) {
   __shared__ double s_dh[NA], s_u[3][NA];
   __shared__ T s_qv[2][NB];
   __shared__ T s_F[3][NC];           // mass flux (exactly a T value in both precisions)
@@ -168,6 +170,7 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
   __shared__ T s_gf[4][NB];          // Coriolis parameter of both triangles, northern / southern lozenges
   __shared__ T s_gcurl[6][NB2];      // curl weights of the second B slot
   __shared__ T s_gke[6][NC];         // kinetic-energy weights
+  __shared__ uint8_t s_act[ML ? LBS : 1];   // masked form: activity bits of the tile elements
 
   // Tiles are dealt to the 8 XCDs (workgroups go round-robin) in contiguous bands, so the
   // workgroups running together on one XCD hold neighbouring tiles and share halos in its L2.
@@ -326,6 +329,10 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
       adh = pdh.acc[id];
       au[0] = pu.acc[3 * id]; au[1] = pu.acc[3 * id + 1]; au[2] = pu.acc[3 * id + 2];
     }
+    // masked form: activity of the element's node and edges, parked in LDS until phase D
+    if constexpr (ML)
+      s_act[tid] = uint8_t(uint32_t(m.na[id] != 0) | uint32_t(m.ea[3 * id] != 0) << 1 |
+                           uint32_t(m.ea[3 * id + 1] != 0) << 2 | uint32_t(m.ea[3 * id + 2] != 0) << 3);
     // ---- phase C: F, q_e at the three edges and B at the node, positions [-1, TI+1) x [-1, TJ+1)
     auto c_at = [&](int idx) {
       const int ci = idx / CJ, cj = idx % CJ;
@@ -356,9 +363,15 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
       const double div = gdiv[0] * double(s_F[0][lc]) + gdiv[1] * double(s_F[1][lc]) +
                          gdiv[2] * double(s_F[2][lc]) + gdiv[3] * double(s_F[0][lc - CJ]) +
                          gdiv[4] * double(s_F[1][lc - CJ - 1]) + gdiv[5] * double(s_F[2][lc - 1]);
-      const double k = -div;
+      const uint32_t act = ML ? uint32_t(s_act[tid]) : 0xfu;
+      const double k = (act & 1u) ? -div : 0.0;
       pdh.o1[id] = c.d1 * k + c.a1 * ydh + c.b1 * adh + c.c1 * s_dh[la_d];
       if (EPI & EPI_O2) pdh.o2[id] = c.d2 * k + c.a2 * ydh + c.b2 * adh + c.c2 * s_dh[la_d];
+      if constexpr (ML) {
+        static_cast<T*>(m.B)[id] = s_B[lc];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) m.F[3 * id + d] = double(s_F[d][lc]);
+      }
     }
     // Q_e = (1/d_e) sum_e' w l' F' (q_e + q_e')/2 = (q_e S1 + S2) / 2 with S1 = sum w l'/d F' and
     // S2 = sum w l'/d F' q_e', summed over the distinct stencil edges
@@ -378,6 +391,7 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
         if (u % 5 == 4) __builtin_amdgcn_sched_barrier(0);
       }
       const int lb = (di + 2) * BJ + (dj + 2);
+      const uint32_t act = ML ? uint32_t(s_act[tid]) : 0xfu;
       const T qe[3] = {T(0.5) * (s_qv[0][lb] + s_qv[1][lb - 1]), T(0.5) * (s_qv[0][lb] + s_qv[1][lb]),
                        T(0.5) * (s_qv[1][lb] + s_qv[0][lb - BJ])};
 #pragma unroll
@@ -385,7 +399,8 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
         const T Q = T(0.5) * (qe[d] * S1[d] + S2[d]);
         const int lo = lc + DD0[d] * CJ + DD1[d];
         const T gradB = (s_B[lo] - s_B[lc]) * ginvd[d];
-        const double k = double(-Q - gradB);
+        const double k = (act & (2u << d)) ? double(-Q - gradB) : 0.0;
+        if constexpr (ML) static_cast<T*>(m.Q)[3 * id + d] = Q;
         const double x = s_u[d][la_d];
         pu.o1[3 * id + d] = c.d1 * k + c.a1 * yu[d] + c.b1 * au[d] + c.c1 * x;
         if (EPI & EPI_O2) pu.o2[3 * id + d] = c.d2 * k + c.a2 * yu[d] + c.b2 * au[d] + c.c2 * x;
@@ -397,15 +412,19 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
 }
 
 void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,
-                    const StageOut& c, hipStream_t s) {
+                    const StageOut& c, hipStream_t s, const LatML* ml) {
   const unsigned grid = unsigned((a.ntile + 7) / 8) * 8u;
   const bool ry = c.a1 != 0.0 || c.a2 != 0.0, racc = c.b1 != 0.0 || c.b2 != 0.0;
   if (!pdh.o1 || !pu.o1 || (pdh.o2 == nullptr) != (pu.o2 == nullptr))
     throw std::runtime_error("lattice stage: needs the first output, and the second for both or neither of dh, u");
   const int epi = (ry ? EPI_Y : 0) | (racc ? EPI_ACC : 0) | (pdh.o2 ? EPI_O2 : 0);
+  if (ml && (!ml->na || !ml->ea || !ml->F || !ml->Q || !ml->B))
+    throw std::runtime_error("lattice stage: the masked form needs masks and the F, Q, B outputs");
+  const LatML m = ml ? *ml : LatML{};
   auto go = [&](auto tag, auto e) {
     using T = decltype(tag);
-    k_lattice<T, decltype(e)::value><<<grid, LBS, 0, s>>>(a, pdh, pu, c);
+    if (ml) k_lattice<T, decltype(e)::value, true><<<grid, LBS, 0, s>>>(a, pdh, pu, c, m);
+    else k_lattice<T, decltype(e)::value, false><<<grid, LBS, 0, s>>>(a, pdh, pu, c, m);
   };
   auto dispatch = [&](auto tag) {
     switch (epi) {
@@ -450,13 +469,21 @@ void upload_lattice(const LatticeHost& h, DevLattice& d) {
   d.n_sup_elems = int64_t(h.sup_elems.size());
   d.sup_tris = st;
   d.n_sup_tris = int64_t(h.sup_tris.size());
+  std::vector<int32_t> re;
+  for (int32_t id : h.rim_elems)
+    if (int64_t(id) < 10 * h.n * h.n)
+      for (int q = 0; q < 3; ++q) re.push_back(3 * id + q);
+  int32_t* rep;
+  up(re, &rep);
+  d.rim_edges = rep;
+  d.n_rim_edges = int64_t(re.size());
   d.n_reg_elems = int64_t(d.args.ntile) * LT_TI * LT_TJ * 10;
   d.table_bytes = int64_t(h.tab.size()) * 8;
   d.ok = true;
 }
 
 void free_lattice(DevLattice& d) {
-  const void* ps[] = {d.args.tab, d.args.tiles, d.rim, d.sup_elems, d.sup_tris};
+  const void* ps[] = {d.args.tab, d.args.tiles, d.rim, d.sup_elems, d.sup_tris, d.rim_edges};
   for (const void* p : ps)
     if (p) (void)wt::dfree(const_cast<void*>(p));
   d = DevLattice{};

@@ -22,12 +22,25 @@ struct DevLattice {
   bool ok = false;
   LatArgs args;
   const int32_t *rim = nullptr, *sup_elems = nullptr, *sup_tris = nullptr;
-  int64_t n_rim = 0, n_sup_elems = 0, n_sup_tris = 0, n_reg_elems = 0, table_bytes = 0;
+  const int32_t* rim_edges = nullptr;   // the three edges of every rim element (not the poles)
+  int64_t n_rim = 0, n_sup_elems = 0, n_sup_tris = 0, n_rim_edges = 0, n_reg_elems = 0, table_bytes = 0;
+};
+
+// Finest level of an adaptive grid: the tendencies are zero at inactive points (masks na, ea),
+// and the kernel also stores what the restriction chain to the coarser level reads: the mass
+// flux F (double), qF^perp Q and the Bernoulli function B (compute type) of every tile element.
+struct LatML {
+  const uint8_t* na = nullptr;
+  const uint8_t* ea = nullptr;
+  double* F = nullptr;
+  void* Q = nullptr;
+  void* B = nullptr;
 };
 
 void upload_lattice(const LatticeHost& h, DevLattice& d);
 void free_lattice(DevLattice& d);
+// ml null: the uniform stage; otherwise the masked form above.
 void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,
-                    const StageOut& c, hipStream_t s);
+                    const StageOut& c, hipStream_t s, const LatML* ml = nullptr);
 
 }  // namespace wt

@@ -104,6 +104,7 @@ SIGNATURES = [
     ("wt_debug_force_drop", C.c_int, [_P, C.c_int, C.c_int64]),
     ("wt_set_work_lists", C.c_int, [_P, C.c_int]),
     ("wt_set_step_phases", C.c_int, [_P, C.c_int]),
+    ("wt_set_dense_levels", C.c_int, [_P, C.c_double]),
     ("wt_ensemble_create", _P, [C.POINTER(_P), C.c_int]),
     ("wt_ensemble_destroy", None, [_P]),
     ("wt_ensemble_adapt", C.c_int, [_P, _D]),
@@ -415,6 +416,11 @@ class Grid:
     def set_step_phases(self, enable):
         """Merge the independent launches of the listed step (default) or launch per kernel."""
         _check(load().wt_set_step_phases(self._h, 1 if enable else 0))
+
+    def set_dense_levels(self, min_fraction):
+        """Run the finest level through the masked lattice kernel when its listed support holds
+        at least `min_fraction` of its elements (above 1: off, the default)."""
+        _check(load().wt_set_dense_levels(self._h, float(min_fraction)))
 
     def debug_force_drop(self, level, patch):
         """Withhold the children rule of a patch at the next gated adapt (test hook)."""
