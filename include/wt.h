@@ -214,10 +214,11 @@ int wt_set_step_phases(wt_grid* g, int enable);
 /* Dense finest level (Sec. 3.1 stage on the finest level, Sec. 4.1-4.3 restriction from it):
  * when the 3-ring support of the finest level's active points holds at least min_fraction of
  * its elements (always, when the stage runs over whole levels), the level's tile elements run
- * whole through the lattice kernel of the uniform stage in a masked form -- tendencies zero at
+ * through the lattice kernel of the uniform stage in a masked form -- tendencies zero at
  * inactive points, and the mass flux F, qF^perp Q and the Bernoulli function B of every element
- * stored for the restriction chain -- and only the rim round the twelve lozenge corners through
- * the listed table-driven kernels.  Results agree with the listed stage to round-off (the lattice
+ * stored for the restriction chain; with work lists only the tiles of each lozenge that hold a
+ * point of the 5-ring support -- and only the rim round the twelve lozenge corners through the
+ * listed table-driven kernels.  Results agree with the listed stage to round-off (the lattice
  * kernel sums in another order), not bitwise.  min_fraction > 1 turns it off (the default);
  * enabling builds the level's lattice geometry (finest level 6 or more, inviscid shallow-water
  * form only: other forms and ensemble steps keep the listed kernels).  WT_EINVAL for a negative

@@ -68,6 +68,10 @@ struct LevelState {
   uint8_t* pf = nullptr;        // 8 x 8 patch flags of the ring dilation
   int32_t* plist = nullptr;     // patches the ring dilation visits (count after the list)
   WorkList l_tri, l_elem, l_edge, l_node, l_tend;
+  // finest level, masked lattice form: tiles of each lozenge holding support points
+  uint8_t* tflag = nullptr;
+  int32_t* tcount = nullptr;
+  bool tflag_ok = false;   // the flags match the current work lists
 };
 
 struct PairState {
@@ -164,7 +168,7 @@ static void free_work(LevelState& ls) {
                 ls.na, ls.ea, ls.nn, ls.ne, ls.sn, ls.se,
                 ls.rn, ls.re, ls.stats, ls.X, ls.Pr, ls.allow, ls.dropped, ls.viol,
                 ls.snap_dh, ls.snap_u, ls.snap_na, ls.snap_ea, ls.s3n, ls.s3e, ls.s5n, ls.s5e, ls.rn_, ls.re_, ls.pred_t,
-                ls.pred_e, ls.pred_a, ls.pf, ls.plist};
+                ls.pred_e, ls.pred_a, ls.pf, ls.plist, ls.tflag, ls.tcount};
   for (void* p : ps)
     if (p) (void)wt::dfree(p);
   w = DevWork{};
@@ -377,6 +381,7 @@ static void touch_epoch(wt_grid* g) {
   sig.push_back(nub);
   sig.push_back(g->prm.equations);
   sig.push_back(dense_finest(g));
+  sig.push_back(g->lev.back()->tflag_ok);
   auto add = [&](const WorkList& L) {
     sig.push_back(reinterpret_cast<int64_t>(L.idx));
     sig.push_back(L.bound);
@@ -403,8 +408,23 @@ static void touch_epoch(wt_grid* g) {
 
 // Support rings of the active points of every level and the index lists of the adaptive stage
 // (ballot / prefix-scan compaction).  Called whenever the masks change.
+// Tile flags of the finest level's masked lattice form from the 5-ring support of the work lists
+// just built (without lists the masked form runs every tile).
+static void update_tile_flags(wt_grid* g) {
+  LevelState& l = *g->lev.back();
+  l.tflag_ok = false;
+  if (!g->multi() || !(g->dense_min <= 1.0) || !l.lat.ok || !(g->use_lists && g->lists_ok)) return;
+  if (!l.tflag) {
+    HIPCHK(wt::dmalloc(&l.tflag, size_t(l.lat.args.ntile) * 10));
+    HIPCHK(wt::dmalloc(&l.tcount, sizeof(int32_t)));
+  }
+  lattice_tile_flags(l.lat, l.s5n, l.s5e, l.tflag, l.tcount, g->stream);
+  l.tflag_ok = true;
+}
+
 static void build_work_lists(wt_grid* g, bool touch = true) {
   g->lists_ok = false;
+  g->lev.back()->tflag_ok = false;
   if (!g->multi() || !g->use_lists) {
     if (touch) touch_epoch(g);
     return;
@@ -486,7 +506,23 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
   pred_batch(pr.data(), int(pr.size()), s);
   cb.run(s);
   g->lists_ok = true;
+  update_tile_flags(g);
   if (touch) touch_epoch(g);
+}
+
+// The finest level's stage through the masked lattice kernel (flagged tiles only when the flags
+// are current; their count is read back only for the byte count of a timed launch).
+static void dense_stage(wt_grid* g, const StageSpec& sp, const PhysParams& p, bool fp32) {
+  LevelState& l = *g->lev.back();
+  const uint8_t* tf = l.tflag_ok ? l.tflag : nullptr;
+  int64_t flagged = 0;
+  if (tf && g->timer.enabled) {
+    int32_t c = 0;
+    HIPCHK(hipMemcpyAsync(&c, l.tcount, sizeof(c), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    flagged = c;
+  }
+  launch_lattice_masked(l.lat, l.work, l.na, l.ea, tf, flagged, p, fp32, sp.pdh, sp.pu, sp.c, g->stream, &g->timer);
 }
 
 static void ml_step(wt_grid* g, double dt) {
@@ -517,7 +553,7 @@ static void ml_step(wt_grid* g, double dt) {
       LevelState& l = *g->lev[q];
       if (dense && q == nl - 1) {
         // the tile elements whole through the lattice kernel, then the rim from the tables
-        launch_lattice_masked(lat, l.work, l.na, l.ea, p, fp32, sp[q].pdh, sp[q].pu, sp[q].c, g->stream, &g->timer);
+        dense_stage(g, sp[q], p, fp32);
         ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, Span{lat.sup_tris, lat.n_sup_tris},
                                Span{lat.sup_elems, lat.n_sup_elems}, Span{lat.rim_edges, lat.n_rim_edges});
         continue;
@@ -1443,9 +1479,7 @@ static void ml_step_phases(wt_grid* g) {
   for (const PhaseArgs& a : g->sphase) {
     if (a.j0 < 0) {
       // marker of the finest level's masked lattice launch of stage -1 - j0
-      const StageSpec sp = rk_stage(g->prm.rk, -1 - a.j0, fl.work, g->splan_dt);
-      launch_lattice_masked(fl.lat, fl.work, fl.na, fl.ea, p, fp32_of(g), sp.pdh, sp.pu, sp.c, g->stream,
-                            &g->timer);
+      dense_stage(g, rk_stage(g->prm.rk, -1 - a.j0, fl.work, g->splan_dt), p, fp32_of(g));
     } else {
       phase_launch(g->splan, a, g->stream);
     }
@@ -1569,6 +1603,7 @@ int wt_set_dense_levels(wt_grid* g, double min_fraction) {
       }
     }
     g->dense_min = min_fraction;
+    update_tile_flags(g);
     touch_epoch(g);
   } catch (const std::bad_alloc&) {
     return fail(WT_ENOMEM, "wt_set_dense_levels: out of memory");

@@ -100,10 +100,12 @@ void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32
 
 // The tile elements of the finest level of an adaptive grid through the masked lattice kernel:
 // tendencies zero at inactive points (na, ea), F, Q, B of every tile element stored for the
-// restriction.  The rim round the lozenge corners is left to the listed kernels.
+// restriction.  tflag (10 per tile; null: every tile) limits it to the tiles of each lozenge that
+// hold support points, `flagged` of them (for the byte count).  The rim round the lozenge
+// corners is left to the listed kernels.
 void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na, const uint8_t* ea,
-                           const PhysParams& p, bool fp32, const StagePtrs& sdh, const StagePtrs& su,
-                           const StageOut& c, hipStream_t s, Timer* tm);
+                           const uint8_t* tflag, int64_t flagged, const PhysParams& p, bool fp32,
+                           const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm);
 
 // q_v, B, F, q_e of one level (no tendency, no stage output): every triangle / element, or the
 // listed ones (nt, ne < 0: the whole level).

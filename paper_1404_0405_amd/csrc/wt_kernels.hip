@@ -227,8 +227,8 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
 }
 
 void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na, const uint8_t* ea,
-                           const PhysParams& p, bool fp32, const StagePtrs& sdh, const StagePtrs& su,
-                           const StageOut& c_in, hipStream_t s, Timer* tm) {
+                           const uint8_t* tflag, int64_t flagged, const PhysParams& p, bool fp32, const StagePtrs& sdh,
+                           const StagePtrs& su, const StageOut& c_in, hipStream_t s, Timer* tm) {
   if (!lat.ok) throw std::runtime_error("masked lattice stage: the level has no lattice form");
   if (p.nu != 0.0 || p.adv) throw std::runtime_error("masked lattice stage: inviscid shallow-water form only");
   // a stage array that is the stage input itself is read once (as in the uniform stage)
@@ -241,23 +241,26 @@ void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na,
     c.c1 += c.b1; c.b1 = 0.0;
     c.c2 += c.b2; c.b2 = 0.0;
   }
-  // algorithmic bytes per element: the uniform kernel's (stage input, Runge-Kutta arrays, shared
-  // geometry) plus the four mask bytes and the stored F (3 doubles), Q (3) and B (1)
+  // algorithmic bytes per element of the flagged tiles (all tiles without flags): the uniform
+  // kernel's (stage input, Runge-Kutta arrays, the shared geometry's share) plus the four mask
+  // bytes and the stored F (3 doubles), Q (3) and B (1)
   int r = 0;
   if (c.a1 != 0.0 || c.a2 != 0.0) ++r;
   if (c.b1 != 0.0 || c.b2 != 0.0) ++r;
   if (sdh.o1) ++r;
   if (sdh.o2) ++r;
   const double sz = fp32 ? 4.0 : 8.0;
-  const double nreg = double(lat.n_reg_elems);
+  const int64_t units = tflag ? flagged * LT_TI * LT_TJ : lat.n_reg_elems;
+  const double nreg = double(units);
   TimedLaunch tl_(tm, K_LATTICE_ML, s,
-                  nreg * (32.0 + 4.0 * 8.0 * r + 4.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0, lat.n_reg_elems);
+                  nreg * (32.0 + 4.0 * 8.0 * r + 4.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0, units);
   LatArgs a = lat.args;
   a.g = p.g;
   a.H = p.H;
   LatML m;
   m.na = na;
   m.ea = ea;
+  m.tflag = tflag;
   m.F = static_cast<double*>(w.F);
   m.Q = w.Q;
   m.B = w.B;

@@ -178,6 +178,16 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
   const int per = (a.ntile + 7) >> 3;
   const int t = (b & 7) * per + (b >> 3);
   if (t >= a.ntile) return;  // uniform per workgroup
+  // masked form: only the lozenges in which this tile holds a point of the support (all when
+  // no flags are given)
+  uint32_t lmask = 0x3ffu;
+  if constexpr (ML) {
+    if (m.tflag) {
+      lmask = 0u;
+      for (int L = 0; L < 10; ++L) lmask |= uint32_t(m.tflag[t * 10 + L] != 0) << L;
+      if (lmask == 0u) return;  // uniform per workgroup
+    }
+  }
   const int i0 = a.tiles[2 * t], j0 = a.tiles[2 * t + 1];
   const int n = a.n;
   const int64_t W = a.W, W2 = a.W2;
@@ -270,14 +280,15 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
       r_neg[sl] = ad.neg;
     }
   };
-  issue_a(0);
+  const int L0 = ML ? __builtin_ctz(lmask) : 0;
+  issue_a(L0);
 
   const int la_d = (di + 2) * AJ + (dj + 2);   // tile element in the A layout
   const int lc = (di + 1) * CJ + (dj + 1);     // tile element in the C layout
 
   // One lozenge; the next lozenge's input is prefetched in all but the last.  The last is a
   // separate copy so that no memory operation sits under a run-time branch.
-  auto lozenge = [&](int L, auto prefetch) {
+  auto lozenge = [&](int L, int Lnext, auto prefetch) {
     __syncthreads();   // the previous lozenge's phase D has read s_dh, s_u
     s_dh[tid] = r_dh[0];
     s_u[0][tid] = (r_neg[0] & 1) ? -r_u0[0] : r_u0[0];
@@ -291,7 +302,7 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
     }
     // stage-combination operands of this lozenge, then the next lozenge's input
     const int64_t id = (int64_t(L) * n + i0 + di) * n + (j0 + dj);
-    if constexpr (decltype(prefetch)::value) issue_a(L + 1);
+    if constexpr (decltype(prefetch)::value) issue_a(Lnext);
     __syncthreads();
 
     // ---- phase B: q_v of both triangles, positions [-2, TI+1) x [-2, TJ+1)
@@ -407,8 +418,51 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
       }
     }
   };
-  for (int L = 0; L < 9; ++L) lozenge(L, std::true_type{});
-  lozenge(9, std::false_type{});
+  if constexpr (ML) {
+    uint32_t rest = lmask & (lmask - 1u);   // the flagged lozenges after the first
+    int L = L0;
+    while (rest) {
+      const int Ln = __builtin_ctz(rest);
+      rest &= rest - 1u;
+      lozenge(L, Ln, std::true_type{});
+      L = Ln;
+    }
+    lozenge(L, 0, std::false_type{});
+  } else {
+    for (int L = 0; L < 9; ++L) lozenge(L, L + 1, std::true_type{});
+    lozenge(9, 0, std::false_type{});
+  }
+}
+
+// Tile flags of the masked form: flag[10 t + L] = 1 when tile t of lozenge L holds a node or an
+// edge of the 5-ring support (sn, se); every point whose F, Q, B or tendency is read lies within
+// four rings of an active point, so unflagged tiles have nothing to compute.  *count receives the
+// number of flagged pairs (cleared here first).
+__global__ void k_tile_count_clear(int32_t* count) {
+  if (threadIdx.x == 0) *count = 0;
+}
+
+__global__ __launch_bounds__(LBS) void k_tile_flags(const int32_t* __restrict__ tiles, int n,
+                                                    const uint8_t* __restrict__ sn, const uint8_t* __restrict__ se,
+                                                    uint8_t* __restrict__ flag, int32_t* __restrict__ count) {
+  const int t = blockIdx.x, L = blockIdx.y;
+  const int i0 = tiles[2 * t], j0 = tiles[2 * t + 1];
+  const int di = threadIdx.x / LT_TJ, dj = threadIdx.x % LT_TJ;
+  const int64_t id = (int64_t(L) * n + i0 + di) * n + (j0 + dj);
+  const int v = (sn[id] | se[3 * id] | se[3 * id + 1] | se[3 * id + 2]) != 0;
+  const int any = __syncthreads_or(v);
+  if (threadIdx.x == 0) {
+    flag[10 * t + L] = uint8_t(any != 0);
+    if (any) atomicAdd(count, 1);
+  }
+}
+
+void lattice_tile_flags(const DevLattice& lat, const uint8_t* sn, const uint8_t* se, uint8_t* flag, int32_t* count,
+                        hipStream_t s) {
+  if (!lat.ok || lat.args.ntile <= 0) return;
+  k_tile_count_clear<<<1, 64, 0, s>>>(count);
+  k_tile_flags<<<dim3(unsigned(lat.args.ntile), 10u), LBS, 0, s>>>(lat.args.tiles, lat.args.n, sn, se, flag, count);
+  HIPCHK(hipGetLastError());
 }
 
 void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,

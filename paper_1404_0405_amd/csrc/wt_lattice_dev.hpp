@@ -32,11 +32,16 @@ struct DevLattice {
 struct LatML {
   const uint8_t* na = nullptr;
   const uint8_t* ea = nullptr;
+  const uint8_t* tflag = nullptr;   // per (tile, lozenge): 1 if it holds support points (null: all)
   double* F = nullptr;
   void* Q = nullptr;
   void* B = nullptr;
 };
 
+// flag[10 t + L] = 1 when tile t of lozenge L holds a point of the support (sn, se); *count the
+// number of flagged pairs.
+void lattice_tile_flags(const DevLattice& lat, const uint8_t* sn, const uint8_t* se, uint8_t* flag, int32_t* count,
+                        hipStream_t s);
 void upload_lattice(const LatticeHost& h, DevLattice& d);
 void free_lattice(DevLattice& d);
 // ml null: the uniform stage; otherwise the masked form above.

@@ -111,8 +111,9 @@ def test_dense_launch_forms_agree_bitwise(rk, prec):
 
 def test_dense_agrees_with_listed_stage_and_switches_by_density():
     """The same run with and without the dense finest level agrees to round-off (FP64, rel
-    L-inf 1e-12 on every level, identical masks).  A threshold above the level's density keeps
-    the listed stage (bitwise equal to dense off, no masked launch); 1.5 turns it off."""
+    L-inf 1e-12 on every level, identical masks), the masked kernel running only the tiles that
+    hold support points.  A threshold above the level's density keeps the listed stage (bitwise
+    equal to dense off, no masked launch); 1.5 turns it off."""
     jmin, jmax, eps = 4, 7, 5e-3
     out = {}
     for mode in ("off", "on", "high", "above1"):
@@ -130,10 +131,14 @@ def test_dense_agrees_with_listed_stage_and_switches_by_density():
                 g.adapt(eps)
                 g.step(dt)
             out[mode] = ([g.get_state(j) for j in range(jmin, jmax + 1)], _masked_launches(g),
-                         g.diagnostics()[0].active_nodes[jmax])
+                         g.diagnostics()[0].active_nodes[jmax], wt.kernel_units(g, "trisk_lattice_masked"))
     n_fine = 10 * 4 ** jmax + 2
-    _say(f"finest level active nodes {out['off'][2]} of {n_fine}")
+    tiles = wt.host_lattice_check(jmax)[0]
+    _say(f"finest level active nodes {out['off'][2]} of {n_fine}; masked kernel ran {out['on'][3]} of "
+         f"{tiles * 512 * 10} tile elements")
     assert out["off"][2] < 0.5 * n_fine
+    # the masked kernel skips the tiles of each lozenge without support points
+    assert 0 < out["on"][3] < tiles * 512 * 10 and out["on"][3] % 512 == 0
     assert out["on"][1] == 20 and out["off"][1] == 0 and out["high"][1] == 0 and out["above1"][1] == 0
     for mode in ("high", "above1"):
         for s1, s2 in zip(out["off"][0], out[mode][0]):
