@@ -271,3 +271,24 @@ def perfect_gate_bound(H, eps, dt, p, steps, scheme="rk4"):
         # continue from the blanket run so both series see the same states
         restore(H, blanket_state)
     return blanket, gated, misses
+
+
+def zone_turnover(H, eps, dt, p, steps, scheme="rk4"):
+    """The most any adjacent-zone gate can drop under a judge that asks only that every point the
+    blanket zone requires after the step was active during it (a looser judge than the threshold
+    test above, and one that covers gates on any rule, not just the children rule): per step, the
+    points active under the blanket zone before the step that the blanket zone of the state after
+    the step no longer holds.  Returns (dropped, active) per step; the blanket run continues."""
+    out = []
+    H.adapt(eps)
+    for _ in range(steps):
+        before = [(H.node_act[j].copy(), H.edge_act[j].copy()) for j in H.levels]
+        H.step(dt, p, scheme)
+        H.adapt(eps)
+        gone = active = 0
+        for (bn, be), j in zip(before, H.levels):
+            gone += int((bn & ~H.node_act[j]).sum()) + int((be & ~H.edge_act[j]).sum())
+            active += int(bn.sum()) + int(be.sum())
+        out.append((gone, active))
+    return out
+

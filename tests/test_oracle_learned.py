@@ -138,3 +138,24 @@ def test_no_gate_gains_much_under_the_threshold_test():
     gain = 1.0 - sum(gated) / sum(blanket)
     print(f"perfect gate: {gain:.4f} of the active dof, {misses} misses in 6 steps")
     assert gain < 0.02, gain
+
+
+@pytest.mark.slow
+def test_zone_turnover_bounds_every_gate():
+    """Under the loosest judge (every point the blanket zone requires after the step was active
+    during it) a gate can drop at most the points that leave the blanket zone within one step: on
+    the jet (levels 4..7, eps 5e-3) under 5 % of the active dof per step, on the turbulence start
+    (levels 3..6, eps 1e-2) none, since its zone only grows."""
+    H, p, dt = _jet(4, 7)
+    r = learned.zone_turnover(H, 5e-3, dt, p, 6)
+    frac = [g / a for g, a in r]
+    print("jet zone turnover per step", [f"{f:.4f}" for f in frac])
+    assert max(frac) < 0.05 and sum(g for g, _ in r) > 0
+    H = Hierarchy(3, 6)
+    g = H.g[6]
+    dh, u, Hd = inputs.turbulence(g.xyz, g.e_mid, g.e_tan)
+    H.set_state(6, dh, u)
+    p = trisk.Params(mean_depth=Hd)
+    r = learned.zone_turnover(H, 1e-2, 60.0, p, 4)
+    assert all(g == 0 for g, _ in r), r
+
