@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "trisk_lattice": {
         "sources": ("paper_1404_0405_amd/csrc/wt_lattice.hip", "paper_1404_0405_amd/csrc/wt_lattice_dev.hpp"),
-        "sha256": ("ec08c740b852bed348b84f672177da9d9175b7af9d65d3b0021e82b171777206",
-                   "67492eda7ad1558bc8dfcf39ef6757221c2ebd22ca59db129d4cf93d8c38dd94"),
-        "level": 10, "fetch_kib": 673320.1, "write_kib": 572320.5, "fetch_scale": 2.000, "write_scale": 1.000,
+        "sha256": ("09fa2baef353a9e5881b87efcbea19fcd45f6faadce364e96235d08d2b5c7c92",
+                   "95585fe743f23e6ec3c70561e12091327b6aab3d28cd0be88de41d69e84473a5"),
+        "level": 10, "fetch_kib": 673009.1, "write_kib": 572320.4, "fetch_scale": 2.000, "write_scale": 1.000,
     },
 }
 
