@@ -698,8 +698,8 @@ def main():
                                                    ensemble_members=args.ensemble_members)}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "the multi-GPU path is not part of it", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (--gpus {args.gpus} requested); "
+              "a multi-GPU path is not implemented", file=sys.stderr)
         sys.exit(2)
     _progress("uniform stage")
     res, (N, E, T), dt = run_gpu(args)

@@ -30,9 +30,9 @@ __device__ __forceinline__ T pair_pred(const DevPair& P, int64_t e, const int32_
   int32_t tl = e_v[2 * e], tr = e_v[2 * e + 1];
   T s = T(0);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s += T(P.w_pl[9 * e + k]) * T(uc[P.v_sten[9 * tl + k]]);
+  for (int k = 0; k < 9; ++k) s += tv<T>(P.w_pl, P.w_pl_f, 9 * e + k) * T(uc[P.v_sten[9 * tl + k]]);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s += T(P.w_pr[9 * e + k]) * T(uc[P.v_sten[9 * tr + k]]);
+  for (int k = 0; k < 9; ++k) s += tv<T>(P.w_pr, P.w_pr_f, 9 * e + k) * T(uc[P.v_sten[9 * tr + k]]);
   return s;
 }
 
@@ -41,7 +41,7 @@ template <typename T>
 __device__ __forceinline__ T int_pred(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
   T v = T(0);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) v += T(P.w_int[27 * t + 9 * s + k]) * T(uc[P.v_sten[9 * t + k]]);
+  for (int k = 0; k < 9; ++k) v += tv<T>(P.w_int, P.w_int_f, 27 * t + 9 * s + k) * T(uc[P.v_sten[9 * t + k]]);
   return v;
 }
 
@@ -107,10 +107,10 @@ __device__ __forceinline__ void body_vertex(int64_t t, const DevTables& tb, cons
   T z = T(0), hv = T(0);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    z += T(tb.t_curl[3 * t + s]) * T(u[tb.t_e[3 * t + s]]);
-    hv += T(tb.t_R[3 * t + s]) * (T(H) + T(dh[tb.t_n[3 * t + s]]));
+    z += tv<T>(tb.t_curl, tb.t_curl_f, 3 * t + s) * T(u[tb.t_e[3 * t + s]]);
+    hv += tv<T>(tb.t_R, tb.t_R_f, 3 * t + s) * (T(H) + T(dh[tb.t_n[3 * t + s]]));
   }
-  qv[t] = (z + T(tb.f_v[t])) / hv;
+  qv[t] = (z + tv<T>(tb.f_v, tb.f_v_f, t)) / hv;
 }
 
 // B_i = g dh_i + K_i at node id; F_e = h_e u_e and q_e at its three edges.  Viscous form
@@ -125,8 +125,8 @@ __device__ __forceinline__ void body_edge_cell(int64_t id, const DevTables& tb, 
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     T ue = T(u[tb.c_e[6 * id + k]]);
-    K += T(tb.c_ke[6 * id + k]) * ue * ue;
-    if (ph.nu != 0.0) D += T(tb.c_div[6 * id + k]) * ue;
+    K += tv<T>(tb.c_ke, tb.c_ke_f, 6 * id + k) * ue * ue;
+    if (ph.nu != 0.0) D += tv<T>(tb.c_div, tb.c_div_f, 6 * id + k) * ue;
   }
   T b = T(ph.g) * T(dh[id]) + K;
   if (ph.nu != 0.0) b -= T(ph.nu) * D;
@@ -150,7 +150,7 @@ template <typename T>
 __device__ __forceinline__ T tri_curl(int64_t v, const DevTables& tb, const double* __restrict__ u) {
   T z = T(0);
 #pragma unroll
-  for (int s = 0; s < 3; ++s) z += T(tb.t_curl[3 * v + s]) * T(u[tb.t_e[3 * v + s]]);
+  for (int s = 0; s < 3; ++s) z += tv<T>(tb.t_curl, tb.t_curl_f, 3 * v + s) * T(u[tb.t_e[3 * v + s]]);
   return z;
 }
 
@@ -165,10 +165,10 @@ __device__ __forceinline__ void body_Q(int64_t e, const DevTables& tb, const dou
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
     int32_t ep = tb.ecp[10 * e + k];
-    s += T(tb.wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
+    s += tv<T>(tb.wl, tb.wl_f, 10 * e + k) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
   }
   if (nu != 0.0)
-    s += T(nu) * (tri_curl<T>(tb.e_v[2 * e], tb, u) - tri_curl<T>(tb.e_v[2 * e + 1], tb, u)) / T(tb.l_e[e]);
+    s += T(nu) * (tri_curl<T>(tb.e_v[2 * e], tb, u) - tri_curl<T>(tb.e_v[2 * e + 1], tb, u)) / tv<T>(tb.l_e, tb.l_e_f, e);
   Q[e] = s;
 }
 
@@ -252,7 +252,7 @@ __device__ __forceinline__ void body_tend_ml(int64_t id, const DevTables& tb, co
   for (int d = 0; d < 3; ++d) {
     int64_t e = 3 * id + d;
     double ku = 0.0;
-    if (ea[e] && !adv) ku = double(-Q[e] - (B[tb.e_c[2 * e + 1]] - B[tb.e_c[2 * e]]) * T(tb.inv_d[e]));
+    if (ea[e] && !adv) ku = double(-Q[e] - (B[tb.e_c[2 * e + 1]] - B[tb.e_c[2 * e]]) * tv<T>(tb.inv_d, tb.inv_d_f, e));
     rk_out(e, ku, pu, c);
   }
 }

@@ -30,7 +30,20 @@ struct DevTables {
   double* A_i = nullptr;      // N
   double* l_e = nullptr;      // E
   double* d_e = nullptr;      // E
+  // single-precision copies of the weights the single-precision stage reads (each the same
+  // rounding as converting the FP64 value on load, so results are unchanged; half the bytes)
+  float *c_div_f = nullptr, *c_ke_f = nullptr, *inv_d_f = nullptr, *wl_f = nullptr;
+  float *t_curl_f = nullptr, *t_R_f = nullptr, *f_v_f = nullptr, *l_e_f = nullptr;
 };
+
+// A table value in the compute type T: the FP64 table for double, its single-precision copy
+// for float.
+template <typename T>
+__host__ __device__ __forceinline__ T tv(const double* d, const float* f, int64_t i);
+template <>
+__host__ __device__ __forceinline__ double tv<double>(const double* d, const float*, int64_t i) { return d[i]; }
+template <>
+__host__ __device__ __forceinline__ float tv<float>(const double*, const float* f, int64_t i) { return f[i]; }
 
 // Work buffers of one level (double unless noted).
 struct DevWork {

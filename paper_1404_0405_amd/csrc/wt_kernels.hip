@@ -117,11 +117,11 @@ __global__ __launch_bounds__(BS) void k_tend(int64_t N, int64_t n_elem,
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
       int32_t ep = ecp[10 * e + k];
-      Q += T(wl[10 * e + k]) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
+      Q += tv<T>(wl, tb.wl_f, 10 * e + k) * T(F[ep]) * (T(0.5) * (q0 + qe[ep]));
     }
     if (nu != 0.0)
-      Q += T(nu) * (tri_curl<T>(tb.e_v[2 * e], tb, pu.x) - tri_curl<T>(tb.e_v[2 * e + 1], tb, pu.x)) / T(tb.l_e[e]);
-    T gradB = (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * T(inv_d[e]);
+      Q += T(nu) * (tri_curl<T>(tb.e_v[2 * e], tb, pu.x) - tri_curl<T>(tb.e_v[2 * e + 1], tb, pu.x)) / tv<T>(tb.l_e, tb.l_e_f, e);
+    T gradB = (B[e_c[2 * e + 1]] - B[e_c[2 * e]]) * tv<T>(inv_d, tb.inv_d_f, e);
     rk_epilogue(e, double(-Q - gradB), pu, c);
   }
 }
@@ -445,11 +445,21 @@ void upload_tables(const Level& L, const std::vector<double>& A_i, DevTables& t)
   t.A_i = dev_upload(A_i);
   t.l_e = dev_upload(L.l_e);
   t.d_e = dev_upload(L.d_e);
+  auto f32 = [](const std::vector<double>& v) { return dev_upload(std::vector<float>(v.begin(), v.end())); };
+  t.c_div_f = f32(c_div);
+  t.c_ke_f = f32(c_ke);
+  t.inv_d_f = f32(inv_d);
+  t.wl_f = f32(wl);
+  t.t_curl_f = f32(t_curl);
+  t.t_R_f = f32(t_R);
+  t.f_v_f = f32(L.f_v);
+  t.l_e_f = f32(L.l_e);
 }
 
 void free_tables(DevTables& t) {
   void* ps[] = {t.c_e, t.c_div, t.c_ke, t.e_c, t.e_v, t.inv_d, t.ecp, t.wl,
-                t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, t.A_i, t.l_e, t.d_e};
+                t.t_n, t.t_e, t.t_curl, t.t_R, t.f_v, t.A_i, t.l_e, t.d_e,
+                t.c_div_f, t.c_ke_f, t.inv_d_f, t.wl_f, t.t_curl_f, t.t_R_f, t.f_v_f, t.l_e_f};
   for (void* p : ps)
     if (p) (void)wt::dfree(p);
   t = DevTables{};

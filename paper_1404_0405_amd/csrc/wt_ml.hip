@@ -1040,11 +1040,13 @@ void upload_pair(const PairTables& P, DevPair& d) {
   d.mk = up(P.mk); d.int_e = up(P.int_e); d.v_sten = up(P.v_sten); d.rf_f = up(P.rf_f); d.rf_c = up(P.rf_c);
   d.st = up(P.st); d.s_upd = up(P.s_upd); d.w_int = up(P.w_int); d.w_pl = up(P.w_pl); d.w_pr = up(P.w_pr);
   d.rf_fw = up(P.rf_fw); d.rf_cw = up(P.rf_cw);
+  auto f32 = [](const std::vector<double>& v) { return up(std::vector<float>(v.begin(), v.end())); };
+  d.w_int_f = f32(P.w_int); d.w_pl_f = f32(P.w_pl); d.w_pr_f = f32(P.w_pr);
 }
 
 void free_pair(DevPair& d) {
   const void* ps[] = {d.even, d.mid, d.h1, d.h2, d.cells, d.mk, d.int_e, d.v_sten, d.rf_f, d.rf_c,
-                      d.st, d.s_upd, d.w_int, d.w_pl, d.w_pr, d.rf_fw, d.rf_cw};
+                      d.st, d.s_upd, d.w_int, d.w_pl, d.w_pr, d.rf_fw, d.rf_cw, d.w_int_f, d.w_pl_f, d.w_pr_f};
   for (const void* p : ps)
     if (p) (void)wt::dfree(const_cast<void*>(p));
   d = DevPair{};

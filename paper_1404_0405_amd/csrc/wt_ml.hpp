@@ -20,6 +20,7 @@ struct DevPair {
   int64_t Nc, Ec, Tc, Nf, Ef;
   const int32_t *even, *mid, *h1, *h2, *cells, *mk, *int_e, *v_sten, *rf_f, *rf_c;
   const double *st, *s_upd, *w_int, *w_pl, *w_pr, *rf_fw, *rf_cw;
+  const float *w_int_f, *w_pl_f, *w_pr_f;   // single-precision copies of the velocity predictions
 };
 
 constexpr int MAX_LEVJOBS = 16;   // level or pair jobs per batched launch
