@@ -206,8 +206,8 @@ int wt_set_work_lists(wt_grid* g, int enable);
 /* The listed step of a multilevel grid (Sec. 3.1 per stage: prolongation, intermediates,
  * restriction, tendencies; then the partial height transform) merges the launches of work that
  * does not depend on each other -- the same kernel on every level, the odd and interior
- * prolongation of a pair, the edge and B restriction of a pair -- into one launch each (84
- * launches per RK4 step for five levels instead of ~180).  enable = 0 launches one kernel per
+ * prolongation of a pair, the edge and B restriction of a pair -- into one launch each (88
+ * launches per RK4 step for five levels instead of ~185).  enable = 0 launches one kernel per
  * level and kind (test hook: the two agree bitwise).  Default: enabled.  Synchronises. */
 int wt_set_step_phases(wt_grid* g, int enable);
 
@@ -301,8 +301,8 @@ int wt_host_level_tables(int level, double radius, double omega, double* A_i_hos
  * (eq. (WTupd)); A_c_host[Nc] effective coarse cell areas; v_sten_host[9Tc] the coarse edges of
  * each coarse triangle's velocity stencil; w_int_host[27Tc] prediction weights of its three
  * interior fine edges (Sec. 4.1); w_pl_host[9Ec], w_pr_host[9Ec] weights of (p1 - p2) on the
- * stencils of the left / right triangle; rf_f_host[3Ec], rf_fw_host[3Ec], rf_c_host[16Ec],
- * rf_cw_host[16Ec] the flux restriction (eqs. (restr_flux), (ho_flux), (kml)): integrated
+ * stencils of the left / right triangle; rf_f_host[3Ec], rf_fw_host[3Ec], rf_c_host[8Ec],
+ * rf_cw_host[8Ec] the flux restriction (eqs. (restr_flux), (ho_flux), (kml)): integrated
  * coarse flux = sum rf_fw * (l F)[rf_f] + sum rf_cw * c[rf_c], fine edge / node ids.  Any
  * pointer may be NULL.  For tests of the builder. */
 int wt_host_pair_tables(int jc, int jmax, double radius, double omega, int32_t* cells_host,

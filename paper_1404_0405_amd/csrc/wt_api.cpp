@@ -76,6 +76,8 @@ struct LevelState {
 
 struct PairState {
   WorkList l_cn, l_ce, l_ct;   // coarse nodes / edges / triangles with a fine point in the 5-ring support
+  double* ph_det = nullptr;    // partial height transform: odd-node details of every coarse edge
+  uint8_t* ph_act = nullptr;   // and their stencil activity
   uint8_t* pred = nullptr;     // their predicates (Nc + Ec + Tc bytes)
   PairTables host;
   DevPair dev{};
@@ -576,7 +578,8 @@ static void ml_step(wt_grid* g, double dt) {
   // partial height transform at complete nodes, bottom-up
   for (int j = g->jmax - 1; j >= g->jmin; --j) {
     LevelState &C = g->L(j), &F = g->L(j + 1);
-    ml_partial_h(g->P(j).dev, C.tab, C.na, F.na, F.ea, F.work.dh, C.work.dh, g->stream, LS(g->P(j).l_cn));
+    PairState& P = g->P(j);
+    ml_partial_h(P.dev, C.tab, C.na, F.na, F.ea, F.work.dh, C.work.dh, P.ph_det, P.ph_act, g->stream, LS(P.l_cn));
   }
 }
 
@@ -1119,6 +1122,9 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
       upload_pair(ps->host, ps->dev);
       auto A2 = [](double** q, int64_t n) { HIPCHK(wt::dmalloc(q, n * sizeof(double))); HIPCHK(hipMemset(*q, 0, n * sizeof(double))); };
       A2(&ps->d_h, ps->host.Ec); A2(&ps->d_p, ps->host.Ec); A2(&ps->d_k, ps->host.Ec); A2(&ps->d_i, 3 * ps->host.Tc);
+      A2(&ps->ph_det, ps->host.Ec);
+      HIPCHK(wt::dmalloc(&ps->ph_act, ps->host.Ec));
+      HIPCHK(hipMemset(ps->ph_act, 0, ps->host.Ec));
       A2(&ps->r_h, ps->host.Ec); A2(&ps->r_p, ps->host.Ec); A2(&ps->r_i, 3 * ps->host.Tc);
       // keep only what the device path needs on the host
       ps->host = PairTables{};
@@ -1151,7 +1157,7 @@ void wt_grid_destroy(wt_grid* g) {
     free_list(ps->l_ce);
     free_list(ps->l_ct);
     if (ps->pred) (void)wt::dfree(ps->pred);
-    void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k, ps->r_h, ps->r_p, ps->r_i};
+    void* q[] = {ps->d_h, ps->d_p, ps->d_i, ps->d_k, ps->r_h, ps->r_p, ps->r_i, ps->ph_det, ps->ph_act};
     for (void* x : q)
       if (x) (void)wt::dfree(x);
   }
@@ -1424,7 +1430,7 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
 // prolongation of a pair, then its odd and interior prolongation together, the three
 // intermediate kernels each over all levels, per pair the fine divergence, then the edge and B
 // restriction together, the tendencies of all levels; then the partial transform pair by pair
-// (84 launches for five levels instead of ~180).  Every entry runs the same per-point body as
+// (88 launches for five levels instead of ~185).  Every entry runs the same per-point body as
 // ml_step, so the results are bitwise equal.
 // Whether the merged form applies, with its plan brought up to date (this synchronises when the
 // plan is rebuilt, so it is called before a capture, not inside one).
@@ -2102,7 +2108,8 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
       pl.levels.push_back(bl);
     }
     for (int j = g->jmin; j < g->jmax; ++j)
-      pl.pairs.push_back(BatchPair{g->P(j).dev, x.lev0 + (j - g->jmin), x.lev0 + (j + 1 - g->jmin)});
+      pl.pairs.push_back(BatchPair{g->P(j).dev, x.lev0 + (j - g->jmin), x.lev0 + (j + 1 - g->jmin), g->P(j).ph_det,
+                                   g->P(j).ph_act});
     J0 = std::min(J0, g->jmin);
     J1 = std::max(J1, g->jmax);
     mi.push_back(x);
@@ -2190,7 +2197,16 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
     }
     flush();
   }
+  // the partial transform pair by pair downwards, each in two passes: the details and stencil
+  // activity of every coarse edge (whole pair, so none is stale), then the listed coarse nodes
   for (int j = J1 - 1; j >= J0; --j) {
+    for (size_t k = 0; k < mi.size(); ++k)
+      if (mi[k].jmin <= j && j < mi[k].jmax) {
+        const PairState& P = members[k]->P(j);
+        if (mi[k].wl ? P.l_cn.bound > 0 : P.dev.Nc > 0)
+          fixed(BK_PARTIAL_D, mi[k].pair0 + j - mi[k].jmin, 0, mi[k], nullptr, P.dev.Ec);
+      }
+    flush();
     for (size_t k = 0; k < mi.size(); ++k)
       if (mi[k].jmin <= j && j < mi[k].jmax) {
         const PairState& P = members[k]->P(j);

@@ -86,10 +86,16 @@ __device__ __forceinline__ void batch_entry(const BatchJob& jb, int64_t i, const
                       L.pu[s], L.so[s], L.ph.adv);
       break;
     }
+    case BK_PARTIAL_D: {
+      const BatchPair& bp = PR[jb.a];
+      const BatchLevel& F = LV[bp.f];
+      body_partial_d(i, bp.P, F.na, F.dh, bp.det, bp.act);
+      break;
+    }
     case BK_PARTIAL_H: {
       const BatchPair& bp = PR[jb.a];
       const BatchLevel &C = LV[bp.c], &F = LV[bp.f];
-      body_partial_h(i, bp.P, C.t.c_e, C.na, F.na, F.ea, F.dh, C.dh);
+      body_partial_h(i, bp.P, C.t.c_e, C.na, F.na, F.ea, bp.det, bp.act, F.dh, C.dh);
       break;
     }
     default:

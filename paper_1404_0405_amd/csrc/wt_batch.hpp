@@ -20,7 +20,7 @@ namespace wt {
 
 enum BatchKind : int32_t {
   BK_PRO_EVEN = 0, BK_PRO_ODD, BK_PRO_INT, BK_VERTEX, BK_EDGE_CELL, BK_Q, BK_DIV, BK_RES_E, BK_RES_B, BK_TEND,
-  BK_PARTIAL_H
+  BK_PARTIAL_H, BK_PARTIAL_D
 };
 
 // one level of one member
@@ -40,6 +40,8 @@ struct BatchLevel {
 struct BatchPair {
   DevPair P;
   int32_t c, f;
+  double* det;    // partial transform scratch: details and stencil activity of every coarse edge
+  uint8_t* act;
 };
 
 // a job: kind, the level (a) or pair (a) it works on, the stage, the member's tendency precision

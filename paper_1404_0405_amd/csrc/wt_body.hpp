@@ -258,12 +258,27 @@ __device__ __forceinline__ void body_tend_ml(int64_t id, const DevTables& tb, co
 }
 
 // ------------------------------------------------------------------ partial height transform
-// h^j_k <- R_h(h^{j+1})_k at complete coarse node k: the whole height-restriction stencil is
-// active and every coarse edge of the node is non-leaf.  The conditions combine mask bytes (0 / 1)
-// without early exits, so their loads are issued together.
+// Two passes per pair.  First, for every coarse edge e: whether the height-prediction stencil of
+// its odd fine node is active (the node and its four even neighbours), and where it is, that
+// node's detail (each detail is used by the 2-4 coarse cells sharing area with the odd node, so
+// it is computed once here rather than once per cell).  Mask bytes are combined without early
+// exits, so their loads are issued together.
+__device__ __forceinline__ void body_partial_d(int64_t e, const DevPair& P, const uint8_t* __restrict__ naf,
+                                               const double* __restrict__ hf, double* __restrict__ det,
+                                               uint8_t* __restrict__ act) {
+  const uint8_t a = naf[P.mid[e]] & naf[P.even[P.cells[4 * e]]] & naf[P.even[P.cells[4 * e + 1]]] &
+                    naf[P.even[P.cells[4 * e + 2]]] & naf[P.even[P.cells[4 * e + 3]]];
+  act[e] = a;
+  if (a) det[e] = h_detail(P, e, hf);
+}
+
+// Then h^j_k <- R_h(h^{j+1})_k at complete coarse node k: every stencil of its odd nodes is
+// active and every coarse edge of the node is non-leaf (the same sum, in the same order, as
+// R_h written out with the details).
 __device__ __forceinline__ void body_partial_h(int64_t k, const DevPair& P, const int32_t* __restrict__ c_e_c,
                                                const uint8_t* __restrict__ nac, const uint8_t* __restrict__ naf,
-                                               const uint8_t* __restrict__ eaf, const double* __restrict__ hf,
+                                               const uint8_t* __restrict__ eaf, const double* __restrict__ det,
+                                               const uint8_t* __restrict__ act, const double* __restrict__ hf,
                                                double* __restrict__ hc) {
   const int32_t ev = P.even[k];
   int32_t ecs[MK_MAX];
@@ -271,13 +286,8 @@ __device__ __forceinline__ void body_partial_h(int64_t k, const DevPair& P, cons
   for (int q = 0; q < MK_MAX; ++q) ecs[q] = P.mk[MK_MAX * k + q];   // valid entries first, then -1
   uint32_t ok = nac[k] & naf[ev];
 #pragma unroll
-  for (int q = 0; q < MK_MAX; ++q) {
-    if (ecs[q] >= 0) {
-      const int64_t e = ecs[q] >> 2;
-      ok &= naf[P.mid[e]] & naf[P.even[P.cells[4 * e]]] & naf[P.even[P.cells[4 * e + 1]]] &
-            naf[P.even[P.cells[4 * e + 2]]] & naf[P.even[P.cells[4 * e + 3]]];
-    }
-  }
+  for (int q = 0; q < MK_MAX; ++q)
+    if (ecs[q] >= 0) ok &= act[ecs[q] >> 2];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int32_t e = c_e_c[6 * k + q];
@@ -287,7 +297,7 @@ __device__ __forceinline__ void body_partial_h(int64_t k, const DevPair& P, cons
   double s = hf[ev];
 #pragma unroll
   for (int q = 0; q < MK_MAX; ++q)
-    if (ecs[q] >= 0) s += P.s_upd[ecs[q]] * h_detail(P, ecs[q] >> 2, hf);
+    if (ecs[q] >= 0) s += P.s_upd[ecs[q]] * det[ecs[q] >> 2];
   hc[k] = s;
 }
 

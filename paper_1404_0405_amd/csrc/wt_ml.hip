@@ -228,20 +228,33 @@ void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, dou
 
 // Partial height transform at complete coarse nodes: the whole height-restriction stencil is
 // active and every coarse edge of the node is non-leaf.
+__global__ __launch_bounds__(BS) void k_partial_d(DevPair P, const uint8_t* __restrict__ naf,
+                                                  const double* __restrict__ hf, double* __restrict__ det,
+                                                  uint8_t* __restrict__ act) {
+  const int64_t e = TID;
+  if (e >= P.Ec) return;
+  body_partial_d(e, P, naf, hf, det, act);
+}
+
 __global__ __launch_bounds__(BS) void k_partial_h(DevPair P, const int32_t* __restrict__ c_e_c,
                                                   const uint8_t* __restrict__ nac,
                                                   const uint8_t* __restrict__ naf,
                                                   const uint8_t* __restrict__ eaf,
+                                                  const double* __restrict__ det, const uint8_t* __restrict__ act,
                                                   const double* __restrict__ hf, double* __restrict__ hc,
                                                   const int32_t* __restrict__ lst, int64_t cnt) {
   LISTED(k, cnt, lst)
-  body_partial_h(k, P, c_e_c, nac, naf, eaf, hf, hc);
+  body_partial_h(k, P, c_e_c, nac, naf, eaf, det, act, hf, hc);
 }
 
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
-                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s, Span lcn) {
+                  const uint8_t* eaf, const double* hf, double* hc, double* det, uint8_t* act, hipStream_t s,
+                  Span lcn) {
   const int64_t n = span_n(lcn, P.Nc);
-  if (n) k_partial_h<<<nb(n), BS, 0, s>>>(P, tc.c_e, nac, naf, eaf, hf, hc, lcn.idx, n);
+  if (!n) return;
+  // every coarse edge's stencil activity (so none is stale), then the listed coarse nodes
+  k_partial_d<<<nb(P.Ec), BS, 0, s>>>(P, naf, hf, det, act);
+  k_partial_h<<<nb(n), BS, 0, s>>>(P, tc.c_e, nac, naf, eaf, det, act, hf, hc, lcn.idx, n);
   HIPCHK(hipGetLastError());
 }
 

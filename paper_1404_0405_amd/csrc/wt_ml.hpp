@@ -44,8 +44,11 @@ void ml_tend(const DevTables& t, DevWork& w, const uint8_t* na, const uint8_t* e
              const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Span lel = {});
 void ml_restrict_state(const DevPair& P, const double* hf, const double* uf, double* hc, double* uc,
                        hipStream_t s);
+// det (Ec doubles) and act (Ec bytes): scratch of the two passes (details and stencil activity
+// of every coarse edge's odd node)
 void ml_partial_h(const DevPair& P, const DevTables& tc, const uint8_t* nac, const uint8_t* naf,
-                  const uint8_t* eaf, const double* hf, double* hc, hipStream_t s, Span lcn = {});
+                  const uint8_t* eaf, const double* hf, double* hc, double* det, uint8_t* act, hipStream_t s,
+                  Span lcn = {});
 // Details of a pair (edge and interior jobs), R1 significance of a pair, R2 of a level and R3 of
 // a pair as jobs of ml_mask_ops, which runs any number of them, MAX_MASK_JOBS per launch
 // (blockIdx.y = job): jobs of one call must not depend on each other (the mask rules only set

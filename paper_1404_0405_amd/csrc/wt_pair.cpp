@@ -362,9 +362,11 @@ void finish_pair(const Level& C, const Level& F, const std::vector<double>& Af, 
     for (int64_t e2 : {e, eap, eaq, ebp, ebq}) odd_node_terms(lc, P, Af, e2, terms);
     for (auto& t : terms)
       if (t.edge == e) cw[t.node] += t.w;
-    PAIR_CHECK(cw.size() <= size_t(RF_NC), "flux restriction stencil too wide");
+    // nodes whose terms cancel exactly carry no weight: drop them (the sum is unchanged)
     int k = 0;
     for (auto& kv : cw) {
+      if (kv.second == 0.0) continue;
+      PAIR_CHECK(k < RF_NC, "flux restriction stencil too wide");
       P.rf_c[RF_NC * e + k] = int32_t(kv.first);
       P.rf_cw[RF_NC * e + k] = kv.second;
       ++k;

@@ -9,7 +9,7 @@
 
 namespace wt {
 
-constexpr int RF_NC = 16;   // fine divergences per coarse-edge flux restriction (padded)
+constexpr int RF_NC = 8;    // nonzero fine-divergence weights per coarse-edge flux restriction (at most 7; padded)
 constexpr int MK_MAX = 12;  // odd fine nodes sharing area with one coarse cell
 
 struct PairTables {
@@ -29,8 +29,8 @@ struct PairTables {
   std::vector<double> w_pl, w_pr; // 9Ec each: (p1 - p2) weights on v_sten of left/right triangle
   std::vector<int32_t> rf_f;      // 3Ec: fine edges of the basic flux restriction
   std::vector<double> rf_fw;      // 3Ec: weights on l_f F_f
-  std::vector<int32_t> rf_c;      // 16Ec: fine nodes whose divergence enters
-  std::vector<double> rf_cw;      // 16Ec: weights on c_n (integrated flux units)
+  std::vector<int32_t> rf_c;      // 8Ec: fine nodes whose divergence enters (nonzero weights first)
+  std::vector<double> rf_cw;      // 8Ec: weights on c_n (integrated flux units; 0 on padding)
 };
 
 // Geometry-only part (maps, overlap areas, s~, velocity weights).

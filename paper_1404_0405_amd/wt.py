@@ -246,7 +246,7 @@ def host_pair_tables(jc, jmax, radius=6.371e6, omega=7.292e-5):
     o = dict(cells=np.empty((Ec, 4), np.int32), st=np.empty((Ec, 4)), s_upd=np.empty((Ec, 4)),
              A_c=np.empty(Nc), v_sten=np.empty((Tc, 9), np.int32), w_int=np.empty((Tc, 3, 9)),
              w_pl=np.empty((Ec, 9)), w_pr=np.empty((Ec, 9)), rf_f=np.empty((Ec, 3), np.int32),
-             rf_fw=np.empty((Ec, 3)), rf_c=np.empty((Ec, 16), np.int32), rf_cw=np.empty((Ec, 16)))
+             rf_fw=np.empty((Ec, 3)), rf_c=np.empty((Ec, 8), np.int32), rf_cw=np.empty((Ec, 8)))
     d, i = C.c_double, C.c_int32
     _check(lib.wt_host_pair_tables(jc, jmax, radius, omega, _ptr(o["cells"], i), _ptr(o["st"], d),
                                    _ptr(o["s_upd"], d), _ptr(o["A_c"], d), _ptr(o["v_sten"], i),
