@@ -193,7 +193,7 @@ __device__ __forceinline__ int32_t phase_prefix(const BatchJob* __restrict__ JB,
 // Every workgroup takes chunks of the current phase until none is left -- from the phase's counter
 // (queue != 0) or every gridDim-th chunk from its own index -- then waits at the phase's grid
 // barrier.  The loop exits are uniform per workgroup, so every workgroup reaches every barrier.
-__global__ __launch_bounds__(BB) void k_batch(const BatchLevel* __restrict__ LV, const BatchPair* __restrict__ PR,
+__global__ __launch_bounds__(BB, 4) void k_batch(const BatchLevel* __restrict__ LV, const BatchPair* __restrict__ PR,
                                               const BatchJob* __restrict__ JB, const BatchPhase* __restrict__ PH,
                                               int nphase, int chunk, int queue, int32_t* __restrict__ ctr,
                                               uint32_t* __restrict__ bar, uint32_t* __restrict__ err) {

@@ -45,6 +45,15 @@ __device__ __forceinline__ T int_pred(const DevPair& P, int64_t t, int s, const 
   return v;
 }
 
+// the same from the column copies of the tables (identical arithmetic)
+template <typename T>
+__device__ __forceinline__ T int_pred_c(const DevPair& P, int64_t t, int s, const double* __restrict__ uc) {
+  T v = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v += tv<T>(P.w_int_c, P.w_int_cf, P.ct(9 * s + k, t)) * T(uc[P.v_sten_c[P.ct(k, t)]]);
+  return v;
+}
+
 // height at the midpoint of coarse edge e predicted from its four even fine neighbours
 // (s~-weighted mean, eq. (WTpred))
 __device__ __forceinline__ double h_pred(const DevPair& P, int64_t e, const double* __restrict__ hf) {
@@ -283,7 +292,7 @@ __device__ __forceinline__ void body_partial_h(int64_t k, const DevPair& P, cons
   const int32_t ev = P.even[k];
   int32_t ecs[MK_MAX];
 #pragma unroll
-  for (int q = 0; q < MK_MAX; ++q) ecs[q] = P.mk[MK_MAX * k + q];   // valid entries first, then -1
+  for (int q = 0; q < MK_MAX; ++q) ecs[q] = P.mk[P.cn(q, k)];   // valid entries first, then -1
   uint32_t ok = nac[k] & naf[ev];
 #pragma unroll
   for (int q = 0; q < MK_MAX; ++q)
@@ -297,7 +306,7 @@ __device__ __forceinline__ void body_partial_h(int64_t k, const DevPair& P, cons
   double s = hf[ev];
 #pragma unroll
   for (int q = 0; q < MK_MAX; ++q)
-    if (ecs[q] >= 0) s += P.s_upd[ecs[q]] * det[ecs[q] >> 2];
+    if (ecs[q] >= 0) s += P.s_upd[P.upd(ecs[q])] * det[ecs[q] >> 2];
   hc[k] = s;
 }
 

@@ -45,9 +45,10 @@ __global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* _
 
 // odd nodes / half-edges and interior edges of a pair in one launch (they do not read each
 // other's outputs; both read the even nodes written before): blocks [0, bo) take the coarse
-// edges, the rest the coarse triangles
+// edges, the rest the coarse triangles.  8 waves per SIMD: its gathers over the sparse support
+// lists are bound by load latency (measured faster than the compiler's own choice of 6).
 template <typename T>
-__global__ __launch_bounds__(BS) void k_prolong_odd_int(DevPair P, const uint8_t* __restrict__ naf,
+__global__ __launch_bounds__(BS, 8) void k_prolong_odd_int(DevPair P, const uint8_t* __restrict__ naf,
                                                         const uint8_t* __restrict__ eaf,
                                                         const int32_t* __restrict__ e_v_c,
                                                         const double* __restrict__ uc, double* __restrict__ hf,
@@ -206,8 +207,8 @@ __global__ __launch_bounds__(BS) void k_restrict_h(DevPair P, const double* __re
   double s = hf[P.even[k]];
 #pragma unroll
   for (int q = 0; q < MK_MAX; ++q) {   // valid entries first, then -1: same order as a break
-    const int32_t ec = P.mk[MK_MAX * k + q];
-    if (ec >= 0) s += P.s_upd[ec] * h_detail(P, ec >> 2, hf);
+    const int32_t ec = P.mk[P.cn(q, k)];
+    if (ec >= 0) s += P.s_upd[P.upd(ec)] * h_detail(P, ec >> 2, hf);
   }
   hc[k] = s;
 }
@@ -353,20 +354,28 @@ __global__ __launch_bounds__(BS) void k_ring_b(RingJobs J) {
   if (int(blockIdx.x) >= jb.nblk) return;
   const int sh = jb.sh, ps = sh - 3, m = 1 << ps;
   const int tid = threadIdx.x;
+  const bool node = tid < 64;   // wave 0 the nodes of the patch, waves 1-3 their edges
+  const int q = node ? tid : (tid - 64) / 3, d = node ? 0 : (tid - 64) - 3 * q;
   const int32_t cnt = *jb.pcount;
-  for (int32_t b = blockIdx.x; b < cnt; b += jb.nblk) {
-    const int32_t p = jb.plist[b];
+  auto point = [&](int32_t p) {
     const int32_t L = p >> (2 * ps);
     const int pi = (p >> ps) & (m - 1), pj = p & (m - 1);
-    if (tid < 64) {
-      const int32_t id = (((L << sh) + 8 * pi + (tid >> 3)) << sh) + 8 * pj + (tid & 7);
-      jb.bn[id] = ring_node(id, sh, jb.c_e, jb.e_c, jb.an, jb.ae) ? 1 : 0;
-    } else {
-      const int q = (tid - 64) / 3, d = (tid - 64) - 3 * q;
-      const int32_t id = (((L << sh) + 8 * pi + (q >> 3)) << sh) + 8 * pj + (q & 7);
-      const int32_t e = 3 * id + d;
-      jb.be[e] = ring_edge(e, sh, jb.e_c, jb.e_v, jb.t_e, jb.an, jb.ae) ? 1 : 0;
-    }
+    const int32_t id = (((L << sh) + 8 * pi + (q >> 3)) << sh) + 8 * pj + (q & 7);
+    return node ? id : 3 * id + d;
+  };
+  auto ring = [&](int32_t x) {
+    return node ? ring_node(x, sh, jb.c_e, jb.e_c, jb.an, jb.ae) : ring_edge(x, sh, jb.e_c, jb.e_v, jb.t_e, jb.an, jb.ae);
+  };
+  uint8_t* __restrict__ out = node ? jb.bn : jb.be;
+  // two patches per pass with their mask loads issued together: the loop is bound by the
+  // latency of its dependent loads (list entry, then mask bytes), not by bandwidth
+  for (int32_t b = blockIdx.x; b < cnt; b += 2 * jb.nblk) {
+    const int32_t b2 = b + jb.nblk;
+    const bool two = b2 < cnt;
+    const int32_t x1 = point(jb.plist[b]), x2 = point(jb.plist[two ? b2 : b]);
+    const uint8_t m1 = ring(x1), m2 = ring(x2);
+    out[x1] = m1 ? 1 : 0;
+    if (two) out[x2] = m2 ? 1 : 0;
   }
   const int32_t pole = (10 << (2 * sh)) + tid;
   if (blockIdx.x == 0 && pole < jb.N) jb.bn[pole] = ring_node(pole, sh, jb.c_e, jb.e_c, jb.an, jb.ae) ? 1 : 0;
@@ -382,7 +391,7 @@ RingJob ring_job(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae
   RingJob j{};
   j.N = int32_t(t.N);
   j.sh = __builtin_ctz(unsigned(n));
-  j.nblk = int32_t(np < 1024 ? np : 1024);
+  j.nblk = int32_t(np < 8192 ? np : 8192);
   j.plist = plist;
   j.pcount = plist + np;
   j.c_e = t.c_e; j.e_c = t.e_c; j.e_v = t.e_v; j.t_e = t.t_e;
@@ -486,7 +495,7 @@ template <typename T>
 __device__ __forceinline__ void op_det_int_t(int64_t t, const MaskJob& j) {
   const DevPair& P = j.P;
 #pragma unroll
-  for (int s = 0; s < 3; ++s) j.di[3 * t + s] = j.uf[P.int_e[3 * t + s]] - double(int_pred<T>(P, t, s, j.uc));
+  for (int s = 0; s < 3; ++s) j.di[3 * t + s] = j.uf[P.int_e[3 * t + s]] - double(int_pred_c<T>(P, t, s, j.uc));
 }
 
 __device__ __forceinline__ void op_det_edge(int64_t e, const MaskJob& j) {
@@ -575,8 +584,12 @@ __device__ __forceinline__ void op_r3_edge(int64_t e, const MaskJob& j) {
 }
 
 // Each job owns a range of workgroups, pre[j] <= blockIdx.x < pre[j+1], about one thread per
-// entry (a list, padding -1 skipped, or 0..cnt), striding if the job has more entries.
-__global__ __launch_bounds__(BS) void k_mask_b(MaskJobs J) {
+// entry (a list, padding -1 skipped, or 0..cnt), striding if the job has more entries.  Two
+// instances: with the details (DET, every op) and without them (the mask rules only): the rules
+// are byte gathers bound by load latency and run best at 6 waves per SIMD, which the register
+// budget of the detail arithmetic would not allow.
+template <bool DET>
+__global__ __launch_bounds__(BS, DET ? 4 : 6) void k_mask_b(MaskJobs J) {
   const int32_t c = int32_t(blockIdx.x);
   int q = 0;
   while (q + 1 < J.n && J.pre[q + 1] <= c) ++q;
@@ -631,8 +644,12 @@ __global__ __launch_bounds__(BS) void k_mask_b(MaskJobs J) {
       if (i < 0) continue;
     }
     switch (jb.op) {
-      case MO_DET_EDGE: op_det_edge(i, jb); break;
-      case MO_DET_INT: op_det_int(i, jb); break;
+      case MO_DET_EDGE:
+        if constexpr (DET) op_det_edge(i, jb);
+        break;
+      case MO_DET_INT:
+        if constexpr (DET) op_det_int(i, jb);
+        break;
       case MO_SIG_EDGE: op_sig_edge(i, jb); break;
       case MO_SIG_INT: op_sig_int(i, jb); break;
       case MO_R2_NODE: op_r2_node(i, jb); break;
@@ -650,9 +667,11 @@ void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s) {
     MaskJobs J{};
     int nk = 0;
     int64_t run = 0;
+    bool det = false;
     for (int k = k0; k < njobs && k < k0 + MAX_MASK_JOBS; ++k) {
       if (jobs[k].cnt <= 0) continue;
       const MaskJob& jk = jobs[k];
+      det |= jk.op == MO_DET_EDGE || jk.op == MO_DET_INT;
       if (jk.op >= MO_R2_NODE && jk.lst)
         throw std::runtime_error("ml_mask_ops: the mask rules run over whole levels");
       if (jk.op >= MO_R2_NODE &&
@@ -670,7 +689,10 @@ void ml_mask_ops(const MaskJob* jobs, int njobs, hipStream_t s) {
     if (nk == 0) continue;
     J.pre[nk] = int32_t(run);
     J.n = nk;
-    k_mask_b<<<unsigned(run), BS, 0, s>>>(J);
+    if (det)
+      k_mask_b<true><<<unsigned(run), BS, 0, s>>>(J);
+    else
+      k_mask_b<false><<<unsigned(run), BS, 0, s>>>(J);
     HIPCHK(hipGetLastError());
   }
 }
@@ -798,8 +820,8 @@ __device__ __forceinline__ void inv_even(int64_t k, const DevPair& P, const doub
   double s = hc[k];
 #pragma unroll
   for (int q = 0; q < MK_MAX; ++q) {   // valid entries first, then -1: same order as a break
-    const int32_t ec = P.mk[MK_MAX * k + q];
-    if (ec >= 0) s -= P.s_upd[ec] * dk[ec >> 2];
+    const int32_t ec = P.mk[P.cn(q, k)];
+    if (ec >= 0) s -= P.s_upd[P.upd(ec)] * dk[ec >> 2];
   }
   hf[P.even[k]] = s;
 }
@@ -812,7 +834,7 @@ __device__ __forceinline__ void inv_int(int64_t t, const DevPair& P, const uint8
   for (int s = 0; s < 3; ++s) {
     const int32_t f = P.int_e[3 * t + s];
     const bool keep = ea_old[f] && ea_new[f];
-    uf[f] = (keep ? di[3 * t + s] : 0.0) + double(int_pred<T>(P, t, s, uc));
+    uf[f] = (keep ? di[3 * t + s] : 0.0) + double(int_pred_c<T>(P, t, s, uc));
   }
 }
 
@@ -1047,19 +1069,37 @@ static const X* up(const std::vector<X>& v) {
   return p;
 }
 
+// rows of w entries per element (element-major on the host) as columns (entry-major)
+template <typename X>
+static std::vector<X> columns(const std::vector<X>& v, int w) {
+  const size_t n = v.size() / size_t(w);
+  if (n * size_t(w) != v.size()) throw std::runtime_error("upload_pair: table is not a whole number of rows");
+  std::vector<X> o(v.size());
+  for (size_t x = 0; x < n; ++x)
+    for (int q = 0; q < w; ++q) o[size_t(q) * n + x] = v[x * size_t(w) + size_t(q)];
+  return o;
+}
+
 void upload_pair(const PairTables& P, DevPair& d) {
   d.Nc = P.Nc; d.Ec = P.Ec; d.Tc = P.Tc; d.Nf = P.Nf; d.Ef = P.Ef;
-  d.even = up(P.even); d.mid = up(P.mid); d.h1 = up(P.h1); d.h2 = up(P.h2); d.cells = up(P.cells);
-  d.mk = up(P.mk); d.int_e = up(P.int_e); d.v_sten = up(P.v_sten); d.rf_f = up(P.rf_f); d.rf_c = up(P.rf_c);
-  d.st = up(P.st); d.s_upd = up(P.s_upd); d.w_int = up(P.w_int); d.w_pl = up(P.w_pl); d.w_pr = up(P.w_pr);
-  d.rf_fw = up(P.rf_fw); d.rf_cw = up(P.rf_cw);
+  if (int64_t(P.cells.size()) != 4 * P.Ec || int64_t(P.mk.size()) != MK_MAX * P.Nc ||
+      int64_t(P.v_sten.size()) != 9 * P.Tc || int64_t(P.w_int.size()) != 27 * P.Tc ||
+      int64_t(P.w_pl.size()) != 9 * P.Ec || int64_t(P.rf_cw.size()) != RF_NC * P.Ec)
+    throw std::runtime_error("upload_pair: table sizes do not match the level pair");
+  d.even = up(P.even); d.mid = up(P.mid); d.h1 = up(P.h1); d.h2 = up(P.h2); d.int_e = up(P.int_e);
+  d.cells = up(P.cells); d.st = up(P.st); d.s_upd = up(columns(P.s_upd, 4));
+  d.mk = up(columns(P.mk, MK_MAX)); d.v_sten = up(P.v_sten);
+  d.rf_f = up(P.rf_f); d.rf_fw = up(P.rf_fw); d.rf_c = up(P.rf_c); d.rf_cw = up(P.rf_cw);
+  d.w_int = up(P.w_int); d.w_pl = up(P.w_pl); d.w_pr = up(P.w_pr);
   auto f32 = [](const std::vector<double>& v) { return up(std::vector<float>(v.begin(), v.end())); };
   d.w_int_f = f32(P.w_int); d.w_pl_f = f32(P.w_pl); d.w_pr_f = f32(P.w_pr);
+  const std::vector<double> wc = columns(P.w_int, 27);
+  d.w_int_c = up(wc); d.w_int_cf = f32(wc); d.v_sten_c = up(columns(P.v_sten, 9));
 }
 
 void free_pair(DevPair& d) {
   const void* ps[] = {d.even, d.mid, d.h1, d.h2, d.cells, d.mk, d.int_e, d.v_sten, d.rf_f, d.rf_c,
-                      d.st, d.s_upd, d.w_int, d.w_pl, d.w_pr, d.rf_fw, d.rf_cw, d.w_int_f, d.w_pl_f, d.w_pr_f};
+                      d.st, d.s_upd, d.w_int, d.w_pl, d.w_pr, d.rf_fw, d.rf_cw, d.w_int_f, d.w_pl_f, d.w_pr_f, d.w_int_c, d.w_int_cf, d.v_sten_c};
   for (const void* p : ps)
     if (p) (void)wt::dfree(const_cast<void*>(p));
   d = DevPair{};

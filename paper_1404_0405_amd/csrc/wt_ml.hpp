@@ -16,11 +16,29 @@ struct Span {
   int64_t n = 0;
 };
 
+// Inter-scale tables of a level pair on the device.  Most fixed-width rows keep one row per
+// element (cells, st, w_pl, w_pr: per coarse edge; w_int, v_sten: per coarse triangle; rf_*):
+// their kernels run over sparse support lists or gather the rows of other elements (an edge
+// reads the stencils of its two triangles), and a lane then finds its whole row in one or two
+// cache lines.  Column layouts (entry q of element x at q * count + x, so that the lanes of a
+// wavefront, which take consecutive elements, read consecutive words of one column) serve the
+// rest: mk (MK_MAX odd-node codes per coarse node) and s_upd (4 per coarse edge, reached through
+// the codes ec = 4 e + c of mk), and column copies of w_int and v_sten for the passes over the
+// dense triangle lists of the details and the inverse transform.  Each choice was measured;
+// columns everywhere made the sparse-list kernels slower.
 struct DevPair {
   int64_t Nc, Ec, Tc, Nf, Ef;
   const int32_t *even, *mid, *h1, *h2, *cells, *mk, *int_e, *v_sten, *rf_f, *rf_c;
   const double *st, *s_upd, *w_int, *w_pl, *w_pr, *rf_fw, *rf_cw;
   const float *w_int_f, *w_pl_f, *w_pr_f;   // single-precision copies of the velocity predictions
+  // column copies of w_int (and its single-precision copy) and v_sten
+  const double* w_int_c;
+  const float* w_int_cf;
+  const int32_t* v_sten_c;
+  // column-layout positions
+  __host__ __device__ int64_t ct(int q, int64_t t) const { return q * Tc + t; }   // per coarse triangle
+  __host__ __device__ int64_t cn(int q, int64_t k) const { return q * Nc + k; }   // per coarse node
+  __host__ __device__ int64_t upd(int32_t ec) const { return (ec & 3) * Ec + (ec >> 2); }   // s_upd of code ec
 };
 
 constexpr int MAX_LEVJOBS = 16;   // level or pair jobs per batched launch
