@@ -644,6 +644,32 @@ def cpu_baseline(level=9, stages=2, procs=None):
                                              "cores": 1, "eps": 1e-3}}
 
 
+def stream_reference(ndouble, reps=10):
+    """What this GPU streams for plain elementwise work on arrays the size of one state array
+    (torch's own kernels, FP64): a copy (1 read, 1 write) and an add (2 reads, 1 write, near the
+    lattice stage's mix of counted reads and writes).  Context for the lattice kernel's counted
+    traffic rate; the roofline fraction stays against the published peak."""
+    import torch
+    a = torch.rand(ndouble, dtype=torch.float64, device="cuda")
+    b = torch.rand_like(a)
+    o = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy_1r_1w", lambda: o.copy_(a), 2 * 8 * ndouble),
+                             ("add_2r_1w", lambda: torch.add(a, b, alpha=0.5, out=o), 3 * 8 * ndouble)):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        out[name] = {"avg_ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes}
+    del a, b, o
+    return out
+
+
 def copy_probe(nbytes=1 << 31, reps=5):
     """A plain device copy of known size (torch's copy kernel), for scaling the HBM byte
     counters: FETCH_SIZE and WRITE_SIZE of one copy should each read `nbytes`."""
@@ -738,6 +764,7 @@ def main():
                                            "frac": kd["gbs"] / HBM_PEAK_GBS,
                                            "model": "stage input + Runge-Kutta arrays read and written + "
                                                     "58 FP64 geometry values per tile position / 10"}},
+        "stream_reference": None,
         "kernels_fp64": f64["kernels"],
         "stage_ms_fp64": f64["ms_per_step"] / 4,
         "fp32_tendency": ({"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"],
@@ -748,6 +775,12 @@ def main():
         "energy_drift_fp64": f64["energy_drift"],
         "pcie_inclusive_fp64": f64.get("pcie_inclusive"),
     }
+    sref = stream_reference(N + E)
+    tr = line["roofline"]["traffic"]
+    if tr:
+        for v in sref.values():
+            v["lattice_traffic_rate_frac"] = tr / (kd["avg_ms"] * 1e-3) / 1e9 / v["GB/s"]
+    line["stream_reference"] = sref
     if not args.no_adaptive:
         _progress("adaptive jet")
         line["adaptive"] = run_adaptive(steps=args.adaptive_steps, spinup_days=args.jet_days,

@@ -45,10 +45,9 @@ __global__ __launch_bounds__(BS) void k_prolong_even(DevPair P, const uint8_t* _
 
 // odd nodes / half-edges and interior edges of a pair in one launch (they do not read each
 // other's outputs; both read the even nodes written before): blocks [0, bo) take the coarse
-// edges, the rest the coarse triangles.  8 waves per SIMD: its gathers over the sparse support
-// lists are bound by load latency (measured faster than the compiler's own choice of 6).
+// edges, the rest the coarse triangles
 template <typename T>
-__global__ __launch_bounds__(BS, 8) void k_prolong_odd_int(DevPair P, const uint8_t* __restrict__ naf,
+__global__ __launch_bounds__(BS) void k_prolong_odd_int(DevPair P, const uint8_t* __restrict__ naf,
                                                         const uint8_t* __restrict__ eaf,
                                                         const int32_t* __restrict__ e_v_c,
                                                         const double* __restrict__ uc, double* __restrict__ hf,
@@ -391,7 +390,7 @@ RingJob ring_job(const DevTables& t, int n, const uint8_t* an, const uint8_t* ae
   RingJob j{};
   j.N = int32_t(t.N);
   j.sh = __builtin_ctz(unsigned(n));
-  j.nblk = int32_t(np < 8192 ? np : 8192);
+  j.nblk = int32_t(np < 2048 ? np : 2048);   // one round of workgroups at full occupancy (8 per CU)
   j.plist = plist;
   j.pcount = plist + np;
   j.c_e = t.c_e; j.e_c = t.e_c; j.e_v = t.e_v; j.t_e = t.t_e;
