@@ -367,14 +367,20 @@ __global__ __launch_bounds__(BS) void k_ring_b(RingJobs J) {
   };
   uint8_t* __restrict__ out = node ? jb.bn : jb.be;
   // two patches per pass with their mask loads issued together: the loop is bound by the
-  // latency of its dependent loads (list entry, then mask bytes), not by bandwidth
+  // latency of its dependent loads (list entry, then mask bytes), not by bandwidth.  A block with
+  // one patch left (the usual case on sparse levels) takes the single path: the branch is
+  // uniform per block.
   for (int32_t b = blockIdx.x; b < cnt; b += 2 * jb.nblk) {
     const int32_t b2 = b + jb.nblk;
-    const bool two = b2 < cnt;
-    const int32_t x1 = point(jb.plist[b]), x2 = point(jb.plist[two ? b2 : b]);
-    const uint8_t m1 = ring(x1), m2 = ring(x2);
-    out[x1] = m1 ? 1 : 0;
-    if (two) out[x2] = m2 ? 1 : 0;
+    if (b2 < cnt) {
+      const int32_t x1 = point(jb.plist[b]), x2 = point(jb.plist[b2]);
+      const uint8_t m1 = ring(x1), m2 = ring(x2);
+      out[x1] = m1 ? 1 : 0;
+      out[x2] = m2 ? 1 : 0;
+    } else {
+      const int32_t x1 = point(jb.plist[b]);
+      out[x1] = ring(x1) ? 1 : 0;
+    }
   }
   const int32_t pole = (10 << (2 * sh)) + tid;
   if (blockIdx.x == 0 && pole < jb.N) jb.bn[pole] = ring_node(pole, sh, jb.c_e, jb.e_c, jb.an, jb.ae) ? 1 : 0;
