@@ -218,11 +218,15 @@ int wt_set_step_phases(wt_grid* g, int enable);
  * inactive points, and the mass flux F, qF^perp Q and the Bernoulli function B of every element
  * stored for the restriction chain; with work lists only the tiles of each lozenge that hold a
  * point of the 5-ring support -- and only the rim round the twelve lozenge corners through the
- * listed table-driven kernels.  Results agree with the listed stage to round-off (the lattice
- * kernel sums in another order), not bitwise.  min_fraction > 1 turns it off (the default);
- * enabling builds the level's lattice geometry (finest level 6 or more, inviscid shallow-water
- * form only: other forms and ensemble steps keep the listed kernels).  WT_EINVAL for a negative
- * or non-finite fraction or a finest level below 6.  Synchronises. */
+ * listed table-driven kernels.  When the level below the finest is 6 or more and its support
+ * is as dense by the same measure, it computes its intermediates F, Q and B the same way, in an
+ * intermediates-only form of the kernel (no tendency, no stage output; the level's tendencies
+ * stay listed, after the restriction from the finest level has replaced F, Q and B at its
+ * non-leaf points).  Results agree with the listed stage to round-off (the lattice kernel sums
+ * in another order), not bitwise.  min_fraction > 1 turns it off (the default); enabling builds
+ * the two levels' lattice geometry (finest level 6 or more, inviscid shallow-water form only:
+ * other forms and ensemble steps keep the listed kernels).  WT_EINVAL for a negative or
+ * non-finite fraction or a finest level below 6.  Synchronises. */
 int wt_set_dense_levels(wt_grid* g, double min_fraction);
 
 /* Replace the active masks of `level` (host arrays of N and E bytes, 1 = active).  Test hook,
@@ -272,13 +276,16 @@ int wt_alloc_stats(const wt_grid* g, int64_t* n_hook, int64_t* bytes_hook, int64
  * stage's Runge-Kutta arrays (tend); the lattice kernel per element the stage input (32 B)
  * and the Runge-Kutta arrays, plus its shared geometry (464 B per tile position) once for the
  * 10 lozenges; its masked form on a dense finest level (trisk_lattice_masked) also the four mask
- * bytes and the stored F, Q and B.  Names are listed by wt_kernel_names (comma separated). */
+ * bytes and the stored F, Q and B; its intermediates-only form on the level below
+ * (trisk_lattice_inter) the stage input, the geometry's share and the stored F, Q and B.  Names
+ * are listed by wt_kernel_names (comma separated). */
 int wt_timing_enable(wt_grid* g, int enable);
 int wt_timing_reset(wt_grid* g);
 int wt_kernel_time(wt_grid* g, const char* name, double* total_ms, int64_t* launches, double* total_bytes);
 /* Units the last timed launch of kernel `name` processed: elements (a node and its three edges)
- * for trisk_edge_cell, trisk_tend, trisk_lattice and trisk_lattice_masked (the lattice kernel:
- * its regular tiles of all ten lozenges), triangles for trisk_vertex; 0 if none was timed. */
+ * for trisk_edge_cell, trisk_tend, trisk_lattice, trisk_lattice_masked and trisk_lattice_inter
+ * (the lattice kernel: its regular tiles of all ten lozenges, or the flagged ones), triangles for
+ * trisk_vertex; 0 if none was timed. */
 int wt_kernel_units(wt_grid* g, const char* name, int64_t* units);
 const char* wt_kernel_names(void);
 

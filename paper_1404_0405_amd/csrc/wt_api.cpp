@@ -108,6 +108,7 @@ struct wt_grid {
   // at least this fraction of its elements (above 1: never; built by wt_set_dense_levels).
   double dense_min = 2.0;
   bool splan_dense = false;   // the merged-phase plan was built with the finest level dense
+  bool splan_dense2 = false;  // ... and with the level below it running the intermediates-only form
   bool lists_ok = false;      // the lists match the current masks
   bool details_partial = false;   // the stored details cover only the work-list support
   uint64_t epoch = 0;         // bumped whenever the launches of a step change (see touch_epoch)
@@ -364,6 +365,18 @@ static bool dense_finest(const wt_grid* g) {
   return double(l.l_elem.n) >= g->dense_min * double(l.tab.N);
 }
 
+// Whether the level below the finest computes its intermediates (F, Q, B) through the masked
+// lattice kernel's intermediates-only form: the finest level is dense, the level has a lattice
+// form and is as dense by the same measure.  Its tendencies stay listed: they follow the
+// restriction from the finest level, which replaces F, Q and B at its non-leaf points.
+static bool dense_second(const wt_grid* g) {
+  if (!dense_finest(g)) return false;
+  const LevelState& l = *g->lev[g->lev.size() - 2];
+  if (!l.lat.ok) return false;
+  if (!(g->use_lists && g->lists_ok)) return true;
+  return double(l.l_elem.n) >= g->dense_min * double(l.tab.N);
+}
+
 // The launches of a multilevel step depend on whether the work lists are used, on the lists'
 // addresses and padded bounds, and on the mask addresses; a captured step stays valid while
 // none of these change.
@@ -384,6 +397,8 @@ static void touch_epoch(wt_grid* g) {
   sig.push_back(g->prm.equations);
   sig.push_back(dense_finest(g));
   sig.push_back(g->lev.back()->tflag_ok);
+  sig.push_back(g->multi() && dense_second(g));
+  if (g->multi()) sig.push_back(g->lev[g->lev.size() - 2]->tflag_ok);
   auto add = [&](const WorkList& L) {
     sig.push_back(reinterpret_cast<int64_t>(L.idx));
     sig.push_back(L.bound);
@@ -410,23 +425,26 @@ static void touch_epoch(wt_grid* g) {
 
 // Support rings of the active points of every level and the index lists of the adaptive stage
 // (ballot / prefix-scan compaction).  Called whenever the masks change.
-// Tile flags of the finest level's masked lattice form from the 5-ring support of the work lists
-// just built (without lists the masked form runs every tile).
+// Tile flags of the masked lattice forms of the two finest levels from the 5-ring support of the
+// work lists just built (without lists the masked form runs every tile).
 static void update_tile_flags(wt_grid* g) {
-  LevelState& l = *g->lev.back();
-  l.tflag_ok = false;
-  if (!g->multi() || !(g->dense_min <= 1.0) || !l.lat.ok || !(g->use_lists && g->lists_ok)) return;
-  if (!l.tflag) {
-    HIPCHK(wt::dmalloc(&l.tflag, size_t(l.lat.args.ntile) * 10));
-    HIPCHK(wt::dmalloc(&l.tcount, sizeof(int32_t)));
+  for (auto& lp : g->lev) lp->tflag_ok = false;
+  if (!g->multi() || !(g->dense_min <= 1.0) || !(g->use_lists && g->lists_ok)) return;
+  for (size_t q = g->lev.size() - 2; q < g->lev.size(); ++q) {
+    LevelState& l = *g->lev[q];
+    if (!l.lat.ok) continue;
+    if (!l.tflag) {
+      HIPCHK(wt::dmalloc(&l.tflag, size_t(l.lat.args.ntile) * 10));
+      HIPCHK(wt::dmalloc(&l.tcount, sizeof(int32_t)));
+    }
+    lattice_tile_flags(l.lat, l.s5n, l.s5e, l.tflag, l.tcount, g->stream);
+    l.tflag_ok = true;
   }
-  lattice_tile_flags(l.lat, l.s5n, l.s5e, l.tflag, l.tcount, g->stream);
-  l.tflag_ok = true;
 }
 
 static void build_work_lists(wt_grid* g, bool touch = true) {
   g->lists_ok = false;
-  g->lev.back()->tflag_ok = false;
+  for (auto& lp : g->lev) lp->tflag_ok = false;
   if (!g->multi() || !g->use_lists) {
     if (touch) touch_epoch(g);
     return;
@@ -512,10 +530,11 @@ static void build_work_lists(wt_grid* g, bool touch = true) {
   if (touch) touch_epoch(g);
 }
 
-// The finest level's stage through the masked lattice kernel (flagged tiles only when the flags
-// are current; their count is read back only for the byte count of a timed launch).
-static void dense_stage(wt_grid* g, const StageSpec& sp, const PhysParams& p, bool fp32) {
-  LevelState& l = *g->lev.back();
+// A level's stage through the masked lattice kernel (flagged tiles only when the flags are
+// current; their count is read back only for the byte count of a timed launch): the finest
+// level whole, or (inter) the intermediates of the level below it.
+static void dense_stage(wt_grid* g, LevelState& l, const StageSpec& sp, const PhysParams& p, bool fp32,
+                        bool inter = false) {
   const uint8_t* tf = l.tflag_ok ? l.tflag : nullptr;
   int64_t flagged = 0;
   if (tf && g->timer.enabled) {
@@ -524,7 +543,8 @@ static void dense_stage(wt_grid* g, const StageSpec& sp, const PhysParams& p, bo
     HIPCHK(hipStreamSynchronize(g->stream));
     flagged = c;
   }
-  launch_lattice_masked(l.lat, l.work, l.na, l.ea, tf, flagged, p, fp32, sp.pdh, sp.pu, sp.c, g->stream, &g->timer);
+  launch_lattice_masked(l.lat, l.work, l.na, l.ea, tf, flagged, p, fp32, sp.pdh, sp.pu, sp.c, g->stream, &g->timer,
+                        inter);
 }
 
 static void ml_step(wt_grid* g, double dt) {
@@ -534,7 +554,7 @@ static void ml_step(wt_grid* g, double dt) {
   PhysParams p = phys(g);
   const bool wl = g->use_lists && g->lists_ok;
   auto LS = [&](const WorkList& L) { return wl ? span(L) : Span{}; };
-  const bool dense = dense_finest(g);
+  const bool dense = dense_finest(g), dense2 = dense_second(g);
   const DevLattice& lat = g->lev.back()->lat;
   for (int s = 0; s < 4; ++s) {
     std::vector<StageSpec> sp(nl);
@@ -553,11 +573,13 @@ static void ml_step(wt_grid* g, double dt) {
     }
     for (int q = 0; q < nl; ++q) {
       LevelState& l = *g->lev[q];
-      if (dense && q == nl - 1) {
-        // the tile elements whole through the lattice kernel, then the rim from the tables
-        dense_stage(g, sp[q], p, fp32);
-        ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, Span{lat.sup_tris, lat.n_sup_tris},
-                               Span{lat.sup_elems, lat.n_sup_elems}, Span{lat.rim_edges, lat.n_rim_edges});
+      if ((dense && q == nl - 1) || (dense2 && q == nl - 2)) {
+        // the tile elements through the lattice kernel (the finest level whole, the level below
+        // it its intermediates only), then the rim's intermediates from the tables
+        const DevLattice& lt = l.lat;
+        dense_stage(g, l, sp[q], p, fp32, q == nl - 2);
+        ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, Span{lt.sup_tris, lt.n_sup_tris},
+                               Span{lt.sup_elems, lt.n_sup_elems}, Span{lt.rim_edges, lt.n_rim_edges});
         continue;
       }
       ml_level_intermediates(l.tab, l.work, p, fp32, xdh[q], xu[q], g->stream, LS(l.l_tri), LS(l.l_elem),
@@ -1041,7 +1063,9 @@ void wt_table_cache_clear(void) {
   g_pair_cache.clear();
 }
 
-const char* wt_kernel_names(void) { return "trisk_vertex,trisk_edge_cell,trisk_tend,trisk_lattice,trisk_lattice_masked"; }
+const char* wt_kernel_names(void) {
+  return "trisk_vertex,trisk_edge_cell,trisk_tend,trisk_lattice,trisk_lattice_masked,trisk_lattice_inter";
+}
 
 wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
   if (jmin < 0 || jmax < jmin || jmax > 12) {
@@ -1440,6 +1464,7 @@ static bool phase_plan_ready(wt_grid* g, double dt) {
   if (g->sphase.empty() || g->splan_sig != g->step_sig || g->splan_dt != dt) {
     build_batch_plan({g}, &dt, g->splan, true);
     g->splan_dense = dense_finest(g);
+    g->splan_dense2 = dense_second(g);
     g->splan.upload(g->stream);
     phase_prepare(g->splan, g->sphase);
     g->splan_sig = g->step_sig;
@@ -1477,15 +1502,19 @@ static void check_plan(const BatchPlan& pl, const std::vector<wt_grid*>& members
 // the step with a ready plan: launches only (capturable)
 static void ml_step_phases(wt_grid* g) {
   check_plan(g->splan, {g});
-  if (g->splan_dense != dense_finest(g))
-    throw std::runtime_error("step plan built for another choice of the finest level's kernel");
+  if (g->splan_dense != dense_finest(g) || g->splan_dense2 != dense_second(g))
+    throw std::runtime_error("step plan built for another choice of the finest levels' kernels");
   ++g->state_ver;
   LevelState& fl = *g->lev.back();
+  LevelState& sl = *g->lev[g->lev.size() - 2];
   const PhysParams p = phys(g);
   for (const PhaseArgs& a : g->sphase) {
-    if (a.j0 < 0) {
+    if (a.j0 < 0 && a.j0 >= -4) {
       // marker of the finest level's masked lattice launch of stage -1 - j0
-      dense_stage(g, rk_stage(g->prm.rk, -1 - a.j0, fl.work, g->splan_dt), p, fp32_of(g));
+      dense_stage(g, fl, rk_stage(g->prm.rk, -1 - a.j0, fl.work, g->splan_dt), p, fp32_of(g));
+    } else if (a.j0 < 0) {
+      // marker of the intermediates-only launch of the level below, stage -5 - j0
+      dense_stage(g, sl, rk_stage(g->prm.rk, -5 - a.j0, sl.work, g->splan_dt), p, fp32_of(g), true);
     } else {
       phase_launch(g->splan, a, g->stream);
     }
@@ -1606,6 +1635,13 @@ int wt_set_dense_levels(wt_grid* g, double min_fraction) {
         LatticeHost lh;
         if (!build_lattice(*lv, lh)) return fail(WT_EINVAL, "wt_set_dense_levels: no regular tiles");
         upload_lattice(lh, l.lat);
+      }
+      // the level below it, when it has a lattice form (level 6 and up)
+      LevelState& l2 = g->L(g->jmax - 1);
+      if (!l2.lat.ok && g->jmax - 1 >= 6) {
+        auto lv = cached_level(g->jmax - 1, g->prm.radius, g->prm.omega);
+        LatticeHost lh;
+        if (build_lattice(*lv, lh)) upload_lattice(lh, l2.lat);
       }
     }
     g->dense_min = min_fraction;
@@ -2072,7 +2108,7 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
   pl.phases.clear();
   struct MInfo {
     int lev0, pair0, jmin, jmax;
-    bool wl, fp32, dense;
+    bool wl, fp32, dense, dense2;
   };
   std::vector<MInfo> mi;
   int J0 = 1 << 30, J1 = -1;
@@ -2080,7 +2116,7 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
     wt_grid* g = members[k];
     if (!g->multi()) throw std::runtime_error("the batched step needs multilevel members");
     MInfo x{int(pl.levels.size()), int(pl.pairs.size()), g->jmin, g->jmax, g->use_lists && g->lists_ok,
-            g->prm.precision == WT_FP32_TENDENCY, allow_dense && dense_finest(g)};
+            g->prm.precision == WT_FP32_TENDENCY, allow_dense && dense_finest(g), allow_dense && dense_second(g)};
     if (x.dense && members.size() != 1) throw std::runtime_error("batched step: dense finest level of a member");
     const PhysParams p = phys(g);
     for (auto& lp : g->lev) {
@@ -2149,15 +2185,17 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
         }
       flush();
     }
-    for (size_t k = 0; k < mi.size(); ++k)
+    for (size_t k = 0; k < mi.size(); ++k) {
       if (mi[k].dense) pl.phases.push_back(BatchPhase{-1 - st, -1 - st});
+      if (mi[k].dense2) pl.phases.push_back(BatchPhase{-5 - st, -5 - st});
+    }
     const int kinds[3] = {BK_VERTEX, BK_EDGE_CELL, BK_Q};
     for (int kind : kinds) {
       for (size_t k = 0; k < mi.size(); ++k) {
         wt_grid* g = members[k];
         for (int q = 0; q < int(g->lev.size()); ++q) {
           const LevelState& l = *g->lev[q];
-          if (mi[k].dense && q + 1 == int(g->lev.size())) {
+          if ((mi[k].dense && q + 1 == int(g->lev.size())) || (mi[k].dense2 && q + 2 == int(g->lev.size()))) {
             const DevLattice& lt = l.lat;
             if (kind == BK_VERTEX) fixed(kind, mi[k].lev0 + q, st, mi[k], lt.sup_tris, lt.n_sup_tris);
             else if (kind == BK_EDGE_CELL) fixed(kind, mi[k].lev0 + q, st, mi[k], lt.sup_elems, lt.n_sup_elems);

@@ -84,7 +84,7 @@ struct StagePtrs {
   double *o1, *o2;
 };
 
-enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_LATTICE, K_LATTICE_ML, K_COUNT };
+enum KernelId { K_VERTEX = 0, K_EDGE_CELL, K_TEND, K_LATTICE, K_LATTICE_ML, K_LATTICE_INTER, K_COUNT };
 extern const char* const kKernelNames[K_COUNT];
 
 struct Timer {
@@ -115,10 +115,12 @@ void launch_stage(const DevTables& t, DevWork& w, const PhysParams& p, bool fp32
 // tendencies zero at inactive points (na, ea), F, Q, B of every tile element stored for the
 // restriction.  tflag (10 per tile; null: every tile) limits it to the tiles of each lozenge that
 // hold support points, `flagged` of them (for the byte count).  The rim round the lozenge
-// corners is left to the listed kernels.
+// corners is left to the listed kernels.  inter: F, Q, B alone (no tendency, no stage output; the
+// level's tendencies follow the restriction from the level above).
 void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na, const uint8_t* ea,
                            const uint8_t* tflag, int64_t flagged, const PhysParams& p, bool fp32,
-                           const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm);
+                           const StagePtrs& sdh, const StagePtrs& su, const StageOut& c, hipStream_t s, Timer* tm,
+                           bool inter = false);
 
 // q_v, B, F, q_e of one level (no tendency, no stage output): every triangle / element, or the
 // listed ones (nt, ne < 0: the whole level).

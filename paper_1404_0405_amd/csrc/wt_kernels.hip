@@ -25,7 +25,7 @@
 namespace wt {
 
 const char* const kKernelNames[K_COUNT] = {"trisk_vertex", "trisk_edge_cell", "trisk_tend", "trisk_lattice",
-                                             "trisk_lattice_masked"};
+                                             "trisk_lattice_masked", "trisk_lattice_inter"};
 
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
@@ -228,7 +228,7 @@ static void stage_impl(const DevTables& t, DevWork& w, const PhysParams& p, cons
 
 void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na, const uint8_t* ea,
                            const uint8_t* tflag, int64_t flagged, const PhysParams& p, bool fp32, const StagePtrs& sdh,
-                           const StagePtrs& su, const StageOut& c_in, hipStream_t s, Timer* tm) {
+                           const StagePtrs& su, const StageOut& c_in, hipStream_t s, Timer* tm, bool inter) {
   if (!lat.ok) throw std::runtime_error("masked lattice stage: the level has no lattice form");
   if (p.nu != 0.0 || p.adv) throw std::runtime_error("masked lattice stage: inviscid shallow-water form only");
   // a stage array that is the stage input itself is read once (as in the uniform stage)
@@ -252,8 +252,11 @@ void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na,
   const double sz = fp32 ? 4.0 : 8.0;
   const int64_t units = tflag ? flagged * LT_TI * LT_TJ : lat.n_reg_elems;
   const double nreg = double(units);
-  TimedLaunch tl_(tm, K_LATTICE_ML, s,
-                  nreg * (32.0 + 4.0 * 8.0 * r + 4.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0, units);
+  // the intermediates-only form: the stage input, the geometry's share and the stored F, Q, B
+  TimedLaunch tl_(tm, inter ? K_LATTICE_INTER : K_LATTICE_ML, s,
+                  inter ? nreg * (32.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0
+                        : nreg * (32.0 + 4.0 * 8.0 * r + 4.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0,
+                  units);
   LatArgs a = lat.args;
   a.g = p.g;
   a.H = p.H;
@@ -264,7 +267,7 @@ void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na,
   m.F = static_cast<double*>(w.F);
   m.Q = w.Q;
   m.B = w.B;
-  launch_lattice(a, fp32, sdh, su, c, s, &m);
+  launch_lattice(a, fp32, sdh, su, c, s, &m, inter);
 }
 
 template <typename T>

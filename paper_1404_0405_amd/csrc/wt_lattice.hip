@@ -157,8 +157,10 @@ __device__ __forceinline__ AAddr a_address(const ASlot& sl, int L, int n) {
 // Epilogue variants: which of y and acc the stage combination reads from HBM (x comes from LDS)
 // and whether there is a second output (the first is always written).  Keeping these out of
 // run-time branches lets the compiler count outstanding memory operations exactly, so waiting
-// for this lozenge's operands never waits for the next lozenge's prefetch.
-enum { EPI_Y = 1, EPI_ACC = 2, EPI_O2 = 4 };
+// for this lozenge's operands never waits for the next lozenge's prefetch.  EPI_INTER (masked
+// form only): the intermediates alone -- F, Q and B stored, no tendency and no stage output -- for
+// a level below the finest, whose tendencies wait for the restriction from the level above.
+enum { EPI_Y = 1, EPI_ACC = 2, EPI_O2 = 4, EPI_INTER = 8 };
 
 template <typename T, int EPI, bool ML>
 __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, StagePtrs pu, StageOut c, LatML m) {
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
       au[0] = pu.acc[3 * id]; au[1] = pu.acc[3 * id + 1]; au[2] = pu.acc[3 * id + 2];
     }
     // masked form: activity of the element's node and edges, parked in LDS until phase D
-    if constexpr (ML)
+    if constexpr (ML && !(EPI & EPI_INTER))
       s_act[tid] = uint8_t(uint32_t(m.na[id] != 0) | uint32_t(m.ea[3 * id] != 0) << 1 |
                            uint32_t(m.ea[3 * id + 1] != 0) << 2 | uint32_t(m.ea[3 * id + 2] != 0) << 3);
     // ---- phase C: F, q_e at the three edges and B at the node, positions [-1, TI+1) x [-1, TJ+1)
@@ -371,13 +373,15 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
 
     // ---- phase D: tendencies of the tile element of this thread and the stage combination
     {
-      const double div = gdiv[0] * double(s_F[0][lc]) + gdiv[1] * double(s_F[1][lc]) +
-                         gdiv[2] * double(s_F[2][lc]) + gdiv[3] * double(s_F[0][lc - CJ]) +
-                         gdiv[4] * double(s_F[1][lc - CJ - 1]) + gdiv[5] * double(s_F[2][lc - 1]);
-      const uint32_t act = ML ? uint32_t(s_act[tid]) : 0xfu;
-      const double k = (act & 1u) ? -div : 0.0;
-      pdh.o1[id] = c.d1 * k + c.a1 * ydh + c.b1 * adh + c.c1 * s_dh[la_d];
-      if (EPI & EPI_O2) pdh.o2[id] = c.d2 * k + c.a2 * ydh + c.b2 * adh + c.c2 * s_dh[la_d];
+      if constexpr (!(EPI & EPI_INTER)) {
+        const double div = gdiv[0] * double(s_F[0][lc]) + gdiv[1] * double(s_F[1][lc]) +
+                           gdiv[2] * double(s_F[2][lc]) + gdiv[3] * double(s_F[0][lc - CJ]) +
+                           gdiv[4] * double(s_F[1][lc - CJ - 1]) + gdiv[5] * double(s_F[2][lc - 1]);
+        const uint32_t act = ML ? uint32_t(s_act[tid]) : 0xfu;
+        const double k = (act & 1u) ? -div : 0.0;
+        pdh.o1[id] = c.d1 * k + c.a1 * ydh + c.b1 * adh + c.c1 * s_dh[la_d];
+        if (EPI & EPI_O2) pdh.o2[id] = c.d2 * k + c.a2 * ydh + c.b2 * adh + c.c2 * s_dh[la_d];
+      }
       if constexpr (ML) {
         static_cast<T*>(m.B)[id] = s_B[lc];
 #pragma unroll
@@ -402,19 +406,21 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
         if (u % 5 == 4) __builtin_amdgcn_sched_barrier(0);
       }
       const int lb = (di + 2) * BJ + (dj + 2);
-      const uint32_t act = ML ? uint32_t(s_act[tid]) : 0xfu;
+      const uint32_t act = ML && !(EPI & EPI_INTER) ? uint32_t(s_act[tid]) : 0xfu;
       const T qe[3] = {T(0.5) * (s_qv[0][lb] + s_qv[1][lb - 1]), T(0.5) * (s_qv[0][lb] + s_qv[1][lb]),
                        T(0.5) * (s_qv[1][lb] + s_qv[0][lb - BJ])};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const T Q = T(0.5) * (qe[d] * S1[d] + S2[d]);
-        const int lo = lc + DD0[d] * CJ + DD1[d];
-        const T gradB = (s_B[lo] - s_B[lc]) * ginvd[d];
-        const double k = (act & (2u << d)) ? double(-Q - gradB) : 0.0;
         if constexpr (ML) static_cast<T*>(m.Q)[3 * id + d] = Q;
-        const double x = s_u[d][la_d];
-        pu.o1[3 * id + d] = c.d1 * k + c.a1 * yu[d] + c.b1 * au[d] + c.c1 * x;
-        if (EPI & EPI_O2) pu.o2[3 * id + d] = c.d2 * k + c.a2 * yu[d] + c.b2 * au[d] + c.c2 * x;
+        if constexpr (!(EPI & EPI_INTER)) {
+          const int lo = lc + DD0[d] * CJ + DD1[d];
+          const T gradB = (s_B[lo] - s_B[lc]) * ginvd[d];
+          const double k = (act & (2u << d)) ? double(-Q - gradB) : 0.0;
+          const double x = s_u[d][la_d];
+          pu.o1[3 * id + d] = c.d1 * k + c.a1 * yu[d] + c.b1 * au[d] + c.c1 * x;
+          if (EPI & EPI_O2) pu.o2[3 * id + d] = c.d2 * k + c.a2 * yu[d] + c.b2 * au[d] + c.c2 * x;
+        }
       }
     }
   };
@@ -466,15 +472,23 @@ void lattice_tile_flags(const DevLattice& lat, const uint8_t* sn, const uint8_t*
 }
 
 void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,
-                    const StageOut& c, hipStream_t s, const LatML* ml) {
+                    const StageOut& c, hipStream_t s, const LatML* ml, bool inter) {
   const unsigned grid = unsigned((a.ntile + 7) / 8) * 8u;
   const bool ry = c.a1 != 0.0 || c.a2 != 0.0, racc = c.b1 != 0.0 || c.b2 != 0.0;
-  if (!pdh.o1 || !pu.o1 || (pdh.o2 == nullptr) != (pu.o2 == nullptr))
+  if (!pdh.x || !pu.x) throw std::runtime_error("lattice stage: needs the stage input");
+  if (!inter && (!pdh.o1 || !pu.o1 || (pdh.o2 == nullptr) != (pu.o2 == nullptr)))
     throw std::runtime_error("lattice stage: needs the first output, and the second for both or neither of dh, u");
   const int epi = (ry ? EPI_Y : 0) | (racc ? EPI_ACC : 0) | (pdh.o2 ? EPI_O2 : 0);
   if (ml && (!ml->na || !ml->ea || !ml->F || !ml->Q || !ml->B))
     throw std::runtime_error("lattice stage: the masked form needs masks and the F, Q, B outputs");
+  if (inter && !ml) throw std::runtime_error("lattice stage: the intermediates-only form is a masked form");
   const LatML m = ml ? *ml : LatML{};
+  if (inter) {
+    if (fp32) k_lattice<float, EPI_INTER, true><<<grid, LBS, 0, s>>>(a, pdh, pu, c, m);
+    else k_lattice<double, EPI_INTER, true><<<grid, LBS, 0, s>>>(a, pdh, pu, c, m);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   auto go = [&](auto tag, auto e) {
     using T = decltype(tag);
     if (ml) k_lattice<T, decltype(e)::value, true><<<grid, LBS, 0, s>>>(a, pdh, pu, c, m);

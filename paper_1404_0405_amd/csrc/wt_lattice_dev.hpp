@@ -44,8 +44,9 @@ void lattice_tile_flags(const DevLattice& lat, const uint8_t* sn, const uint8_t*
                         hipStream_t s);
 void upload_lattice(const LatticeHost& h, DevLattice& d);
 void free_lattice(DevLattice& d);
-// ml null: the uniform stage; otherwise the masked form above.
+// ml null: the uniform stage; otherwise the masked form above.  inter (masked form only): the
+// intermediates F, Q, B alone, no tendency and no stage output (pdh.o*, pu.o* unused).
 void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const StagePtrs& pu,
-                    const StageOut& c, hipStream_t s, const LatML* ml = nullptr);
+                    const StageOut& c, hipStream_t s, const LatML* ml = nullptr, bool inter = false);
 
 }  // namespace wt

@@ -1,7 +1,9 @@
-"""GPU parity of the dense finest level: the finest level of an adaptive grid run whole through
+"""GPU parity of the dense finest levels: the finest level of an adaptive grid run whole through
 the masked lattice kernel (tendencies zero at inactive points, F, Q and B stored for the
-restriction chain), the rim round the lozenge corners through the listed kernels.  Against the
-FP64 oracle, against the listed stage, and between the step's launch forms."""
+restriction chain), the level below it (from level 6 up) its intermediates F, Q, B through the
+kernel's intermediates-only form (its tendencies stay listed, after the restriction), the rims
+round the lozenge corners through the listed kernels.  Against the FP64 oracle, against the
+listed stage, and between the step's launch forms."""
 import sys
 
 import numpy as np
@@ -35,13 +37,18 @@ def _masked_launches(g):
     return g.kernel_time("trisk_lattice_masked")[1]
 
 
+def _inter_launches(g):
+    return g.kernel_time("trisk_lattice_inter")[1]
+
+
 @pytest.mark.parametrize("case,jmin,jmax,eps,steps,rk", [("turb", 3, 6, 1e-2, 4, wt.WT_RK4),
                                                           ("tc2p", 4, 6, 1e-3, 12, wt.WT_RK4),
                                                           ("jet", 4, 7, 5e-3, 8, wt.WT_SSPRK43)])
 def test_dense_finest_level_against_oracle(case, jmin, jmax, eps, steps, rk):
-    """Adapt + step with the finest level always dense: masks identical to the oracle's, every
+    """Adapt + step with the finest levels always dense: masks identical to the oracle's, every
     level within 1e-11 (rel L-inf), mass conserved to 1e-13, and the masked lattice kernel
-    launched once per stage."""
+    launched once per stage, its intermediates-only form too when the level below the finest is
+    6 or more."""
     _say(f"dense finest level vs oracle: {case} {jmin}..{jmax} eps={eps} rk={rk}")
     H = Hierarchy(jmin, jmax)
     og = H.g[jmax]
@@ -72,12 +79,13 @@ def test_dense_finest_level_against_oracle(case, jmin, jmax, eps, steps, rk):
             assert np.array_equal(gea.astype(bool), ea), f"edge mask differs on level {j}"
             worst = max(worst, _rel(x, a), _rel(y, b))
         d, code = g.diagnostics()
-        launches = _masked_launches(g)
-    _say(f"worst rel L-inf {worst:.2e}, masked lattice launches {launches}")
+        launches, inter = _masked_launches(g), _inter_launches(g)
+    _say(f"worst rel L-inf {worst:.2e}, masked lattice launches {launches}, intermediates-only {inter}")
     assert code == wt.WT_OK
     assert worst < 1e-11, worst
     assert abs(d.mass / m0 - 1) < 1e-13
     assert launches == 4 * steps
+    assert inter == (4 * steps if jmax - 1 >= 6 else 0)
 
 
 @pytest.mark.parametrize("rk,prec", [(wt.WT_RK4, wt.WT_FP64), (wt.WT_SSPRK43, wt.WT_FP32_TENDENCY)])
@@ -131,7 +139,8 @@ def test_dense_agrees_with_listed_stage_and_switches_by_density():
                 g.adapt(eps)
                 g.step(dt)
             out[mode] = ([g.get_state(j) for j in range(jmin, jmax + 1)], _masked_launches(g),
-                         g.diagnostics()[0].active_nodes[jmax], wt.kernel_units(g, "trisk_lattice_masked"))
+                         g.diagnostics()[0].active_nodes[jmax], wt.kernel_units(g, "trisk_lattice_masked"),
+                         _inter_launches(g))
     n_fine = 10 * 4 ** jmax + 2
     tiles = wt.host_lattice_check(jmax)[0]
     _say(f"finest level active nodes {out['off'][2]} of {n_fine}; masked kernel ran {out['on'][3]} of "
@@ -140,6 +149,8 @@ def test_dense_agrees_with_listed_stage_and_switches_by_density():
     # the masked kernel skips the tiles of each lozenge without support points
     assert 0 < out["on"][3] < tiles * 512 * 10 and out["on"][3] % 512 == 0
     assert out["on"][1] == 20 and out["off"][1] == 0 and out["high"][1] == 0 and out["above1"][1] == 0
+    # level 6 below the finest: its intermediates through the lattice kernel when on
+    assert out["on"][4] == 20 and out["off"][4] == 0 and out["high"][4] == 0 and out["above1"][4] == 0
     for mode in ("high", "above1"):
         for s1, s2 in zip(out["off"][0], out[mode][0]):
             for a, b in zip(s1, s2):
@@ -206,7 +217,7 @@ def test_dense_levels_argument_errors():
         g.set_state(6, dh, u)
         g.adapt(1e-3)
         g.step(100.0)
-        assert _masked_launches(g) == 0
+        assert _masked_launches(g) == 0 and _inter_launches(g) == 0
 
 
 def test_dense_full_size_turbulence_agrees_with_listed():
@@ -234,9 +245,11 @@ def test_dense_full_size_turbulence_agrees_with_listed():
                 g.step(dt)
             d, code = g.diagnostics()
             assert code == wt.WT_OK
-            runs.append(([g.get_state(j) for j in range(jmin, jmax + 1)], _masked_launches(g), d.mass))
-    (sa, la, ma), (sb, lb, mb) = runs
-    assert la > 0 and lb == 0
+            runs.append(([g.get_state(j) for j in range(jmin, jmax + 1)], _masked_launches(g), d.mass,
+                         _inter_launches(g)))
+    (sa, la, ma, ia), (sb, lb, mb, ib) = runs
+    _say(f"intermediates-only launches (level 9): {ia}")
+    assert la > 0 and ia > 0 and lb == 0 and ib == 0
     worst, flips, total = 0.0, 0, 0
     for (x, y, na, ea), (x2, y2, na2, ea2) in zip(sa, sb):
         flips += int((na != na2).sum()) + int((ea != ea2).sum())
