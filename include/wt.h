@@ -228,6 +228,11 @@ int wt_set_step_phases(wt_grid* g, int enable);
  * other forms and ensemble steps keep the listed kernels).  WT_EINVAL for a negative or
  * non-finite fraction or a finest level below 6.  Synchronises. */
 int wt_set_dense_levels(wt_grid* g, double min_fraction);
+/* The level below the finest runs its intermediates through the lattice kernel only when its
+ * lattice has at least min_tiles tile positions (the kernel runs one workgroup per position):
+ * -1, the default, takes the device's compute-unit count, below which the listed kernels are
+ * faster; 0 lets any size through (test hook for small grids).  WT_EINVAL below -1. */
+int wt_set_dense_min_tiles(wt_grid* g, int min_tiles);
 
 /* Replace the active masks of `level` (host arrays of N and E bytes, 1 = active).  Test hook,
  * used to resynchronise masks with a reference at exact threshold ties. */

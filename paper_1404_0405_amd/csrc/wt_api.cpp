@@ -107,6 +107,8 @@ struct wt_grid {
   // The finest level runs whole through the masked lattice kernel when its listed support holds
   // at least this fraction of its elements (above 1: never; built by wt_set_dense_levels).
   double dense_min = 2.0;
+  int dense2_min_tiles = -1;   // tile positions the level below the finest needs to run dense (-1: cus)
+  int cus = 0;                 // compute units of the grid's device
   bool splan_dense = false;   // the merged-phase plan was built with the finest level dense
   bool splan_dense2 = false;  // ... and with the level below it running the intermediates-only form
   bool lists_ok = false;      // the lists match the current masks
@@ -373,6 +375,10 @@ static bool dense_second(const wt_grid* g) {
   if (!dense_finest(g)) return false;
   const LevelState& l = *g->lev[g->lev.size() - 2];
   if (!l.lat.ok) return false;
+  // one workgroup per tile position: with fewer positions than compute units the launch leaves
+  // part of the device idle and the listed kernels are faster (the spun-up jet's level 8: 124
+  // positions, its step 1.61 -> 1.69 ms)
+  if (l.lat.args.ntile < (g->dense2_min_tiles >= 0 ? g->dense2_min_tiles : g->cus)) return false;
   if (!(g->use_lists && g->lists_ok)) return true;
   return double(l.l_elem.n) >= g->dense_min * double(l.tab.N);
 }
@@ -1096,6 +1102,7 @@ wt_grid* wt_grid_create(int jmin, int jmax, int patch) {
     }
     auto g = std::make_unique<wt_grid>();
     g->jmin = jmin; g->jmax = jmax; g->patch = patch;
+    g->cus = prop.multiProcessorCount;
     g->prm.radius = 6.371e6;
     g->prm.omega = 7.292e-5;
     g->prm.gravity = 9.80616;
@@ -1651,6 +1658,19 @@ int wt_set_dense_levels(wt_grid* g, double min_fraction) {
     return fail(WT_ENOMEM, "wt_set_dense_levels: out of memory");
   } catch (const std::exception& e) {
     return fail(WT_EDEVICE, std::string("wt_set_dense_levels: ") + e.what());
+  }
+  return WT_OK;
+}
+
+int wt_set_dense_min_tiles(wt_grid* g, int min_tiles) {
+  GridScope scope_(g);
+  if (!g) return fail(WT_EINVAL, "wt_set_dense_min_tiles: null grid");
+  if (min_tiles < -1) return fail(WT_EINVAL, "wt_set_dense_min_tiles: min_tiles must be >= -1");
+  try {
+    g->dense2_min_tiles = min_tiles;
+    touch_epoch(g);
+  } catch (const std::exception& e) {
+    return fail(WT_EDEVICE, std::string("wt_set_dense_min_tiles: ") + e.what());
   }
   return WT_OK;
 }

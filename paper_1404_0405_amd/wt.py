@@ -105,6 +105,7 @@ SIGNATURES = [
     ("wt_set_work_lists", C.c_int, [_P, C.c_int]),
     ("wt_set_step_phases", C.c_int, [_P, C.c_int]),
     ("wt_set_dense_levels", C.c_int, [_P, C.c_double]),
+    ("wt_set_dense_min_tiles", C.c_int, [_P, C.c_int]),
     ("wt_ensemble_create", _P, [C.POINTER(_P), C.c_int]),
     ("wt_ensemble_destroy", None, [_P]),
     ("wt_ensemble_adapt", C.c_int, [_P, _D]),
@@ -421,6 +422,10 @@ class Grid:
         """Run the finest level through the masked lattice kernel when its listed support holds
         at least `min_fraction` of its elements (above 1: off, the default)."""
         _check(load().wt_set_dense_levels(self._h, float(min_fraction)))
+
+    def set_dense_min_tiles(self, min_tiles):
+        """Tile positions the level below the finest needs to run dense (-1: the device's CU count)."""
+        _check(load().wt_set_dense_min_tiles(self._h, int(min_tiles)))
 
     def debug_force_drop(self, level, patch):
         """Withhold the children rule of a patch at the next gated adapt (test hook)."""

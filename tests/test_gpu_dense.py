@@ -59,6 +59,7 @@ def test_dense_finest_level_against_oracle(case, jmin, jmax, eps, steps, rk):
     with g:
         g.set_params(mean_depth=Hd, rk=rk)
         g.set_dense_levels(0.0)
+        g.set_dense_min_tiles(0)
         g.timing(True)
         g.set_state(jmax, dh, u)
         H.set_state(jmax, dh, u)
@@ -103,6 +104,7 @@ def test_dense_launch_forms_agree_bitwise(rk, prec):
             dh, u, Hd = inputs.tc2_perturbed(x, m, t, amplitude=300.0)
             g.set_params(mean_depth=Hd, rk=rk, precision=prec)
             g.set_dense_levels(0.0)
+            g.set_dense_min_tiles(0)
             g.set_step_phases(merged)
             g.set_work_lists(lists)
             g.set_state(jmax, dh, u)
@@ -132,6 +134,7 @@ def test_dense_agrees_with_listed_stage_and_switches_by_density():
             dh, u, Hd = inputs.jet(x, m, t)
             g.set_params(mean_depth=Hd)
             g.set_dense_levels({"off": 2.0, "on": 0.0, "high": 0.99, "above1": 1.5}[mode])
+            g.set_dense_min_tiles(0)
             g.timing(True)
             g.set_state(jmax, dh, u)
             dt = g.suggest_dt(0.8)
@@ -209,6 +212,8 @@ def test_dense_levels_argument_errors():
         for bad in (-0.5, float("nan"), float("inf")):
             with pytest.raises(wt.WtError):
                 g.set_dense_levels(bad)
+        with pytest.raises(wt.WtError):
+            g.set_dense_min_tiles(-2)
         x, m, t = g.coords(6)
         dh, u, Hd = inputs.tc2_perturbed(x, m, t, amplitude=300.0)
         g.set_params(mean_depth=Hd, viscosity=1e5)
