@@ -594,7 +594,9 @@ static void ml_step(wt_grid* g, double dt) {
     for (int j = g->jmax - 1; j >= g->jmin; --j) {
       LevelState &C = g->L(j), &F = g->L(j + 1);
       PairState& P = g->P(j);
-      ml_restrict(P.dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, p, fp32, g->stream, LS(F.l_node), LS(P.l_ce),
+      // a dense finest level's tile nodes have their divergence from the lattice kernel: the rim's
+      const Span lfn = dense && j + 1 == g->jmax ? Span{lat.rim, lat.n_rim} : LS(F.l_node);
+      ml_restrict(P.dev, C.tab, F.tab, C.work, F.work, F.na, F.ea, p, fp32, g->stream, lfn, LS(P.l_ce),
                   LS(P.l_cn));
     }
     for (int q = 0; q < nl; ++q) {
@@ -2233,7 +2235,10 @@ static void build_batch_plan(const std::vector<wt_grid*>& members, const double*
       for (size_t k = 0; k < mi.size(); ++k)
         if (mi[k].jmin <= j && j < mi[k].jmax) {
           const LevelState& F = members[k]->L(j + 1);
-          job(BK_DIV, mi[k].lev0 + (j + 1 - mi[k].jmin), st, mi[k], F.l_node, F.tab.N);
+          if (mi[k].dense && j + 1 == mi[k].jmax)   // the tile nodes' divergence comes from the lattice
+            fixed(BK_DIV, mi[k].lev0 + (j + 1 - mi[k].jmin), st, mi[k], F.lat.rim, F.lat.n_rim);
+          else
+            job(BK_DIV, mi[k].lev0 + (j + 1 - mi[k].jmin), st, mi[k], F.l_node, F.tab.N);
         }
       flush();
       for (size_t k = 0; k < mi.size(); ++k)

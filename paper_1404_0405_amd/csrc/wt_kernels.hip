@@ -252,10 +252,11 @@ void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na,
   const double sz = fp32 ? 4.0 : 8.0;
   const int64_t units = tflag ? flagged * LT_TI * LT_TJ : lat.n_reg_elems;
   const double nreg = double(units);
-  // the intermediates-only form: the stage input, the geometry's share and the stored F, Q, B
+  // (+ 8 B of the stored divergence); the intermediates-only form: the stage input, the
+  // geometry's share and the stored F, Q, B
   TimedLaunch tl_(tm, inter ? K_LATTICE_INTER : K_LATTICE_ML, s,
                   inter ? nreg * (32.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0
-                        : nreg * (32.0 + 4.0 * 8.0 * r + 4.0 + 24.0 + 4.0 * sz) + nreg / 10.0 * 58.0 * 8.0,
+                        : nreg * (32.0 + 4.0 * 8.0 * r + 4.0 + 24.0 + 4.0 * sz + 8.0) + nreg / 10.0 * 58.0 * 8.0,
                   units);
   LatArgs a = lat.args;
   a.g = p.g;
@@ -267,6 +268,7 @@ void launch_lattice_masked(const DevLattice& lat, DevWork& w, const uint8_t* na,
   m.F = static_cast<double*>(w.F);
   m.Q = w.Q;
   m.B = w.B;
+  m.c = inter ? nullptr : w.c;
   launch_lattice(a, fp32, sdh, su, c, s, &m, inter);
 }
 

@@ -381,6 +381,7 @@ __global__ __launch_bounds__(LBS) void k_lattice(LatArgs a, StagePtrs pdh, Stage
         const double k = (act & 1u) ? -div : 0.0;
         pdh.o1[id] = c.d1 * k + c.a1 * ydh + c.b1 * adh + c.c1 * s_dh[la_d];
         if (EPI & EPI_O2) pdh.o2[id] = c.d2 * k + c.a2 * ydh + c.b2 * adh + c.c2 * s_dh[la_d];
+        if constexpr (ML) m.c[id] = div;   // the fine divergence of the restriction
       }
       if constexpr (ML) {
         static_cast<T*>(m.B)[id] = s_B[lc];
@@ -482,6 +483,7 @@ void launch_lattice(const LatArgs& a, bool fp32, const StagePtrs& pdh, const Sta
   if (ml && (!ml->na || !ml->ea || !ml->F || !ml->Q || !ml->B))
     throw std::runtime_error("lattice stage: the masked form needs masks and the F, Q, B outputs");
   if (inter && !ml) throw std::runtime_error("lattice stage: the intermediates-only form is a masked form");
+  if (ml && !inter && !ml->c) throw std::runtime_error("lattice stage: the masked form needs the divergence output");
   const LatML m = ml ? *ml : LatML{};
   if (inter) {
     if (fp32) k_lattice<float, EPI_INTER, true><<<grid, LBS, 0, s>>>(a, pdh, pu, c, m);

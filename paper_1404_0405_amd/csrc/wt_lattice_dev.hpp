@@ -28,7 +28,8 @@ struct DevLattice {
 
 // Finest level of an adaptive grid: the tendencies are zero at inactive points (masks na, ea),
 // and the kernel also stores what the restriction chain to the coarser level reads: the mass
-// flux F (double), qF^perp Q and the Bernoulli function B (compute type) of every tile element.
+// flux F (double), qF^perp Q and the Bernoulli function B (compute type) of every tile element,
+// and (not in the intermediates-only form) the divergence of F at every tile node.
 struct LatML {
   const uint8_t* na = nullptr;
   const uint8_t* ea = nullptr;
@@ -36,6 +37,7 @@ struct LatML {
   double* F = nullptr;
   void* Q = nullptr;
   void* B = nullptr;
+  double* c = nullptr;   // div F of every tile node (the fine divergence the restriction reads)
 };
 
 // flag[10 t + L] = 1 when tile t of lozenge L holds a point of the support (sn, se); *count the
