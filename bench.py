@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "trisk_lattice": {
         "sources": ("paper_1404_0405_amd/csrc/wt_lattice.hip", "paper_1404_0405_amd/csrc/wt_lattice_dev.hpp"),
-        "sha256": ("09fa2baef353a9e5881b87efcbea19fcd45f6faadce364e96235d08d2b5c7c92",
-                   "95585fe743f23e6ec3c70561e12091327b6aab3d28cd0be88de41d69e84473a5"),
-        "level": 10, "fetch_kib": 673009.1, "write_kib": 572320.4, "fetch_scale": 2.000, "write_scale": 1.000,
+        "sha256": ("5d73a7b03dc4a251609a248e8297c797dba1ebe8a5af6c463f729d6ae9318ead",
+                   "18c6e1fc6b3178e275b06de215aab33aef8588bb6fad7c1be6311c5c0a6aefcd"),
+        "level": 10, "fetch_kib": 673251.9, "write_kib": 572320.5, "fetch_scale": 2.000, "write_scale": 1.000,
     },
 }
 
