@@ -166,37 +166,44 @@ def test_dense_agrees_with_listed_stage_and_switches_by_density():
     assert worst < 1e-12
 
 
-def test_dense_fp32_close_to_fp64_oracle():
-    """FP32 tendencies with the dense finest level on the turbulence start (levels 3..6): rel L2
-    height error against the FP64 oracle below 1e-5 of the depth, mass conserved."""
-    _say("dense fp32 turbulence 3..6")
-    H = Hierarchy(3, 6)
-    og = H.g[6]
-    dh, u, Hd = _ic("turb", og.xyz, og.e_mid, og.e_tan)
+@pytest.mark.parametrize("case,jmin,jmax,eps", [("turb", 3, 6, 1e-2), ("jet", 4, 7, 5e-3)])
+def test_dense_fp32_close_to_fp64_oracle(case, jmin, jmax, eps):
+    """FP32 tendencies with the dense finest levels (the turbulence start on levels 3..6; the jet on
+    levels 4..7, where level 6 runs the intermediates-only form): rel L2 height error against the
+    FP64 oracle below 1e-5 of the depth on the finest level, mass conserved."""
+    _say(f"dense fp32 {case} {jmin}..{jmax}")
+    H = Hierarchy(jmin, jmax)
+    og = H.g[jmax]
+    dh, u, Hd = _ic(case, og.xyz, og.e_mid, og.e_tan)
     p = trisk.Params(mean_depth=Hd)
-    g = wt.Grid(3, 6, 8)
+    g = wt.Grid(jmin, jmax, 8)
     with g:
         g.set_params(mean_depth=Hd, precision=wt.WT_FP32_TENDENCY)
         g.set_dense_levels(0.0)
-        g.set_state(6, dh, u)
-        H.set_state(6, dh, u)
+        g.set_dense_min_tiles(0)
+        g.timing(True)
+        g.set_state(jmax, dh, u)
+        H.set_state(jmax, dh, u)
+        dt = 60.0 if case == "turb" else 0.8 * trisk.suggest_dt(og, dh, u, p, 1.0)
         m0 = None
         for _ in range(4):
-            g.adapt(1e-2)
-            H.adapt(1e-2)
+            g.adapt(eps)
+            H.adapt(eps)
             if m0 is None:
                 m0 = g.diagnostics()[0].mass
-            g.step(60.0)
-            H.step(60.0, p)
-        x = g.get_state(6)[0]
+            g.step(dt)
+            H.step(dt, p)
+        x = g.get_state(jmax)[0]
         d, code = g.diagnostics()
-    a = H.get_state(6)[0]
-    A = H.A[6]
+        inter = _inter_launches(g)
+    a = H.get_state(jmax)[0]
+    A = H.A[jmax]
     err = float(np.sqrt((A * (x - a) ** 2).sum() / (A * (Hd + a) ** 2).sum()))
-    _say(f"dense fp32: rel L2 height vs FP64 oracle {err:.2e}")
+    _say(f"dense fp32: rel L2 height vs FP64 oracle {err:.2e}, intermediates-only launches {inter}")
     assert code == wt.WT_OK
     assert err < 1e-5
     assert abs(d.mass / m0 - 1) < 1e-13
+    assert inter == (16 if jmax - 1 >= 6 else 0)
 
 
 def test_dense_levels_argument_errors():
