@@ -60,6 +60,29 @@ def test_host_builder_matches_oracle(J, oracle_grid):
         assert all(abs(mine[k] - ref[k]) < 1e-14 for k in ref)
 
 
+@pytest.mark.parametrize("jc,jmax", [(2, 4), (3, 4)])
+def test_host_flux_restriction_matches_oracle(jc, jmax):
+    """The library's flux-restriction rows between levels jc and jc+1 (eqs. (restr_flux),
+    (ho_flux), (kml); effective areas from level jmax) give the oracle's restricted flux on random
+    fine fluxes and divergences, on every coarse edge.  A row keeps at most 7 nonzero weights of its
+    8 slots -- fine nodes whose terms cancel exactly are left out when it is built -- and its
+    padding, after the nonzero entries, carries zero weight."""
+    from oracle.multiscale import Hierarchy
+    t = wt.host_pair_tables(jc, jmax)
+    lf = wt.host_level_tables(jc + 1)["l_e"]
+    lc = wt.host_level_tables(jc)["l_e"]
+    H = Hierarchy(jc, jmax)
+    rng = np.random.default_rng(7)
+    Ff = rng.standard_normal(lf.size)
+    cf = rng.standard_normal(H.g[jc + 1].N)
+    phi = (t["rf_fw"] * (lf[t["rf_f"]] * Ff[t["rf_f"]])).sum(1) + (t["rf_cw"] * cf[t["rf_c"]]).sum(1)
+    ref = H.flux_restrict(jc, Ff, cf)
+    assert np.abs(phi / lc - ref).max() <= 1e-12 * np.abs(ref).max()
+    nz = t["rf_cw"] != 0
+    assert nz.sum(1).max() <= 7
+    assert (np.diff(nz.astype(int), axis=1) <= 0).all()
+
+
 @pytest.mark.parametrize("J", [6, 7, 8])
 def test_lattice_reference_geometry(J):
     """The 10 lozenges are congruent (rotations of the icosahedron map lattice to lattice), so
