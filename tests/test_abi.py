@@ -83,6 +83,35 @@ def test_host_flux_restriction_matches_oracle(jc, jmax):
     assert (np.diff(nz.astype(int), axis=1) <= 0).all()
 
 
+@pytest.mark.parametrize("jc,jmax", [(2, 4), (3, 4)])
+def test_host_pair_tables_match_oracle(jc, jmax):
+    """The library's inter-scale tables between levels jc and jc+1 against the oracle's (same
+    numbering of nodes, edges and triangles): the height-prediction weights s~ per coarse edge
+    (eq. (WTpred)), the effective coarse areas, and the velocity predictions -- the three
+    interior fine edges of every coarse triangle and (p1 - p2) of every coarse edge -- evaluated
+    on random coarse velocities, all to round-off."""
+    from oracle.multiscale import Hierarchy
+    t = wt.host_pair_tables(jc, jmax)
+    H = Hierarchy(jc, jmax)
+    P, gc = H.pairs[jc], H.g[jc]
+    for e in range(gc.E):
+        mine = {int(c): w for c, w in zip(t["cells"][e], t["st"][e])}
+        ref = {int(c): w for c, w in zip(P.cells[e], P.st[e])}
+        assert mine.keys() == ref.keys()
+        # areas of clipped spherical polygons summed in another order: measured 1.1e-14
+        assert all(abs(mine[c] - ref[c]) < 1e-13 for c in ref)
+    assert np.abs(t["A_c"] - H.A[jc]).max() <= 1e-13 * np.abs(H.A[jc]).max()
+    uc = np.random.default_rng(3).standard_normal(gc.E)
+    mine = (t["w_int"] * uc[t["v_sten"]][:, None, :]).sum(2)
+    ref = P.u_int_pred(uc)
+    # the interior edges of a triangle may be listed in another order
+    assert np.abs(np.sort(mine, 1) - np.sort(ref, 1)).max() <= 1e-13 * np.abs(ref).max()
+    tl, tr = gc.e_tris[:, 0], gc.e_tris[:, 1]
+    mine = (t["w_pl"] * uc[t["v_sten"][tl]]).sum(1) + (t["w_pr"] * uc[t["v_sten"][tr]]).sum(1)
+    ref = P.u_pair_pred(uc)
+    assert np.abs(mine - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("J", [6, 7, 8])
 def test_lattice_reference_geometry(J):
     """The 10 lozenges are congruent (rotations of the icosahedron map lattice to lattice), so
